@@ -1,0 +1,230 @@
+/*
+ * fsmlmc.h -- C ABI of the MI355X (gfx950) Frequency-Splitting MLMC library.
+ *
+ * The library computes stochastic estimates of Tr(Gamma_n Omega_p D^-1) for the
+ * Wilson-Dirac operator D by Frequency Splitting (Whyte, Stathopoulos, Romero,
+ * Orginos, "Optimizing Shift Selection in Multilevel Monte Carlo for
+ * Disconnected Diagrams in Lattice QCD"): the inverse is split into levels with
+ * shifts 0 = sigma_0 < ... < sigma_L (Sec. 2.2, eq. tele_sum_prod_disp), each
+ * level is estimated with independent Z4 noise (eq. fs_trace_est) and its
+ * variance with eq. practical_variance.  The hot path -- shifted BiCGStab
+ * solves, Wilson dslash, BLAS-1, Z4 noise, the Wilson-line displacement and
+ * the bilinear reductions -- runs in HIP kernels for gfx950.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  * Sites: site = x + Lx*(y + Ly*(z + Lz*t)); mu = 0,1,2,3 is x,y,z,t.
+ *  * Canonical layouts (the only layouts that cross this ABI), interleaved
+ *    complex128 (re, im pairs of double):
+ *      gauge  [mu][site][row][col]       -- 4*V*9 complex
+ *      spinor [site][spin][colour]       -- 12*V complex; n_rhs spinors are
+ *                                           stored one after another.
+ *  * gamma matrices: DeGrand-Rossi basis, gamma_5 = g1 g2 g3 g4 =
+ *    diag(1,1,-1,-1).  Gamma_n = g1^b0 g2^b1 g3^b2 g4^b3 for n = sum b_k 2^k;
+ *    this 4-bit order is the row order of the paper's appendix speedup table.
+ *  * D + sigma: ((D+sigma) psi)(x) = (4 + m0 + sigma) psi(x)
+ *      - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu)],
+ *    periodic, optionally antiperiodic in t.
+ *  * Omega_p (Introduction: Omega_p = W Pi_p along z):
+ *      (Omega_p psi)(x) = U_z(x) U_z(x+z) ... U_z(x+(p-1)z) psi(x+pz).
+ *  * Pointers flagged is_device are device pointers on the context's device
+ *    (e.g. a torch tensor's data_ptr); otherwise host pointers.  The caller
+ *    owns every buffer it passes; the library never frees or keeps them.
+ *  * Every call returns fs_status and never aborts or throws across the ABI.
+ *    FS_E_ARG is returned before anything is written.  The message of the
+ *    last failing call on this thread is returned by fs_last_error().
+ *  * Work is issued on the context's HIP stream.  Calls that return results
+ *    through host pointers synchronise that stream before returning; calls
+ *    whose outputs are device pointers also synchronise (the ABI is
+ *    synchronous), so outputs are ready on return.
+ */
+#ifndef FSMLMC_H
+#define FSMLMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FS_OK = 0,
+    FS_E_ARG = -1,       /* invalid argument (nothing written)                 */
+    FS_E_HIP = -2,       /* HIP runtime error                                  */
+    FS_E_OOM = -3,       /* device allocation failed                           */
+    FS_E_NOCONV = -4,    /* a solve hit max_iter; outputs and stats still set  */
+    FS_E_BREAKDOWN = -5, /* unrecoverable BiCGStab breakdown (NaN/Inf)         */
+    FS_E_STATE = -6      /* call out of order (e.g. no gauge uploaded)         */
+} fs_status;
+
+typedef enum { FS_F64 = 0, FS_F32 = 1, FS_F16 = 2, FS_BF16 = 3 } fs_prec;
+
+typedef struct fs_ctx_s* fs_ctx;
+typedef struct fs_batch_s* fs_batch;
+
+/* Library version string (static storage). */
+const char* fs_version(void);
+
+/* Message of the last failing call on the calling thread (never NULL). */
+const char* fs_last_error(void);
+
+/*
+ * fs_create -- one lattice instance on one device.
+ *   dims[4]        Lx, Ly, Lz, Lt; each >= 2 (FS_E_ARG otherwise).
+ *   t_antiperiodic 0: periodic in t; 1: antiperiodic in t.
+ *   device         HIP device ordinal.
+ *   hip_stream     hipStream_t to issue work on (borrowed, never destroyed);
+ *                  NULL: the context creates and owns a default-priority stream.
+ * The context owns its device gauge copies, work buffers and autotune table.
+ */
+fs_status fs_create(fs_ctx* out, const int32_t dims[4], int32_t t_antiperiodic,
+                    int32_t device, void* hip_stream);
+fs_status fs_destroy(fs_ctx ctx);
+
+/* Per-process-unique instance index used in the noise counter (default 0). */
+fs_status fs_set_instance(fs_ctx ctx, uint32_t instance);
+
+/*
+ * fs_upload_gauge -- copy the links (canonical layout, 4*V*9 complex128) into
+ * the context, which keeps FP64, FP32, FP16 and BF16 device copies in its
+ * internal structure-of-arrays layout.  Links are used as given (no
+ * re-unitarisation).  Must precede every operator call (FS_E_STATE).
+ */
+fs_status fs_upload_gauge(fs_ctx ctx, const double* links, int32_t is_device);
+
+/*
+ * fs_apply_dirac -- out = (D + sigma) in for n_rhs spinors (canonical layout).
+ * storage: precision the spinors and links are held in while the stencil runs
+ * (inputs are rounded to it; FP64 accumulates in FP64, the others in FP32).
+ * Used for parity tests and the bandwidth benchmark.
+ */
+fs_status fs_apply_dirac(fs_ctx ctx, double m0, double sigma, fs_prec storage,
+                         const double* in, double* out, int32_t n_rhs, int32_t is_device);
+
+/*
+ * fs_z4_noise -- the Z4 noise vector for (seed, instance, level, sample) in
+ * canonical layout: component c = (site*4+spin)*3+colour takes the 2-bit code
+ * k = bits [2(c%32), 2(c%32)+1] of word (c%128)/32 of the Philox4x64-10 block
+ * with counter (c/128, sample, level, instance) and key (seed, 0); the value
+ * is i^k.  Bit-exact across implementations (paper eq. test: Z4 entries).
+ */
+fs_status fs_z4_noise(fs_ctx ctx, uint64_t seed, uint32_t instance, uint32_t level,
+                      uint64_t sample, double* out, int32_t is_device);
+
+/* fs_displace -- out = Omega_p in (one spinor, canonical layout), p >= 0. */
+fs_status fs_displace(fs_ctx ctx, int32_t p, const double* in, double* out, int32_t is_device);
+
+/*
+ * fs_bilinear -- out[p][n] = y^dagger Gamma_n Omega_p x for p = 0..p_max and
+ * all 16 n (complex128, host pointer), y and x one spinor each (canonical).
+ * This is the displaced bilinear of eq. fs_trace_est, computed by the fused
+ * hop + 4x4 spin-correlation reduction in FP64.
+ */
+fs_status fs_bilinear(fs_ctx ctx, int32_t p_max, const double* y, const double* x,
+                      double* out, int32_t is_device);
+
+typedef struct {
+    double m0;             /* bare mass                                            */
+    double tol;            /* stop when FP64 ||b - (D+sigma)x|| / ||b|| <= tol      */
+    int32_t max_iter;      /* Krylov iterations per system (all precisions)        */
+    fs_prec storage;       /* Krylov storage: FS_F64 plain; FS_F32/F16/BF16 mixed   */
+    int32_t rhs_block;     /* RHS per block in batched launches: 1,2,4,8,16; 0=tuned */
+    int32_t use_graph;     /* capture the inner iterations in a hipGraph            */
+    double reliable_delta; /* mixed: FP64 reliable update when ||r|| drops by this  */
+    int32_t check_every;   /* iterations between host convergence checks (0 = 8)    */
+    int32_t batched;       /* 0: one system at a time; 1: all systems in one batch  */
+} fs_solve_params;
+
+typedef struct {
+    int32_t iters;             /* Krylov iterations                              */
+    int32_t reliable_updates;  /* FP64 residual recomputations                   */
+    int32_t status;            /* FS_OK, FS_E_NOCONV or FS_E_BREAKDOWN            */
+    int32_t restarts;          /* breakdown restarts                             */
+    double true_rel_residual;  /* FP64 ||b - (D+sigma)x|| / ||b|| at exit        */
+} fs_solve_stats;
+
+/*
+ * fs_solve_shifted -- X[s][r] = (D + sigma[s])^-1 B[r] for s < n_shift, r < n_rhs
+ * (paper eq. shifted_linear_systems), B and X canonical spinors (FP64),
+ * X laid out [n_shift][n_rhs][spinor].  stats: [n_shift*n_rhs] or NULL.
+ * Returns FS_E_NOCONV if any system missed tol (X still holds its iterate).
+ */
+fs_status fs_solve_shifted(fs_ctx ctx, const fs_solve_params* prm, const double* sigma,
+                           int32_t n_shift, const double* B, int32_t n_rhs, double* X,
+                           int32_t is_device, fs_solve_stats* stats);
+
+typedef struct {
+    uint64_t seed;           /* noise seed                                          */
+    int32_t n_noise;         /* Z4 vectors per level (>= 2 for a variance)          */
+    uint16_t gamma_mask;     /* bit n -> report Gamma_n (0 = all 16)                */
+    int32_t p_max;           /* displacements p = 0..p_max, p_max < Lz              */
+    fs_solve_params solve;   /* solver settings (storage FS_F64 = plain path)       */
+} fs_est_params;
+
+typedef struct {
+    double tr_re, tr_im;     /* level mean (1/N) sum X_s                            */
+    double var_paper;        /* (1/N) sum |X_s|^2 - |mean|^2 (eq. practical_variance) */
+    double var_unbiased;     /* var_paper * N/(N-1)                                 */
+    int64_t n;               /* samples                                             */
+    double max_rel_residual; /* worst FP64 true residual of this level's solves     */
+} fs_level_stat;
+
+typedef struct {
+    int64_t systems;         /* shifted systems solved                              */
+    int64_t iterations;      /* sum of Krylov iterations                            */
+    int64_t reliable_updates;
+    int64_t dslash_calls;    /* stencil launches (each covers a batch of systems)   */
+    double max_rel_residual; /* worst FP64 true residual                            */
+    double seconds;          /* wall time of the call                               */
+} fs_est_report;
+
+/*
+ * fs_estimate -- per-level FS estimates for all requested Gamma_n and
+ * p = 0..p_max on this context's lattice.  sigma[0..L] with sigma[0] = 0 and
+ * strictly increasing (FS_E_ARG otherwise).  Level l < L uses
+ * X = (sigma_{l+1}-sigma_l) y^+ Gamma_n Omega_p x with x = (D+sigma_{l+1})^-1 z,
+ * y = g5 (D+sigma_l)^-1 g5 z; level L uses X = z^+ Gamma_n Omega_p (D+sigma_L)^-1 z;
+ * z is the Z4 vector (seed, instance, level, sample), samples 0..n_noise-1.
+ *   out          [(L+1)][16][p_max+1] fs_level_stat (unrequested Gamma zeroed)
+ *   samples_out  NULL or host [(L+1)][n_noise][16][p_max+1] complex128: every X_s
+ *   report       NULL or totals of the call
+ */
+fs_status fs_estimate(fs_ctx ctx, const fs_est_params* prm, const double* sigma, int32_t L,
+                      fs_level_stat* out, double* samples_out, fs_est_report* report);
+
+/*
+ * Batches of uneven lattice instances that share persistent launches: every
+ * stencil, BLAS and reduction launch of fs_batch_estimate covers the systems
+ * of all instances.  Contexts must be on the same device and have gauge
+ * uploaded; instance k uses noise instance index (its fs_set_instance value).
+ *   out [n][(L+1)][16][p_max+1]
+ */
+fs_status fs_batch_create(fs_batch* out, const fs_ctx* ctxs, int32_t n);
+fs_status fs_batch_estimate(fs_batch b, const fs_est_params* prm, const double* sigma,
+                            int32_t L, fs_level_stat* out, fs_est_report* report);
+fs_status fs_batch_destroy(fs_batch b);
+
+/*
+ * fs_autotune -- time the batched stencil for rhs_block in {1,2,4,8,16} x
+ * work-group size in {64,128,256,512} at the given storage precision and keep
+ * the fastest per (precision, n_rhs class) in the context.  cache_path: a text
+ * file keyed by (arch, dims, precision, rhs_block) read first and appended
+ * to; NULL keeps the table in memory only.  best_rhs_block / best_wg may be NULL.
+ */
+fs_status fs_autotune(fs_ctx ctx, fs_prec storage, const char* cache_path,
+                      int32_t* best_rhs_block, int32_t* best_wg);
+
+/*
+ * fs_time_dslash -- average duration (ms, HIP events on the context's stream)
+ * of n_launch back-to-back stencil launches at (storage, rhs_block,
+ * work-group size wg; 0 = tuned) on n_sys systems, and the algorithmic
+ * bytes one launch moves.  For roofline reporting.
+ */
+fs_status fs_time_dslash(fs_ctx ctx, fs_prec storage, int32_t n_sys, int32_t rhs_block,
+                         int32_t wg, int32_t n_launch, double* avg_ms, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSMLMC_H */

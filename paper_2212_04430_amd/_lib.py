@@ -1,0 +1,293 @@
+"""ctypes binding of libfsmlmc.so: the C-ABI entry points under the same names.
+
+Argument marshalling only: every computation runs in the HIP library.  Arrays
+may be numpy arrays (host, complex128/float64, C-contiguous) or torch tensors
+on the GPU (device pointers are passed straight through); outputs are returned
+as the same kind of array.  If the library is not built or cannot be loaded
+this module raises at import time -- there is no fallback.
+"""
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfsmlmc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2212_04430_amd.build`")
+# One HIP runtime per process: when torch is present its runtime is loaded
+# first and the library binds to it (same soname), so torch tensors and
+# streams are valid handles for the library.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    torch = None
+_lib = C.CDLL(LIB_PATH)
+
+FS_OK, FS_E_ARG, FS_E_HIP, FS_E_OOM, FS_E_NOCONV, FS_E_BREAKDOWN, FS_E_STATE = 0, -1, -2, -3, -4, -5, -6
+FS_F64, FS_F32, FS_F16, FS_BF16 = 0, 1, 2, 3
+PREC = {"f64": FS_F64, "f32": FS_F32, "f16": FS_F16, "bf16": FS_BF16}
+STATUS_NAME = {0: "FS_OK", -1: "FS_E_ARG", -2: "FS_E_HIP", -3: "FS_E_OOM", -4: "FS_E_NOCONV",
+               -5: "FS_E_BREAKDOWN", -6: "FS_E_STATE"}
+
+
+class FsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAME.get(code, code)}: {msg}")
+        self.code = code
+
+
+class fs_solve_params(C.Structure):
+    _fields_ = [("m0", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("storage", C.c_int32), ("rhs_block", C.c_int32), ("use_graph", C.c_int32),
+                ("reliable_delta", C.c_double), ("check_every", C.c_int32), ("batched", C.c_int32)]
+
+
+class fs_solve_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("reliable_updates", C.c_int32), ("status", C.c_int32),
+                ("restarts", C.c_int32), ("true_rel_residual", C.c_double)]
+
+
+class fs_est_params(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("n_noise", C.c_int32), ("gamma_mask", C.c_uint16),
+                ("p_max", C.c_int32), ("solve", fs_solve_params)]
+
+
+class fs_level_stat(C.Structure):
+    _fields_ = [("tr_re", C.c_double), ("tr_im", C.c_double), ("var_paper", C.c_double),
+                ("var_unbiased", C.c_double), ("n", C.c_int64), ("max_rel_residual", C.c_double)]
+
+
+class fs_est_report(C.Structure):
+    _fields_ = [("systems", C.c_int64), ("iterations", C.c_int64), ("reliable_updates", C.c_int64),
+                ("dslash_calls", C.c_int64), ("max_rel_residual", C.c_double), ("seconds", C.c_double)]
+
+
+_P = C.c_void_p
+_sig = {
+    "fs_version": (C.c_char_p, []),
+    "fs_last_error": (C.c_char_p, []),
+    "fs_create": (C.c_int, [C.POINTER(_P), C.POINTER(C.c_int32), C.c_int32, C.c_int32, _P]),
+    "fs_destroy": (C.c_int, [_P]),
+    "fs_set_instance": (C.c_int, [_P, C.c_uint32]),
+    "fs_upload_gauge": (C.c_int, [_P, _P, C.c_int32]),
+    "fs_apply_dirac": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, _P, _P, C.c_int32, C.c_int32]),
+    "fs_z4_noise": (C.c_int, [_P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, _P, C.c_int32]),
+    "fs_displace": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int32]),
+    "fs_bilinear": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int32]),
+    "fs_solve_shifted": (C.c_int, [_P, C.POINTER(fs_solve_params), _P, C.c_int32, _P, C.c_int32, _P,
+                                   C.c_int32, C.POINTER(fs_solve_stats)]),
+    "fs_estimate": (C.c_int, [_P, C.POINTER(fs_est_params), _P, C.c_int32, C.POINTER(fs_level_stat), _P,
+                              C.POINTER(fs_est_report)]),
+    "fs_batch_create": (C.c_int, [C.POINTER(_P), C.POINTER(_P), C.c_int32]),
+    "fs_batch_estimate": (C.c_int, [_P, C.POINTER(fs_est_params), _P, C.c_int32, C.POINTER(fs_level_stat),
+                                    C.POINTER(fs_est_report)]),
+    "fs_batch_destroy": (C.c_int, [_P]),
+    "fs_autotune": (C.c_int, [_P, C.c_int32, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "fs_time_dslash": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+def _check(code, allow=()):
+    if code != FS_OK and code not in allow:
+        raise FsError(code, _lib.fs_last_error().decode())
+    return code
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a):
+    """(pointer, is_device) of a numpy array or a CUDA/HIP torch tensor."""
+    if _is_torch(a):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return C.c_void_p(a.data_ptr()), 1 if a.is_cuda else 0
+    if not a.flags.c_contiguous:
+        raise ValueError("array must be C-contiguous")
+    return C.c_void_p(a.ctypes.data), 0
+
+
+def _host_c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _like(a, shape):
+    if _is_torch(a):
+        import torch
+        return torch.empty(shape, dtype=torch.complex128, device=a.device)
+    return np.empty(shape, dtype=np.complex128)
+
+
+def _prec(p):
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+def solve_params(m0, tol=1e-10, max_iter=10000, storage="f64", rhs_block=0, use_graph=0,
+                 reliable_delta=0.0, check_every=0, batched=0):
+    return fs_solve_params(m0, tol, max_iter, _prec(storage), rhs_block, int(use_graph), reliable_delta,
+                           check_every, int(batched))
+
+
+# ------------------------------------------------------------------ entry points
+
+def fs_version():
+    return _lib.fs_version().decode()
+
+
+def fs_last_error():
+    return _lib.fs_last_error().decode()
+
+
+def fs_create(dims, t_antiperiodic=0, device=0, stream=None):
+    h = C.c_void_p()
+    d = (C.c_int32 * 4)(*[int(x) for x in dims])
+    _check(_lib.fs_create(C.byref(h), d, int(t_antiperiodic), int(device),
+                          C.c_void_p(stream) if stream else None))
+    return h
+
+
+def fs_destroy(ctx):
+    _check(_lib.fs_destroy(ctx))
+
+
+def fs_set_instance(ctx, instance):
+    _check(_lib.fs_set_instance(ctx, int(instance)))
+
+
+def fs_upload_gauge(ctx, links):
+    if not _is_torch(links):
+        links = _host_c128(links)
+    p, dev = _ptr(links)
+    _check(_lib.fs_upload_gauge(ctx, p, dev))
+
+
+def fs_apply_dirac(ctx, m0, sigma, storage, psi):
+    """(D + sigma) psi for one spinor (V,4,3) or a stack (n,V,4,3)."""
+    if not _is_torch(psi):
+        psi = _host_c128(psi)
+    n = 1 if psi.ndim == 3 else psi.shape[0]
+    out = _like(psi, tuple(psi.shape))
+    pi, dev = _ptr(psi)
+    po, _ = _ptr(out)
+    _check(_lib.fs_apply_dirac(ctx, float(m0), float(sigma), _prec(storage), pi, po, n, dev))
+    return out
+
+
+def fs_z4_noise(ctx, V, seed, instance, level, sample, device=None):
+    out = _like(device, (V, 4, 3)) if device is not None else np.empty((V, 4, 3), dtype=np.complex128)
+    po, dev = _ptr(out)
+    _check(_lib.fs_z4_noise(ctx, int(seed), int(instance), int(level), int(sample), po, dev))
+    return out
+
+
+def fs_displace(ctx, p, psi):
+    if not _is_torch(psi):
+        psi = _host_c128(psi)
+    out = _like(psi, tuple(psi.shape))
+    pi, dev = _ptr(psi)
+    po, _ = _ptr(out)
+    _check(_lib.fs_displace(ctx, int(p), pi, po, dev))
+    return out
+
+
+def fs_bilinear(ctx, p_max, y, x):
+    """out[p, n] = y^+ Gamma_n Omega_p x (host complex128 array (p_max+1, 16))."""
+    if not _is_torch(y):
+        y = _host_c128(y)
+        x = _host_c128(x)
+    out = np.empty((p_max + 1, 16), dtype=np.complex128)
+    py, dev = _ptr(y)
+    px, _ = _ptr(x)
+    _check(_lib.fs_bilinear(ctx, int(p_max), py, px, C.c_void_p(out.ctypes.data), 0))
+    return out
+
+
+def fs_solve_shifted(ctx, params, sigma, B, allow_noconv=False):
+    """X[s, r] = (D + sigma_s)^-1 B[r]; returns (X, stats list, status)."""
+    if not _is_torch(B):
+        B = _host_c128(B)
+    if B.ndim == 3:
+        B = B.reshape((1,) + tuple(B.shape))
+    n_rhs = B.shape[0]
+    sig = np.ascontiguousarray(sigma, dtype=np.float64)
+    X = _like(B, (len(sig),) + tuple(B.shape))
+    st = (fs_solve_stats * (len(sig) * n_rhs))()
+    pb, dev = _ptr(B)
+    px, _ = _ptr(X)
+    code = _lib.fs_solve_shifted(ctx, C.byref(params), C.c_void_p(sig.ctypes.data), len(sig), pb, n_rhs, px,
+                                 dev, st)
+    _check(code, allow=(FS_E_NOCONV,) if allow_noconv else ())
+    return X, [st[i] for i in range(len(st))], code
+
+
+def _stats_array(stats, shape):
+    a = np.zeros(shape + (6,))
+    flat = a.reshape(-1, 6)
+    for i, s in enumerate(stats):
+        flat[i] = (s.tr_re, s.tr_im, s.var_paper, s.var_unbiased, s.n, s.max_rel_residual)
+    return a
+
+
+def fs_estimate(ctx, params, sigma, want_samples=False, allow_noconv=False):
+    """Per-level stats as an array [L+1, 16, p_max+1, 6] (tr_re, tr_im, var_paper,
+    var_unbiased, n, max_rel_residual), the per-sample X [L+1, N, 16, p_max+1]
+    (or None) and the report."""
+    sig = np.ascontiguousarray(sigma, dtype=np.float64)
+    L = len(sig) - 1
+    P1 = params.p_max + 1
+    out = (fs_level_stat * ((L + 1) * 16 * P1))()
+    samples = np.zeros((L + 1, params.n_noise, 16, P1), dtype=np.complex128) if want_samples else None
+    rep = fs_est_report()
+    code = _lib.fs_estimate(ctx, C.byref(params), C.c_void_p(sig.ctypes.data), L, out,
+                            C.c_void_p(samples.ctypes.data) if want_samples else None, C.byref(rep))
+    _check(code, allow=(FS_E_NOCONV,) if allow_noconv else ())
+    return _stats_array(list(out), (L + 1, 16, P1)), samples, rep
+
+
+def fs_batch_create(ctxs):
+    h = C.c_void_p()
+    arr = (C.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    _check(_lib.fs_batch_create(C.byref(h), arr, len(ctxs)))
+    return h
+
+
+def fs_batch_estimate(batch, n_inst, params, sigma, allow_noconv=False):
+    sig = np.ascontiguousarray(sigma, dtype=np.float64)
+    L = len(sig) - 1
+    P1 = params.p_max + 1
+    out = (fs_level_stat * (n_inst * (L + 1) * 16 * P1))()
+    rep = fs_est_report()
+    code = _lib.fs_batch_estimate(batch, C.byref(params), C.c_void_p(sig.ctypes.data), L, out, C.byref(rep))
+    _check(code, allow=(FS_E_NOCONV,) if allow_noconv else ())
+    return _stats_array(list(out), (n_inst, L + 1, 16, P1)), rep
+
+
+def fs_batch_destroy(batch):
+    _check(_lib.fs_batch_destroy(batch))
+
+
+def fs_autotune(ctx, storage, cache_path=None):
+    nr = C.c_int32()
+    wg = C.c_int32()
+    _check(_lib.fs_autotune(ctx, _prec(storage), cache_path.encode() if cache_path else None, C.byref(nr),
+                            C.byref(wg)))
+    return nr.value, wg.value
+
+
+def fs_time_dslash(ctx, storage, n_sys, rhs_block=0, wg=0, n_launch=20):
+    ms = C.c_double()
+    b = C.c_double()
+    _check(_lib.fs_time_dslash(ctx, _prec(storage), int(n_sys), int(rhs_block), int(wg), int(n_launch),
+                               C.byref(ms), C.byref(b)))
+    return ms.value, b.value

@@ -1,0 +1,1264 @@
+// C ABI and host runtime of the FS-MLMC library: contexts, gauge upload, work
+// plans, the batched BiCGStab driver (FP64 or mixed precision with FP64
+// reliable updates, optionally hipGraph-captured), the Frequency-Splitting
+// estimator over one or several lattices, the autotuner and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fsmlmc.h"
+#include "fs_kernels.h"
+
+using namespace fs;
+
+// ============================================================== errors
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+struct FsError : std::runtime_error {
+    fs_status code;
+    FsError(fs_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(fs_status c, const std::string& m) { throw FsError(c, m); }
+
+void hipchk(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+            fail(FS_E_OOM, std::string(what) + ": " + hipGetErrorString(e));
+        fail(FS_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+#define HC(x) hipchk((x), #x)
+
+template <typename F>
+fs_status guard(F&& f) {
+    try {
+        f();
+        return FS_OK;
+    } catch (const FsError& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return FS_E_OOM;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return FS_E_HIP;
+    } catch (...) {
+        g_err = "unknown error";
+        return FS_E_HIP;
+    }
+}
+
+// ============================================================== device memory
+
+// Caching device allocator: freed blocks are kept per (device, size) and
+// reused, so repeated solves and estimates do not call hipMalloc/hipFree in
+// their loops.  Sizes are rounded up to 2 MiB above 1 MiB.
+struct Pool {
+    std::multimap<std::pair<int, size_t>, void*> free_;
+    size_t cached = 0;
+    static constexpr size_t kMaxCached = (size_t)8 << 30;
+    static size_t round(size_t n) {
+        if (n <= (1u << 20)) return (n + 255) & ~(size_t)255;
+        const size_t g = (size_t)2 << 20;
+        return (n + g - 1) / g * g;
+    }
+    void* get(size_t n, hipError_t* err) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        auto it = free_.find({dev, n});
+        if (it != free_.end()) {
+            void* p = it->second;
+            free_.erase(it);
+            cached -= n;
+            *err = hipSuccess;
+            return p;
+        }
+        void* p = nullptr;
+        *err = hipMalloc(&p, n);
+        if (*err != hipSuccess) {
+            trim(0);
+            *err = hipMalloc(&p, n);
+        }
+        return *err == hipSuccess ? p : nullptr;
+    }
+    void put(void* p, size_t n) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        free_.insert({{dev, n}, p});
+        cached += n;
+        if (cached > kMaxCached) trim(kMaxCached / 2);
+    }
+    void trim(size_t keep) {
+        while (cached > keep && !free_.empty()) {
+            auto it = std::prev(free_.end());  // largest first
+            (void)hipDeviceSynchronize();
+            (void)hipFree(it->second);
+            cached -= it->first.second;
+            free_.erase(it);
+        }
+    }
+};
+Pool& pool() {
+    static Pool* p = new Pool();  // never destroyed: blocks live until process exit
+    return *p;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t bytes) { alloc(bytes); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            n = o.n;
+            o.p = nullptr;
+            o.n = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t bytes) {
+        release();
+        const size_t nb = Pool::round(bytes == 0 ? 16 : bytes);
+        hipError_t e;
+        p = pool().get(nb, &e);
+        hipchk(e, "device allocation");
+        n = nb;
+    }
+    void release() {
+        if (p) pool().put(p, n);
+        p = nullptr;
+        n = 0;
+    }
+    template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// Pinned host staging buffer.
+struct HostBuf {
+    void* p = nullptr;
+    size_t n = 0;
+    ~HostBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+    void ensure(size_t bytes) {
+        if (bytes <= n) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        HC(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+        n = bytes;
+    }
+};
+
+int prec_group_bytes_spinor(int P) { return P == P64 ? 192 : P == P32 ? 96 : 48; }
+int prec_link_complex_bytes(int P) { return P == P64 ? 16 : P == P32 ? 8 : 4; }
+int prec_groups(int P) { return P == P64 ? 12 : P == P32 ? 6 : 3; }
+
+// ============================================================== gamma table
+
+GammaTab make_gamma_tab() {
+    using C = std::complex<double>;
+    const C I(0, 1);
+    C g[4][4][4] = {
+        {{0, 0, 0, I}, {0, 0, I, 0}, {0, -I, 0, 0}, {-I, 0, 0, 0}},
+        {{0, 0, 0, -1}, {0, 0, 1, 0}, {0, 1, 0, 0}, {-1, 0, 0, 0}},
+        {{0, 0, I, 0}, {0, 0, 0, -I}, {-I, 0, 0, 0}, {0, I, 0, 0}},
+        {{0, 0, 1, 0}, {0, 0, 0, 1}, {1, 0, 0, 0}, {0, 1, 0, 0}},
+    };
+    GammaTab t;
+    for (int n = 0; n < 16; ++n) {
+        C M[4][4] = {};
+        for (int a = 0; a < 4; ++a) M[a][a] = 1;
+        for (int k = 0; k < 4; ++k) {
+            if (!((n >> k) & 1)) continue;
+            C R[4][4] = {};
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b)
+                    for (int c = 0; c < 4; ++c) R[a][b] += M[a][c] * g[k][c][b];
+            std::memcpy(M, R, sizeof(M));
+        }
+        for (int a = 0; a < 4; ++a) {
+            int col = -1, ph = -1;
+            for (int b = 0; b < 4; ++b) {
+                if (std::abs(M[a][b]) > 0.5) {
+                    col = b;
+                    const C v = M[a][b];
+                    ph = std::abs(v - C(1, 0)) < 1e-12 ? 0 : std::abs(v - I) < 1e-12 ? 1 : std::abs(v + C(1, 0)) < 1e-12 ? 2 : 3;
+                }
+            }
+            t.perm[n][a] = (int8_t)col;
+            t.ph[n][a] = (int8_t)ph;
+        }
+    }
+    return t;
+}
+
+}  // namespace
+
+// ============================================================== context
+
+struct TuneEntry {
+    int nr = 0, wg = 0;
+    double ms_per_sys = 0;
+};
+
+struct fs_ctx_s {
+    int dims[4] = {0, 0, 0, 0};
+    int V = 0;
+    int tsign = 1;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint32_t instance = 0;
+    bool has_gauge = false;
+    DevBuf gauge[4];                 // [mu][9][site] per precision
+    std::map<int, TuneEntry> tune;   // per precision
+    HostBuf pinned;
+};
+
+struct fs_batch_s {
+    std::vector<fs_ctx> ctxs;
+};
+
+namespace {
+
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev) {
+        HC(hipGetDevice(&prev));
+        if (prev != dev) HC(hipSetDevice(dev));
+    }
+    ~DeviceScope() {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && prev >= 0 && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+LatDesc lat_desc(const fs_ctx_s* c, int P) {
+    LatDesc d;
+    for (int i = 0; i < 4; ++i) d.L[i] = c->dims[i];
+    d.V = c->V;
+    d.tsign = c->tsign;
+    d.gauge = c->gauge[P].p;
+    return d;
+}
+
+int ilog2(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+bool pow2_ok(int n) { return n >= 1 && n <= 16 && (n & (n - 1)) == 0; }
+
+// ============================================================== plans
+
+// A batch of blocks (each NR systems of one lattice) mapped to workgroups.
+struct Plan {
+    int nr = 1, lognr = 0, wg = 256, tpw = 1;
+    int nsys = 0;                     // nblk * nr
+    std::vector<BlockDesc> blocks;
+    std::vector<int> wg_start;        // nblk + 1
+    std::vector<int> lat_V;           // per lattice
+    long long total_slots = 0;
+    // device tables
+    DevBuf d_blocks, d_wg_start, d_blk_on;
+    DevBuf d_lats[4];
+    DevBuf d_wg_start_alt;            // alternative start table (hop launches)
+
+    Work work(int P, bool use_blk_on) const {
+        Work w;
+        w.lats = d_lats[P].as<LatDesc>();
+        w.blocks = d_blocks.as<BlockDesc>();
+        w.wg_start = d_wg_start.as<int>();
+        w.nblk = (int)blocks.size();
+        w.total_wg = wg_start.back();
+        w.tpw = tpw;
+        w.wg = wg;
+        w.nr = nr;
+        w.lognr = lognr;
+        w.blk_on = use_blk_on ? d_blk_on.as<int>() : nullptr;
+        return w;
+    }
+};
+
+constexpr int kTargetWG = 4096;  // workgroups per launch to aim for (256 CUs x 16)
+
+// blk_lat[b]: lattice of block b; lats: the contexts of the lattices.
+std::unique_ptr<Plan> make_plan(const std::vector<int>& blk_lat, const std::vector<fs_ctx_s*>& lats, int nr, int wg,
+                                hipStream_t s) {
+    auto pl = std::make_unique<Plan>();
+    pl->nr = nr;
+    pl->lognr = ilog2(nr);
+    pl->wg = wg;
+    const int nblk = (int)blk_lat.size();
+    pl->nsys = nblk * nr;
+    for (auto* c : lats) pl->lat_V.push_back(c->V);
+    long long tiles_total = 0;
+    std::vector<long long> tiles(nblk);
+    for (int b = 0; b < nblk; ++b) {
+        const long long slots = (long long)lats[blk_lat[b]]->V * nr;
+        tiles[b] = (slots + wg - 1) / wg;
+        tiles_total += tiles[b];
+    }
+    pl->tpw = (int)std::max<long long>(1, tiles_total / kTargetWG);
+    pl->wg_start.resize(nblk + 1);
+    pl->wg_start[0] = 0;
+    long long off = 0;
+    pl->blocks.resize(nblk);
+    for (int b = 0; b < nblk; ++b) {
+        pl->blocks[b].lat = blk_lat[b];
+        pl->blocks[b].sys0 = b * nr;
+        pl->blocks[b].slot_off = off;
+        off += (long long)lats[blk_lat[b]]->V * nr;
+        const long long nwg = (tiles[b] + pl->tpw - 1) / pl->tpw;
+        if (pl->wg_start[b] + nwg > (1ll << 30)) fail(FS_E_ARG, "batch too large for one launch");
+        pl->wg_start[b + 1] = pl->wg_start[b] + (int)nwg;
+    }
+    pl->total_slots = off;
+    pl->d_blocks.alloc(sizeof(BlockDesc) * nblk);
+    pl->d_wg_start.alloc(sizeof(int) * (nblk + 1));
+    pl->d_blk_on.alloc(sizeof(int) * nblk);
+    HC(hipMemcpyAsync(pl->d_blocks.p, pl->blocks.data(), sizeof(BlockDesc) * nblk, hipMemcpyHostToDevice, s));
+    HC(hipMemcpyAsync(pl->d_wg_start.p, pl->wg_start.data(), sizeof(int) * (nblk + 1), hipMemcpyHostToDevice, s));
+    std::vector<int> ones(nblk, 1);
+    HC(hipMemcpyAsync(pl->d_blk_on.p, ones.data(), sizeof(int) * nblk, hipMemcpyHostToDevice, s));
+    std::vector<LatDesc> ld[4];
+    for (int P = 0; P < 4; ++P) {
+        for (auto* c : lats) ld[P].push_back(lat_desc(c, P));
+        pl->d_lats[P].alloc(sizeof(LatDesc) * ld[P].size());
+        HC(hipMemcpyAsync(pl->d_lats[P].p, ld[P].data(), sizeof(LatDesc) * ld[P].size(), hipMemcpyHostToDevice, s));
+    }
+    HC(hipStreamSynchronize(s));
+    return pl;
+}
+
+// A block-layout field over a whole plan.
+struct Field {
+    int P = P64;
+    DevBuf v, n;
+    void alloc(int prec, long long slots) {
+        P = prec;
+        v.alloc((size_t)slots * prec_group_bytes_spinor(prec));
+        if (prec == P16) n.alloc((size_t)slots * sizeof(float));
+    }
+    Fld f() const {
+        Fld r;
+        r.v = v.as<uint4>();
+        r.n = n.as<float>();
+        return r;
+    }
+};
+
+// ============================================================== solver
+
+struct SolveOpts {
+    int P = P64;
+    double tol = 1e-10;
+    int max_iter = 10000;
+    double delta = 0.0;
+    int check_every = 8;
+    bool use_graph = false;
+};
+
+// Systems of a plan, with sources in `b` (FP64 block layout) and per-system
+// shifts.  On return xhi holds the solutions and `st_host` the final states.
+struct BatchSolver {
+    Plan& pl;
+    std::vector<fs_ctx_s*> lats;
+    hipStream_t s;
+    SolveOpts o;
+    Field b, xhi, rhi, r, rhat, p, v, t, xlo;
+    DevBuf d_diag, d_st, d_part;
+    std::vector<SysState> st_host;
+    long long dslash_calls = 0;
+
+    BatchSolver(Plan& plan, const std::vector<fs_ctx_s*>& l, hipStream_t stream, const SolveOpts& opts)
+        : pl(plan), lats(l), s(stream), o(opts) {
+        const long long S = pl.total_slots;
+        b.alloc(P64, S);
+        xhi.alloc(P64, S);
+        rhi.alloc(P64, S);
+        for (Field* f : {&r, &rhat, &p, &v, &t, &xlo}) f->alloc(o.P, S);
+        d_diag.alloc(sizeof(double) * pl.nsys);
+        d_st.alloc(sizeof(SysState) * pl.nsys);
+        // partial sums: max 4 doubles per rhs per workgroup (32 for hop launches)
+        d_part.alloc(sizeof(double) * (size_t)pl.wg_start.back() * 32 * pl.nr);
+        st_host.resize(pl.nsys);
+    }
+
+    // diag[sys] = 4 + m0 + sigma; idle marks padding systems.
+    void setup(const std::vector<double>& diag, const std::vector<char>& idle) {
+        HC(hipMemcpyAsync(d_diag.p, diag.data(), sizeof(double) * pl.nsys, hipMemcpyHostToDevice, s));
+        for (int i = 0; i < pl.nsys; ++i) {
+            SysState z;
+            std::memset(&z, 0, sizeof(z));
+            z.tol2 = o.tol * o.tol;
+            z.delta2 = o.delta * o.delta;
+            z.max_iter = o.max_iter;
+            z.state = idle[i] ? S_IDLE : S_RUN;
+            st_host[i] = z;
+        }
+        HC(hipMemcpyAsync(d_st.p, st_host.data(), sizeof(SysState) * pl.nsys, hipMemcpyHostToDevice, s));
+    }
+
+    SysState* st() { return d_st.as<SysState>(); }
+    double* part() { return d_part.as<double>(); }
+    int* blk_on() { return pl.d_blk_on.as<int>(); }
+
+    void iteration(const Work& w) {
+        const double* dg = d_diag.as<double>();
+        launch_dslash(o.P, D_RHAT, w, v.f(), p.f(), rhat.f(), dg, st(), M_RUN, part(), s);
+        launch_finish(F_ALPHA, w, st(), part(), blk_on(), s);
+        launch_axpy_s(o.P, w, r.f(), v.f(), st(), s);
+        launch_dslash(o.P, D_TS, w, t.f(), r.f(), Fld(), dg, st(), M_RUN, part(), s);
+        launch_finish(F_OMEGA, w, st(), part(), blk_on(), s);
+        launch_update_xr(o.P, w, xlo.f(), p.f(), r.f(), t.f(), rhat.f(), st(), part(), s);
+        launch_finish(F_RHO, w, st(), part(), blk_on(), s);
+        launch_update_p(o.P, w, p.f(), r.f(), v.f(), st(), s);
+        dslash_calls += 2;
+    }
+
+    void reliable(const Work& w, const Work& w64) {
+        launch_blk_mask(w, st(), M_PEND, blk_on(), s);
+        launch_fold(o.P, w, xhi.f(), xlo.f(), st(), s);
+        launch_dslash(P64, D_RESID, w64, rhi.f(), xhi.f(), b.f(), d_diag.as<double>(), st(), M_PEND, part(), s);
+        launch_finish(F_TRUE, w, st(), part(), blk_on(), s);
+        launch_convert(o.P, w, rhi.f(), r.f(), rhat.f(), p.f(), st(), part(), s);
+        launch_finish(F_RESUME, w, st(), part(), blk_on(), s);
+        launch_blk_mask(w, st(), M_RUN, blk_on(), s);
+        dslash_calls += 1;
+    }
+
+    void run() {
+        const Work w = pl.work(o.P, true);
+        const Work w64 = pl.work(P64, true);
+        Work winit = pl.work(o.P, false);
+        launch_init(o.P, winit, b.f(), xhi.f(), xlo.f(), rhi.f(), r.f(), rhat.f(), p.f(), part(), s);
+        launch_finish(F_INIT, w, st(), part(), blk_on(), s);
+        const int k = std::max(1, o.check_every);
+        hipGraphExec_t exec = nullptr;
+        hipGraph_t graph = nullptr;
+        if (o.use_graph) {
+            HC(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < k; ++i) iteration(w);
+            dslash_calls -= 2 * k;
+            HC(hipStreamEndCapture(s, &graph));
+            HC(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        }
+        const long long cap = (long long)o.max_iter * 4 + 64;  // host-side bound on chunks
+        long long chunks = 0;
+        try {
+            while (true) {
+                if (exec) {
+                    HC(hipGraphLaunch(exec, s));
+                    dslash_calls += 2 * k;
+                } else {
+                    for (int i = 0; i < k; ++i) iteration(w);
+                }
+                HC(hipMemcpyAsync(st_host.data(), d_st.p, sizeof(SysState) * pl.nsys, hipMemcpyDeviceToHost, s));
+                HC(hipStreamSynchronize(s));
+                int n_run = 0, n_pend = 0;
+                for (const auto& x : st_host) {
+                    if (x.state == S_RUN) ++n_run;
+                    else if (x.state == S_REL || x.state == S_CHK || x.state == S_BRK || x.state == S_MAXIT) ++n_pend;
+                }
+                if (n_pend > 0) reliable(w, w64);
+                if (n_pend == 0 && n_run == 0) break;
+                if (++chunks > cap) fail(FS_E_HIP, "solver driver did not terminate");
+            }
+        } catch (...) {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        if (exec) HC(hipGraphExecDestroy(exec));
+        if (graph) HC(hipGraphDestroy(graph));
+        HC(hipMemcpyAsync(st_host.data(), d_st.p, sizeof(SysState) * pl.nsys, hipMemcpyDeviceToHost, s));
+        HC(hipStreamSynchronize(s));
+    }
+};
+
+// ============================================================== argument checks
+
+void check_ctx(fs_ctx c, bool need_gauge = true) {
+    if (!c) fail(FS_E_ARG, "null context");
+    if (need_gauge && !c->has_gauge) fail(FS_E_STATE, "no gauge field uploaded");
+}
+
+void check_prec(int P) {
+    if (P < 0 || P > 3) fail(FS_E_ARG, "invalid precision");
+}
+
+// Copy n bytes of a user buffer to a fresh device buffer.
+DevBuf to_device(const void* src, size_t n, int is_device, hipStream_t s) {
+    DevBuf d(n);
+    HC(hipMemcpyAsync(d.p, src, n, is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    return d;
+}
+
+void from_device(void* dst, const DevBuf& d, size_t n, int is_device, hipStream_t s) {
+    HC(hipMemcpyAsync(dst, d.p, n, is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    HC(hipStreamSynchronize(s));
+}
+
+int tuned_nr(fs_ctx c, int P, int n_sys) {
+    auto it = c->tune.find(P);
+    int nr = it != c->tune.end() ? it->second.nr : (P == P64 ? 4 : 8);
+    while (nr > 1 && nr > n_sys) nr >>= 1;
+    return nr;
+}
+int tuned_wg(fs_ctx c, int P) {
+    auto it = c->tune.find(P);
+    return it != c->tune.end() ? it->second.wg : 256;
+}
+
+// ============================================================== estimator
+
+struct EstSys {
+    int inst, level, sample;
+    double sigma;
+    bool is_x, g5;
+};
+
+struct EstResult {
+    std::vector<double> stats;   // per instance [L+1][16][P+1][4]
+    std::vector<double> samples; // per instance [L+1][N][16][P+1][2]
+    std::vector<double> level_res;  // per instance [L+1] worst relative true residual
+    fs_est_report rep;
+    bool noconv = false;
+};
+
+// One batched pass over a set of (instance, level, sample) units.  For each
+// unit level l < L: an x-system at sigma_{l+1} and a y-system at sigma_l on
+// g5 z; level L: one x-system.  x- and y-blocks are paired rhs by rhs.
+void run_units(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm, const std::vector<double>& sigma,
+               const std::vector<std::array<int, 3>>& units, int nr, int wg, hipStream_t s, EstResult& res,
+               int n_noise) {
+    const int L = (int)sigma.size() - 1;
+    const int P1 = prm->p_max + 1;
+    // group units by (inst, level) into blocks of nr samples
+    std::vector<int> blk_lat;
+    std::vector<EstSys> sysv;  // per system slot
+    std::vector<std::pair<int, int>> pairs;  // (x-block, y-block or -1)
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (auto& u : units) groups[{u[0], u[1]}].push_back(u[2]);
+    for (auto& kv : groups) {
+        const int inst = kv.first.first, l = kv.first.second;
+        const auto& smp = kv.second;
+        for (size_t c0 = 0; c0 < smp.size(); c0 += nr) {
+            const int xb = (int)blk_lat.size();
+            blk_lat.push_back(inst);
+            for (int r = 0; r < nr; ++r) {
+                EstSys e{inst, l, -1, l < L ? sigma[l + 1] : sigma[L], true, false};
+                if (c0 + r < smp.size()) e.sample = smp[c0 + r];
+                sysv.push_back(e);
+            }
+            int yb = -1;
+            if (l < L) {
+                yb = (int)blk_lat.size();
+                blk_lat.push_back(inst);
+                for (int r = 0; r < nr; ++r) {
+                    EstSys e{inst, l, -1, sigma[l], false, true};
+                    if (c0 + r < smp.size()) e.sample = smp[c0 + r];
+                    sysv.push_back(e);
+                }
+            }
+            pairs.push_back({xb, yb});
+        }
+    }
+    auto pl = make_plan(blk_lat, ctxs, nr, wg, s);
+    SolveOpts o;
+    o.P = prm->solve.storage;
+    o.tol = prm->solve.tol;
+    o.max_iter = prm->solve.max_iter;
+    o.delta = o.P == P64 ? 0.0 : (prm->solve.reliable_delta > 0 ? prm->solve.reliable_delta : 0.1);
+    o.check_every = prm->solve.check_every > 0 ? prm->solve.check_every : 8;
+    o.use_graph = prm->solve.use_graph != 0;
+    BatchSolver bs(*pl, ctxs, s, o);
+    const int nsys = pl->nsys;
+    std::vector<double> diag(nsys);
+    std::vector<char> idle(nsys);
+    std::vector<NoiseKey> keys(nsys);
+    for (int i = 0; i < nsys; ++i) {
+        const EstSys& e = sysv[i];
+        diag[i] = 4.0 + prm->solve.m0 + e.sigma;
+        idle[i] = e.sample < 0;
+        NoiseKey k;
+        std::memset(&k, 0, sizeof(k));
+        k.seed = prm->seed;
+        k.instance = ctxs[e.inst]->instance;
+        k.level = (uint32_t)e.level;
+        k.sample = (uint64_t)std::max(0, e.sample);
+        k.g5 = e.g5 ? 1 : 0;
+        k.pad = e.sample < 0 ? 1 : 0;
+        keys[i] = k;
+    }
+    bs.setup(diag, idle);
+    DevBuf d_keys = to_device(keys.data(), sizeof(NoiseKey) * nsys, 0, s);
+    launch_noise_block(P64, pl->work(P64, false), bs.b.f(), d_keys.as<NoiseKey>(), s);
+    bs.run();
+    res.rep.dslash_calls += bs.dslash_calls;
+
+    // bilinears: hop launches over x-blocks only (y-blocks get no workgroups)
+    const int nblk = (int)blk_lat.size();
+    std::vector<int> yb(2 * nblk, -1), hop_start(nblk + 1, 0);
+    std::vector<char> is_x(nblk, 0);
+    for (auto& pr : pairs) {
+        is_x[pr.first] = 1;
+        yb[2 * pr.first] = pr.second;
+        yb[2 * pr.first + 1] = pr.second >= 0 ? 1 : 0;
+    }
+    for (int b = 0; b < nblk; ++b)
+        hop_start[b + 1] = hop_start[b] + (is_x[b] ? pl->wg_start[b + 1] - pl->wg_start[b] : 0);
+    DevBuf d_hop_start = to_device(hop_start.data(), sizeof(int) * (nblk + 1), 0, s);
+    DevBuf d_yb = to_device(yb.data(), sizeof(int) * 2 * nblk, 0, s);
+    Work wh = pl->work(P64, false);
+    wh.wg_start = d_hop_start.as<int>();
+    wh.total_wg = hop_start.back();
+    DevBuf d_M(sizeof(double) * (size_t)nsys * P1 * 32);
+    Field phi1;
+    phi1.alloc(P64, pl->total_slots);
+    // ping-pong: p=0 reads xhi; then phi in rhi / phi1
+    Fld cur = bs.xhi.f();
+    for (int p = 0; p <= prm->p_max; ++p) {
+        Fld out = (p % 2 == 1) ? bs.rhi.f() : phi1.f();
+        launch_hop_reduce(wh, p, out, cur, bs.xhi.f(), bs.b.f(), d_yb.as<int>(), bs.part(), s);
+        launch_hop_finish(wh, bs.part(), d_M.as<double>(), P1, p, s);
+        if (p > 0) cur = out;
+    }
+    // contraction into the per-sample estimates
+    std::vector<XMap> xm(nsys);
+    for (int i = 0; i < nsys; ++i) {
+        const EstSys& e = sysv[i];
+        XMap m;
+        std::memset(&m, 0, sizeof(m));
+        m.level = (e.is_x && e.sample >= 0) ? e.level : -1;
+        m.sample = std::max(0, e.sample);
+        m.g5 = e.level < L ? 1 : 0;
+        m.coef = e.level < L ? sigma[e.level + 1] - sigma[e.level] : 1.0;
+        xm[i] = m;
+    }
+    // one X array per instance: contract per instance with masked maps
+    static const GammaTab gt = make_gamma_tab();
+    const size_t xsz = (size_t)(L + 1) * n_noise * 16 * P1 * 2;
+    for (size_t inst = 0; inst < ctxs.size(); ++inst) {
+        std::vector<XMap> xi = xm;
+        bool any = false;
+        for (int i = 0; i < nsys; ++i) {
+            if (sysv[i].inst != (int)inst) xi[i].level = -1;
+            any |= xi[i].level >= 0;
+        }
+        if (!any) continue;
+        DevBuf d_xm = to_device(xi.data(), sizeof(XMap) * nsys, 0, s);
+        DevBuf d_X(sizeof(double) * xsz);
+        HC(hipMemcpyAsync(d_X.p, res.samples.data() + inst * xsz, sizeof(double) * xsz, hipMemcpyHostToDevice, s));
+        launch_gamma_contract(d_M.as<double>(), P1, nsys, d_xm.as<XMap>(), gt, d_X.as<double>(), n_noise, s);
+        HC(hipMemcpyAsync(res.samples.data() + inst * xsz, d_X.p, sizeof(double) * xsz, hipMemcpyDeviceToHost, s));
+        HC(hipStreamSynchronize(s));
+    }
+    for (int i = 0; i < nsys; ++i) {
+        const EstSys& e = sysv[i];
+        const SysState& S = bs.st_host[i];
+        if (e.sample < 0) continue;
+        res.rep.systems += 1;
+        res.rep.iterations += S.iters;
+        res.rep.reliable_updates += S.n_rel;
+        const double rel = S.bb > 0 ? std::sqrt(S.rr_true / S.bb) : 0.0;
+        double& lr = res.level_res[(size_t)e.inst * (L + 1) + e.level];
+        lr = std::max(lr, rel);
+        res.rep.max_rel_residual = std::max(res.rep.max_rel_residual, rel);
+        if (S.state != S_DONE) res.noconv = true;
+    }
+}
+
+void estimate_impl(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm, const double* sigma_in, int L,
+                   fs_level_stat* out, double* samples_out, fs_est_report* report) {
+    if (!prm || !sigma_in || !out) fail(FS_E_ARG, "null argument");
+    if (L < 0) fail(FS_E_ARG, "L must be >= 0");
+    if (prm->n_noise < 1) fail(FS_E_ARG, "n_noise must be >= 1");
+    if (prm->p_max < 0) fail(FS_E_ARG, "p_max must be >= 0");
+    check_prec(prm->solve.storage);
+    if (!(prm->solve.tol > 0)) fail(FS_E_ARG, "tol must be > 0");
+    if (prm->solve.max_iter < 1) fail(FS_E_ARG, "max_iter must be >= 1");
+    std::vector<double> sigma(sigma_in, sigma_in + L + 1);
+    if (sigma[0] != 0.0) fail(FS_E_ARG, "sigma[0] must be 0");
+    for (int l = 0; l < L; ++l)
+        if (!(sigma[l + 1] > sigma[l])) fail(FS_E_ARG, "sigma must be strictly increasing");
+    for (auto* c : ctxs) {
+        check_ctx(c);
+        if (prm->p_max >= c->dims[2]) fail(FS_E_ARG, "p_max must be < Lz");
+        if (c->device != ctxs[0]->device) fail(FS_E_ARG, "batch contexts must share a device");
+    }
+    if (prm->solve.rhs_block != 0 && !pow2_ok(prm->solve.rhs_block)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
+    auto t0 = std::chrono::steady_clock::now();
+    fs_ctx_s* c0 = ctxs[0];
+    DeviceScope ds(c0->device);
+    hipStream_t s = c0->stream;
+    const int N = prm->n_noise;
+    const int P1 = prm->p_max + 1;
+    EstResult res;
+    std::memset(&res.rep, 0, sizeof(res.rep));
+    const size_t xsz = (size_t)(L + 1) * N * 16 * P1 * 2;
+    res.samples.assign(xsz * ctxs.size(), 0.0);
+    res.level_res.assign((size_t)(L + 1) * ctxs.size(), 0.0);
+    const int P = prm->solve.storage;
+    if (!prm->solve.batched) {
+        // plain path: one system at a time, NR = 1
+        for (size_t i = 0; i < ctxs.size(); ++i)
+            for (int l = 0; l <= L; ++l)
+                for (int smp = 0; smp < N; ++smp) {
+                    std::vector<fs_ctx_s*> one{ctxs[i]};
+                    EstResult r1;
+                    std::memset(&r1.rep, 0, sizeof(r1.rep));
+                    r1.samples.assign(xsz, 0.0);
+                    r1.level_res.assign(L + 1, 0.0);
+                    run_units(one, prm, sigma, {{0, l, smp}}, 1, tuned_wg(ctxs[i], P), s, r1, N);
+                    for (size_t k = 0; k < xsz; ++k) res.samples[i * xsz + k] += r1.samples[k];
+                    for (int k = 0; k <= L; ++k)
+                        res.level_res[i * (L + 1) + k] = std::max(res.level_res[i * (L + 1) + k], r1.level_res[k]);
+                    res.rep.systems += r1.rep.systems;
+                    res.rep.iterations += r1.rep.iterations;
+                    res.rep.reliable_updates += r1.rep.reliable_updates;
+                    res.rep.dslash_calls += r1.rep.dslash_calls;
+                    res.rep.max_rel_residual = std::max(res.rep.max_rel_residual, r1.rep.max_rel_residual);
+                    res.noconv |= r1.noconv;
+                }
+    } else {
+        int nr = prm->solve.rhs_block ? prm->solve.rhs_block : tuned_nr(c0, P, N);
+        const int wg = tuned_wg(c0, P);
+        // memory budget per pass: fields per system ~ (4 FP64 + 6 low) spinors
+        size_t bytes_per_site_sys = 4 * 192 + 6 * (size_t)prec_group_bytes_spinor(P) + (P == P16 ? 24 : 0);
+        size_t free_b = 0, total_b = 0;
+        HC(hipMemGetInfo(&free_b, &total_b));
+        const size_t budget = std::min<size_t>(free_b / 2, (size_t)96 << 30);
+        std::vector<std::array<int, 3>> units;
+        size_t used = 0;
+        auto flush = [&]() {
+            if (units.empty()) return;
+            run_units(ctxs, prm, sigma, units, nr, wg, s, res, N);
+            units.clear();
+            used = 0;
+        };
+        for (int l = 0; l <= L; ++l)
+            for (int smp = 0; smp < N; ++smp)
+                for (size_t i = 0; i < ctxs.size(); ++i) {
+                    const size_t need = (size_t)ctxs[i]->V * bytes_per_site_sys * (l < L ? 2 : 1);
+                    if (used + need > budget && !units.empty()) flush();
+                    units.push_back({(int)i, l, smp});
+                    used += need;
+                }
+        flush();
+    }
+    // level statistics from the per-sample estimates (device, FP64, fixed order)
+    for (size_t i = 0; i < ctxs.size(); ++i) {
+        DevBuf d_X = to_device(res.samples.data() + i * xsz, sizeof(double) * xsz, 0, s);
+        DevBuf d_st(sizeof(double) * (size_t)(L + 1) * 16 * P1 * 4);
+        launch_level_stats(d_X.as<double>(), L + 1, N, P1, d_st.as<double>(), s);
+        std::vector<double> stv((size_t)(L + 1) * 16 * P1 * 4);
+        HC(hipMemcpyAsync(stv.data(), d_st.p, sizeof(double) * stv.size(), hipMemcpyDeviceToHost, s));
+        HC(hipStreamSynchronize(s));
+        const uint16_t mask = prm->gamma_mask ? prm->gamma_mask : 0xffff;
+        for (int l = 0; l <= L; ++l)
+            for (int n = 0; n < 16; ++n)
+                for (int p = 0; p < P1; ++p) {
+                    fs_level_stat& o = out[i * (size_t)(L + 1) * 16 * P1 + ((size_t)l * 16 + n) * P1 + p];
+                    std::memset(&o, 0, sizeof(o));
+                    if (!((mask >> n) & 1)) continue;
+                    const double* d = &stv[(((size_t)l * 16 + n) * P1 + p) * 4];
+                    o.tr_re = d[0];
+                    o.tr_im = d[1];
+                    o.var_paper = d[2];
+                    o.var_unbiased = d[3];
+                    o.n = N;
+                    o.max_rel_residual = res.level_res[i * (L + 1) + l];
+                }
+        if (samples_out) std::memcpy(samples_out + i * xsz, res.samples.data() + i * xsz, sizeof(double) * xsz);
+    }
+    res.rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (report) *report = res.rep;
+    if (res.noconv) throw FsError(FS_E_NOCONV, "a shifted solve did not reach tol (outputs are filled)");
+}
+
+// ============================================================== dslash timing
+
+double dslash_bytes(int P, long long V, int n_sys, int nr) {
+    const double ws = P == P64 ? 8 : P == P32 ? 4 : 2;
+    const double wg = ws;
+    double per_sys = 48.0 * ws + (P == P16 ? 8.0 : 0.0);
+    const long long nblk = (n_sys + nr - 1) / nr;
+    return (double)V * (per_sys * n_sys + 72.0 * wg * nblk);
+}
+
+double time_dslash_impl(fs_ctx c, int P, int n_sys, int nr, int wg, int n_launch) {
+    hipStream_t s = c->stream;
+    const int nblk = (n_sys + nr - 1) / nr;
+    std::vector<int> blk_lat(nblk, 0);
+    std::vector<fs_ctx_s*> lats{c};
+    auto pl = make_plan(blk_lat, lats, nr, wg, s);
+    Field in, out;
+    in.alloc(P, pl->total_slots);
+    out.alloc(P, pl->total_slots);
+    std::vector<NoiseKey> keys(pl->nsys);
+    for (int i = 0; i < pl->nsys; ++i) {
+        std::memset(&keys[i], 0, sizeof(NoiseKey));
+        keys[i].seed = 12345;
+        keys[i].sample = (uint64_t)i;
+    }
+    DevBuf d_keys = to_device(keys.data(), sizeof(NoiseKey) * keys.size(), 0, s);
+    // Z4 noise input in the storage precision (out gets a copy so both are valid)
+    launch_noise_block(P, pl->work(P, false), in.f(), d_keys.as<NoiseKey>(), s);
+    launch_noise_block(P, pl->work(P, false), out.f(), d_keys.as<NoiseKey>(), s);
+    std::vector<double> diag(pl->nsys, 4.1);
+    DevBuf d_diag = to_device(diag.data(), sizeof(double) * diag.size(), 0, s);
+    HC(hipStreamSynchronize(s));
+    const Work w = pl->work(P, false);
+    for (int i = 0; i < 3; ++i)
+        launch_dslash(P, D_PLAIN, w, out.f(), in.f(), Fld(), d_diag.as<double>(), nullptr, M_ALL, nullptr, s);
+    hipEvent_t e0, e1;
+    HC(hipEventCreate(&e0));
+    HC(hipEventCreate(&e1));
+    HC(hipEventRecord(e0, s));
+    for (int i = 0; i < n_launch; ++i)
+        launch_dslash(P, D_PLAIN, w, (i & 1) ? in.f() : out.f(), (i & 1) ? out.f() : in.f(), Fld(),
+                      d_diag.as<double>(), nullptr, M_ALL, nullptr, s);
+    HC(hipEventRecord(e1, s));
+    HC(hipEventSynchronize(e1));
+    float ms = 0;
+    HC(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return (double)ms / n_launch;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+
+extern "C" {
+
+const char* fs_version(void) { return "fsmlmc 0.1 (gfx950)"; }
+
+const char* fs_last_error(void) { return g_err.c_str(); }
+
+fs_status fs_create(fs_ctx* out, const int32_t dims[4], int32_t t_antiperiodic, int32_t device, void* hip_stream) {
+    return guard([&] {
+        if (!out || !dims) fail(FS_E_ARG, "null argument");
+        *out = nullptr;
+        long long V = 1;
+        for (int i = 0; i < 4; ++i) {
+            if (dims[i] < 2) fail(FS_E_ARG, "every lattice extent must be >= 2");
+            V *= dims[i];
+        }
+        if (V > (1ll << 28)) fail(FS_E_ARG, "lattice too large");
+        int ndev = 0;
+        HC(hipGetDeviceCount(&ndev));
+        if (device < 0 || device >= ndev) fail(FS_E_ARG, "invalid device ordinal");
+        auto c = std::make_unique<fs_ctx_s>();
+        for (int i = 0; i < 4; ++i) c->dims[i] = dims[i];
+        c->V = (int)V;
+        c->tsign = t_antiperiodic ? -1 : 1;
+        c->device = device;
+        DeviceScope ds(device);
+        if (hip_stream) {
+            c->stream = (hipStream_t)hip_stream;
+        } else {
+            HC(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+        *out = c.release();
+    });
+}
+
+fs_status fs_destroy(fs_ctx c) {
+    return guard([&] {
+        if (!c) return;
+        {
+            DeviceScope ds(c->device);
+            (void)hipStreamSynchronize(c->stream);
+            for (auto& g : c->gauge) g.release();
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        }
+        delete c;
+    });
+}
+
+fs_status fs_set_instance(fs_ctx c, uint32_t instance) {
+    return guard([&] {
+        check_ctx(c, false);
+        c->instance = instance;
+    });
+}
+
+fs_status fs_upload_gauge(fs_ctx c, const double* links, int32_t is_device) {
+    return guard([&] {
+        check_ctx(c, false);
+        if (!links) fail(FS_E_ARG, "null links");
+        DeviceScope ds(c->device);
+        const size_t n = sizeof(double) * 18 * 4 * (size_t)c->V;
+        DevBuf src = to_device(links, n, is_device, c->stream);
+        for (int P = 0; P < 4; ++P) {
+            c->gauge[P].alloc((size_t)4 * 9 * c->V * prec_link_complex_bytes(P));
+            launch_gauge_convert(P, c->gauge[P].p, src.as<double>(), c->V, c->stream);
+        }
+        HC(hipStreamSynchronize(c->stream));
+        c->has_gauge = true;
+    });
+}
+
+fs_status fs_apply_dirac(fs_ctx c, double m0, double sigma, fs_prec storage, const double* in, double* out,
+                         int32_t n_rhs, int32_t is_device) {
+    return guard([&] {
+        check_ctx(c);
+        check_prec(storage);
+        if (!in || !out) fail(FS_E_ARG, "null buffer");
+        if (n_rhs < 1) fail(FS_E_ARG, "n_rhs must be >= 1");
+        DeviceScope ds(c->device);
+        hipStream_t s = c->stream;
+        int nr = 1;
+        while (nr < 16 && n_rhs % (nr * 2) == 0) nr *= 2;
+        const int nblk = n_rhs / nr;
+        std::vector<int> blk_lat(nblk, 0);
+        std::vector<fs_ctx_s*> lats{c};
+        auto pl = make_plan(blk_lat, lats, nr, 256, s);
+        const size_t nb = sizeof(double) * 24 * (size_t)c->V * n_rhs;
+        DevBuf din = to_device(in, nb, is_device, s);
+        DevBuf dout(nb);
+        Field fi, fo;
+        fi.alloc(storage, pl->total_slots);
+        fo.alloc(storage, pl->total_slots);
+        const long long stride = 24ll * c->V;
+        launch_pack(storage, pl->work(storage, false), fi.f(), din.as<double>(), stride, nullptr, s);
+        std::vector<double> diag(pl->nsys, 4.0 + m0 + sigma);
+        DevBuf d_diag = to_device(diag.data(), sizeof(double) * diag.size(), 0, s);
+        launch_dslash(storage, D_PLAIN, pl->work(storage, false), fo.f(), fi.f(), Fld(), d_diag.as<double>(), nullptr,
+                      M_ALL, nullptr, s);
+        launch_unpack(storage, pl->work(storage, false), dout.as<double>(), fo.f(), stride, nullptr, s);
+        HC(hipGetLastError());
+        from_device(out, dout, nb, is_device, s);
+    });
+}
+
+fs_status fs_z4_noise(fs_ctx c, uint64_t seed, uint32_t instance, uint32_t level, uint64_t sample, double* out,
+                      int32_t is_device) {
+    return guard([&] {
+        check_ctx(c, false);
+        if (!out) fail(FS_E_ARG, "null buffer");
+        DeviceScope ds(c->device);
+        const size_t nb = sizeof(double) * 24 * (size_t)c->V;
+        DevBuf d(nb);
+        NoiseKey k;
+        std::memset(&k, 0, sizeof(k));
+        k.seed = seed;
+        k.instance = instance;
+        k.level = level;
+        k.sample = sample;
+        launch_noise_canonical(d.as<double>(), c->V, k, c->stream);
+        HC(hipGetLastError());
+        from_device(out, d, nb, is_device, c->stream);
+    });
+}
+
+fs_status fs_displace(fs_ctx c, int32_t p, const double* in, double* out, int32_t is_device) {
+    return guard([&] {
+        check_ctx(c);
+        if (!in || !out) fail(FS_E_ARG, "null buffer");
+        if (p < 0) fail(FS_E_ARG, "p must be >= 0");
+        DeviceScope ds(c->device);
+        const size_t nb = sizeof(double) * 24 * (size_t)c->V;
+        DevBuf a = to_device(in, nb, is_device, c->stream);
+        DevBuf b(nb);
+        const LatDesc ld = lat_desc(c, P64);
+        for (int k = 0; k < p; ++k) {
+            launch_displace_canonical(b.as<double>(), a.as<double>(), c->gauge[P64].as<double>(), ld, c->stream);
+            std::swap(a, b);
+        }
+        HC(hipGetLastError());
+        from_device(out, a, nb, is_device, c->stream);
+    });
+}
+
+fs_status fs_bilinear(fs_ctx c, int32_t p_max, const double* y, const double* x, double* out, int32_t is_device) {
+    return guard([&] {
+        check_ctx(c);
+        if (!y || !x || !out) fail(FS_E_ARG, "null buffer");
+        if (p_max < 0 || p_max >= c->dims[2]) fail(FS_E_ARG, "p_max must be in [0, Lz)");
+        DeviceScope ds(c->device);
+        hipStream_t s = c->stream;
+        const int P1 = p_max + 1;
+        std::vector<int> blk_lat{0, 0};  // block 0: x, block 1: y (no workgroups in hop launches)
+        std::vector<fs_ctx_s*> lats{c};
+        auto pl = make_plan(blk_lat, lats, 1, 256, s);
+        const size_t nb = sizeof(double) * 24 * (size_t)c->V;
+        DevBuf dx = to_device(x, nb, is_device, s);
+        DevBuf dy = to_device(y, nb, is_device, s);
+        Field fx, f1, f2;
+        fx.alloc(P64, pl->total_slots);
+        f1.alloc(P64, pl->total_slots);
+        f2.alloc(P64, pl->total_slots);
+        std::vector<int> map_x{0, -2}, map_y{-2, 0};
+        DevBuf dmx = to_device(map_x.data(), sizeof(int) * 2, 0, s);
+        DevBuf dmy = to_device(map_y.data(), sizeof(int) * 2, 0, s);
+        launch_pack(P64, pl->work(P64, false), fx.f(), dx.as<double>(), 0, dmx.as<int>(), s);
+        launch_pack(P64, pl->work(P64, false), fx.f(), dy.as<double>(), 0, dmy.as<int>(), s);
+        std::vector<int> hop_start{0, pl->wg_start[1], pl->wg_start[1]};
+        DevBuf d_hs = to_device(hop_start.data(), sizeof(int) * 3, 0, s);
+        std::vector<int> yb{1, 0, -1, 0};
+        DevBuf d_yb = to_device(yb.data(), sizeof(int) * 4, 0, s);
+        Work wh = pl->work(P64, false);
+        wh.wg_start = d_hs.as<int>();
+        wh.total_wg = hop_start.back();
+        DevBuf d_part(sizeof(double) * (size_t)pl->wg_start.back() * 32);
+        DevBuf d_M(sizeof(double) * 2 * P1 * 32);
+        Fld cur = fx.f();
+        for (int p = 0; p <= p_max; ++p) {
+            Fld o = (p % 2 == 1) ? f1.f() : f2.f();
+            launch_hop_reduce(wh, p, o, cur, fx.f(), Fld(), d_yb.as<int>(), d_part.as<double>(), s);
+            launch_hop_finish(wh, d_part.as<double>(), d_M.as<double>(), P1, p, s);
+            if (p > 0) cur = o;
+        }
+        std::vector<XMap> xm(2);
+        std::memset(xm.data(), 0, sizeof(XMap) * 2);
+        xm[0].level = 0;
+        xm[0].coef = 1.0;
+        xm[1].level = -1;
+        DevBuf d_xm = to_device(xm.data(), sizeof(XMap) * 2, 0, s);
+        static const GammaTab gt = make_gamma_tab();
+        DevBuf d_X(sizeof(double) * 16 * P1 * 2);
+        launch_gamma_contract(d_M.as<double>(), P1, 2, d_xm.as<XMap>(), gt, d_X.as<double>(), 1, s);
+        HC(hipGetLastError());
+        // X layout [n][p] -> out [p][n]
+        std::vector<double> X(16 * P1 * 2);
+        HC(hipMemcpyAsync(X.data(), d_X.p, sizeof(double) * X.size(), hipMemcpyDeviceToHost, s));
+        HC(hipStreamSynchronize(s));
+        std::vector<double> o(16 * P1 * 2);
+        for (int n = 0; n < 16; ++n)
+            for (int p = 0; p < P1; ++p) {
+                o[2 * (p * 16 + n)] = X[2 * (n * P1 + p)];
+                o[2 * (p * 16 + n) + 1] = X[2 * (n * P1 + p) + 1];
+            }
+        if (is_device) {
+            HC(hipMemcpyAsync(out, o.data(), sizeof(double) * o.size(), hipMemcpyHostToDevice, s));
+            HC(hipStreamSynchronize(s));
+        } else {
+            std::memcpy(out, o.data(), sizeof(double) * o.size());
+        }
+    });
+}
+
+fs_status fs_solve_shifted(fs_ctx c, const fs_solve_params* prm, const double* sigma, int32_t n_shift, const double* B,
+                           int32_t n_rhs, double* X, int32_t is_device, fs_solve_stats* stats) {
+    fs_status worst = FS_OK;
+    fs_status st = guard([&] {
+        check_ctx(c);
+        if (!prm || !sigma || !B || !X) fail(FS_E_ARG, "null argument");
+        if (n_shift < 1 || n_rhs < 1) fail(FS_E_ARG, "n_shift and n_rhs must be >= 1");
+        check_prec(prm->storage);
+        if (!(prm->tol > 0)) fail(FS_E_ARG, "tol must be > 0");
+        if (prm->max_iter < 1) fail(FS_E_ARG, "max_iter must be >= 1");
+        if (prm->rhs_block != 0 && !pow2_ok(prm->rhs_block)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
+        DeviceScope ds(c->device);
+        hipStream_t s = c->stream;
+        const size_t nb1 = sizeof(double) * 24 * (size_t)c->V;
+        DevBuf dB = to_device(B, nb1 * n_rhs, is_device, s);
+        DevBuf dX(nb1 * n_rhs * n_shift);
+        const int P = prm->storage;
+        SolveOpts o;
+        o.P = P;
+        o.tol = prm->tol;
+        o.max_iter = prm->max_iter;
+        o.delta = P == P64 ? 0.0 : (prm->reliable_delta > 0 ? prm->reliable_delta : 0.1);
+        o.check_every = prm->check_every > 0 ? prm->check_every : 8;
+        o.use_graph = prm->use_graph != 0;
+        std::vector<fs_ctx_s*> lats{c};
+        // groups: (shift, rhs range) solved together
+        std::vector<std::vector<std::pair<int, int>>> passes;  // each pass: list of (shift, rhs)
+        int nr = 1;
+        if (prm->batched) {
+            nr = prm->rhs_block ? prm->rhs_block : tuned_nr(c, P, n_rhs);
+            std::vector<std::pair<int, int>> all;
+            for (int sh = 0; sh < n_shift; ++sh)
+                for (int r = 0; r < n_rhs; ++r) all.push_back({sh, r});
+            passes.push_back(all);
+        } else {
+            for (int sh = 0; sh < n_shift; ++sh)
+                for (int r = 0; r < n_rhs; ++r) passes.push_back({{sh, r}});
+        }
+        for (auto& pass : passes) {
+            // blocks: per shift, rhs chunks of nr
+            std::vector<int> blk_lat;
+            std::vector<int> sys_src, sys_dst;
+            std::vector<double> diag;
+            std::vector<char> idle;
+            std::map<int, std::vector<int>> by_shift;
+            for (auto& pr : pass) by_shift[pr.first].push_back(pr.second);
+            for (auto& kv : by_shift) {
+                const auto& rr = kv.second;
+                for (size_t c0 = 0; c0 < rr.size(); c0 += nr) {
+                    blk_lat.push_back(0);
+                    for (int q = 0; q < nr; ++q) {
+                        const bool ok = c0 + q < rr.size();
+                        sys_src.push_back(ok ? rr[c0 + q] : -1);
+                        sys_dst.push_back(ok ? kv.first * n_rhs + rr[c0 + q] : -1);
+                        diag.push_back(4.0 + prm->m0 + sigma[kv.first]);
+                        idle.push_back(!ok);
+                    }
+                }
+            }
+            auto pl = make_plan(blk_lat, lats, nr, tuned_wg(c, P), s);
+            BatchSolver bs(*pl, lats, s, o);
+            bs.setup(diag, idle);
+            DevBuf d_src = to_device(sys_src.data(), sizeof(int) * sys_src.size(), 0, s);
+            DevBuf d_dst = to_device(sys_dst.data(), sizeof(int) * sys_dst.size(), 0, s);
+            launch_pack(P64, pl->work(P64, false), bs.b.f(), dB.as<double>(), 24ll * c->V, d_src.as<int>(), s);
+            bs.run();
+            launch_unpack(P64, pl->work(P64, false), dX.as<double>(), bs.xhi.f(), 24ll * c->V, d_dst.as<int>(), s);
+            HC(hipGetLastError());
+            for (int i = 0; i < pl->nsys; ++i) {
+                if (sys_dst[i] < 0) continue;
+                const SysState& S = bs.st_host[i];
+                fs_status code = S.state == S_DONE ? FS_OK : FS_E_NOCONV;
+                if (code != FS_OK) worst = code;
+                if (stats) {
+                    fs_solve_stats& o2 = stats[sys_dst[i]];
+                    o2.iters = S.iters;
+                    o2.reliable_updates = S.n_rel;
+                    o2.status = code;
+                    o2.restarts = S.restarts;
+                    o2.true_rel_residual = S.bb > 0 ? std::sqrt(S.rr_true / S.bb) : 0.0;
+                }
+            }
+        }
+        from_device(X, dX, nb1 * n_rhs * n_shift, is_device, s);
+    });
+    if (st != FS_OK) return st;
+    if (worst != FS_OK) g_err = "some systems did not reach tol";
+    return worst;
+}
+
+fs_status fs_estimate(fs_ctx c, const fs_est_params* prm, const double* sigma, int32_t L, fs_level_stat* out,
+                      double* samples_out, fs_est_report* report) {
+    return guard([&] {
+        check_ctx(c);
+        estimate_impl({c}, prm, sigma, L, out, samples_out, report);
+    });
+}
+
+fs_status fs_batch_create(fs_batch* out, const fs_ctx* ctxs, int32_t n) {
+    return guard([&] {
+        if (!out || !ctxs || n < 1) fail(FS_E_ARG, "invalid batch");
+        *out = nullptr;
+        auto b = std::make_unique<fs_batch_s>();
+        for (int i = 0; i < n; ++i) {
+            check_ctx(ctxs[i]);
+            if (ctxs[i]->device != ctxs[0]->device) fail(FS_E_ARG, "batch contexts must share a device");
+            b->ctxs.push_back(ctxs[i]);
+        }
+        *out = b.release();
+    });
+}
+
+fs_status fs_batch_estimate(fs_batch b, const fs_est_params* prm, const double* sigma, int32_t L, fs_level_stat* out,
+                            fs_est_report* report) {
+    return guard([&] {
+        if (!b) fail(FS_E_ARG, "null batch");
+        std::vector<fs_ctx_s*> v(b->ctxs.begin(), b->ctxs.end());
+        estimate_impl(v, prm, sigma, L, out, nullptr, report);
+    });
+}
+
+fs_status fs_batch_destroy(fs_batch b) {
+    return guard([&] { delete b; });
+}
+
+fs_status fs_time_dslash(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_block, int32_t wg, int32_t n_launch,
+                         double* avg_ms, double* bytes) {
+    return guard([&] {
+        check_ctx(c);
+        check_prec(storage);
+        if (n_sys < 1 || n_launch < 1) fail(FS_E_ARG, "n_sys and n_launch must be >= 1");
+        int nr = rhs_block ? rhs_block : tuned_nr(c, storage, n_sys);
+        if (!pow2_ok(nr)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
+        int w = wg ? wg : tuned_wg(c, storage);
+        if (w != 64 && w != 128 && w != 256) fail(FS_E_ARG, "wg must be 64, 128 or 256");
+        DeviceScope ds(c->device);
+        const double ms = time_dslash_impl(c, storage, n_sys, nr, w, n_launch);
+        if (avg_ms) *avg_ms = ms;
+        if (bytes) *bytes = dslash_bytes(storage, c->V, n_sys, nr);
+    });
+}
+
+fs_status fs_autotune(fs_ctx c, fs_prec storage, const char* cache_path, int32_t* best_rhs_block, int32_t* best_wg) {
+    return guard([&] {
+        check_ctx(c);
+        check_prec(storage);
+        DeviceScope ds(c->device);
+        hipDeviceProp_t prop;
+        HC(hipGetDeviceProperties(&prop, c->device));
+        std::string arch = prop.gcnArchName;
+        arch = arch.substr(0, arch.find(':'));
+        std::ostringstream key;
+        key << arch << " " << c->dims[0] << " " << c->dims[1] << " " << c->dims[2] << " " << c->dims[3] << " "
+            << (int)storage;
+        TuneEntry best;
+        bool found = false;
+        if (cache_path) {
+            std::ifstream in(cache_path);
+            std::string line;
+            while (std::getline(in, line)) {
+                if (line.rfind(key.str() + " ", 0) == 0) {
+                    std::istringstream ls(line.substr(key.str().size()));
+                    TuneEntry e;
+                    if (ls >> e.nr >> e.wg >> e.ms_per_sys && pow2_ok(e.nr) && (e.wg == 64 || e.wg == 128 || e.wg == 256)) {
+                        best = e;
+                        found = true;
+                    }
+                }
+            }
+        }
+        if (!found) {
+            const int n_sys = 16;
+            best.ms_per_sys = 1e30;
+            for (int nr : {1, 2, 4, 8, 16})
+                for (int wg : {64, 128, 256}) {
+                    const double ms = time_dslash_impl(c, storage, n_sys, nr, wg, 10) / n_sys;
+                    if (ms < best.ms_per_sys) {
+                        best.ms_per_sys = ms;
+                        best.nr = nr;
+                        best.wg = wg;
+                    }
+                }
+            if (cache_path) {
+                std::ofstream outf(cache_path, std::ios::app);
+                outf << key.str() << " " << best.nr << " " << best.wg << " " << best.ms_per_sys << "\n";
+            }
+        }
+        c->tune[storage] = best;
+        if (best_rhs_block) *best_rhs_block = best.nr;
+        if (best_wg) *best_wg = best.wg;
+    });
+}
+
+}  // extern "C"

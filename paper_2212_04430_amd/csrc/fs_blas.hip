@@ -1,0 +1,804 @@
+// Vector, reduction, noise and displacement kernels of the FS-MLMC hot path.
+//
+//  * BiCGStab (van der Vorst 1992) updates, one lane per (site, rhs), fused
+//    with the dot products each step needs; partial sums are FP64 and reduced
+//    in a fixed order, so results are run-to-run reproducible.
+//  * Per-system scalar updates and the convergence / reliable-update state
+//    machine (one workgroup per block of NR systems).
+//  * Z4 noise from Philox4x64-10 (paper Introduction, eq. test: entries in
+//    {1,-1,i,-i}), written straight into the solver's block layout.
+//  * The Wilson-line displacement Omega_p (Introduction: Omega_p = W Pi_p along
+//    z) fused with the 4x4 spin-correlation M_ab = sum_{x,c} conj(y_ac) phi_bc,
+//    from which every bilinear y^+ Gamma_n Omega_p x of eq. fs_trace_est is a
+//    16-term contraction.
+#include "fs_kernels.h"
+
+namespace fs {
+
+namespace {
+
+__device__ __forceinline__ bool mask_ok(int mask, const SysState* __restrict__ st, int sys) {
+    if (mask == M_ALL) return true;
+    const int s = st[sys].state;
+    if (mask == M_RUN) return s == S_RUN;
+    if (mask == M_PEND) return s == S_REL || s == S_CHK || s == S_BRK || s == S_MAXIT;
+    if (mask == M_CONVERT) return s == S_CONV || s == S_RST;
+    return st[sys].upd_p != 0;
+}
+
+// Common prologue: map this workgroup to (block, first slot) and set locals.
+#define FS_WG_PROLOGUE(w)                                                   \
+    const int wg_id = xcd_remap(blockIdx.x, gridDim.x);                     \
+    if (wg_id >= (w).total_wg) return;                                      \
+    const int b = find_block((w).wg_start, (w).nblk, wg_id);                \
+    if ((w).blk_on && !(w).blk_on[b]) return;                               \
+    const BlockDesc bd = (w).blocks[b];                                     \
+    const LatDesc ld = (w).lats[bd.lat];                                    \
+    const int wgb = wg_id - (w).wg_start[b];                                \
+    const size_t gs = (size_t)ld.V << (w).lognr;
+
+#define FS_SLOT_LOOP(w)                                                     \
+    for (int it = 0; it < (w).tpw; ++it) {                                  \
+        const size_t slot = ((size_t)wgb * (w).tpw + it) * (w).wg + threadIdx.x; \
+        if (slot >= gs) break;                                              \
+        const int rhs = (int)(slot & (size_t)((w).nr - 1));                 \
+        const int sys = bd.sys0 + rhs;
+
+#define FS_SLOT_LOOP_END }
+
+template <int P>
+__device__ __forceinline__ const uint4* fbase(const Fld& f, const BlockDesc& bd) {
+    return f.v + (size_t)bd.slot_off * Tr<P>::G;
+}
+template <int P>
+__device__ __forceinline__ uint4* fbase_w(const Fld& f, const BlockDesc& bd) {
+    return f.v + (size_t)bd.slot_off * Tr<P>::G;
+}
+__device__ __forceinline__ float* nbase(const Fld& f, const BlockDesc& bd) {
+    return f.n ? f.n + bd.slot_off : nullptr;
+}
+
+// ------------------------------------------------------------------ BiCGStab
+
+// s = r - alpha v  (stored in r)
+template <int P>
+__global__ void __launch_bounds__(256) k_axpy_s(Work w, Fld r, Fld v, const SysState* __restrict__ st) {
+    using A = typename Tr<P>::acc;
+    FS_WG_PROLOGUE(w)
+    uint4* rb = fbase_w<P>(r, bd);
+    float* rn = nbase(r, bd);
+    const uint4* vb = fbase<P>(v, bd);
+    const float* vn = nbase(v, bd);
+    FS_SLOT_LOOP(w)
+        if (st[sys].state != S_RUN) continue;
+        const A ar = (A)st[sys].alpha[0], ai = (A)st[sys].alpha[1];
+        A x[24], y[24];
+        load_sp<P, A>(rb, rn, gs, slot, x);
+        load_sp<P, A>(vb, vn, gs, slot, y);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            x[2 * k] -= ar * y[2 * k] - ai * y[2 * k + 1];
+            x[2 * k + 1] -= ar * y[2 * k + 1] + ai * y[2 * k];
+        }
+        store_sp<P, A>(rb, rn, gs, slot, x);
+    FS_SLOT_LOOP_END
+}
+
+// x += alpha p + omega s;  r = s - omega t  (s is held in r);  partials (rhat, r), |r|^2
+template <int P>
+__global__ void __launch_bounds__(256) k_update_xr(Work w, Fld x, Fld p, Fld r, Fld t, Fld rhat,
+                                                   const SysState* __restrict__ st, double* __restrict__ part) {
+    using A = typename Tr<P>::acc;
+    FS_WG_PROLOGUE(w)
+    double acc[3] = {0.0, 0.0, 0.0};
+    uint4* xb = fbase_w<P>(x, bd);
+    float* xn = nbase(x, bd);
+    uint4* rb = fbase_w<P>(r, bd);
+    float* rn = nbase(r, bd);
+    FS_SLOT_LOOP(w)
+        if (st[sys].state != S_RUN) continue;
+        const A ar = (A)st[sys].alpha[0], ai = (A)st[sys].alpha[1];
+        const A wr = (A)st[sys].omega[0], wi = (A)st[sys].omega[1];
+        A xv[24], pv[24], sv[24];
+        load_sp<P, A>(xb, xn, gs, slot, xv);
+        load_sp<P, A>(fbase<P>(p, bd), nbase(p, bd), gs, slot, pv);
+        load_sp<P, A>(rb, rn, gs, slot, sv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            xv[2 * k] += ar * pv[2 * k] - ai * pv[2 * k + 1] + wr * sv[2 * k] - wi * sv[2 * k + 1];
+            xv[2 * k + 1] += ar * pv[2 * k + 1] + ai * pv[2 * k] + wr * sv[2 * k + 1] + wi * sv[2 * k];
+        }
+        store_sp<P, A>(xb, xn, gs, slot, xv);
+        A tv[24];
+        load_sp<P, A>(fbase<P>(t, bd), nbase(t, bd), gs, slot, tv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            sv[2 * k] -= wr * tv[2 * k] - wi * tv[2 * k + 1];
+            sv[2 * k + 1] -= wr * tv[2 * k + 1] + wi * tv[2 * k];
+        }
+        store_sp<P, A>(rb, rn, gs, slot, sv);
+        A hv[24];
+        load_sp<P, A>(fbase<P>(rhat, bd), nbase(rhat, bd), gs, slot, hv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const double hr = hv[2 * k], hi = hv[2 * k + 1], qr = sv[2 * k], qi = sv[2 * k + 1];
+            acc[0] += hr * qr + hi * qi;
+            acc[1] += hr * qi - hi * qr;
+            acc[2] += qr * qr + qi * qi;
+        }
+    FS_SLOT_LOOP_END
+    block_partials<3, 4>(acc, w.nr, part, wg_id);
+}
+
+// p = r + beta (p - omega v)
+template <int P>
+__global__ void __launch_bounds__(256) k_update_p(Work w, Fld p, Fld r, Fld v, const SysState* __restrict__ st) {
+    using A = typename Tr<P>::acc;
+    FS_WG_PROLOGUE(w)
+    uint4* pb = fbase_w<P>(p, bd);
+    float* pn = nbase(p, bd);
+    FS_SLOT_LOOP(w)
+        if (!st[sys].upd_p) continue;
+        const A br = (A)st[sys].beta[0], bi = (A)st[sys].beta[1];
+        const A wr = (A)st[sys].omega[0], wi = (A)st[sys].omega[1];
+        A pv[24], rv[24], vv[24];
+        load_sp<P, A>(pb, pn, gs, slot, pv);
+        load_sp<P, A>(fbase<P>(r, bd), nbase(r, bd), gs, slot, rv);
+        load_sp<P, A>(fbase<P>(v, bd), nbase(v, bd), gs, slot, vv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const A qr = pv[2 * k] - (wr * vv[2 * k] - wi * vv[2 * k + 1]);
+            const A qi = pv[2 * k + 1] - (wr * vv[2 * k + 1] + wi * vv[2 * k]);
+            pv[2 * k] = rv[2 * k] + br * qr - bi * qi;
+            pv[2 * k + 1] = rv[2 * k + 1] + br * qi + bi * qr;
+        }
+        store_sp<P, A>(pb, pn, gs, slot, pv);
+    FS_SLOT_LOOP_END
+}
+
+// x_hi += x_lo; x_lo = 0  (systems pending a reliable update)
+template <int P>
+__global__ void __launch_bounds__(256) k_fold(Work w, Fld xhi, Fld xlo, const SysState* __restrict__ st) {
+    using A = typename Tr<P>::acc;
+    FS_WG_PROLOGUE(w)
+    uint4* hb = xhi.v + (size_t)bd.slot_off * 12;
+    uint4* lb = fbase_w<P>(xlo, bd);
+    float* ln = nbase(xlo, bd);
+    FS_SLOT_LOOP(w)
+        if (!mask_ok(M_PEND, st, sys)) continue;
+        double h[24];
+        A l[24];
+        load_sp<P64, double>(hb, nullptr, gs, slot, h);
+        load_sp<P, A>(lb, ln, gs, slot, l);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            h[k] += (double)l[k];
+            l[k] = A(0);
+        }
+        store_sp<P64, double>(hb, nullptr, gs, slot, h);
+        store_sp<P, A>(lb, ln, gs, slot, l);
+    FS_SLOT_LOOP_END
+}
+
+// r = round(r_hi); restart systems also set rhat = p = r.  Partials (rhat, r), |r|^2
+template <int P>
+__global__ void __launch_bounds__(256) k_convert(Work w, Fld rhi, Fld r, Fld rhat, Fld p,
+                                                 const SysState* __restrict__ st, double* __restrict__ part) {
+    using A = typename Tr<P>::acc;
+    FS_WG_PROLOGUE(w)
+    double acc[3] = {0.0, 0.0, 0.0};
+    const uint4* hb = rhi.v + (size_t)bd.slot_off * 12;
+    uint4* rb = fbase_w<P>(r, bd);
+    float* rn = nbase(r, bd);
+    FS_SLOT_LOOP(w)
+        const int s = st[sys].state;
+        if (s != S_CONV && s != S_RST) continue;
+        double h[24];
+        A q[24];
+        load_sp<P64, double>(hb, nullptr, gs, slot, h);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) q[k] = (A)h[k];
+        store_sp<P, A>(rb, rn, gs, slot, q);
+        load_sp<P, A>(rb, rn, gs, slot, q);  // the rounded value the iteration will see
+        A hv[24];
+        if (s == S_RST) {
+            store_sp<P, A>(fbase_w<P>(rhat, bd), nbase(rhat, bd), gs, slot, q);
+            store_sp<P, A>(fbase_w<P>(p, bd), nbase(p, bd), gs, slot, q);
+#pragma unroll
+            for (int k = 0; k < 24; ++k) hv[k] = q[k];
+        } else {
+            load_sp<P, A>(fbase<P>(rhat, bd), nbase(rhat, bd), gs, slot, hv);
+        }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const double hr = hv[2 * k], hi = hv[2 * k + 1], qr = q[2 * k], qi = q[2 * k + 1];
+            acc[0] += hr * qr + hi * qi;
+            acc[1] += hr * qi - hi * qr;
+            acc[2] += qr * qr + qi * qi;
+        }
+    FS_SLOT_LOOP_END
+    block_partials<3, 4>(acc, w.nr, part, wg_id);
+}
+
+// x_hi = x_lo = 0, r_hi = b, r = rhat = p = round(b).  Partials |b|^2, (rhat, r), |r|^2
+template <int P>
+__global__ void __launch_bounds__(256) k_init(Work w, Fld bf, Fld xhi, Fld xlo, Fld rhi, Fld r, Fld rhat,
+                                              Fld p, double* __restrict__ part) {
+    using A = typename Tr<P>::acc;
+    FS_WG_PROLOGUE(w)
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const uint4* bb = bf.v + (size_t)bd.slot_off * 12;
+    FS_SLOT_LOOP(w)
+        (void)sys;
+        double h[24], z[24];
+        A q[24];
+        load_sp<P64, double>(bb, nullptr, gs, slot, h);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            z[k] = 0.0;
+            q[k] = (A)h[k];
+            acc[0] += h[k] * h[k];
+        }
+        store_sp<P64, double>(xhi.v + (size_t)bd.slot_off * 12, nullptr, gs, slot, z);
+        store_sp<P64, double>(rhi.v + (size_t)bd.slot_off * 12, nullptr, gs, slot, h);
+        A zl[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) zl[k] = A(0);
+        store_sp<P, A>(fbase_w<P>(xlo, bd), nbase(xlo, bd), gs, slot, zl);
+        store_sp<P, A>(fbase_w<P>(r, bd), nbase(r, bd), gs, slot, q);
+        load_sp<P, A>(fbase<P>(r, bd), nbase(r, bd), gs, slot, q);
+        store_sp<P, A>(fbase_w<P>(rhat, bd), nbase(rhat, bd), gs, slot, q);
+        store_sp<P, A>(fbase_w<P>(p, bd), nbase(p, bd), gs, slot, q);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[1] += (double)q[k] * (double)q[k];
+    FS_SLOT_LOOP_END
+    acc[3] = acc[1];
+    acc[2] = 0.0;
+    block_partials<4, 4>(acc, w.nr, part, wg_id);
+}
+
+// ------------------------------------------------------------------ finish
+
+__device__ __forceinline__ bool finite_d(double x) { return x == x && fabs(x) <= 1.7976931348623157e308; }
+
+template <int STAGE>
+__global__ void __launch_bounds__(256) k_finish(Work w, SysState* __restrict__ st, const double* __restrict__ part,
+                                                int* __restrict__ blk_on) {
+    constexpr int ND = STAGE == F_INIT ? 4 : STAGE == F_ALPHA ? 2 : STAGE == F_TRUE ? 1 : 3;
+    __shared__ double q[ND * 16];
+    __shared__ int any;
+    const int b = blockIdx.x;
+    const int nr = w.nr;
+    const BlockDesc bd = w.blocks[b];
+    // skip blocks whose launch was skipped (no fresh partials)
+    if (w.blk_on && !w.blk_on[b] && STAGE != F_INIT) {
+        return;
+    }
+    reduce_rows(part, ND * nr, w.wg_start[b], w.wg_start[b + 1], q);
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    int on = 0;
+    if (threadIdx.x < nr) {
+        const int r = threadIdx.x;
+        SysState& S = st[bd.sys0 + r];
+        auto Q = [&](int k) { return q[k * nr + r]; };
+        if constexpr (STAGE == F_INIT) {
+            if (S.state != S_IDLE) {
+                S.bb = Q(0);
+                S.rho[0] = Q(1);
+                S.rho[1] = Q(2);
+                S.rr = Q(3);
+                S.rr_max = S.rr;
+                S.rhat2 = S.rr;
+                S.rr_true = S.bb;
+                S.iters = 0;
+                S.n_rel = 0;
+                S.restarts = 0;
+                S.upd_p = 0;
+                S.alpha[0] = S.omega[0] = 1.0;
+                S.alpha[1] = S.omega[1] = 0.0;
+                S.beta[0] = S.beta[1] = 0.0;
+                S.state = (S.bb == 0.0) ? S_DONE : S_RUN;
+            }
+            on = S.state == S_RUN;
+        } else if constexpr (STAGE == F_ALPHA) {
+            if (S.state == S_RUN) {
+                const double vr = Q(0), vi = Q(1);
+                const double d = vr * vr + vi * vi;
+                if (!(d > 0.0) || !finite_d(d)) {
+                    S.state = S_BRK;
+                } else {
+                    // alpha = rho / (rhat, v)
+                    S.alpha[0] = (S.rho[0] * vr + S.rho[1] * vi) / d;
+                    S.alpha[1] = (S.rho[1] * vr - S.rho[0] * vi) / d;
+                }
+            }
+            on = S.state == S_RUN;
+        } else if constexpr (STAGE == F_OMEGA) {
+            if (S.state == S_RUN) {
+                const double tsr = Q(0), tsi = Q(1), tt = Q(2);
+                if (!finite_d(tt) || !finite_d(tsr) || !finite_d(tsi)) {
+                    S.state = S_BRK;
+                } else if (tt > 0.0) {
+                    S.omega[0] = tsr / tt;
+                    S.omega[1] = tsi / tt;
+                } else {
+                    S.omega[0] = S.omega[1] = 0.0;
+                }
+            }
+            on = S.state == S_RUN;
+        } else if constexpr (STAGE == F_RHO) {
+            if (S.state == S_RUN) {
+                const double nr_ = Q(0), ni = Q(1), rr = Q(2);
+                S.iters += 1;
+                S.upd_p = 0;
+                S.rr = rr;
+                const double om2 = S.omega[0] * S.omega[0] + S.omega[1] * S.omega[1];
+                const double rho2 = S.rho[0] * S.rho[0] + S.rho[1] * S.rho[1];
+                int ns = S_RUN;
+                if (!finite_d(rr) || !finite_d(nr_) || !finite_d(ni)) {
+                    ns = S_BRK;
+                } else {
+                    if (rr <= S.tol2 * S.bb) ns = S_CHK;
+                    else if (S.delta2 > 0.0 && rr < S.delta2 * S.rr_max) ns = S_REL;
+                    else if (S.iters >= S.max_iter) ns = S_MAXIT;
+                    const double nn2 = nr_ * nr_ + ni * ni;
+                    if (om2 > 0.0 && rho2 > 0.0) {
+                        // beta = (rho_new / rho) * (alpha / omega)
+                        const double ar = (nr_ * S.rho[0] + ni * S.rho[1]) / rho2;
+                        const double ai = (ni * S.rho[0] - nr_ * S.rho[1]) / rho2;
+                        const double cr = (S.alpha[0] * S.omega[0] + S.alpha[1] * S.omega[1]) / om2;
+                        const double ci = (S.alpha[1] * S.omega[0] - S.alpha[0] * S.omega[1]) / om2;
+                        S.beta[0] = ar * cr - ai * ci;
+                        S.beta[1] = ar * ci + ai * cr;
+                        S.upd_p = 1;
+                    } else if (ns == S_RUN) {
+                        ns = S_BRK;
+                    }
+                    if (ns == S_RUN && nn2 <= 1e-28 * rr * S.rhat2) ns = S_BRK;  // rho ~ 0
+                    S.rho[0] = nr_;
+                    S.rho[1] = ni;
+                }
+                if (ns == S_BRK) S.upd_p = 0;
+                if (rr > S.rr_max) S.rr_max = rr;
+                S.state = ns;
+            } else {
+                S.upd_p = 0;
+            }
+            on = (S.state == S_RUN) || S.upd_p;
+        } else if constexpr (STAGE == F_TRUE) {
+            const int s = S.state;
+            if (s == S_REL || s == S_CHK || s == S_BRK || s == S_MAXIT) {
+                S.rr_true = Q(0);
+                S.n_rel += 1;
+                if (S.rr_true <= S.tol2 * S.bb) S.state = S_DONE;
+                else if (s == S_MAXIT || !finite_d(S.rr_true)) S.state = S_FAIL;
+                else if (s == S_BRK) {
+                    S.restarts += 1;
+                    S.state = S.restarts > 64 ? S_FAIL : S_RST;
+                } else S.state = S_CONV;
+            }
+            on = S.state == S_CONV || S.state == S_RST;
+        } else {  // F_RESUME
+            const int s = S.state;
+            if (s == S_CONV || s == S_RST) {
+                S.rho[0] = Q(0);
+                S.rho[1] = Q(1);
+                S.rr = Q(2);
+                S.rr_max = S.rr;
+                if (s == S_RST) S.rhat2 = S.rr;
+                S.state = S_RUN;
+            }
+            on = S.state == S_RUN;
+        }
+    }
+    if (on) atomicOr(&any, 1);
+    __syncthreads();
+    if (threadIdx.x == 0 && blk_on) blk_on[b] = any;
+}
+
+// Per-block mask "has systems in the given class" (sets blk_on for eager launches).
+__global__ void k_blk_mask(Work w, const SysState* __restrict__ st, int mask, int* __restrict__ blk_on) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= w.nblk) return;
+    const int s0 = w.blocks[b].sys0;
+    int any = 0;
+    for (int r = 0; r < w.nr; ++r) any |= mask_ok(mask, st, s0 + r) ? 1 : 0;
+    blk_on[b] = any;
+}
+
+// ------------------------------------------------------------------ layout conversion
+
+template <int P>
+__global__ void __launch_bounds__(256) k_pack(Work w, Fld dst, const double* __restrict__ src, long long sys_stride,
+                                              const int* __restrict__ sys_map) {
+    using A = typename Tr<P>::acc;
+    FS_WG_PROLOGUE(w)
+    FS_SLOT_LOOP(w)
+        const int site = (int)(slot >> w.lognr);
+        const int ci = sys_map ? sys_map[sys] : sys;
+        if (ci < -1) continue;  // leave this system untouched
+        A v[24];
+        if (ci < 0) {
+#pragma unroll
+            for (int k = 0; k < 24; ++k) v[k] = A(0);
+        } else {
+            const double* s = src + (size_t)ci * (size_t)sys_stride + (size_t)site * 24;
+#pragma unroll
+            for (int k = 0; k < 24; ++k) v[k] = (A)s[k];
+        }
+        store_sp<P, A>(fbase_w<P>(dst, bd), nbase(dst, bd), gs, slot, v);
+    FS_SLOT_LOOP_END
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_unpack(Work w, double* __restrict__ dst, Fld src, long long sys_stride,
+                                                const int* __restrict__ sys_map) {
+    using A = typename Tr<P>::acc;
+    FS_WG_PROLOGUE(w)
+    FS_SLOT_LOOP(w)
+        const int site = (int)(slot >> w.lognr);
+        const int ci = sys_map ? sys_map[sys] : sys;
+        if (ci < 0) continue;
+        A v[24];
+        load_sp<P, A>(fbase<P>(src, bd), nbase(src, bd), gs, slot, v);
+        double* d = dst + (size_t)ci * (size_t)sys_stride + (size_t)site * 24;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) d[k] = (double)v[k];
+    FS_SLOT_LOOP_END
+}
+
+template <int P>
+__global__ void k_gauge_convert(void* __restrict__ dst, const double* __restrict__ src, int V) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)4 * V) return;
+    const int mu = (int)(i / V);
+    const int site = (int)(i % V);
+    const double* s = src + i * 18;
+    for (int k = 0; k < 9; ++k) {
+        const size_t o = ((size_t)mu * 9 + k) * V + site;
+        const double re = s[2 * k], im = s[2 * k + 1];
+        if constexpr (P == P64) {
+            reinterpret_cast<double2*>(dst)[o] = make_double2(re, im);
+        } else if constexpr (P == P32) {
+            reinterpret_cast<float2*>(dst)[o] = make_float2((float)re, (float)im);
+        } else if constexpr (P == P16) {
+            reinterpret_cast<uint32_t*>(dst)[o] = (uint32_t)f_to_h((float)re) | ((uint32_t)f_to_h((float)im) << 16);
+        } else {
+            reinterpret_cast<uint32_t*>(dst)[o] =
+                (uint32_t)f_to_bf16((float)re) | ((uint32_t)f_to_bf16((float)im) << 16);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ Z4 noise
+
+// The 12 components of `site` for key k: z_c = i^code(c), optionally times g5
+// (spins 2, 3 negated).  Component c = site*12 + j draws 2 bits of Philox block
+// c/128 (counter (c/128, sample, level, instance), key (seed, 0)).
+__device__ __forceinline__ void z4_site(const NoiseKey& k, long long site, double v[24]) {
+    const long long c0 = site * 12;
+    const long long b0 = c0 >> 7, b1 = (c0 + 11) >> 7;
+    U64x4 o0 = philox4x64_10((uint64_t)b0, k.sample, k.level, k.instance, k.seed, 0ull);
+    U64x4 o1 = o0;
+    if (b1 != b0) o1 = philox4x64_10((uint64_t)b1, k.sample, k.level, k.instance, k.seed, 0ull);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        const long long c = c0 + j;
+        const int e = (int)(c & 127);
+        const uint64_t word = ((c >> 7) == b0) ? o0.v[e >> 5] : o1.v[e >> 5];
+        const int code = (int)((word >> (2 * (e & 31))) & 3ull);
+        double re = code == 0 ? 1.0 : code == 2 ? -1.0 : 0.0;
+        double im = code == 1 ? 1.0 : code == 3 ? -1.0 : 0.0;
+        if (k.g5 && j >= 6) {
+            re = -re;
+            im = -im;
+        }
+        v[2 * j] = re;
+        v[2 * j + 1] = im;
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_noise_block(Work w, Fld dst, const NoiseKey* __restrict__ keys) {
+    using A = typename Tr<P>::acc;
+    FS_WG_PROLOGUE(w)
+    FS_SLOT_LOOP(w)
+        const int site = (int)(slot >> w.lognr);
+        const NoiseKey k = keys[sys];
+        double v[24];
+        if (k.pad) {  // padding system: zero source
+#pragma unroll
+            for (int j = 0; j < 24; ++j) v[j] = 0.0;
+        } else {
+            z4_site(k, site, v);
+        }
+        A q[24];
+#pragma unroll
+        for (int j = 0; j < 24; ++j) q[j] = (A)v[j];
+        store_sp<P, A>(fbase_w<P>(dst, bd), nbase(dst, bd), gs, slot, q);
+    FS_SLOT_LOOP_END
+}
+
+__global__ void k_noise_canonical(double* __restrict__ dst, int V, NoiseKey k) {
+    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    if (site >= V) return;
+    double v[24];
+    z4_site(k, site, v);
+    double2* d = reinterpret_cast<double2*>(dst) + (size_t)site * 12;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) d[j] = make_double2(v[2 * j], v[2 * j + 1]);
+}
+
+// ------------------------------------------------------------------ displacement + bilinear
+
+// phi(x) = U_z(x) phi_in(x + z) per spin (colour product), or phi_in(x) at p = 0;
+// M_ab += conj(y_a(x)) . phi_b(x) (colour dot), 16 complex per rhs.
+__global__ void __launch_bounds__(256) k_hop_reduce(Work w, int p, Fld phi_out, Fld phi_in, Fld yfld, Fld ysrc,
+                                                    const int* __restrict__ yb, double* __restrict__ part) {
+    FS_WG_PROLOGUE(w)
+    double acc[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) acc[k] = 0.0;
+    const int pb = yb[2 * b];
+    const uint4* ybase = pb >= 0 ? yfld.v + (size_t)w.blocks[pb].slot_off * 12 : ysrc.v + (size_t)bd.slot_off * 12;
+    const uint4* ib = phi_in.v + (size_t)bd.slot_off * 12;
+    uint4* ob = phi_out.v + (size_t)bd.slot_off * 12;
+    const int Lz = ld.L[2];
+    const int sz = ld.L[0] * ld.L[1];
+    FS_SLOT_LOOP(w)
+        (void)sys;
+        const int site = (int)(slot >> w.lognr);
+        double f[24];
+        if (p == 0) {
+            load_sp<P64, double>(ib, nullptr, gs, slot, f);
+        } else {
+            const int z = (site / sz) % Lz;
+            const int sn = (z == Lz - 1) ? site - (Lz - 1) * sz : site + sz;
+            double v[24], u[18];
+            load_sp<P64, double>(ib, nullptr, gs, ((size_t)sn << w.lognr) + rhs, v);
+            load_link<P64, double>(ld.gauge, ld.V, 2, site, u);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    double re = 0.0, im = 0.0;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const double ur = u[2 * (3 * i + j)], ui = u[2 * (3 * i + j) + 1];
+                        const double hr = v[2 * (3 * s + j)], hi = v[2 * (3 * s + j) + 1];
+                        re += ur * hr - ui * hi;
+                        im += ur * hi + ui * hr;
+                    }
+                    f[2 * (3 * s + i)] = re;
+                    f[2 * (3 * s + i) + 1] = im;
+                }
+            store_sp<P64, double>(ob, nullptr, gs, slot, f);
+        }
+        double y[24];
+        load_sp<P64, double>(ybase, nullptr, gs, slot, y);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) {
+                double re = 0.0, im = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double yr = y[2 * (3 * a + c)], yi = y[2 * (3 * a + c) + 1];
+                    const double fr = f[2 * (3 * bb + c)], fi = f[2 * (3 * bb + c) + 1];
+                    re += yr * fr + yi * fi;
+                    im += yr * fi - yi * fr;
+                }
+                acc[2 * (4 * a + bb)] += re;
+                acc[2 * (4 * a + bb) + 1] += im;
+            }
+    FS_SLOT_LOOP_END
+    block_partials<32, 4>(acc, w.nr, part, wg_id);
+}
+
+// M[(sys * M_stride + p) * 32 + k] = reduced partial k of system sys.
+__global__ void __launch_bounds__(256) k_hop_finish(Work w, const double* __restrict__ part, double* __restrict__ M,
+                                                    int M_stride, int p) {
+    __shared__ double q[32 * 16];
+    const int b = blockIdx.x;
+    const int nr = w.nr;
+    const BlockDesc bd = w.blocks[b];
+    if (w.blk_on && !w.blk_on[b]) return;
+    reduce_rows(part, 32 * nr, w.wg_start[b], w.wg_start[b + 1], q);
+    for (int i = threadIdx.x; i < 32 * nr; i += blockDim.x) {
+        const int k = i / nr, r = i % nr;
+        M[((size_t)(bd.sys0 + r) * M_stride + p) * 32 + k] = q[i];
+    }
+}
+
+__global__ void k_displace1(double* __restrict__ out, const double* __restrict__ in, const double* __restrict__ g,
+                            LatDesc ld) {
+    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    if (site >= ld.V) return;
+    const int sz = ld.L[0] * ld.L[1];
+    const int Lz = ld.L[2];
+    const int z = (site / sz) % Lz;
+    const int sn = (z == Lz - 1) ? site - (Lz - 1) * sz : site + sz;
+    const double2* U = reinterpret_cast<const double2*>(g) + (size_t)2 * 9 * ld.V + site;
+    const double2* v = reinterpret_cast<const double2*>(in) + (size_t)sn * 12;
+    double2* o = reinterpret_cast<double2*>(out) + (size_t)site * 12;
+    for (int s = 0; s < 4; ++s)
+        for (int i = 0; i < 3; ++i) {
+            double re = 0.0, im = 0.0;
+            for (int j = 0; j < 3; ++j) {
+                const double2 u = U[(size_t)(3 * i + j) * ld.V];
+                const double2 h = v[3 * s + j];
+                re += u.x * h.x - u.y * h.y;
+                im += u.x * h.y + u.y * h.x;
+            }
+            o[3 * s + i] = make_double2(re, im);
+        }
+}
+
+
+// X[level][sample][n][p] = coef * sum_a Gamma_n[a, perm_n(a)] * sy_a * M_{a, perm_n(a)}:
+// every Gamma_n of the DeGrand-Rossi basis has one nonzero (a power of i) per row.
+// sy_a = -1 for a >= 2 when y carries a gamma_5 (y = g5 (D+sigma)^-1 g5 z).
+__global__ void k_gamma_contract(const double* __restrict__ M, int P1, int nsys, const XMap* __restrict__ xm,
+                                 GammaTab gt, double* __restrict__ X, int n_noise) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsys * P1 * 16) return;
+    const int n = i % 16;
+    const int p = (i / 16) % P1;
+    const int sys = i / (16 * P1);
+    const XMap m = xm[sys];
+    if (m.level < 0) return;
+    const double* Mp = M + ((size_t)sys * P1 + p) * 32;
+    double re = 0.0, im = 0.0;
+    for (int a = 0; a < 4; ++a) {
+        const int c = gt.perm[n][a];
+        double mr = Mp[2 * (4 * a + c)], mi = Mp[2 * (4 * a + c) + 1];
+        if (m.g5 && a >= 2) {
+            mr = -mr;
+            mi = -mi;
+        }
+        const int ph = gt.ph[n][a];
+        const double gr = ph == 0 ? 1.0 : ph == 2 ? -1.0 : 0.0;
+        const double gi = ph == 1 ? 1.0 : ph == 3 ? -1.0 : 0.0;
+        re += gr * mr - gi * mi;
+        im += gr * mi + gi * mr;
+    }
+    const size_t o = (((size_t)m.level * n_noise + m.sample) * 16 + n) * P1 + p;
+    X[2 * o] = m.coef * re;
+    X[2 * o + 1] = m.coef * im;
+}
+
+// Per (level, n, p): mean and the variance of eq. practical_variance over the
+// samples, summed in sample order (FP64).
+__global__ void k_level_stats(const double* __restrict__ X, int L1, int n_noise, int P1, double* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L1 * 16 * P1) return;
+    const int p = i % P1;
+    const int n = (i / P1) % 16;
+    const int l = i / (16 * P1);
+    double sr = 0.0, si = 0.0, s2 = 0.0;
+    for (int s = 0; s < n_noise; ++s) {
+        const size_t o = (((size_t)l * n_noise + s) * 16 + n) * P1 + p;
+        const double xr = X[2 * o], xi = X[2 * o + 1];
+        sr += xr;
+        si += xi;
+        s2 += xr * xr + xi * xi;
+    }
+    const double N = (double)n_noise;
+    const double tr = sr / N, ti = si / N;
+    const double vp = s2 / N - (tr * tr + ti * ti);
+    double* d = out + (size_t)i * 4;
+    d[0] = tr;
+    d[1] = ti;
+    d[2] = vp;
+    d[3] = n_noise > 1 ? vp * N / (N - 1.0) : 0.0;
+}
+
+__global__ void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+static int grid_of(const Work& w) { return (w.total_wg + 7) / 8 * 8; }
+
+#define FS_DISPATCH_P(prec, CALL)          \
+    switch (prec) {                         \
+        case P64: { constexpr int PP = P64; CALL; } break; \
+        case P32: { constexpr int PP = P32; CALL; } break; \
+        case P16: { constexpr int PP = P16; CALL; } break; \
+        case PBF: { constexpr int PP = PBF; CALL; } break; \
+        default: break;                     \
+    }
+
+void launch_axpy_s(int prec, const Work& w, Fld r, Fld v, const SysState* st, hipStream_t s) {
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_axpy_s<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, r, v, st))
+}
+void launch_update_xr(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, Fld rhat, const SysState* st,
+                      double* part, hipStream_t s) {
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_update_xr<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, x, p, r, t, rhat,
+                                           st, part))
+}
+void launch_update_p(int prec, const Work& w, Fld p, Fld r, Fld v, const SysState* st, hipStream_t s) {
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_update_p<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, p, r, v, st))
+}
+void launch_fold(int prec, const Work& w, Fld xhi, Fld xlo, const SysState* st, hipStream_t s) {
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_fold<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, xhi, xlo, st))
+}
+void launch_convert(int prec, const Work& w, Fld rhi, Fld r, Fld rhat, Fld p, const SysState* st, double* part,
+                    hipStream_t s) {
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_convert<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, rhi, r, rhat, p, st,
+                                           part))
+}
+void launch_init(int prec, const Work& w, Fld b, Fld xhi, Fld xlo, Fld rhi, Fld r, Fld rhat, Fld p, double* part,
+                 hipStream_t s) {
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_init<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, b, xhi, xlo, rhi, r,
+                                           rhat, p, part))
+}
+void launch_finish(int stage, const Work& w, SysState* st, const double* part, int* blk_on, hipStream_t s) {
+    // Finish kernels read w.blk_on (the flags of the launch they complete) and
+    // write the flags for the next launch; both alias the same array.
+    Work wf = w;
+    switch (stage) {
+        case F_INIT: wf.blk_on = nullptr; hipLaunchKernelGGL(k_finish<F_INIT>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, blk_on); break;
+        case F_ALPHA: hipLaunchKernelGGL(k_finish<F_ALPHA>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, blk_on); break;
+        case F_OMEGA: hipLaunchKernelGGL(k_finish<F_OMEGA>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, blk_on); break;
+        case F_RHO: hipLaunchKernelGGL(k_finish<F_RHO>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, blk_on); break;
+        case F_TRUE: hipLaunchKernelGGL(k_finish<F_TRUE>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, blk_on); break;
+        case F_RESUME: hipLaunchKernelGGL(k_finish<F_RESUME>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, blk_on); break;
+        default: break;
+    }
+}
+void launch_blk_mask(const Work& w, const SysState* st, int mask, int* blk_on, hipStream_t s) {
+    hipLaunchKernelGGL(k_blk_mask, dim3((w.nblk + 255) / 256), dim3(256), 0, s, w, st, mask, blk_on);
+}
+void launch_pack(int prec, const Work& w, Fld dst, const double* src, long long sys_stride, const int* sys_map,
+                 hipStream_t s) {
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_pack<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, dst, src, sys_stride,
+                                           sys_map))
+}
+void launch_unpack(int prec, const Work& w, double* dst, Fld src, long long sys_stride, const int* sys_map,
+                   hipStream_t s) {
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_unpack<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, dst, src, sys_stride,
+                                           sys_map))
+}
+void launch_gauge_convert(int prec, void* dst, const double* src, int V, hipStream_t s) {
+    const int n = 4 * V;
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_gauge_convert<PP>, dim3((n + 255) / 256), dim3(256), 0, s, dst, src, V))
+}
+void launch_noise_block(int prec, const Work& w, Fld dst, const NoiseKey* keys, hipStream_t s) {
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_noise_block<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, dst, keys))
+}
+void launch_noise_canonical(double* dst, int V, NoiseKey key, hipStream_t s) {
+    hipLaunchKernelGGL(k_noise_canonical, dim3((V + 255) / 256), dim3(256), 0, s, dst, V, key);
+}
+void launch_hop_reduce(const Work& w, int p, Fld phi_out, Fld phi_in, Fld yfld, Fld ysrc, const int* yb,
+                       double* part, hipStream_t s) {
+    hipLaunchKernelGGL(k_hop_reduce, dim3(grid_of(w)), dim3(w.wg), 0, s, w, p, phi_out, phi_in, yfld, ysrc, yb, part);
+}
+void launch_hop_finish(const Work& w, const double* part, double* M, int M_stride, int p, hipStream_t s) {
+    hipLaunchKernelGGL(k_hop_finish, dim3(w.nblk), dim3(256), 0, s, w, part, M, M_stride, p);
+}
+void launch_displace_canonical(double* out, const double* in, const double* gauge64, LatDesc ld, hipStream_t s) {
+    hipLaunchKernelGGL(k_displace1, dim3((ld.V + 127) / 128), dim3(128), 0, s, out, in, gauge64, ld);
+}
+void launch_gamma_contract(const double* M, int P1, int nsys, const XMap* xm, const GammaTab& gt, double* X,
+                           int n_noise, hipStream_t s) {
+    const int n = nsys * P1 * 16;
+    hipLaunchKernelGGL(k_gamma_contract, dim3((n + 255) / 256), dim3(256), 0, s, M, P1, nsys, xm, gt, X, n_noise);
+}
+void launch_level_stats(const double* X, int L1, int n_noise, int P1, double* out, hipStream_t s) {
+    const int n = L1 * 16 * P1;
+    hipLaunchKernelGGL(k_level_stats, dim3((n + 255) / 256), dim3(256), 0, s, X, L1, n_noise, P1, out);
+}
+void launch_copy(uint4* dst, const uint4* src, size_t n16, hipStream_t s) {
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, n16);
+}
+
+}  // namespace fs

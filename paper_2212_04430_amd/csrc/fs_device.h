@@ -1,0 +1,343 @@
+// Device-side building blocks for the FS-MLMC kernels (gfx950, wave64).
+//
+// Field layout in HBM ("block" AoSoA).  A block holds NR systems (right-hand
+// sides) on one lattice of V sites.  A spinor field of a block is
+//     [group g][site][r]          r = 0..NR-1 fastest
+// where a group is 16 bytes of the spinor's 24 reals (component order
+// c = spin*3 + colour, re/im interleaved):
+//     FP64: 1 complex per group, 12 groups
+//     FP32: 2 complex per group,  6 groups
+//     FP16: 4 complex per group,  3 groups  + one float scale per (site, r)
+//     BF16: 4 complex per group,  3 groups
+// so lane (site, r) issues 16-byte loads and a wave reads contiguous memory.
+// Gauge links of one lattice: [mu][k = row*3 + col][site] complex in the
+// storage precision (16, 8, 4, 4 bytes per complex).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fs {
+
+enum Prec : int { P64 = 0, P32 = 1, P16 = 2, PBF = 3 };
+
+// ----------------------------------------------------------- descriptors
+
+struct LatDesc {
+    int L[4];          // Lx, Ly, Lz, Lt
+    int V;             // sites
+    int tsign;         // +1 periodic, -1 antiperiodic in t
+    const void* gauge; // links in the launch's storage precision
+};
+
+struct BlockDesc {
+    int lat;            // index into the lattice table
+    int sys0;           // first system id (per-system arrays are indexed sys0 + r)
+    long long slot_off; // offset of this block in slot units (site*NR + r)
+};
+
+// ----------------------------------------------------------- scalars
+
+__device__ __forceinline__ float bf16_to_f(uint16_t h) {
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+__device__ __forceinline__ uint16_t f_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float h_to_f(uint16_t h) {
+    _Float16 v;
+    __builtin_memcpy(&v, &h, 2);
+    return (float)v;
+}
+__device__ __forceinline__ uint16_t f_to_h(float f) {
+    _Float16 v = (_Float16)f;
+    uint16_t h;
+    __builtin_memcpy(&h, &v, 2);
+    return h;
+}
+
+// ----------------------------------------------------------- precision traits
+
+template <int P> struct Tr;
+template <> struct Tr<P64> {
+    using acc = double;
+    static constexpr int G = 12;   // 16-byte groups per spinor
+    static constexpr int GB = 16;  // bytes per stored link complex
+    static constexpr int SB = 192; // spinor bytes (without scale)
+};
+template <> struct Tr<P32> {
+    using acc = float;
+    static constexpr int G = 6;
+    static constexpr int GB = 8;
+    static constexpr int SB = 96;
+};
+template <> struct Tr<P16> {
+    using acc = float;
+    static constexpr int G = 3;
+    static constexpr int GB = 4;
+    static constexpr int SB = 48;
+};
+template <> struct Tr<PBF> {
+    using acc = float;
+    static constexpr int G = 3;
+    static constexpr int GB = 4;
+    static constexpr int SB = 48;
+};
+
+// Load / store the 24 reals of spinor (slot) from a block base.  gs = group
+// stride in 16-byte units (= V * NR).  `nrm` is the FP16 per-slot scale array.
+template <int P, typename A>
+__device__ __forceinline__ void load_sp(const uint4* __restrict__ base, const float* __restrict__ nrm,
+                                        size_t gs, size_t slot, A v[24]) {
+    if constexpr (P == P64) {
+        const double2* b = reinterpret_cast<const double2*>(base);
+#pragma unroll
+        for (int g = 0; g < 12; ++g) {
+            double2 d = b[g * gs + slot];
+            v[2 * g] = (A)d.x;
+            v[2 * g + 1] = (A)d.y;
+        }
+    } else if constexpr (P == P32) {
+        const float4* b = reinterpret_cast<const float4*>(base);
+#pragma unroll
+        for (int g = 0; g < 6; ++g) {
+            float4 d = b[g * gs + slot];
+            v[4 * g] = (A)d.x;
+            v[4 * g + 1] = (A)d.y;
+            v[4 * g + 2] = (A)d.z;
+            v[4 * g + 3] = (A)d.w;
+        }
+    } else {
+        float s = 1.0f;
+        if constexpr (P == P16) s = nrm[slot];
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            uint4 d = base[g * gs + slot];
+            uint32_t w[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float lo, hi;
+                if constexpr (P == P16) {
+                    lo = h_to_f((uint16_t)(w[k] & 0xffff)) * s;
+                    hi = h_to_f((uint16_t)(w[k] >> 16)) * s;
+                } else {
+                    lo = bf16_to_f((uint16_t)(w[k] & 0xffff));
+                    hi = bf16_to_f((uint16_t)(w[k] >> 16));
+                }
+                v[8 * g + 2 * k] = (A)lo;
+                v[8 * g + 2 * k + 1] = (A)hi;
+            }
+        }
+    }
+}
+
+template <int P, typename A>
+__device__ __forceinline__ void store_sp(uint4* __restrict__ base, float* __restrict__ nrm,
+                                         size_t gs, size_t slot, const A v[24]) {
+    if constexpr (P == P64) {
+        double2* b = reinterpret_cast<double2*>(base);
+#pragma unroll
+        for (int g = 0; g < 12; ++g) b[g * gs + slot] = make_double2((double)v[2 * g], (double)v[2 * g + 1]);
+    } else if constexpr (P == P32) {
+        float4* b = reinterpret_cast<float4*>(base);
+#pragma unroll
+        for (int g = 0; g < 6; ++g)
+            b[g * gs + slot] = make_float4((float)v[4 * g], (float)v[4 * g + 1], (float)v[4 * g + 2], (float)v[4 * g + 3]);
+    } else {
+        float inv = 1.0f;
+        if constexpr (P == P16) {
+            float m = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf((float)v[k]));
+            nrm[slot] = m;
+            inv = m > 0.0f ? 1.0f / m : 0.0f;
+        }
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            uint32_t w[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float lo = (float)v[8 * g + 2 * k], hi = (float)v[8 * g + 2 * k + 1];
+                if constexpr (P == P16) {
+                    w[k] = (uint32_t)f_to_h(lo * inv) | ((uint32_t)f_to_h(hi * inv) << 16);
+                } else {
+                    w[k] = (uint32_t)f_to_bf16(lo) | ((uint32_t)f_to_bf16(hi) << 16);
+                }
+            }
+            base[g * gs + slot] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+}
+
+// Load link U_mu(site) as 18 reals (row-major complex).
+template <int P, typename A>
+__device__ __forceinline__ void load_link(const void* __restrict__ gauge, int V, int mu, int site, A u[18]) {
+    if constexpr (P == P64) {
+        const double2* g = reinterpret_cast<const double2*>(gauge) + (size_t)mu * 9 * V + site;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            double2 d = g[(size_t)k * V];
+            u[2 * k] = (A)d.x;
+            u[2 * k + 1] = (A)d.y;
+        }
+    } else if constexpr (P == P32) {
+        const float2* g = reinterpret_cast<const float2*>(gauge) + (size_t)mu * 9 * V + site;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            float2 d = g[(size_t)k * V];
+            u[2 * k] = (A)d.x;
+            u[2 * k + 1] = (A)d.y;
+        }
+    } else {
+        const uint32_t* g = reinterpret_cast<const uint32_t*>(gauge) + (size_t)mu * 9 * V + site;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            uint32_t w = g[(size_t)k * V];
+            if constexpr (P == P16) {
+                u[2 * k] = (A)h_to_f((uint16_t)(w & 0xffff));
+                u[2 * k + 1] = (A)h_to_f((uint16_t)(w >> 16));
+            } else {
+                u[2 * k] = (A)bf16_to_f((uint16_t)(w & 0xffff));
+                u[2 * k + 1] = (A)bf16_to_f((uint16_t)(w >> 16));
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------- lattice geometry
+
+struct Coord {
+    int x, y, z, t;
+};
+
+__device__ __forceinline__ Coord coords(int site, const LatDesc& ld) {
+    Coord c;
+    int s = site;
+    c.x = s % ld.L[0];
+    s /= ld.L[0];
+    c.y = s % ld.L[1];
+    s /= ld.L[1];
+    c.z = s % ld.L[2];
+    c.t = s / ld.L[2];
+    return c;
+}
+
+// ----------------------------------------------------------- work mapping
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2);
+// remap so that XCD k receives a contiguous range of logical workgroups and
+// neighbouring tiles of the stencil share one L2.
+__device__ __forceinline__ int xcd_remap(int wg, int n_wg) {
+    const int nx = 8;
+    int per = (n_wg + nx - 1) / nx;
+    return (wg % nx) * per + wg / nx;
+}
+
+// First index b with start[b+1] > w (start is non-decreasing, start[0] = 0).
+__device__ __forceinline__ int find_block(const int* __restrict__ start, int nblk, int w) {
+    int lo = 0, hi = nblk - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ----------------------------------------------------------- reductions
+
+// Sum `ND` doubles per rhs over the workgroup (lanes with equal r = lane % NR)
+// in a fixed order and write them to part[(wg*ND + k)*NR + r].  At most MAXW
+// waves per workgroup and NR <= 16.
+template <int ND, int MAXW>
+__device__ __forceinline__ void block_partials(double (&v)[ND], int nr, double* __restrict__ part, int wg) {
+    __shared__ double red[MAXW][ND * 16];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwave = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        double x = v[k];
+        for (int off = 32; off >= nr; off >>= 1) x += __shfl_xor(x, off, 64);
+        v[k] = x;
+    }
+    if (lane < nr) {
+#pragma unroll
+        for (int k = 0; k < ND; ++k) red[wave][k * nr + lane] = v[k];
+    }
+    __syncthreads();
+    const int nq = ND * nr;
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+        double s = 0.0;
+        for (int w = 0; w < nwave; ++w) s += red[w][q];
+        part[(size_t)wg * nq + q] = s;
+    }
+}
+
+// Reduce part rows [w0, w1) of width nq into out[q] (shared), fixed order.
+// Must be called by all threads of a 256-thread workgroup.
+__device__ __forceinline__ void reduce_rows(const double* __restrict__ part, int nq, int w0, int w1,
+                                            double* __restrict__ out /* shared, nq */) {
+    __shared__ double tmp[256];
+    const int T = blockDim.x;
+    for (int q0 = 0; q0 < nq; q0 += T) {
+        int nqc = min(T, nq - q0);
+        int nqp = 1;
+        while (nqp < nqc) nqp <<= 1;
+        int C = T / nqp;
+        int q = threadIdx.x % nqp;
+        int c = threadIdx.x / nqp;
+        int cnt = w1 - w0;
+        double s = 0.0;
+        if (q < nqc && c < C) {
+            int a = w0 + (int)((long long)cnt * c / C);
+            int b = w0 + (int)((long long)cnt * (c + 1) / C);
+            for (int w = a; w < b; ++w) s += part[(size_t)w * nq + q0 + q];
+        }
+        tmp[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x < nqc) {
+            double t = 0.0;
+            for (int cc = 0; cc < C; ++cc) t += tmp[cc * nqp + threadIdx.x];
+            out[q0 + threadIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------- Philox4x64-10
+
+struct U64x4 {
+    uint64_t v[4];
+};
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    U64x4 o;
+    o.v[0] = c0;
+    o.v[1] = c1;
+    o.v[2] = c2;
+    o.v[3] = c3;
+    return o;
+}
+
+}  // namespace fs

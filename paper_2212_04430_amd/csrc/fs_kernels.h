@@ -1,0 +1,136 @@
+// Host-visible launchers of the FS-MLMC HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fs_device.h"
+
+namespace fs {
+
+// Per-system solver state (device).  Codes of `state`:
+enum SysCode : int {
+    S_RUN = 0,     // iterating
+    S_REL = 1,     // reliable update due (residual fell by delta)
+    S_CHK = 2,     // iterated residual below tol: verify in FP64
+    S_DONE = 3,    // converged (FP64 true residual <= tol)
+    S_BRK = 4,     // breakdown: restart from the FP64 residual
+    S_MAXIT = 5,   // iteration limit: fold x and measure the true residual
+    S_CONV = 8,    // transient: copy FP64 residual to the Krylov residual, resume
+    S_RST = 9,     // transient: as S_CONV and restart the Krylov space
+    S_FAIL = 10,   // gave up (max_iter); x holds the last iterate
+    S_IDLE = 11    // padding slot of a partially filled block (never runs)
+};
+
+struct SysState {
+    double rho[2], alpha[2], omega[2], beta[2];
+    double rr, bb, rr_max, rr_true;
+    double tol2;      // tol^2 (relative)
+    double delta2;    // reliable-update trigger (0 = only at convergence)
+    double rhat2;     // |rhat|^2 (breakdown test)
+    int state, iters, upd_p, n_rel;
+    int restarts, max_iter;
+};
+
+// One batched launch: a set of blocks of NR systems on possibly different lattices.
+struct Work {
+    const LatDesc* lats;      // device table (gauge pointer in the launch precision)
+    const BlockDesc* blocks;  // device table
+    const int* wg_start;      // device [nblk+1], first workgroup of each block
+    int nblk;
+    int total_wg;
+    int tpw;                  // tiles (of wg threads) per workgroup
+    int wg;                   // threads per workgroup
+    int nr, lognr;            // systems per block
+    const int* blk_on;        // device [nblk]: 0 => workgroups of the block exit (may be null)
+};
+
+struct Fld {
+    uint4* v = nullptr;    // block-layout field (16-byte groups)
+    float* n = nullptr;    // FP16 scales (per slot) or null
+};
+
+enum Mask : int { M_ALL = 0, M_RUN = 1, M_PEND = 2, M_CONVERT = 3, M_UPDP = 4 };
+
+// dslash modes
+enum DMode : int {
+    D_PLAIN = 0,   // out = (D + sigma) in
+    D_RHAT = 1,    // + partial (rhat, out)             [2 doubles]
+    D_TS = 2,      // + partials (out, in), (out, out)  [3 doubles]
+    D_RESID = 3    // out = b - (D + sigma) in (b FP64 in aux) + |out|^2 [1 double]
+};
+
+void launch_dslash(int prec, int mode, const Work& w, Fld out, Fld in, Fld aux, const double* diag,
+                   const SysState* st, int mask, double* part, hipStream_t s);
+
+// BiCGStab vector kernels (precision of the Krylov fields)
+void launch_axpy_s(int prec, const Work& w, Fld r, Fld v, const SysState* st, hipStream_t s);
+void launch_update_xr(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, Fld rhat,
+                      const SysState* st, double* part, hipStream_t s);
+void launch_update_p(int prec, const Work& w, Fld p, Fld r, Fld v, const SysState* st, hipStream_t s);
+
+// finish kernels: one workgroup per block, reduce partials, update state
+enum FStage : int { F_INIT = 0, F_ALPHA = 1, F_OMEGA = 2, F_RHO = 3, F_TRUE = 4, F_RESUME = 5 };
+void launch_finish(int stage, const Work& w, SysState* st, const double* part, int* blk_on, hipStream_t s);
+
+// reliable update / init
+void launch_fold(int prec, const Work& w, Fld xhi, Fld xlo, const SysState* st, hipStream_t s);
+void launch_convert(int prec, const Work& w, Fld rhi, Fld r, Fld rhat, Fld p, const SysState* st,
+                    double* part, hipStream_t s);
+void launch_init(int prec, const Work& w, Fld b, Fld xhi, Fld xlo, Fld rhi, Fld r, Fld rhat, Fld p,
+                 double* part, hipStream_t s);
+
+// layout conversion between canonical complex128 [sys][site][spin][col] and block layout;
+// sys_map[sys] = canonical index, -1 = write zeros (pack) / skip (unpack), < -1 = skip
+void launch_pack(int prec, const Work& w, Fld dst, const double* src, long long sys_stride,
+                 const int* sys_map, hipStream_t s);
+void launch_unpack(int prec, const Work& w, double* dst, Fld src, long long sys_stride,
+                   const int* sys_map, hipStream_t s);
+
+// gauge: canonical complex128 [mu][site][3][3] -> [mu][9][site] in precision prec
+void launch_gauge_convert(int prec, void* dst, const double* src, int V, hipStream_t s);
+
+// Z4 noise.  Block layout (FP64) for systems with noise keys, or canonical.
+struct NoiseKey {
+    uint64_t seed;
+    uint32_t instance, level;
+    uint64_t sample;
+    int g5;        // apply gamma_5 to the vector
+    int pad;
+};
+void launch_noise_block(int prec, const Work& w, Fld dst, const NoiseKey* keys /* per system */, hipStream_t s);
+void launch_noise_canonical(double* dst, int V, NoiseKey key, hipStream_t s);
+
+// Displacement + bilinear (FP64).  For each block b (the "x" block) with
+// partner yb[b] (or -1: y is the field `ysrc` of block b itself):
+//   phi_out = hop(phi_in) (p > 0) or phi_in (p == 0),  M_ab += conj(y_a) phi_b
+void launch_hop_reduce(const Work& w, int p, Fld phi_out, Fld phi_in, Fld yfld, Fld ysrc,
+                       const int* yb, double* part, hipStream_t s);
+// reduce hop partials to M[sys][16 complex] for one p
+void launch_hop_finish(const Work& w, const double* part, double* M, int M_stride, int p, hipStream_t s);
+
+// plain single-lattice displacement (canonical in/out, FP64) used by fs_displace
+void launch_displace_canonical(double* out, const double* in, const double* gauge64, LatDesc ld,
+                               hipStream_t s);
+
+// Gamma contraction of the spin correlations and per-level statistics.
+struct XMap {          // per x-system of a hop launch
+    int level;         // -1: not an estimator system
+    int sample;
+    int g5;            // y carries gamma_5
+    int pad;
+    double coef;       // sigma_{l+1} - sigma_l, or 1 on the last level
+};
+struct GammaTab {      // Gamma_n row a: single nonzero i^ph[n][a] at column perm[n][a]
+    int8_t perm[16][4];
+    int8_t ph[16][4];
+};
+void launch_gamma_contract(const double* M, int P1, int nsys, const XMap* xm, const GammaTab& gt, double* X,
+                           int n_noise, hipStream_t s);
+void launch_level_stats(const double* X, int L1, int n_noise, int P1, double* out, hipStream_t s);
+void launch_blk_mask(const Work& w, const SysState* st, int mask, int* blk_on, hipStream_t s);
+
+// copy kernel of known size (bandwidth calibration)
+void launch_copy(uint4* dst, const uint4* src, size_t n16, hipStream_t s);
+
+}  // namespace fs
