@@ -1,0 +1,231 @@
+"""Benchmark of the FS-MLMC hot path on one MI355X.
+
+One step = one Frequency-Splitting estimate (Z4 noise, every shifted solve to
+an FP64 true residual of 1e-10, Wilson-line displacements p = 0..8 with the
+16-Gamma bilinears, per-level mean and variance) over the workload
+
+  16^3 x 32 Wilson, eps 0.2, m0 0.02, shifts {0, 0.05, 0.25, 0.5, 1.0} (4 nonzero),
+  48 Z4 vectors per level (independent per level), 16 Gamma, p = 0..8
+  -> 48 * (2*4 + 1) = 432 shifted systems per step
+
+on the batched mixed-precision path (FP32 storage, FP32 stencil arithmetic,
+FP64 reliable updates and FP64 reductions; RHS blocks sharing link loads;
+hipGraph-captured iterations; autotuned RHS block and work-group size).
+`value` is shifted solves per second over the timed steps.  Also reported:
+the plain FP64 single-RHS path on a subset of the same systems and noise, the
+per-level deviation of the mixed path from it, the dslash roofline of the
+batched kernel timed live with HIP events, a single-RHS dslash at 32^3 x 64
+(working set far above the 256 MB last-level cache) and the CPU oracle.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "dslash GB/s (% HBM peak); shifted solves/sec at 1e-10, mixed+batched vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOAD = dict(dims=(16, 16, 16, 32), eps=0.2, m0=0.02, sigma=[0.0, 0.05, 0.25, 0.5, 1.0], n_noise=48,
+                p_max=8, seed=1, gauge_seed=0, tol=1e-10)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def est_params(L, storage, batched, n_noise, nr=0, graph=1):
+    w = WORKLOAD
+    sp = L.solve_params(w["m0"], tol=w["tol"], storage=storage, batched=batched, rhs_block=nr, use_graph=graph,
+                        max_iter=20000)
+    return L.fs_est_params(w["seed"], n_noise, 0, w["p_max"], sp)
+
+
+def cpu_baseline(U, dims, avg_iters):
+    """Oracle FP64 BiCGStab iterations on the same lattice, single thread,
+    scaled to solves/s with the mean iteration count of the GPU solves."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import lattice as lat
+    from oracle.philox import z4_noise
+    w = WORKLOAD
+    V = int(np.prod(dims))
+    b = z4_noise(V, w["seed"], 0, 0, 0)
+    sigma = w["sigma"][2]
+    n_it = 6
+    with threadpool_limits(1):
+        A = lambda v: lat.wilson_apply(U, v, w["m0"], sigma, dims)
+        t0 = time.perf_counter()
+        # n_it textbook BiCGStab iterations (2 operator applications each)
+        x = np.zeros_like(b)
+        r = b - A(x)
+        rh = r.copy()
+        p = r.copy()
+        rho = np.vdot(rh, r)
+        for _ in range(n_it):
+            v = A(p)
+            al = rho / np.vdot(rh, v)
+            s = r - al * v
+            t = A(s)
+            om = np.vdot(t, s) / np.vdot(t, t)
+            x = x + al * p + om * s
+            r = s - om * t
+            rn = np.vdot(rh, r)
+            be = rn / rho * (al / om)
+            rho = rn
+            p = r + be * (p - om * v)
+        dt = time.perf_counter() - t0
+    per_iter = dt / n_it
+    return {"value": 1.0 / (per_iter * avg_iters), "unit": "shifted solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_it} oracle BiCGStab iterations (numpy FP64, 1 thread) on the 16^3x32 lattice at "
+                      f"sigma={sigma}, {dt:.1f} s; solves/s = 1/(s per iteration x {avg_iters:.1f} mean GPU "
+                      f"iterations per system)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-noise", type=int, default=4, help="noise vectors per level for the FP64 plain path")
+    ap.add_argument("--no-headline", action="store_true", help="skip the 32^3x64 dslash measurement")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the hot path shards over independent systems "
+              "(see the sharding notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import synth
+    from paper_2212_04430_amd import _lib as L
+    w = WORKLOAD
+    dims = w["dims"]
+    V = int(np.prod(dims))
+    log(f"gauge {dims} eps={w['eps']}")
+    U = synth.gauge_field(dims, eps=w["eps"], seed=w["gauge_seed"])
+    ctx = L.fs_create(dims, 0, 0)
+    L.fs_upload_gauge(ctx, U)
+    L_lev = len(w["sigma"]) - 1
+    systems_per_step = w["n_noise"] * (2 * L_lev + 1)
+
+    # autotune the batched stencil (cached on disk next to the profiles)
+    cache = os.path.join(ROOT, "gpurun_out", "autotune.txt")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    nr, wg = L.fs_autotune(ctx, "f32", systems_per_step, cache)
+    nr = max(nr, 4)  # the batched path uses RHS blocks of 4, 8 or 16
+    log(f"autotune f32: rhs_block={nr} wg={wg}")
+
+    # ---- batched mixed path: warmup + timed steps
+    prm = est_params(L, "f32", 1, w["n_noise"], nr=nr)
+    for i in range(args.warmup):
+        t0 = time.perf_counter()
+        L.fs_estimate(ctx, prm, w["sigma"])
+        log(f"warmup step {i}: {time.perf_counter() - t0:.2f} s")
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for i in range(args.steps):
+        stats_b, _, rep = L.fs_estimate(ctx, prm, w["sigma"])
+        reps.append(rep)
+        log(f"step {i}: {rep.seconds:.3f} s, {rep.iterations / rep.systems:.1f} iters/system, "
+            f"{rep.reliable_updates / rep.systems:.2f} reliable updates/system, max res {rep.max_rel_residual:.2e}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt / args.steps
+    value = systems_per_step * args.steps / dt
+    avg_iters = float(np.mean([r.iterations / r.systems for r in reps]))
+    max_res = max(r.max_rel_residual for r in reps)
+
+    # ---- plain FP64 single-RHS path on a subset of the same systems and noise
+    n64 = args.fp64_noise
+    prm64 = est_params(L, "f64", 0, n64, graph=0)
+    t1 = time.perf_counter()
+    stats_a, X_a, rep_a = L.fs_estimate(ctx, prm64, w["sigma"], want_samples=True)
+    dt_a = time.perf_counter() - t1
+    fp64_rate = rep_a.systems / dt_a
+    log(f"fp64 plain: {rep_a.systems} systems in {dt_a:.2f} s ({rep_a.iterations / rep_a.systems:.1f} iters/system)")
+    prm_b_sub = est_params(L, "f32", 1, n64, nr=nr)
+    _, X_b, _ = L.fs_estimate(ctx, prm_b_sub, w["sigma"], want_samples=True)
+    scale = np.abs(X_a).mean(axis=1)
+    scale = np.where(scale > 0, scale, 1.0)
+    lvl_err = (np.abs(X_b - X_a).max(axis=1) / scale).reshape(L_lev + 1, -1).max(axis=1)
+
+    # ---- dslash roofline: the batched FP32 kernel of the solver, live HIP events
+    n_sys_blk = 96
+    ms_d, bytes_d = L.fs_time_dslash(ctx, "f32", n_sys_blk, nr, wg, 50)  # tuned variant / residency
+    achieved = bytes_d / (ms_d * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"k_dslash<P32> D_PLAIN, {n_sys_blk} systems, rhs_block {nr}, wg {wg}",
+                "algorithmic_bytes_per_launch": bytes_d, "avg_launch_ms": round(ms_d, 5)}
+    log(f"dslash f32 batched: {ms_d:.4f} ms, {achieved:.0f} GB/s")
+    L.fs_destroy(ctx)
+
+    # ---- 32^3 x 64 single-RHS dslash (working set >> 256 MB)
+    headline = None
+    if not args.no_headline:
+        hd = (32, 32, 32, 64)
+        log("gauge 32^3x64")
+        Uh = synth.gauge_field(hd, eps=w["eps"], seed=w["gauge_seed"])
+        ch = L.fs_create(hd, 0, 0)
+        L.fs_upload_gauge(ch, Uh)
+        del Uh
+        headline = {}
+        for prec in ("f64", "f32", "f16"):
+            best = None
+            for wgs in (64, 256):
+                for ilp in (0, 1):
+                    for occ in (0, 1, 2, 4):
+                        ms, by = L.fs_time_dslash(ch, prec, 1, 1, wgs, 20, ilp, occ)
+                        if best is None or ms < best[0]:
+                            best = (ms, by, wgs)
+            ms, by, wgs = best
+            gbs = by / (ms * 1e-3) / 1e9
+            headline[prec] = {"ms": round(ms, 4), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                              "bytes": by, "wg": wgs}
+            log(f"dslash 32^3x64 {prec}: {ms:.4f} ms {gbs:.0f} GB/s")
+        L.fs_destroy(ch)
+
+    cpu = None if args.no_cpu else cpu_baseline(U, dims, avg_iters)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "shifted solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "16^3x32 Wilson eps=0.2 m0=0.02, shifts {0,.05,.25,.5,1}, 48 Z4/level, "
+                               "16 Gamma, p=0..8, FP32 storage + FP64 reliable updates, batched",
+                   "systems_per_step": systems_per_step, "rhs_block": nr, "wg": wg, "tol": w["tol"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64_plain_solves_per_s": round(fp64_rate, 3),
+        "fp64_plain_systems": int(rep_a.systems),
+        "speedup_vs_fp64_plain": round(value / fp64_rate, 3),
+        "iters_per_system": round(avg_iters, 2),
+        "fp64_plain_iters_per_system": round(rep_a.iterations / rep_a.systems, 2),
+        "max_true_rel_residual": max_res,
+        "level_rel_dev_vs_fp64": [float(f"{e:.3e}") for e in lvl_err],
+        "dslash_32c64_single_rhs": headline,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -205,23 +205,39 @@ fs_status fs_batch_estimate(fs_batch b, const fs_est_params* prm, const double* 
 fs_status fs_batch_destroy(fs_batch b);
 
 /*
- * fs_autotune -- time the batched stencil for rhs_block in {1,2,4,8,16} x
- * work-group size in {64,128,256,512} at the given storage precision and keep
- * the fastest per (precision, n_rhs class) in the context.  cache_path: a text
- * file keyed by (arch, dims, precision, rhs_block) read first and appended
- * to; NULL keeps the table in memory only.  best_rhs_block / best_wg may be NULL.
+ * fs_autotune -- time the stencil over a batch of n_sys systems (batches above
+ * 96 are timed at 96: the resident set is bounded by the chip) for every
+ * rhs_block in {1,2,4,8,16} (<= n_sys), work-group size in {64,128,256}, both
+ * register variants and a cap of {none,1,2,4} resident waves per SIMD, and
+ * keep the fastest (per system) in the context for this storage precision;
+ * later solves, estimates and stencil calls with rhs_block/wg = 0 use it.
+ * cache_path: text file keyed by (arch, dims, precision, batch class), read
+ * first and appended to; NULL keeps the table in memory only.
+ * best_rhs_block / best_wg may be NULL.
  */
-fs_status fs_autotune(fs_ctx ctx, fs_prec storage, const char* cache_path,
+fs_status fs_autotune(fs_ctx ctx, fs_prec storage, int32_t n_sys, const char* cache_path,
                       int32_t* best_rhs_block, int32_t* best_wg);
 
 /*
  * fs_time_dslash -- average duration (ms, HIP events on the context's stream)
- * of n_launch back-to-back stencil launches at (storage, rhs_block,
- * work-group size wg; 0 = tuned) on n_sys systems, and the algorithmic
- * bytes one launch moves.  For roofline reporting.
+ * of n_launch back-to-back stencil launches on n_sys systems at the given
+ * storage precision, rhs_block (0 = tuned), work-group size wg (0 = tuned),
+ * register variant ilp (1: one wave per SIMD with the whole register file,
+ * 0: default allocation, -1: tuned) and residency cap occ (waves per SIMD,
+ * 0 = none, -1 = tuned); and the algorithmic bytes one launch moves
+ * (per site and system 48 stored reals of spinor in and out, plus 72 reals of
+ * links per block of rhs_block systems; FP16 adds a 4-byte scale per spinor).
  */
 fs_status fs_time_dslash(fs_ctx ctx, fs_prec storage, int32_t n_sys, int32_t rhs_block,
-                         int32_t wg, int32_t n_launch, double* avg_ms, double* bytes);
+                         int32_t wg, int32_t ilp, int32_t occ, int32_t n_launch,
+                         double* avg_ms, double* bytes);
+
+/*
+ * fs_time_copy -- average duration (ms, HIP events on the context's stream) of
+ * n_launch device-to-device copies of `bytes` bytes (rounded down to 16) by a
+ * plain streaming kernel: the achievable-bandwidth reference for the roofline.
+ */
+fs_status fs_time_copy(fs_ctx ctx, uint64_t bytes, int32_t n_launch, double* avg_ms);
 
 #ifdef __cplusplus
 }

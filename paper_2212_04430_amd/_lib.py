@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfsmlmc.so")
+LIB_PATH = os.environ.get("FSMLMC_LIB") or os.path.join(HERE, "libfsmlmc.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2212_04430_amd.build`")
@@ -85,9 +85,10 @@ _sig = {
     "fs_batch_estimate": (C.c_int, [_P, C.POINTER(fs_est_params), _P, C.c_int32, C.POINTER(fs_level_stat),
                                     C.POINTER(fs_est_report)]),
     "fs_batch_destroy": (C.c_int, [_P]),
-    "fs_autotune": (C.c_int, [_P, C.c_int32, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
-    "fs_time_dslash": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+    "fs_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "fs_time_dslash": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "fs_time_copy": (C.c_int, [_P, C.c_uint64, C.c_int32, C.POINTER(C.c_double)]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -277,17 +278,23 @@ def fs_batch_destroy(batch):
     _check(_lib.fs_batch_destroy(batch))
 
 
-def fs_autotune(ctx, storage, cache_path=None):
+def fs_autotune(ctx, storage, n_sys, cache_path=None):
     nr = C.c_int32()
     wg = C.c_int32()
-    _check(_lib.fs_autotune(ctx, _prec(storage), cache_path.encode() if cache_path else None, C.byref(nr),
-                            C.byref(wg)))
+    _check(_lib.fs_autotune(ctx, _prec(storage), int(n_sys), cache_path.encode() if cache_path else None,
+                            C.byref(nr), C.byref(wg)))
     return nr.value, wg.value
 
 
-def fs_time_dslash(ctx, storage, n_sys, rhs_block=0, wg=0, n_launch=20):
+def fs_time_dslash(ctx, storage, n_sys, rhs_block=0, wg=0, n_launch=20, ilp=-1, occ=-1):
     ms = C.c_double()
     b = C.c_double()
-    _check(_lib.fs_time_dslash(ctx, _prec(storage), int(n_sys), int(rhs_block), int(wg), int(n_launch),
-                               C.byref(ms), C.byref(b)))
+    _check(_lib.fs_time_dslash(ctx, _prec(storage), int(n_sys), int(rhs_block), int(wg), int(ilp), int(occ),
+                               int(n_launch), C.byref(ms), C.byref(b)))
     return ms.value, b.value
+
+
+def fs_time_copy(ctx, nbytes, n_launch=20):
+    ms = C.c_double()
+    _check(_lib.fs_time_copy(ctx, int(nbytes), int(n_launch), C.byref(ms)))
+    return ms.value

@@ -220,7 +220,7 @@ GammaTab make_gamma_tab() {
 // ============================================================== context
 
 struct TuneEntry {
-    int nr = 0, wg = 0;
+    int nr = 0, wg = 0, ilp = 0, occ = 0;
     double ms_per_sys = 0;
 };
 
@@ -278,23 +278,33 @@ bool pow2_ok(int n) { return n >= 1 && n <= 16 && (n & (n - 1)) == 0; }
 // A batch of blocks (each NR systems of one lattice) mapped to workgroups.
 struct Plan {
     int nr = 1, lognr = 0, wg = 256, tpw = 1;
+    int ilp = 0, occ = 0;             // stencil register variant and residency cap
     int nsys = 0;                     // nblk * nr
     std::vector<BlockDesc> blocks;
-    std::vector<int> wg_start;        // nblk + 1
+    std::vector<int> wg_start;        // nblk + 1  (tile mapping: vector kernels)
+    std::vector<int> wg_start_d;      // nblk + 1  (t-column mapping: stencil)
+    int tc = 1;                       // t-slices per stencil workgroup
     std::vector<int> lat_V;           // per lattice
     long long total_slots = 0;
     // device tables
-    DevBuf d_blocks, d_wg_start, d_blk_on;
+    DevBuf d_blocks, d_wg_start, d_wg_start_d, d_blk_on;
     DevBuf d_lats[4];
     DevBuf d_wg_start_alt;            // alternative start table (hop launches)
 
-    Work work(int P, bool use_blk_on) const {
+    int max_wg() const { return std::max(wg_start.back(), wg_start_d.back()); }
+
+    // stencil = true: the t-column mapping of the dslash launches (and of the
+    // finish kernels that reduce their partial sums).
+    Work work(int P, bool use_blk_on, bool stencil = false) const {
         Work w;
         w.lats = d_lats[P].as<LatDesc>();
         w.blocks = d_blocks.as<BlockDesc>();
-        w.wg_start = d_wg_start.as<int>();
+        w.wg_start = stencil ? d_wg_start_d.as<int>() : d_wg_start.as<int>();
         w.nblk = (int)blocks.size();
-        w.total_wg = wg_start.back();
+        w.total_wg = stencil ? wg_start_d.back() : wg_start.back();
+        w.tc = stencil ? tc : 0;
+        w.ilp = stencil ? ilp : 0;
+        w.occ = stencil ? occ : 0;
         w.tpw = tpw;
         w.wg = wg;
         w.nr = nr;
@@ -308,9 +318,11 @@ constexpr int kTargetWG = 4096;  // workgroups per launch to aim for (256 CUs x 
 
 // blk_lat[b]: lattice of block b; lats: the contexts of the lattices.
 std::unique_ptr<Plan> make_plan(const std::vector<int>& blk_lat, const std::vector<fs_ctx_s*>& lats, int nr, int wg,
-                                hipStream_t s) {
+                                hipStream_t s, int ilp = 0, int occ = 0) {
     auto pl = std::make_unique<Plan>();
     pl->nr = nr;
+    pl->ilp = ilp;
+    pl->occ = occ;
     pl->lognr = ilog2(nr);
     pl->wg = wg;
     const int nblk = (int)blk_lat.size();
@@ -338,11 +350,39 @@ std::unique_ptr<Plan> make_plan(const std::vector<int>& blk_lat, const std::vect
         pl->wg_start[b + 1] = pl->wg_start[b] + (int)nwg;
     }
     pl->total_slots = off;
+    // stencil: columns of (xyz, rhs) slots walking t in chunks of tc slices;
+    // enough chunks to put ~4 waves on every SIMD of the chip.
+    {
+        long long lanes = 0;
+        int Lt_min = 1 << 30;
+        for (int b = 0; b < nblk; ++b) {
+            const fs_ctx_s* c = lats[blk_lat[b]];
+            lanes += (long long)(c->V / c->dims[3]) * nr;
+            Lt_min = std::min(Lt_min, c->dims[3]);
+        }
+        // size for ~1/8 of the systems running: the slowest shifts iterate
+        // longest, alone, at the end of a batched solve
+        const long long target = 8ll * 256 * 4 * 4 * 64;
+        long long nch = std::max<long long>(1, (target + lanes - 1) / lanes);
+        int tcv = (int)std::max<long long>(2, (Lt_min + nch - 1) / nch);
+        pl->tc = std::min(tcv, Lt_min);
+        pl->wg_start_d.resize(nblk + 1);
+        pl->wg_start_d[0] = 0;
+        for (int b = 0; b < nblk; ++b) {
+            const fs_ctx_s* c = lats[blk_lat[b]];
+            const long long n3 = (long long)(c->V / c->dims[3]) * nr;
+            const long long ntile3 = (n3 + wg - 1) / wg;
+            const long long nchunk = (c->dims[3] + pl->tc - 1) / pl->tc;
+            pl->wg_start_d[b + 1] = pl->wg_start_d[b] + (int)(ntile3 * nchunk);
+        }
+    }
     pl->d_blocks.alloc(sizeof(BlockDesc) * nblk);
     pl->d_wg_start.alloc(sizeof(int) * (nblk + 1));
     pl->d_blk_on.alloc(sizeof(int) * nblk);
     HC(hipMemcpyAsync(pl->d_blocks.p, pl->blocks.data(), sizeof(BlockDesc) * nblk, hipMemcpyHostToDevice, s));
     HC(hipMemcpyAsync(pl->d_wg_start.p, pl->wg_start.data(), sizeof(int) * (nblk + 1), hipMemcpyHostToDevice, s));
+    pl->d_wg_start_d.alloc(sizeof(int) * (nblk + 1));
+    HC(hipMemcpyAsync(pl->d_wg_start_d.p, pl->wg_start_d.data(), sizeof(int) * (nblk + 1), hipMemcpyHostToDevice, s));
     std::vector<int> ones(nblk, 1);
     HC(hipMemcpyAsync(pl->d_blk_on.p, ones.data(), sizeof(int) * nblk, hipMemcpyHostToDevice, s));
     std::vector<LatDesc> ld[4];
@@ -374,6 +414,10 @@ struct Field {
 
 // ============================================================== solver
 
+// Residual reduction between FP64 reliable updates: the iterated residual of a
+// storage format with unit roundoff u drifts from the true one by ~u/delta.
+double default_delta(int P) { return P == P32 ? 1e-3 : P == P16 ? 0.1 : 0.2; }
+
 struct SolveOpts {
     int P = P64;
     double tol = 1e-10;
@@ -391,7 +435,7 @@ struct BatchSolver {
     hipStream_t s;
     SolveOpts o;
     Field b, xhi, rhi, r, rhat, p, v, t, xlo;
-    DevBuf d_diag, d_st, d_part;
+    DevBuf d_diag, d_st, d_part, d_flags;
     std::vector<SysState> st_host;
     long long dslash_calls = 0;
 
@@ -405,7 +449,8 @@ struct BatchSolver {
         d_diag.alloc(sizeof(double) * pl.nsys);
         d_st.alloc(sizeof(SysState) * pl.nsys);
         // partial sums: max 4 doubles per rhs per workgroup (32 for hop launches)
-        d_part.alloc(sizeof(double) * (size_t)pl.wg_start.back() * 32 * pl.nr);
+        d_part.alloc(sizeof(double) * (size_t)pl.max_wg() * 32 * pl.nr);
+        d_flags.alloc(sizeof(int) * 2 * pl.blocks.size());
         st_host.resize(pl.nsys);
     }
 
@@ -426,29 +471,52 @@ struct BatchSolver {
 
     SysState* st() { return d_st.as<SysState>(); }
     double* part() { return d_part.as<double>(); }
-    int* blk_on() { return pl.d_blk_on.as<int>(); }
-
-    void iteration(const Work& w) {
-        const double* dg = d_diag.as<double>();
-        launch_dslash(o.P, D_RHAT, w, v.f(), p.f(), rhat.f(), dg, st(), M_RUN, part(), s);
-        launch_finish(F_ALPHA, w, st(), part(), blk_on(), s);
-        launch_axpy_s(o.P, w, r.f(), v.f(), st(), s);
-        launch_dslash(o.P, D_TS, w, t.f(), r.f(), Fld(), dg, st(), M_RUN, part(), s);
-        launch_finish(F_OMEGA, w, st(), part(), blk_on(), s);
-        launch_update_xr(o.P, w, xlo.f(), p.f(), r.f(), t.f(), rhat.f(), st(), part(), s);
-        launch_finish(F_RHO, w, st(), part(), blk_on(), s);
-        launch_update_p(o.P, w, p.f(), r.f(), v.f(), st(), s);
-        dslash_calls += 2;
+    int* f_run() { return pl.d_blk_on.as<int>(); }
+    int* f_pend() { return d_flags.as<int>(); }
+    int* f_conv() { return d_flags.as<int>() + pl.blocks.size(); }
+    Work with(const Work& w, int* flags) const {
+        Work x = w;
+        x.blk_on = flags;
+        return x;
     }
 
+    // One BiCGStab iteration over every running system.  With in_loop_reliable
+    // the FP64 reliable update of the systems that asked for one in this
+    // iteration follows at once (no host round trip); blocks without such
+    // systems skip those launches at the first instruction.
+    void iteration(const Work& w, const Work& w64, bool in_loop_reliable) {
+        const double* dg = d_diag.as<double>();
+        const Work wr = with(w, f_run());
+        const Work wd = with(pl.work(o.P, true, true), f_run());
+        launch_dslash(o.P, D_RHAT, wd, v.f(), p.f(), rhat.f(), dg, st(), M_RUN, part(), s);
+        launch_finish(F_ALPHA, wd, st(), part(), f_run(), nullptr, s);
+        launch_axpy_s(o.P, wr, r.f(), v.f(), st(), s);
+        launch_dslash(o.P, D_TS, wd, t.f(), r.f(), Fld(), dg, st(), M_RUN, part(), s);
+        launch_finish(F_OMEGA, wd, st(), part(), f_run(), nullptr, s);
+        launch_update_xr(o.P, wr, xlo.f(), p.f(), r.f(), t.f(), rhat.f(), st(), part(), s);
+        launch_finish(F_RHO, wr, st(), part(), f_run(), f_pend(), s);
+        launch_update_p(o.P, wr, p.f(), r.f(), v.f(), st(), s);
+        dslash_calls += 2;
+        if (in_loop_reliable) reliable_chain(w, w64);
+    }
+
+    // FP64 reliable update of the systems flagged in f_pend: x_hi += x_lo,
+    // r_hi = b - (D + sigma) x_hi, then either done or resume with r = r_hi.
+    void reliable_chain(const Work& w, const Work& w64) {
+        const Work wp = with(w, f_pend()), wc = with(w, f_conv());
+        const Work wp64d = with(pl.work(P64, true, true), f_pend()), wpd = with(pl.work(o.P, true, true), f_pend());
+        launch_fold(o.P, wp, xhi.f(), xlo.f(), st(), s);
+        launch_dslash(P64, D_RESID, wp64d, rhi.f(), xhi.f(), b.f(), d_diag.as<double>(), st(), M_PEND, part(), s);
+        launch_finish(F_TRUE, wpd, st(), part(), f_conv(), f_pend(), s);  // clears f_pend
+        launch_convert(o.P, wc, rhi.f(), r.f(), rhat.f(), p.f(), st(), part(), s);
+        launch_finish(F_RESUME, wc, st(), part(), f_run(), f_conv(), s);  // clears f_conv
+    }
+
+    // Host-driven variant: mark pending blocks from the states, then the chain.
     void reliable(const Work& w, const Work& w64) {
-        launch_blk_mask(w, st(), M_PEND, blk_on(), s);
-        launch_fold(o.P, w, xhi.f(), xlo.f(), st(), s);
-        launch_dslash(P64, D_RESID, w64, rhi.f(), xhi.f(), b.f(), d_diag.as<double>(), st(), M_PEND, part(), s);
-        launch_finish(F_TRUE, w, st(), part(), blk_on(), s);
-        launch_convert(o.P, w, rhi.f(), r.f(), rhat.f(), p.f(), st(), part(), s);
-        launch_finish(F_RESUME, w, st(), part(), blk_on(), s);
-        launch_blk_mask(w, st(), M_RUN, blk_on(), s);
+        launch_blk_mask(w, st(), M_PEND, f_pend(), s);
+        reliable_chain(w, w64);
+        launch_blk_mask(w, st(), M_RUN, f_run(), s);
         dslash_calls += 1;
     }
 
@@ -456,14 +524,17 @@ struct BatchSolver {
         const Work w = pl.work(o.P, true);
         const Work w64 = pl.work(P64, true);
         Work winit = pl.work(o.P, false);
+        // reduced precision: reliable updates inside every iteration; FP64:
+        // the only FP64 check is at convergence, driven from the host.
+        const bool in_loop = o.P != P64;
         launch_init(o.P, winit, b.f(), xhi.f(), xlo.f(), rhi.f(), r.f(), rhat.f(), p.f(), part(), s);
-        launch_finish(F_INIT, w, st(), part(), blk_on(), s);
+        launch_finish(F_INIT, w, st(), part(), f_run(), nullptr, s);
         const int k = std::max(1, o.check_every);
         hipGraphExec_t exec = nullptr;
         hipGraph_t graph = nullptr;
         if (o.use_graph) {
             HC(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            for (int i = 0; i < k; ++i) iteration(w);
+            for (int i = 0; i < k; ++i) iteration(w, w64, in_loop);
             dslash_calls -= 2 * k;
             HC(hipStreamEndCapture(s, &graph));
             HC(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -476,7 +547,7 @@ struct BatchSolver {
                     HC(hipGraphLaunch(exec, s));
                     dslash_calls += 2 * k;
                 } else {
-                    for (int i = 0; i < k; ++i) iteration(w);
+                    for (int i = 0; i < k; ++i) iteration(w, w64, in_loop);
                 }
                 HC(hipMemcpyAsync(st_host.data(), d_st.p, sizeof(SysState) * pl.nsys, hipMemcpyDeviceToHost, s));
                 HC(hipStreamSynchronize(s));
@@ -534,6 +605,14 @@ int tuned_wg(fs_ctx c, int P) {
     auto it = c->tune.find(P);
     return it != c->tune.end() ? it->second.wg : 256;
 }
+int tuned_ilp(fs_ctx c, int P) {
+    auto it = c->tune.find(P);
+    return it != c->tune.end() ? it->second.ilp : 1;
+}
+int tuned_occ(fs_ctx c, int P) {
+    auto it = c->tune.find(P);
+    return it != c->tune.end() ? it->second.occ : 0;
+}
 
 // ============================================================== estimator
 
@@ -589,12 +668,13 @@ void run_units(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm, con
             pairs.push_back({xb, yb});
         }
     }
-    auto pl = make_plan(blk_lat, ctxs, nr, wg, s);
+    const int Pst = prm->solve.storage;
+    auto pl = make_plan(blk_lat, ctxs, nr, wg, s, tuned_ilp(ctxs[0], Pst), tuned_occ(ctxs[0], Pst));
     SolveOpts o;
     o.P = prm->solve.storage;
     o.tol = prm->solve.tol;
     o.max_iter = prm->solve.max_iter;
-    o.delta = o.P == P64 ? 0.0 : (prm->solve.reliable_delta > 0 ? prm->solve.reliable_delta : 0.1);
+    o.delta = o.P == P64 ? 0.0 : (prm->solve.reliable_delta > 0 ? prm->solve.reliable_delta : default_delta(o.P));
     o.check_every = prm->solve.check_every > 0 ? prm->solve.check_every : 8;
     o.use_graph = prm->solve.use_graph != 0;
     BatchSolver bs(*pl, ctxs, s, o);
@@ -812,12 +892,12 @@ double dslash_bytes(int P, long long V, int n_sys, int nr) {
     return (double)V * (per_sys * n_sys + 72.0 * wg * nblk);
 }
 
-double time_dslash_impl(fs_ctx c, int P, int n_sys, int nr, int wg, int n_launch) {
+double time_dslash_impl(fs_ctx c, int P, int n_sys, int nr, int wg, int ilp, int occ, int n_launch) {
     hipStream_t s = c->stream;
     const int nblk = (n_sys + nr - 1) / nr;
     std::vector<int> blk_lat(nblk, 0);
     std::vector<fs_ctx_s*> lats{c};
-    auto pl = make_plan(blk_lat, lats, nr, wg, s);
+    auto pl = make_plan(blk_lat, lats, nr, wg, s, ilp, occ);
     Field in, out;
     in.alloc(P, pl->total_slots);
     out.alloc(P, pl->total_slots);
@@ -834,7 +914,7 @@ double time_dslash_impl(fs_ctx c, int P, int n_sys, int nr, int wg, int n_launch
     std::vector<double> diag(pl->nsys, 4.1);
     DevBuf d_diag = to_device(diag.data(), sizeof(double) * diag.size(), 0, s);
     HC(hipStreamSynchronize(s));
-    const Work w = pl->work(P, false);
+    const Work w = pl->work(P, false, true);
     for (int i = 0; i < 3; ++i)
         launch_dslash(P, D_PLAIN, w, out.f(), in.f(), Fld(), d_diag.as<double>(), nullptr, M_ALL, nullptr, s);
     hipEvent_t e0, e1;
@@ -942,7 +1022,7 @@ fs_status fs_apply_dirac(fs_ctx c, double m0, double sigma, fs_prec storage, con
         const int nblk = n_rhs / nr;
         std::vector<int> blk_lat(nblk, 0);
         std::vector<fs_ctx_s*> lats{c};
-        auto pl = make_plan(blk_lat, lats, nr, 256, s);
+        auto pl = make_plan(blk_lat, lats, nr, 256, s, tuned_ilp(c, storage), tuned_occ(c, storage));
         const size_t nb = sizeof(double) * 24 * (size_t)c->V * n_rhs;
         DevBuf din = to_device(in, nb, is_device, s);
         DevBuf dout(nb);
@@ -953,8 +1033,8 @@ fs_status fs_apply_dirac(fs_ctx c, double m0, double sigma, fs_prec storage, con
         launch_pack(storage, pl->work(storage, false), fi.f(), din.as<double>(), stride, nullptr, s);
         std::vector<double> diag(pl->nsys, 4.0 + m0 + sigma);
         DevBuf d_diag = to_device(diag.data(), sizeof(double) * diag.size(), 0, s);
-        launch_dslash(storage, D_PLAIN, pl->work(storage, false), fo.f(), fi.f(), Fld(), d_diag.as<double>(), nullptr,
-                      M_ALL, nullptr, s);
+        launch_dslash(storage, D_PLAIN, pl->work(storage, false, true), fo.f(), fi.f(), Fld(), d_diag.as<double>(),
+                      nullptr, M_ALL, nullptr, s);
         launch_unpack(storage, pl->work(storage, false), dout.as<double>(), fo.f(), stride, nullptr, s);
         HC(hipGetLastError());
         from_device(out, dout, nb, is_device, s);
@@ -1089,7 +1169,7 @@ fs_status fs_solve_shifted(fs_ctx c, const fs_solve_params* prm, const double* s
         o.P = P;
         o.tol = prm->tol;
         o.max_iter = prm->max_iter;
-        o.delta = P == P64 ? 0.0 : (prm->reliable_delta > 0 ? prm->reliable_delta : 0.1);
+        o.delta = P == P64 ? 0.0 : (prm->reliable_delta > 0 ? prm->reliable_delta : default_delta(P));
         o.check_every = prm->check_every > 0 ? prm->check_every : 8;
         o.use_graph = prm->use_graph != 0;
         std::vector<fs_ctx_s*> lats{c};
@@ -1127,7 +1207,7 @@ fs_status fs_solve_shifted(fs_ctx c, const fs_solve_params* prm, const double* s
                     }
                 }
             }
-            auto pl = make_plan(blk_lat, lats, nr, tuned_wg(c, P), s);
+            auto pl = make_plan(blk_lat, lats, nr, tuned_wg(c, P), s, tuned_ilp(c, P), tuned_occ(c, P));
             BatchSolver bs(*pl, lats, s, o);
             bs.setup(diag, idle);
             DevBuf d_src = to_device(sys_src.data(), sizeof(int) * sys_src.size(), 0, s);
@@ -1193,8 +1273,8 @@ fs_status fs_batch_destroy(fs_batch b) {
     return guard([&] { delete b; });
 }
 
-fs_status fs_time_dslash(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_block, int32_t wg, int32_t n_launch,
-                         double* avg_ms, double* bytes) {
+fs_status fs_time_dslash(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_block, int32_t wg, int32_t ilp,
+                         int32_t occ, int32_t n_launch, double* avg_ms, double* bytes) {
     return guard([&] {
         check_ctx(c);
         check_prec(storage);
@@ -1203,25 +1283,60 @@ fs_status fs_time_dslash(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_b
         if (!pow2_ok(nr)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
         int w = wg ? wg : tuned_wg(c, storage);
         if (w != 64 && w != 128 && w != 256) fail(FS_E_ARG, "wg must be 64, 128 or 256");
+        const int il = ilp < 0 ? tuned_ilp(c, storage) : (ilp ? 1 : 0);
+        const int oc = occ < 0 ? tuned_occ(c, storage) : occ;
+        if (oc > 8) fail(FS_E_ARG, "occ must be <= 8");
         DeviceScope ds(c->device);
-        const double ms = time_dslash_impl(c, storage, n_sys, nr, w, n_launch);
+        const double ms = time_dslash_impl(c, storage, n_sys, nr, w, il, oc, n_launch);
         if (avg_ms) *avg_ms = ms;
         if (bytes) *bytes = dslash_bytes(storage, c->V, n_sys, nr);
     });
 }
 
-fs_status fs_autotune(fs_ctx c, fs_prec storage, const char* cache_path, int32_t* best_rhs_block, int32_t* best_wg) {
+fs_status fs_time_copy(fs_ctx c, uint64_t bytes, int32_t n_launch, double* avg_ms) {
+    return guard([&] {
+        check_ctx(c, false);
+        if (bytes < 16 || n_launch < 1 || !avg_ms) fail(FS_E_ARG, "invalid copy size or count");
+        DeviceScope ds(c->device);
+        const size_t n16 = bytes / 16;
+        DevBuf a(n16 * 16), b(n16 * 16);
+        HC(hipMemsetAsync(a.p, 0, n16 * 16, c->stream));
+        launch_copy(b.as<uint4>(), a.as<uint4>(), n16, c->stream);
+        hipEvent_t e0, e1;
+        HC(hipEventCreate(&e0));
+        HC(hipEventCreate(&e1));
+        HC(hipEventRecord(e0, c->stream));
+        for (int i = 0; i < n_launch; ++i)
+            launch_copy((i & 1) ? a.as<uint4>() : b.as<uint4>(), (i & 1) ? b.as<uint4>() : a.as<uint4>(), n16,
+                        c->stream);
+        HC(hipEventRecord(e1, c->stream));
+        HC(hipEventSynchronize(e1));
+        float ms = 0;
+        HC(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *avg_ms = (double)ms / n_launch;
+    });
+}
+
+fs_status fs_autotune(fs_ctx c, fs_prec storage, int32_t n_sys, const char* cache_path, int32_t* best_rhs_block,
+                      int32_t* best_wg) {
     return guard([&] {
         check_ctx(c);
         check_prec(storage);
+        if (n_sys < 1) fail(FS_E_ARG, "n_sys must be >= 1");
         DeviceScope ds(c->device);
         hipDeviceProp_t prop;
         HC(hipGetDeviceProperties(&prop, c->device));
         std::string arch = prop.gcnArchName;
         arch = arch.substr(0, arch.find(':'));
+        // batches above 96 systems behave like 96: the resident set is bounded by the chip
+        const int n_tune = std::min(n_sys, 96);
+        int cls = 1;
+        while (cls < n_tune) cls <<= 1;
         std::ostringstream key;
         key << arch << " " << c->dims[0] << " " << c->dims[1] << " " << c->dims[2] << " " << c->dims[3] << " "
-            << (int)storage;
+            << (int)storage << " " << cls;
         TuneEntry best;
         bool found = false;
         if (cache_path) {
@@ -1231,7 +1346,8 @@ fs_status fs_autotune(fs_ctx c, fs_prec storage, const char* cache_path, int32_t
                 if (line.rfind(key.str() + " ", 0) == 0) {
                     std::istringstream ls(line.substr(key.str().size()));
                     TuneEntry e;
-                    if (ls >> e.nr >> e.wg >> e.ms_per_sys && pow2_ok(e.nr) && (e.wg == 64 || e.wg == 128 || e.wg == 256)) {
+                    if (ls >> e.nr >> e.wg >> e.ilp >> e.occ >> e.ms_per_sys && pow2_ok(e.nr) &&
+                        (e.wg == 64 || e.wg == 128 || e.wg == 256) && e.occ >= 0 && e.occ <= 8) {
                         best = e;
                         found = true;
                     }
@@ -1239,20 +1355,26 @@ fs_status fs_autotune(fs_ctx c, fs_prec storage, const char* cache_path, int32_t
             }
         }
         if (!found) {
-            const int n_sys = 16;
             best.ms_per_sys = 1e30;
-            for (int nr : {1, 2, 4, 8, 16})
-                for (int wg : {64, 128, 256}) {
-                    const double ms = time_dslash_impl(c, storage, n_sys, nr, wg, 10) / n_sys;
-                    if (ms < best.ms_per_sys) {
-                        best.ms_per_sys = ms;
-                        best.nr = nr;
-                        best.wg = wg;
-                    }
-                }
+            for (int nr : {1, 2, 4, 8, 16}) {
+                if (nr > n_tune) break;
+                for (int wg : {64, 128, 256})
+                    for (int ilp : {0, 1})
+                        for (int occ : {0, 1, 2, 4}) {
+                            const double ms = time_dslash_impl(c, storage, n_tune, nr, wg, ilp, occ, 8) / n_tune;
+                            if (ms < best.ms_per_sys) {
+                                best.ms_per_sys = ms;
+                                best.nr = nr;
+                                best.wg = wg;
+                                best.ilp = ilp;
+                                best.occ = occ;
+                            }
+                        }
+            }
             if (cache_path) {
                 std::ofstream outf(cache_path, std::ios::app);
-                outf << key.str() << " " << best.nr << " " << best.wg << " " << best.ms_per_sys << "\n";
+                outf << key.str() << " " << best.nr << " " << best.wg << " " << best.ilp << " " << best.occ << " "
+                     << best.ms_per_sys << "\n";
             }
         }
         c->tune[storage] = best;

@@ -261,140 +261,166 @@ __global__ void __launch_bounds__(256) k_init(Work w, Fld bf, Fld xhi, Fld xlo, 
 
 __device__ __forceinline__ bool finite_d(double x) { return x == x && fabs(x) <= 1.7976931348623157e308; }
 
+// Per-system scalar update after a reduction; one thread per system of the block.
+template <int STAGE>
+__device__ __forceinline__ void finish_system(SysState& S, const double* q, int nr, int r) {
+    auto Q = [&](int k) { return q[k * nr + r]; };
+    if constexpr (STAGE == F_INIT) {
+        if (S.state != S_IDLE) {
+            S.bb = Q(0);
+            S.rho[0] = Q(1);
+            S.rho[1] = Q(2);
+            S.rr = Q(3);
+            S.rr_max = S.rr;
+            S.rhat2 = S.rr;
+            S.rr_true = S.bb;
+            S.iters = 0;
+            S.n_rel = 0;
+            S.restarts = 0;
+            S.upd_p = 0;
+            S.alpha[0] = S.omega[0] = 1.0;
+            S.alpha[1] = S.omega[1] = 0.0;
+            S.beta[0] = S.beta[1] = 0.0;
+            S.state = (S.bb == 0.0) ? S_DONE : S_RUN;
+        }
+    } else if constexpr (STAGE == F_ALPHA) {
+        if (S.state == S_RUN) {
+            const double vr = Q(0), vi = Q(1);
+            const double d = vr * vr + vi * vi;
+            if (!(d > 0.0) || !finite_d(d)) {
+                S.state = S_BRK;
+            } else {
+                // alpha = rho / (rhat, v)
+                S.alpha[0] = (S.rho[0] * vr + S.rho[1] * vi) / d;
+                S.alpha[1] = (S.rho[1] * vr - S.rho[0] * vi) / d;
+            }
+        }
+    } else if constexpr (STAGE == F_OMEGA) {
+        if (S.state == S_RUN) {
+            const double tsr = Q(0), tsi = Q(1), tt = Q(2);
+            if (!finite_d(tt) || !finite_d(tsr) || !finite_d(tsi)) {
+                S.state = S_BRK;
+            } else if (tt > 0.0) {
+                S.omega[0] = tsr / tt;
+                S.omega[1] = tsi / tt;
+            } else {
+                S.omega[0] = S.omega[1] = 0.0;
+            }
+        }
+    } else if constexpr (STAGE == F_RHO) {
+        if (S.state == S_RUN) {
+            const double nr_ = Q(0), ni = Q(1), rr = Q(2);
+            S.iters += 1;
+            S.upd_p = 0;
+            S.rr = rr;
+            const double om2 = S.omega[0] * S.omega[0] + S.omega[1] * S.omega[1];
+            const double rho2 = S.rho[0] * S.rho[0] + S.rho[1] * S.rho[1];
+            int ns = S_RUN;
+            if (!finite_d(rr) || !finite_d(nr_) || !finite_d(ni)) {
+                ns = S_BRK;
+            } else {
+                if (rr <= S.tol2 * S.bb) ns = S_CHK;
+                else if (S.delta2 > 0.0 && rr < S.delta2 * S.rr_max) ns = S_REL;
+                else if (S.iters >= S.max_iter) ns = S_MAXIT;
+                const double nn2 = nr_ * nr_ + ni * ni;
+                if (om2 > 0.0 && rho2 > 0.0) {
+                    // beta = (rho_new / rho) * (alpha / omega)
+                    const double ar = (nr_ * S.rho[0] + ni * S.rho[1]) / rho2;
+                    const double ai = (ni * S.rho[0] - nr_ * S.rho[1]) / rho2;
+                    const double cr = (S.alpha[0] * S.omega[0] + S.alpha[1] * S.omega[1]) / om2;
+                    const double ci = (S.alpha[1] * S.omega[0] - S.alpha[0] * S.omega[1]) / om2;
+                    S.beta[0] = ar * cr - ai * ci;
+                    S.beta[1] = ar * ci + ai * cr;
+                    S.upd_p = 1;
+                } else if (ns == S_RUN) {
+                    ns = S_BRK;
+                }
+                if (ns == S_RUN && nn2 <= 1e-28 * rr * S.rhat2) ns = S_BRK;  // rho ~ 0
+                S.rho[0] = nr_;
+                S.rho[1] = ni;
+            }
+            if (ns == S_BRK) S.upd_p = 0;
+            if (rr > S.rr_max) S.rr_max = rr;
+            S.state = ns;
+        } else {
+            S.upd_p = 0;
+        }
+    } else if constexpr (STAGE == F_TRUE) {
+        const int s = S.state;
+        if (s == S_REL || s == S_CHK || s == S_BRK || s == S_MAXIT) {
+            S.rr_true = Q(0);
+            S.n_rel += 1;
+            if (S.rr_true <= S.tol2 * S.bb) S.state = S_DONE;
+            else if (s == S_MAXIT || !finite_d(S.rr_true)) S.state = S_FAIL;
+            else if (s == S_BRK) {
+                S.restarts += 1;
+                S.state = S.restarts > 64 ? S_FAIL : S_RST;
+            } else S.state = S_CONV;
+        }
+    } else {  // F_RESUME
+        const int s = S.state;
+        if (s == S_CONV || s == S_RST) {
+            S.rho[0] = Q(0);
+            S.rho[1] = Q(1);
+            S.rr = Q(2);
+            S.rr_max = S.rr;
+            if (s == S_RST) S.rhat2 = S.rr;
+            S.state = S_RUN;
+        }
+    }
+}
+
+// One workgroup per block: reduce the partial sums of the launch it completes
+// (fixed order), update the per-system scalars and state, and write the block
+// flags of the next launches.  blk_on (out): blocks that have work in the
+// next iteration kernels (F_TRUE: blocks to convert); blk_pend (out2): after
+// F_RHO, blocks with systems that need an FP64 reliable update (the other
+// stages write 0 there, clearing the flags they consumed).
 template <int STAGE>
 __global__ void __launch_bounds__(256) k_finish(Work w, SysState* __restrict__ st, const double* __restrict__ part,
-                                                int* __restrict__ blk_on) {
+                                                int* __restrict__ blk_on, int* __restrict__ blk_pend) {
     constexpr int ND = STAGE == F_INIT ? 4 : STAGE == F_ALPHA ? 2 : STAGE == F_TRUE ? 1 : 3;
     __shared__ double q[ND * 16];
-    __shared__ int any;
+    __shared__ int any_on, any_rel, any_pend;
     const int b = blockIdx.x;
     const int nr = w.nr;
     const BlockDesc bd = w.blocks[b];
-    // skip blocks whose launch was skipped (no fresh partials)
-    if (w.blk_on && !w.blk_on[b] && STAGE != F_INIT) {
-        return;
-    }
+    // blocks whose launch was skipped have no fresh partial sums
+    if (w.blk_on && !w.blk_on[b] && STAGE != F_INIT) return;
     reduce_rows(part, ND * nr, w.wg_start[b], w.wg_start[b + 1], q);
-    if (threadIdx.x == 0) any = 0;
-    __syncthreads();
-    int on = 0;
-    if (threadIdx.x < nr) {
-        const int r = threadIdx.x;
-        SysState& S = st[bd.sys0 + r];
-        auto Q = [&](int k) { return q[k * nr + r]; };
-        if constexpr (STAGE == F_INIT) {
-            if (S.state != S_IDLE) {
-                S.bb = Q(0);
-                S.rho[0] = Q(1);
-                S.rho[1] = Q(2);
-                S.rr = Q(3);
-                S.rr_max = S.rr;
-                S.rhat2 = S.rr;
-                S.rr_true = S.bb;
-                S.iters = 0;
-                S.n_rel = 0;
-                S.restarts = 0;
-                S.upd_p = 0;
-                S.alpha[0] = S.omega[0] = 1.0;
-                S.alpha[1] = S.omega[1] = 0.0;
-                S.beta[0] = S.beta[1] = 0.0;
-                S.state = (S.bb == 0.0) ? S_DONE : S_RUN;
-            }
-            on = S.state == S_RUN;
-        } else if constexpr (STAGE == F_ALPHA) {
-            if (S.state == S_RUN) {
-                const double vr = Q(0), vi = Q(1);
-                const double d = vr * vr + vi * vi;
-                if (!(d > 0.0) || !finite_d(d)) {
-                    S.state = S_BRK;
-                } else {
-                    // alpha = rho / (rhat, v)
-                    S.alpha[0] = (S.rho[0] * vr + S.rho[1] * vi) / d;
-                    S.alpha[1] = (S.rho[1] * vr - S.rho[0] * vi) / d;
-                }
-            }
-            on = S.state == S_RUN;
-        } else if constexpr (STAGE == F_OMEGA) {
-            if (S.state == S_RUN) {
-                const double tsr = Q(0), tsi = Q(1), tt = Q(2);
-                if (!finite_d(tt) || !finite_d(tsr) || !finite_d(tsi)) {
-                    S.state = S_BRK;
-                } else if (tt > 0.0) {
-                    S.omega[0] = tsr / tt;
-                    S.omega[1] = tsi / tt;
-                } else {
-                    S.omega[0] = S.omega[1] = 0.0;
-                }
-            }
-            on = S.state == S_RUN;
-        } else if constexpr (STAGE == F_RHO) {
-            if (S.state == S_RUN) {
-                const double nr_ = Q(0), ni = Q(1), rr = Q(2);
-                S.iters += 1;
-                S.upd_p = 0;
-                S.rr = rr;
-                const double om2 = S.omega[0] * S.omega[0] + S.omega[1] * S.omega[1];
-                const double rho2 = S.rho[0] * S.rho[0] + S.rho[1] * S.rho[1];
-                int ns = S_RUN;
-                if (!finite_d(rr) || !finite_d(nr_) || !finite_d(ni)) {
-                    ns = S_BRK;
-                } else {
-                    if (rr <= S.tol2 * S.bb) ns = S_CHK;
-                    else if (S.delta2 > 0.0 && rr < S.delta2 * S.rr_max) ns = S_REL;
-                    else if (S.iters >= S.max_iter) ns = S_MAXIT;
-                    const double nn2 = nr_ * nr_ + ni * ni;
-                    if (om2 > 0.0 && rho2 > 0.0) {
-                        // beta = (rho_new / rho) * (alpha / omega)
-                        const double ar = (nr_ * S.rho[0] + ni * S.rho[1]) / rho2;
-                        const double ai = (ni * S.rho[0] - nr_ * S.rho[1]) / rho2;
-                        const double cr = (S.alpha[0] * S.omega[0] + S.alpha[1] * S.omega[1]) / om2;
-                        const double ci = (S.alpha[1] * S.omega[0] - S.alpha[0] * S.omega[1]) / om2;
-                        S.beta[0] = ar * cr - ai * ci;
-                        S.beta[1] = ar * ci + ai * cr;
-                        S.upd_p = 1;
-                    } else if (ns == S_RUN) {
-                        ns = S_BRK;
-                    }
-                    if (ns == S_RUN && nn2 <= 1e-28 * rr * S.rhat2) ns = S_BRK;  // rho ~ 0
-                    S.rho[0] = nr_;
-                    S.rho[1] = ni;
-                }
-                if (ns == S_BRK) S.upd_p = 0;
-                if (rr > S.rr_max) S.rr_max = rr;
-                S.state = ns;
-            } else {
-                S.upd_p = 0;
-            }
-            on = (S.state == S_RUN) || S.upd_p;
-        } else if constexpr (STAGE == F_TRUE) {
-            const int s = S.state;
-            if (s == S_REL || s == S_CHK || s == S_BRK || s == S_MAXIT) {
-                S.rr_true = Q(0);
-                S.n_rel += 1;
-                if (S.rr_true <= S.tol2 * S.bb) S.state = S_DONE;
-                else if (s == S_MAXIT || !finite_d(S.rr_true)) S.state = S_FAIL;
-                else if (s == S_BRK) {
-                    S.restarts += 1;
-                    S.state = S.restarts > 64 ? S_FAIL : S_RST;
-                } else S.state = S_CONV;
-            }
-            on = S.state == S_CONV || S.state == S_RST;
-        } else {  // F_RESUME
-            const int s = S.state;
-            if (s == S_CONV || s == S_RST) {
-                S.rho[0] = Q(0);
-                S.rho[1] = Q(1);
-                S.rr = Q(2);
-                S.rr_max = S.rr;
-                if (s == S_RST) S.rhat2 = S.rr;
-                S.state = S_RUN;
-            }
-            on = S.state == S_RUN;
-        }
+    if (threadIdx.x == 0) {
+        any_on = 0;
+        any_rel = 0;
+        any_pend = 0;
     }
-    if (on) atomicOr(&any, 1);
     __syncthreads();
-    if (threadIdx.x == 0 && blk_on) blk_on[b] = any;
+    const bool mine = threadIdx.x < nr;
+    if (mine) {
+        SysState& S = st[bd.sys0 + threadIdx.x];
+        finish_system<STAGE>(S, q, nr, threadIdx.x);
+        if (STAGE == F_RHO && S.state == S_REL) atomicOr(&any_rel, 1);
+    }
+    __syncthreads();
+    if (mine) {
+        SysState& S = st[bd.sys0 + threadIdx.x];
+        // Reliable updates are taken block by block: when one system of the
+        // block asks for one, every running system of the block joins it, so
+        // the FP64 stencil of the update does useful work on all its lanes.
+        if (STAGE == F_RHO && any_rel && S.state == S_RUN) S.state = S_REL;
+        bool on;
+        if (STAGE == F_RHO) on = (S.state == S_RUN) || S.upd_p;
+        else if (STAGE == F_TRUE) on = S.state == S_CONV || S.state == S_RST;
+        else on = S.state == S_RUN;
+        const bool pend = STAGE == F_RHO &&
+                          (S.state == S_REL || S.state == S_CHK || S.state == S_BRK || S.state == S_MAXIT);
+        if (on) atomicOr(&any_on, 1);
+        if (pend) atomicOr(&any_pend, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (blk_on) blk_on[b] = any_on;
+        if (blk_pend) blk_pend[b] = any_pend;
+    }
 }
 
 // Per-block mask "has systems in the given class" (sets blk_on for eager launches).
@@ -694,10 +720,20 @@ __global__ void k_level_stats(const double* __restrict__ X, int L1, int n_noise,
     d[3] = n_noise > 1 ? vp * N / (N - 1.0) : 0.0;
 }
 
-__global__ void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) dst[i] = src[i];
+// Streaming copy: each lane moves 4 x 16 bytes with all loads issued first.
+__global__ void __launch_bounds__(256) k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n) {
+    const size_t base = (size_t)blockIdx.x * 1024 + threadIdx.x;
+    uint4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const size_t i = base + (size_t)k * 256;
+        if (i < n) v[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const size_t i = base + (size_t)k * 256;
+        if (i < n) dst[i] = v[k];
+    }
 }
 
 }  // namespace
@@ -739,17 +775,15 @@ void launch_init(int prec, const Work& w, Fld b, Fld xhi, Fld xlo, Fld rhi, Fld 
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_init<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, b, xhi, xlo, rhi, r,
                                            rhat, p, part))
 }
-void launch_finish(int stage, const Work& w, SysState* st, const double* part, int* blk_on, hipStream_t s) {
-    // Finish kernels read w.blk_on (the flags of the launch they complete) and
-    // write the flags for the next launch; both alias the same array.
+void launch_finish(int stage, const Work& w, SysState* st, const double* part, int* out, int* out2, hipStream_t s) {
     Work wf = w;
     switch (stage) {
-        case F_INIT: wf.blk_on = nullptr; hipLaunchKernelGGL(k_finish<F_INIT>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, blk_on); break;
-        case F_ALPHA: hipLaunchKernelGGL(k_finish<F_ALPHA>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, blk_on); break;
-        case F_OMEGA: hipLaunchKernelGGL(k_finish<F_OMEGA>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, blk_on); break;
-        case F_RHO: hipLaunchKernelGGL(k_finish<F_RHO>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, blk_on); break;
-        case F_TRUE: hipLaunchKernelGGL(k_finish<F_TRUE>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, blk_on); break;
-        case F_RESUME: hipLaunchKernelGGL(k_finish<F_RESUME>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, blk_on); break;
+        case F_INIT: wf.blk_on = nullptr; hipLaunchKernelGGL(k_finish<F_INIT>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, out, out2); break;
+        case F_ALPHA: hipLaunchKernelGGL(k_finish<F_ALPHA>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, out, out2); break;
+        case F_OMEGA: hipLaunchKernelGGL(k_finish<F_OMEGA>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, out, out2); break;
+        case F_RHO: hipLaunchKernelGGL(k_finish<F_RHO>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, out, out2); break;
+        case F_TRUE: hipLaunchKernelGGL(k_finish<F_TRUE>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, out, out2); break;
+        case F_RESUME: hipLaunchKernelGGL(k_finish<F_RESUME>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, out, out2); break;
         default: break;
     }
 }
@@ -796,8 +830,7 @@ void launch_level_stats(const double* X, int L1, int n_noise, int P1, double* ou
     hipLaunchKernelGGL(k_level_stats, dim3((n + 255) / 256), dim3(256), 0, s, X, L1, n_noise, P1, out);
 }
 void launch_copy(uint4* dst, const uint4* src, size_t n16, hipStream_t s) {
-    size_t blocks = (n16 + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
+    const size_t blocks = (n16 + 1023) / 1024;
     hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, n16);
 }
 

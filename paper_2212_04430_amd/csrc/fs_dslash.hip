@@ -11,6 +11,8 @@
 // divided by NR.  Each hop is spin-projected to a half spinor before the SU(3)
 // product, halving the colour arithmetic.  Fused epilogues produce the
 // per-workgroup partial sums that BiCGStab needs (FP64).
+#include <algorithm>
+
 #include "fs_kernels.h"
 
 namespace fs {
@@ -156,8 +158,26 @@ template <> struct NDots<D_RHAT> { static constexpr int v = 2; };
 template <> struct NDots<D_TS> { static constexpr int v = 3; };
 template <> struct NDots<D_RESID> { static constexpr int v = 1; };
 
-template <int P, int MODE>
-__global__ void __launch_bounds__(256) k_dslash(Work w, Fld out, Fld in, Fld aux,
+// Stencil over t-columns.  A workgroup owns `wg` consecutive (xyz, rhs) slots
+// of one block and walks t through a chunk of `tc` slices; each lane carries
+// the backward-t half spinor U_t(x,t-1)^+ (1+g4) psi(x,t-1) in registers from
+// one slice to the next, so the t-direction needs no cache reuse, while the
+// x/y/z neighbours of slice t are loaded by neighbouring lanes and concurrently
+// running workgroups at the same t (L1/L2 hits).
+// Two register budgets per precision.  ILP = 0 lets the compiler size the
+// allocation for several resident waves; ILP = 1 allows one wave per SIMD the
+// whole register file, so a site's neighbour and link loads are all in flight
+// at once.  Which one wins depends on how much of the stencil's footprint the
+// per-XCD L2 holds, so the autotuner measures both, together with a cap on
+// resident waves (dynamic LDS per workgroup, see launch_dslash).
+template <int P, int ILP> struct Wpe {
+    static constexpr int lo = ILP ? 1 : (P == P64 ? 2 : 1);
+    static constexpr int hi = ILP ? 1 : 8;
+};
+
+template <int P, int MODE, int ILP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Wpe<P, ILP>::lo, Wpe<P, ILP>::hi)))
+k_dslash(Work w, Fld out, Fld in, Fld aux,
                                                 const double* __restrict__ diag,
                                                 const SysState* __restrict__ st, int mask,
                                                 double* __restrict__ part) {
@@ -176,62 +196,105 @@ __global__ void __launch_bounds__(256) k_dslash(Work w, Fld out, Fld in, Fld aux
     const float* inn = in.n ? in.n + bd.slot_off : nullptr;
     uint4* ob = out.v + (size_t)bd.slot_off * G;
     float* on = out.n ? out.n + bd.slot_off : nullptr;
-    const int sy = ld.L[0], sz = ld.L[0] * ld.L[1], stt = sz * ld.L[2];
+    const int sy = ld.L[0], sz = ld.L[0] * ld.L[1], vxyz = sz * ld.L[2];
+    const int Lt = ld.L[3];
+    const int n3 = vxyz << w.lognr;             // (xyz, rhs) slots of one t-slice
+    const int ntile3 = (n3 + w.wg - 1) / w.wg;
+    const int j = wgb % ntile3, ch = wgb / ntile3;
+    const int s3 = j * w.wg + threadIdx.x;
+    const int t0 = ch * w.tc, t1 = min(Lt, t0 + w.tc);
 
     double acc[ND];
 #pragma unroll
     for (int k = 0; k < ND; ++k) acc[k] = 0.0;
 
-    for (int it = 0; it < w.tpw; ++it) {
-        const size_t slot = ((size_t)wgb * w.tpw + it) * w.wg + threadIdx.x;
-        if (slot >= gs) break;
-        const int site = (int)(slot >> w.lognr);
-        const int r = (int)(slot & (size_t)(w.nr - 1));
-        const int sys = bd.sys0 + r;
-        if (!mask_ok(mask, st, sys)) continue;
+    const int xyz = s3 >> w.lognr;
+    const int r = s3 & (w.nr - 1);
+    const int sys = bd.sys0 + r;
+    if (s3 < n3 && mask_ok(mask, st, sys)) {
         const A dg = (A)diag[sys];
-        const Coord c = coords(site, ld);
-        A o[24];
+        Coord c;
         {
-            A v[24];
-            load_sp<P, A>(ib, inn, gs, slot, v);
-#pragma unroll
-            for (int k = 0; k < 24; ++k) o[k] = dg * v[k];
+            int q = xyz;
+            c.x = q % ld.L[0];
+            q /= ld.L[0];
+            c.y = q % ld.L[1];
+            c.z = q / ld.L[1];
         }
-        hop_dir<P, 0, PxM, PxP>(ld, ib, inn, gs, site, c.x, 1, r, w.lognr, o);
-        hop_dir<P, 1, PyM, PyP>(ld, ib, inn, gs, site, c.y, sy, r, w.lognr, o);
-        hop_dir<P, 2, PzM, PzP>(ld, ib, inn, gs, site, c.z, sz, r, w.lognr, o);
-        hop_dir<P, 3, PtM, PtP>(ld, ib, inn, gs, site, c.t, stt, r, w.lognr, o);
-
-        if constexpr (MODE == D_RESID) {
-            // out = b - (D + sigma) x, all FP64
-            A bv[24];
-            load_sp<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
+        // backward-t contribution entering slice t0: from (x, t0-1)
+        A bw[12];
+        {
+            const int tb = (t0 == 0) ? Lt - 1 : t0 - 1;
+            const int sb = xyz + vxyz * tb;
+            A v[24], h[12], u[18];
+            load_sp<P, A>(ib, inn, gs, ((size_t)sb << w.lognr) + r, v);
+            PtP::project(v, h);
+            load_link<P, A>(ld.gauge, ld.V, 3, sb, u);
+            mul_udag(u, h, bw);
+            if (t0 == 0 && ld.tsign < 0) {
 #pragma unroll
-            for (int k = 0; k < 24; ++k) o[k] = bv[k] - o[k];
+                for (int k = 0; k < 12; ++k) bw[k] = -bw[k];
+            }
         }
-        store_sp<P, A>(ob, on, gs, slot, o);
-        if constexpr (MODE == D_RHAT) {
-            A rh[24];
-            load_sp<P, A>(aux.v + (size_t)bd.slot_off * G, aux.n ? aux.n + bd.slot_off : nullptr, gs, slot, rh);
+#pragma unroll 1
+        for (int t = t0; t < t1; ++t) {
+            const int site = xyz + vxyz * t;
+            const size_t slot = ((size_t)site << w.lognr) + r;
+            A o[24];
+            A bn[12];  // backward-t term of slice t+1
+            {
+                // centre: diagonal term, and with U_t(x,t) the next slice's backward term
+                A v[24], h[12], u[18];
+                load_sp<P, A>(ib, inn, gs, slot, v);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
-                acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
+                for (int k = 0; k < 24; ++k) o[k] = dg * v[k];
+                load_link<P, A>(ld.gauge, ld.V, 3, site, u);
+                PtP::project(v, h);
+                mul_udag(u, h, bn);
+                // forward t hop with the same link
+                const bool wrap = (t == Lt - 1);
+                const int sf = wrap ? xyz : site + vxyz;
+                A ww[12];
+                load_sp<P, A>(ib, inn, gs, ((size_t)sf << w.lognr) + r, v);
+                PtM::project(v, h);
+                mul_u(u, h, ww);
+                PtM::accum(o, ww, (wrap && ld.tsign < 0) ? A(0.5) : A(-0.5));
             }
-        } else if constexpr (MODE == D_TS) {
-            A sv[24];
-            load_sp<P, A>(ib, inn, gs, slot, sv);
+            PtP::accum(o, bw, A(-0.5));
+            hop_dir<P, 0, PxM, PxP>(ld, ib, inn, gs, site, c.x, 1, r, w.lognr, o);
+            hop_dir<P, 1, PyM, PyP>(ld, ib, inn, gs, site, c.y, sy, r, w.lognr, o);
+            hop_dir<P, 2, PzM, PzP>(ld, ib, inn, gs, site, c.z, sz, r, w.lognr, o);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                const double tr = o[2 * k], ti = o[2 * k + 1], sr = sv[2 * k], si = sv[2 * k + 1];
-                acc[0] += tr * sr + ti * si;
-                acc[1] += tr * si - ti * sr;
-                acc[2] += tr * tr + ti * ti;
+            for (int k = 0; k < 12; ++k) bw[k] = bn[k];
+            if constexpr (MODE == D_RESID) {
+                A bv[24];
+                load_sp<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
+#pragma unroll
+                for (int k = 0; k < 24; ++k) o[k] = bv[k] - o[k];
             }
-        } else if constexpr (MODE == D_RESID) {
+            store_sp<P, A>(ob, on, gs, slot, o);
+            if constexpr (MODE == D_RHAT) {
+                A rh[24];
+                load_sp<P, A>(aux.v + (size_t)bd.slot_off * G, aux.n ? aux.n + bd.slot_off : nullptr, gs, slot, rh);
 #pragma unroll
-            for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
+                for (int k = 0; k < 12; ++k) {
+                    acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
+                    acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
+                }
+            } else if constexpr (MODE == D_TS) {
+                A sv[24];
+                load_sp<P, A>(ib, inn, gs, slot, sv);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    const double tr = o[2 * k], ti = o[2 * k + 1], sr = sv[2 * k], si = sv[2 * k + 1];
+                    acc[0] += tr * sr + ti * si;
+                    acc[1] += tr * si - ti * sr;
+                    acc[2] += tr * tr + ti * ti;
+                }
+            } else if constexpr (MODE == D_RESID) {
+#pragma unroll
+                for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
+            }
         }
     }
     if constexpr (MODE != D_PLAIN) block_partials<ND, 4>(acc, w.nr, part, wg_id);
@@ -241,20 +304,38 @@ __global__ void __launch_bounds__(256) k_dslash(Work w, Fld out, Fld in, Fld aux
 
 static int grid_of(const Work& w) { return (w.total_wg + 7) / 8 * 8; }
 
-template <int P, int MODE>
+// Dynamic LDS that caps resident workgroups per CU (160 KiB of LDS per CU):
+// waves = target waves per SIMD (0 = no cap).
+static size_t lds_cap(int wg, int waves) {
+    if (waves <= 0) return 0;
+    const int waves_per_wg = (wg + 63) / 64;
+    int wg_per_cu = std::max(1, (waves * 4) / waves_per_wg);
+    size_t bytes = (size_t)(160 * 1024) / (size_t)wg_per_cu;
+    bytes = bytes > 4096 ? bytes - 4096 : 0;  // leave room for the static partial-sum buffer
+    return std::min<size_t>(bytes, 64 * 1024);
+}
+
+template <int P, int MODE, int ILP>
 static void launch_t(const Work& w, Fld out, Fld in, Fld aux, const double* diag, const SysState* st,
                      int mask, double* part, hipStream_t s) {
-    hipLaunchKernelGGL((k_dslash<P, MODE>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, aux, diag, st,
-                       mask, part);
+    hipLaunchKernelGGL((k_dslash<P, MODE, ILP>), dim3(grid_of(w)), dim3(w.wg), lds_cap(w.wg, w.occ), s, w, out, in,
+                       aux, diag, st, mask, part);
+}
+
+template <int P, int MODE>
+static void launch_v(const Work& w, Fld out, Fld in, Fld aux, const double* diag, const SysState* st,
+                     int mask, double* part, hipStream_t s) {
+    if (w.ilp) launch_t<P, MODE, 1>(w, out, in, aux, diag, st, mask, part, s);
+    else launch_t<P, MODE, 0>(w, out, in, aux, diag, st, mask, part, s);
 }
 
 template <int P>
 static void launch_p(int mode, const Work& w, Fld out, Fld in, Fld aux, const double* diag,
                      const SysState* st, int mask, double* part, hipStream_t s) {
     switch (mode) {
-        case D_PLAIN: launch_t<P, D_PLAIN>(w, out, in, aux, diag, st, mask, part, s); break;
-        case D_RHAT: launch_t<P, D_RHAT>(w, out, in, aux, diag, st, mask, part, s); break;
-        case D_TS: launch_t<P, D_TS>(w, out, in, aux, diag, st, mask, part, s); break;
+        case D_PLAIN: launch_v<P, D_PLAIN>(w, out, in, aux, diag, st, mask, part, s); break;
+        case D_RHAT: launch_v<P, D_RHAT>(w, out, in, aux, diag, st, mask, part, s); break;
+        case D_TS: launch_v<P, D_TS>(w, out, in, aux, diag, st, mask, part, s); break;
         default: break;
     }
 }
@@ -262,7 +343,7 @@ static void launch_p(int mode, const Work& w, Fld out, Fld in, Fld aux, const do
 void launch_dslash(int prec, int mode, const Work& w, Fld out, Fld in, Fld aux, const double* diag,
                    const SysState* st, int mask, double* part, hipStream_t s) {
     if (mode == D_RESID) {
-        launch_t<P64, D_RESID>(w, out, in, aux, diag, st, mask, part, s);
+        launch_v<P64, D_RESID>(w, out, in, aux, diag, st, mask, part, s);
         return;
     }
     switch (prec) {

@@ -43,6 +43,9 @@ struct Work {
     int wg;                   // threads per workgroup
     int nr, lognr;            // systems per block
     const int* blk_on;        // device [nblk]: 0 => workgroups of the block exit (may be null)
+    int tc;                   // stencil launches: t-slices per workgroup column (0 = tile mapping)
+    int ilp;                  // stencil: register-rich variant (one wave per SIMD)
+    int occ;                  // stencil: cap on resident waves per SIMD (0 = none)
 };
 
 struct Fld {
@@ -71,7 +74,10 @@ void launch_update_p(int prec, const Work& w, Fld p, Fld r, Fld v, const SysStat
 
 // finish kernels: one workgroup per block, reduce partials, update state
 enum FStage : int { F_INIT = 0, F_ALPHA = 1, F_OMEGA = 2, F_RHO = 3, F_TRUE = 4, F_RESUME = 5 };
-void launch_finish(int stage, const Work& w, SysState* st, const double* part, int* blk_on, hipStream_t s);
+// w.blk_on: flags of the launch being completed (blocks with 0 are skipped);
+// out: flags for the next launch; out2 (F_RHO only): blocks with systems
+// pending a reliable update.
+void launch_finish(int stage, const Work& w, SysState* st, const double* part, int* out, int* out2, hipStream_t s);
 
 // reliable update / init
 void launch_fold(int prec, const Work& w, Fld xhi, Fld xlo, const SysState* st, hipStream_t s);
