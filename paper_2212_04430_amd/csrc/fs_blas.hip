@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256) k_axpy_s(Work w, Fld r, Fld v, const SysS
 
 // x += alpha p + omega s;  r = s - omega t  (s is held in r);  partials (rhat, r), |r|^2
 template <int P>
-__global__ void __launch_bounds__(256) k_update_xr(Work w, Fld x, Fld p, Fld r, Fld t, Fld rhat,
+__global__ void __launch_bounds__(256) k_update_xr(Work w, Fld x, Fld p, Fld r, Fld t, const NoiseKey* __restrict__ rk,
                                                    const SysState* __restrict__ st, double* __restrict__ part) {
     using A = typename Tr<P>::acc;
     FS_WG_PROLOGUE(w)
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(256) k_update_xr(Work w, Fld x, Fld p, Fld r, 
         }
         store_sp<P, A>(rb, rn, gs, slot, sv);
         A hv[24];
-        load_sp<P, A>(fbase<P>(rhat, bd), nbase(rhat, bd), gs, slot, hv);
+        rhat_site<A>(rk[sys], st[sys].restarts, (long long)(slot >> w.lognr), hv);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             const double hr = hv[2 * k], hi = hv[2 * k + 1], qr = sv[2 * k], qi = sv[2 * k + 1];
@@ -180,9 +180,10 @@ __global__ void __launch_bounds__(256) k_fold(Work w, Fld xhi, Fld xlo, const Sy
     FS_SLOT_LOOP_END
 }
 
-// r = round(r_hi); restart systems also set rhat = p = r.  Partials (rhat, r), |r|^2
+// r = round(r_hi); restart systems also set p = r (their shadow residual is a
+// fresh Z4 stream).  Partials (rhat, r), |r|^2
 template <int P>
-__global__ void __launch_bounds__(256) k_convert(Work w, Fld rhi, Fld r, Fld rhat, Fld p,
+__global__ void __launch_bounds__(256) k_convert(Work w, Fld rhi, Fld r, const NoiseKey* __restrict__ rk, Fld p,
                                                  const SysState* __restrict__ st, double* __restrict__ part) {
     using A = typename Tr<P>::acc;
     FS_WG_PROLOGUE(w)
@@ -200,15 +201,9 @@ __global__ void __launch_bounds__(256) k_convert(Work w, Fld rhi, Fld r, Fld rha
         for (int k = 0; k < 24; ++k) q[k] = (A)h[k];
         store_sp<P, A>(rb, rn, gs, slot, q);
         load_sp<P, A>(rb, rn, gs, slot, q);  // the rounded value the iteration will see
+        if (s == S_RST) store_sp<P, A>(fbase_w<P>(p, bd), nbase(p, bd), gs, slot, q);
         A hv[24];
-        if (s == S_RST) {
-            store_sp<P, A>(fbase_w<P>(rhat, bd), nbase(rhat, bd), gs, slot, q);
-            store_sp<P, A>(fbase_w<P>(p, bd), nbase(p, bd), gs, slot, q);
-#pragma unroll
-            for (int k = 0; k < 24; ++k) hv[k] = q[k];
-        } else {
-            load_sp<P, A>(fbase<P>(rhat, bd), nbase(rhat, bd), gs, slot, hv);
-        }
+        rhat_site<A>(rk[sys], st[sys].restarts, (long long)(slot >> w.lognr), hv);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             const double hr = hv[2 * k], hi = hv[2 * k + 1], qr = q[2 * k], qi = q[2 * k + 1];
@@ -220,16 +215,15 @@ __global__ void __launch_bounds__(256) k_convert(Work w, Fld rhi, Fld r, Fld rha
     block_partials<3, 4>(acc, w.nr, part, wg_id);
 }
 
-// x_hi = x_lo = 0, r_hi = b, r = rhat = p = round(b).  Partials |b|^2, (rhat, r), |r|^2
+// x_hi = x_lo = 0, r_hi = b, r = p = round(b).  Partials |b|^2, (rhat, r), |r|^2
 template <int P>
-__global__ void __launch_bounds__(256) k_init(Work w, Fld bf, Fld xhi, Fld xlo, Fld rhi, Fld r, Fld rhat,
-                                              Fld p, double* __restrict__ part) {
+__global__ void __launch_bounds__(256) k_init(Work w, Fld bf, Fld xhi, Fld xlo, Fld rhi, Fld r,
+                                              const NoiseKey* __restrict__ rk, Fld p, double* __restrict__ part) {
     using A = typename Tr<P>::acc;
     FS_WG_PROLOGUE(w)
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const uint4* bb = bf.v + (size_t)bd.slot_off * 12;
     FS_SLOT_LOOP(w)
-        (void)sys;
         double h[24], z[24];
         A q[24];
         load_sp<P64, double>(bb, nullptr, gs, slot, h);
@@ -247,13 +241,17 @@ __global__ void __launch_bounds__(256) k_init(Work w, Fld bf, Fld xhi, Fld xlo, 
         store_sp<P, A>(fbase_w<P>(xlo, bd), nbase(xlo, bd), gs, slot, zl);
         store_sp<P, A>(fbase_w<P>(r, bd), nbase(r, bd), gs, slot, q);
         load_sp<P, A>(fbase<P>(r, bd), nbase(r, bd), gs, slot, q);
-        store_sp<P, A>(fbase_w<P>(rhat, bd), nbase(rhat, bd), gs, slot, q);
         store_sp<P, A>(fbase_w<P>(p, bd), nbase(p, bd), gs, slot, q);
+        A hv[24];
+        rhat_site<A>(rk[sys], 0, (long long)(slot >> w.lognr), hv);
 #pragma unroll
-        for (int k = 0; k < 24; ++k) acc[1] += (double)q[k] * (double)q[k];
+        for (int k = 0; k < 12; ++k) {
+            const double hr = hv[2 * k], hi = hv[2 * k + 1], qr = q[2 * k], qi = q[2 * k + 1];
+            acc[1] += hr * qr + hi * qi;
+            acc[2] += hr * qi - hi * qr;
+            acc[3] += qr * qr + qi * qi;
+        }
     FS_SLOT_LOOP_END
-    acc[3] = acc[1];
-    acc[2] = 0.0;
     block_partials<4, 4>(acc, w.nr, part, wg_id);
 }
 
@@ -263,7 +261,7 @@ __device__ __forceinline__ bool finite_d(double x) { return x == x && fabs(x) <=
 
 // Per-system scalar update after a reduction; one thread per system of the block.
 template <int STAGE>
-__device__ __forceinline__ void finish_system(SysState& S, const double* q, int nr, int r) {
+__device__ __forceinline__ void finish_system(SysState& S, const double* q, int nr, int r, double V) {
     auto Q = [&](int k) { return q[k * nr + r]; };
     if constexpr (STAGE == F_INIT) {
         if (S.state != S_IDLE) {
@@ -272,7 +270,7 @@ __device__ __forceinline__ void finish_system(SysState& S, const double* q, int 
             S.rho[1] = Q(2);
             S.rr = Q(3);
             S.rr_max = S.rr;
-            S.rhat2 = S.rr;
+            S.rhat2 = 12.0 * V;  // |rhat|^2 of a Z4 vector
             S.rr_true = S.bb;
             S.iters = 0;
             S.n_rel = 0;
@@ -364,7 +362,6 @@ __device__ __forceinline__ void finish_system(SysState& S, const double* q, int 
             S.rho[1] = Q(1);
             S.rr = Q(2);
             S.rr_max = S.rr;
-            if (s == S_RST) S.rhat2 = S.rr;
             S.state = S_RUN;
         }
     }
@@ -397,7 +394,7 @@ __global__ void __launch_bounds__(256) k_finish(Work w, SysState* __restrict__ s
     const bool mine = threadIdx.x < nr;
     if (mine) {
         SysState& S = st[bd.sys0 + threadIdx.x];
-        finish_system<STAGE>(S, q, nr, threadIdx.x);
+        finish_system<STAGE>(S, q, nr, threadIdx.x, (double)w.lats[bd.lat].V);
         if (STAGE == F_RHO && S.state == S_REL) atomicOr(&any_rel, 1);
     }
     __syncthreads();
@@ -498,32 +495,6 @@ __global__ void k_gauge_convert(void* __restrict__ dst, const double* __restrict
 }
 
 // ------------------------------------------------------------------ Z4 noise
-
-// The 12 components of `site` for key k: z_c = i^code(c), optionally times g5
-// (spins 2, 3 negated).  Component c = site*12 + j draws 2 bits of Philox block
-// c/128 (counter (c/128, sample, level, instance), key (seed, 0)).
-__device__ __forceinline__ void z4_site(const NoiseKey& k, long long site, double v[24]) {
-    const long long c0 = site * 12;
-    const long long b0 = c0 >> 7, b1 = (c0 + 11) >> 7;
-    U64x4 o0 = philox4x64_10((uint64_t)b0, k.sample, k.level, k.instance, k.seed, 0ull);
-    U64x4 o1 = o0;
-    if (b1 != b0) o1 = philox4x64_10((uint64_t)b1, k.sample, k.level, k.instance, k.seed, 0ull);
-#pragma unroll
-    for (int j = 0; j < 12; ++j) {
-        const long long c = c0 + j;
-        const int e = (int)(c & 127);
-        const uint64_t word = ((c >> 7) == b0) ? o0.v[e >> 5] : o1.v[e >> 5];
-        const int code = (int)((word >> (2 * (e & 31))) & 3ull);
-        double re = code == 0 ? 1.0 : code == 2 ? -1.0 : 0.0;
-        double im = code == 1 ? 1.0 : code == 3 ? -1.0 : 0.0;
-        if (k.g5 && j >= 6) {
-            re = -re;
-            im = -im;
-        }
-        v[2 * j] = re;
-        v[2 * j + 1] = im;
-    }
-}
 
 template <int P>
 __global__ void __launch_bounds__(256) k_noise_block(Work w, Fld dst, const NoiseKey* __restrict__ keys) {
@@ -754,9 +725,9 @@ static int grid_of(const Work& w) { return (w.total_wg + 7) / 8 * 8; }
 void launch_axpy_s(int prec, const Work& w, Fld r, Fld v, const SysState* st, hipStream_t s) {
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_axpy_s<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, r, v, st))
 }
-void launch_update_xr(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, Fld rhat, const SysState* st,
+void launch_update_xr(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, const NoiseKey* rk, const SysState* st,
                       double* part, hipStream_t s) {
-    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_update_xr<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, x, p, r, t, rhat,
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_update_xr<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, x, p, r, t, rk,
                                            st, part))
 }
 void launch_update_p(int prec, const Work& w, Fld p, Fld r, Fld v, const SysState* st, hipStream_t s) {
@@ -765,15 +736,15 @@ void launch_update_p(int prec, const Work& w, Fld p, Fld r, Fld v, const SysStat
 void launch_fold(int prec, const Work& w, Fld xhi, Fld xlo, const SysState* st, hipStream_t s) {
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_fold<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, xhi, xlo, st))
 }
-void launch_convert(int prec, const Work& w, Fld rhi, Fld r, Fld rhat, Fld p, const SysState* st, double* part,
-                    hipStream_t s) {
-    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_convert<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, rhi, r, rhat, p, st,
+void launch_convert(int prec, const Work& w, Fld rhi, Fld r, const NoiseKey* rk, Fld p, const SysState* st,
+                    double* part, hipStream_t s) {
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_convert<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, rhi, r, rk, p, st,
                                            part))
 }
-void launch_init(int prec, const Work& w, Fld b, Fld xhi, Fld xlo, Fld rhi, Fld r, Fld rhat, Fld p, double* part,
-                 hipStream_t s) {
+void launch_init(int prec, const Work& w, Fld b, Fld xhi, Fld xlo, Fld rhi, Fld r, const NoiseKey* rk, Fld p,
+                 double* part, hipStream_t s) {
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_init<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, b, xhi, xlo, rhi, r,
-                                           rhat, p, part))
+                                           rk, p, part))
 }
 void launch_finish(int stage, const Work& w, SysState* st, const double* part, int* out, int* out2, hipStream_t s) {
     Work wf = w;

@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Wpe<P,
 k_dslash(Work w, Fld out, Fld in, Fld aux,
                                                 const double* __restrict__ diag,
                                                 const SysState* __restrict__ st, int mask,
-                                                double* __restrict__ part) {
+                                                double* __restrict__ part, const NoiseKey* __restrict__ rk) {
     using A = typename Tr<P>::acc;
     constexpr int G = Tr<P>::G;
     constexpr int ND = NDots<MODE>::v;
@@ -275,7 +275,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
             store_sp<P, A>(ob, on, gs, slot, o);
             if constexpr (MODE == D_RHAT) {
                 A rh[24];
-                load_sp<P, A>(aux.v + (size_t)bd.slot_off * G, aux.n ? aux.n + bd.slot_off : nullptr, gs, slot, rh);
+                rhat_site<A>(rk[sys], st[sys].restarts, site, rh);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) {
                     acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
@@ -317,40 +317,40 @@ static size_t lds_cap(int wg, int waves) {
 
 template <int P, int MODE, int ILP>
 static void launch_t(const Work& w, Fld out, Fld in, Fld aux, const double* diag, const SysState* st,
-                     int mask, double* part, hipStream_t s) {
+                     int mask, double* part, hipStream_t s, const NoiseKey* rk) {
     hipLaunchKernelGGL((k_dslash<P, MODE, ILP>), dim3(grid_of(w)), dim3(w.wg), lds_cap(w.wg, w.occ), s, w, out, in,
-                       aux, diag, st, mask, part);
+                       aux, diag, st, mask, part, rk);
 }
 
 template <int P, int MODE>
 static void launch_v(const Work& w, Fld out, Fld in, Fld aux, const double* diag, const SysState* st,
-                     int mask, double* part, hipStream_t s) {
-    if (w.ilp) launch_t<P, MODE, 1>(w, out, in, aux, diag, st, mask, part, s);
-    else launch_t<P, MODE, 0>(w, out, in, aux, diag, st, mask, part, s);
+                     int mask, double* part, hipStream_t s, const NoiseKey* rk) {
+    if (w.ilp) launch_t<P, MODE, 1>(w, out, in, aux, diag, st, mask, part, s, rk);
+    else launch_t<P, MODE, 0>(w, out, in, aux, diag, st, mask, part, s, rk);
 }
 
 template <int P>
 static void launch_p(int mode, const Work& w, Fld out, Fld in, Fld aux, const double* diag,
-                     const SysState* st, int mask, double* part, hipStream_t s) {
+                     const SysState* st, int mask, double* part, hipStream_t s, const NoiseKey* rk) {
     switch (mode) {
-        case D_PLAIN: launch_v<P, D_PLAIN>(w, out, in, aux, diag, st, mask, part, s); break;
-        case D_RHAT: launch_v<P, D_RHAT>(w, out, in, aux, diag, st, mask, part, s); break;
-        case D_TS: launch_v<P, D_TS>(w, out, in, aux, diag, st, mask, part, s); break;
+        case D_PLAIN: launch_v<P, D_PLAIN>(w, out, in, aux, diag, st, mask, part, s, rk); break;
+        case D_RHAT: launch_v<P, D_RHAT>(w, out, in, aux, diag, st, mask, part, s, rk); break;
+        case D_TS: launch_v<P, D_TS>(w, out, in, aux, diag, st, mask, part, s, rk); break;
         default: break;
     }
 }
 
 void launch_dslash(int prec, int mode, const Work& w, Fld out, Fld in, Fld aux, const double* diag,
-                   const SysState* st, int mask, double* part, hipStream_t s) {
+                   const SysState* st, int mask, double* part, hipStream_t s, const NoiseKey* rk) {
     if (mode == D_RESID) {
-        launch_v<P64, D_RESID>(w, out, in, aux, diag, st, mask, part, s);
+        launch_v<P64, D_RESID>(w, out, in, aux, diag, st, mask, part, s, rk);
         return;
     }
     switch (prec) {
-        case P64: launch_p<P64>(mode, w, out, in, aux, diag, st, mask, part, s); break;
-        case P32: launch_p<P32>(mode, w, out, in, aux, diag, st, mask, part, s); break;
-        case P16: launch_p<P16>(mode, w, out, in, aux, diag, st, mask, part, s); break;
-        case PBF: launch_p<PBF>(mode, w, out, in, aux, diag, st, mask, part, s); break;
+        case P64: launch_p<P64>(mode, w, out, in, aux, diag, st, mask, part, s, rk); break;
+        case P32: launch_p<P32>(mode, w, out, in, aux, diag, st, mask, part, s, rk); break;
+        case P16: launch_p<P16>(mode, w, out, in, aux, diag, st, mask, part, s, rk); break;
+        case PBF: launch_p<PBF>(mode, w, out, in, aux, diag, st, mask, part, s, rk); break;
         default: break;
     }
 }

@@ -53,6 +53,67 @@ struct Fld {
     float* n = nullptr;    // FP16 scales (per slot) or null
 };
 
+// Z4 noise.  Block layout (FP64) for systems with noise keys, or canonical.
+// The same keys generate the BiCGStab shadow residual rhat on the fly.
+struct NoiseKey {
+    uint64_t seed;
+    uint32_t instance, level;
+    uint64_t sample;
+    int g5;        // apply gamma_5 to the vector
+    int pad;       // padding system: the zero vector
+};
+
+// The 12 components of `site` for key k: z_c = i^code(c), optionally times g5
+// (spins 2, 3 negated).  Component c = site*12 + j draws 2 bits of Philox block
+// c/128 (counter (c/128, sample, level, instance), key (seed, 0)).
+__device__ __forceinline__ void z4_site(const NoiseKey& k, long long site, double v[24]) {
+    const long long c0 = site * 12;
+    const long long b0 = c0 >> 7, b1 = (c0 + 11) >> 7;
+    U64x4 o0 = philox4x64_10((uint64_t)b0, k.sample, k.level, k.instance, k.seed, 0ull);
+    U64x4 o1 = o0;
+    if (b1 != b0) o1 = philox4x64_10((uint64_t)b1, k.sample, k.level, k.instance, k.seed, 0ull);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        const long long c = c0 + j;
+        const int e = (int)(c & 127);
+        // value selects (an indexed or address-taken array would live in private memory)
+        const bool first = (c >> 7) == b0;
+        const int wi = e >> 5;
+        const uint64_t w01 = wi == 0 ? (first ? o0.v[0] : o1.v[0]) : (first ? o0.v[1] : o1.v[1]);
+        const uint64_t w23 = wi == 2 ? (first ? o0.v[2] : o1.v[2]) : (first ? o0.v[3] : o1.v[3]);
+        const uint64_t word = wi < 2 ? w01 : w23;
+        const int code = (int)((word >> (2 * (e & 31))) & 3ull);
+        double re = code == 0 ? 1.0 : code == 2 ? -1.0 : 0.0;
+        double im = code == 1 ? 1.0 : code == 3 ? -1.0 : 0.0;
+        if (k.g5 && j >= 6) {
+            re = -re;
+            im = -im;
+        }
+        v[2 * j] = re;
+        v[2 * j + 1] = im;
+    }
+}
+
+// BiCGStab shadow residual of a system: its Z4 source stream (rhat = r0 = b
+// for estimator systems, x0 = 0); after the n-th breakdown restart a fresh Z4
+// stream (instance bit 31 set, level + n).  Padding systems: zero.
+template <typename A>
+__device__ __forceinline__ void rhat_site(const NoiseKey& k0, int restarts, long long site, A v[24]) {
+    if (k0.pad) {
+#pragma unroll
+        for (int j = 0; j < 24; ++j) v[j] = A(0);
+        return;
+    }
+    NoiseKey k = k0;
+    if (restarts > 0) {
+        k.instance ^= 0x80000000u;
+        k.level += (uint32_t)restarts;
+    }
+    double d[24];
+    z4_site(k, site, d);
+#pragma unroll
+    for (int j = 0; j < 24; ++j) v[j] = (A)d[j];
+}
 enum Mask : int { M_ALL = 0, M_RUN = 1, M_PEND = 2, M_CONVERT = 3, M_UPDP = 4 };
 
 // dslash modes
@@ -63,12 +124,13 @@ enum DMode : int {
     D_RESID = 3    // out = b - (D + sigma) in (b FP64 in aux) + |out|^2 [1 double]
 };
 
+// D_RHAT takes the shadow residual from rk (per-system keys); D_RESID reads b from aux.
 void launch_dslash(int prec, int mode, const Work& w, Fld out, Fld in, Fld aux, const double* diag,
-                   const SysState* st, int mask, double* part, hipStream_t s);
+                   const SysState* st, int mask, double* part, hipStream_t s, const NoiseKey* rk = nullptr);
 
 // BiCGStab vector kernels (precision of the Krylov fields)
 void launch_axpy_s(int prec, const Work& w, Fld r, Fld v, const SysState* st, hipStream_t s);
-void launch_update_xr(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, Fld rhat,
+void launch_update_xr(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, const NoiseKey* rk,
                       const SysState* st, double* part, hipStream_t s);
 void launch_update_p(int prec, const Work& w, Fld p, Fld r, Fld v, const SysState* st, hipStream_t s);
 
@@ -81,9 +143,9 @@ void launch_finish(int stage, const Work& w, SysState* st, const double* part, i
 
 // reliable update / init
 void launch_fold(int prec, const Work& w, Fld xhi, Fld xlo, const SysState* st, hipStream_t s);
-void launch_convert(int prec, const Work& w, Fld rhi, Fld r, Fld rhat, Fld p, const SysState* st,
+void launch_convert(int prec, const Work& w, Fld rhi, Fld r, const NoiseKey* rk, Fld p, const SysState* st,
                     double* part, hipStream_t s);
-void launch_init(int prec, const Work& w, Fld b, Fld xhi, Fld xlo, Fld rhi, Fld r, Fld rhat, Fld p,
+void launch_init(int prec, const Work& w, Fld b, Fld xhi, Fld xlo, Fld rhi, Fld r, const NoiseKey* rk, Fld p,
                  double* part, hipStream_t s);
 
 // layout conversion between canonical complex128 [sys][site][spin][col] and block layout;
@@ -96,14 +158,6 @@ void launch_unpack(int prec, const Work& w, double* dst, Fld src, long long sys_
 // gauge: canonical complex128 [mu][site][3][3] -> [mu][9][site] in precision prec
 void launch_gauge_convert(int prec, void* dst, const double* src, int V, hipStream_t s);
 
-// Z4 noise.  Block layout (FP64) for systems with noise keys, or canonical.
-struct NoiseKey {
-    uint64_t seed;
-    uint32_t instance, level;
-    uint64_t sample;
-    int g5;        // apply gamma_5 to the vector
-    int pad;
-};
 void launch_noise_block(int prec, const Work& w, Fld dst, const NoiseKey* keys /* per system */, hipStream_t s);
 void launch_noise_canonical(double* dst, int V, NoiseKey key, hipStream_t s);
 
