@@ -110,7 +110,7 @@ def committed_traffic(config_key):
         return None
     for line in open(TRAFFIC):
         if line.startswith("traffic:"):
-            f = dict(kv.split("=") for kv in line.split()[1:])
+            f = dict(kv.split("=", 1) for kv in line.split()[1:])
             if f.get("hash") == kernel_source_hash() and f.get("config") == config_key:
                 return float(f["bytes_per_launch"])
     return None
