@@ -305,6 +305,9 @@ struct Plan {
         w.tc = stencil ? tc : 0;
         w.ilp = stencil ? ilp : 0;
         w.occ = stencil ? occ : 0;
+        w.vlist = nullptr;
+        w.vstart = nullptr;
+        w.vcount = nullptr;
         w.tpw = tpw;
         w.wg = wg;
         w.nr = nr;
@@ -315,6 +318,12 @@ struct Plan {
 };
 
 constexpr int kTargetWG = 4096;  // workgroups per launch to aim for (256 CUs x 16)
+
+// Stencil t-chunks: lanes launched per t-slice are sized to this many times
+// the chip's resident capacity at 4 waves per SIMD.
+#ifndef FS_TC_OVERSUB
+#define FS_TC_OVERSUB 8
+#endif
 
 // blk_lat[b]: lattice of block b; lats: the contexts of the lattices.
 // Work tables for a given list of blocks (each block keeps its system ids and
@@ -357,7 +366,7 @@ std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, con
             lanes += (long long)(c->V / c->dims[3]) * nr;
             Lt_min = std::min(Lt_min, c->dims[3]);
         }
-        const long long target = 8ll * 256 * 4 * 4 * 64;
+        const long long target = (long long)FS_TC_OVERSUB * 256 * 4 * 4 * 64;
         long long nch = std::max<long long>(1, (target + lanes - 1) / std::max<long long>(1, lanes));
         int tcv = (int)std::max<long long>(2, (Lt_min + nch - 1) / nch);
         pl->tc = std::min(tcv, Lt_min);
@@ -447,7 +456,8 @@ struct BatchSolver {
     hipStream_t s;
     SolveOpts o;
     Field b, xhi, rhi, r, p, v, t, xlo;
-    DevBuf d_diag, d_st, d_part, d_flags, d_rkeys;
+    DevBuf d_diag, d_st, d_part, d_flags, d_rkeys, d_vl;
+    VList vl_run, vl_pend, vl_conv;
     std::vector<SysState> st_host;
     long long dslash_calls = 0;
     size_t part_rows = 0;
@@ -465,6 +475,16 @@ struct BatchSolver {
         part_rows = (size_t)pl.max_wg();
         d_part.alloc(sizeof(double) * part_rows * 32 * pl.nr);
         d_flags.alloc(sizeof(int) * 2 * pl.blocks.size());
+        const size_t nb = pl.blocks.size();
+        d_vl.alloc(sizeof(int) * 3 * (3 * nb + 3));
+        int* q = d_vl.as<int>();
+        for (VList* v : {&vl_run, &vl_pend, &vl_conv}) {
+            v->list = q;
+            v->vstart_tile = q + nb;
+            v->vstart_sten = q + 2 * nb + 1;
+            v->count = q + 3 * nb + 2;
+            q += 3 * nb + 3;
+        }
         st_host.resize(pl.nsys);
     }
 
@@ -499,44 +519,65 @@ struct BatchSolver {
         x.blk_on = flags;
         return x;
     }
-
-    // One BiCGStab iteration over every running system.  With in_loop_reliable
-    // the FP64 reliable update of the systems that asked for one in this
-    // iteration follows at once (no host round trip); blocks without such
-    // systems skip those launches at the first instruction.
-    void iteration(const Work& w, const Work& w64, bool in_loop_reliable) {
-        const double* dg = d_diag.as<double>();
-        const Work wr = with(w, f_run());
-        const Work wd = with(cur->work(o.P, true, true), f_run());
-        launch_dslash(o.P, D_RHAT, wd, v.f(), p.f(), Fld(), dg, st(), M_RUN, part(), s, rk());
-        launch_finish(F_ALPHA, wd, st(), part(), f_run(), nullptr, s);
-        launch_axpy_s(o.P, wr, r.f(), v.f(), st(), s);
-        launch_dslash(o.P, D_TS, wd, t.f(), r.f(), Fld(), dg, st(), M_RUN, part(), s);
-        launch_finish(F_OMEGA, wd, st(), part(), f_run(), nullptr, s);
-        launch_update_xr(o.P, wr, xlo.f(), p.f(), r.f(), t.f(), rk(), st(), part(), s);
-        launch_finish(F_RHO, wr, st(), part(), f_run(), f_pend(), s);
-        launch_update_p(o.P, wr, p.f(), r.f(), v.f(), st(), s);
-        dslash_calls += 2;
-        if (in_loop_reliable) reliable_chain(w, w64);
+    // persistent launch over the blocks of list vl (tile or stencil mapping)
+    Work listed(const VList& vl, int P, bool stencil) const {
+        Work x = cur->work(P, false, stencil);
+        x.vlist = vl.list;
+        x.vstart = stencil ? vl.vstart_sten : vl.vstart_tile;
+        x.vcount = vl.count;
+        return x;
+    }
+    void build_list(const int* flags, const VList& vl) {
+        launch_vlist(flags, (int)cur->blocks.size(), cur->d_wg_start.as<int>(), cur->d_wg_start_d.as<int>(), vl, s);
     }
 
-    // FP64 reliable update of the systems flagged in f_pend: x_hi += x_lo,
+    // One BiCGStab iteration over every running system.  Every launch walks
+    // the device-side list of running blocks, so finished blocks cost nothing;
+    // the list changes when F_RHO (or a resumed reliable update) says so.
+    // With in_loop_reliable the FP64 reliable update of the blocks that asked
+    // for one follows at once (no host round trip).
+    void iteration(bool in_loop_reliable) {
+        const double* dg = d_diag.as<double>();
+        const Work wr = listed(vl_run, o.P, false), wd = listed(vl_run, o.P, true);
+        launch_dslash(o.P, D_RHAT, wd, v.f(), p.f(), Fld(), dg, st(), M_RUN, part(), s, rk());
+        launch_finish(F_ALPHA, wd, st(), part(), nullptr, nullptr, s);
+        launch_axpy_s(o.P, wr, r.f(), v.f(), st(), s);
+        launch_dslash(o.P, D_TS, wd, t.f(), r.f(), Fld(), dg, st(), M_RUN, part(), s);
+        launch_finish(F_OMEGA, wd, st(), part(), nullptr, nullptr, s);
+        launch_update_xr(o.P, wr, xlo.f(), p.f(), r.f(), t.f(), rk(), st(), part(), s);
+        launch_finish(F_RHO, wr, st(), part(), f_run(), f_pend(), s);
+        build_list(f_run(), vl_run);
+        launch_update_p(o.P, listed(vl_run, o.P, false), p.f(), r.f(), v.f(), st(), s);
+        dslash_calls += 2;
+        if (in_loop_reliable) {
+            build_list(f_pend(), vl_pend);
+            reliable_chain();
+        }
+    }
+
+    // FP64 reliable update of the blocks in vl_pend: x_hi += x_lo,
     // r_hi = b - (D + sigma) x_hi, then either done or resume with r = r_hi.
-    void reliable_chain(const Work& w, const Work& w64) {
-        const Work wp = with(w, f_pend()), wc = with(w, f_conv());
-        const Work wp64d = with(cur->work(P64, true, true), f_pend()), wpd = with(cur->work(o.P, true, true), f_pend());
+    void reliable_chain() {
+        const Work wp = listed(vl_pend, o.P, false), wpd = listed(vl_pend, o.P, true);
+        const Work wp64d = listed(vl_pend, P64, true);
         launch_fold(o.P, wp, xhi.f(), xlo.f(), st(), s);
         launch_dslash(P64, D_RESID, wp64d, rhi.f(), xhi.f(), b.f(), d_diag.as<double>(), st(), M_PEND, part(), s);
         launch_finish(F_TRUE, wpd, st(), part(), f_conv(), f_pend(), s);  // clears f_pend
+        build_list(f_conv(), vl_conv);
+        const Work wc = listed(vl_conv, o.P, false);
         launch_convert(o.P, wc, rhi.f(), r.f(), rk(), p.f(), st(), part(), s);
         launch_finish(F_RESUME, wc, st(), part(), f_run(), f_conv(), s);  // clears f_conv
+        build_list(f_run(), vl_run);
     }
 
     // Host-driven variant: mark pending blocks from the states, then the chain.
-    void reliable(const Work& w, const Work& w64) {
+    void reliable() {
+        const Work w = cur->work(o.P, false);
         launch_blk_mask(w, st(), M_PEND, f_pend(), s);
-        reliable_chain(w, w64);
+        build_list(f_pend(), vl_pend);
+        reliable_chain();
         launch_blk_mask(w, st(), M_RUN, f_run(), s);
+        build_list(f_run(), vl_run);
         dslash_calls += 1;
     }
 
@@ -563,17 +604,24 @@ struct BatchSolver {
         sub = std::move(np);
         cur = sub.get();
         const Work w = cur->work(o.P, false);
-        if (!cur->blocks.empty()) {
-            launch_blk_mask(w, st(), M_RUN, f_run(), s);
-            launch_blk_mask(w, st(), M_PEND, f_pend(), s);
-            launch_blk_mask(w, st(), M_CONVERT, f_conv(), s);
-        }
+        launch_blk_mask(w, st(), M_RUN, f_run(), s);
+        launch_blk_mask(w, st(), M_PEND, f_pend(), s);
+        launch_blk_mask(w, st(), M_CONVERT, f_conv(), s);
+        build_list(f_run(), vl_run);
+        build_list(f_pend(), vl_pend);
+        build_list(f_conv(), vl_conv);
         return true;
     }
 
     void run() {
         launch_init(o.P, pl.work(o.P, false), b.f(), xhi.f(), xlo.f(), rhi.f(), r.f(), rk(), p.f(), part(), s);
-        launch_finish(F_INIT, pl.work(o.P, true), st(), part(), f_run(), nullptr, s);
+        launch_finish(F_INIT, pl.work(o.P, false), st(), part(), f_run(), nullptr, s);
+        {
+            const Work w = cur->work(o.P, false);
+            launch_blk_mask(w, st(), M_PEND, f_pend(), s);  // all zero at start
+            launch_blk_mask(w, st(), M_CONVERT, f_conv(), s);
+        }
+        build_list(f_run(), vl_run);
         // reduced precision: reliable updates inside every iteration; FP64:
         // the only FP64 check is at convergence, driven from the host.
         const bool in_loop = o.P != P64;
@@ -587,9 +635,8 @@ struct BatchSolver {
             graph = nullptr;
         };
         auto capture = [&]() {
-            const Work w = cur->work(o.P, true), w64 = cur->work(P64, true);
             HC(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            for (int i = 0; i < k; ++i) iteration(w, w64, in_loop);
+            for (int i = 0; i < k; ++i) iteration(in_loop);
             dslash_calls -= 2 * k;
             HC(hipStreamEndCapture(s, &graph));
             HC(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -603,8 +650,7 @@ struct BatchSolver {
                     HC(hipGraphLaunch(exec, s));
                     dslash_calls += 2 * k;
                 } else {
-                    const Work w = cur->work(o.P, true), w64 = cur->work(P64, true);
-                    for (int i = 0; i < k; ++i) iteration(w, w64, in_loop);
+                    for (int i = 0; i < k; ++i) iteration(in_loop);
                 }
                 HC(hipMemcpyAsync(st_host.data(), d_st.p, sizeof(SysState) * pl.nsys, hipMemcpyDeviceToHost, s));
                 HC(hipStreamSynchronize(s));
@@ -613,9 +659,9 @@ struct BatchSolver {
                     if (x.state == S_RUN) ++n_run;
                     else if (x.state == S_REL || x.state == S_CHK || x.state == S_BRK || x.state == S_MAXIT) ++n_pend;
                 }
-                if (n_pend > 0) reliable(cur->work(o.P, true), cur->work(P64, true));
+                if (n_pend > 0) reliable();
                 if (n_pend == 0 && n_run == 0) break;
-                // shrink the launches once a good part of the blocks has finished
+                // re-plan the stencil chunks once a good part of the blocks has finished
                 int n_active_blk = 0;
                 for (const BlockDesc& bd : cur->blocks) {
                     bool any = false;

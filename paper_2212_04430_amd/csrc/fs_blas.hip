@@ -11,6 +11,8 @@
 //    z) fused with the 4x4 spin-correlation M_ab = sum_{x,c} conj(y_ac) phi_bc,
 //    from which every bilinear y^+ Gamma_n Omega_p x of eq. fs_trace_est is a
 //    16-term contraction.
+#include <algorithm>
+
 #include "fs_kernels.h"
 
 namespace fs {
@@ -26,16 +28,18 @@ __device__ __forceinline__ bool mask_ok(int mask, const SysState* __restrict__ s
     return st[sys].upd_p != 0;
 }
 
-// Common prologue: map this workgroup to (block, first slot) and set locals.
+// Common prologue: for every virtual workgroup of this launch, bind the block
+// and its geometry; the body runs once per virtual workgroup (FS_WG_EPILOGUE
+// closes it).
 #define FS_WG_PROLOGUE(w)                                                   \
-    const int wg_id = xcd_remap(blockIdx.x, gridDim.x);                     \
-    if (wg_id >= (w).total_wg) return;                                      \
-    const int b = find_block((w).wg_start, (w).nblk, wg_id);                \
-    if ((w).blk_on && !(w).blk_on[b]) return;                               \
+    for_each_vwg((w), [&](const int wg_id, const int b) {                   \
+    (void)b;                                                                \
     const BlockDesc bd = (w).blocks[b];                                     \
     const LatDesc ld = (w).lats[bd.lat];                                    \
     const int wgb = wg_id - (w).wg_start[b];                                \
     const size_t gs = (size_t)ld.V << (w).lognr;
+
+#define FS_WG_EPILOGUE });
 
 #define FS_SLOT_LOOP(w)                                                     \
     for (int it = 0; it < (w).tpw; ++it) {                                  \
@@ -82,6 +86,7 @@ __global__ void __launch_bounds__(256) k_axpy_s(Work w, Fld r, Fld v, const SysS
         }
         store_sp<P, A>(rb, rn, gs, slot, x);
     FS_SLOT_LOOP_END
+    FS_WG_EPILOGUE
 }
 
 // x += alpha p + omega s;  r = s - omega t  (s is held in r);  partials (rhat, r), |r|^2
@@ -128,6 +133,7 @@ __global__ void __launch_bounds__(256) k_update_xr(Work w, Fld x, Fld p, Fld r, 
         }
     FS_SLOT_LOOP_END
     block_partials<3, 4>(acc, w.nr, part, wg_id);
+    FS_WG_EPILOGUE
 }
 
 // p = r + beta (p - omega v)
@@ -154,6 +160,7 @@ __global__ void __launch_bounds__(256) k_update_p(Work w, Fld p, Fld r, Fld v, c
         }
         store_sp<P, A>(pb, pn, gs, slot, pv);
     FS_SLOT_LOOP_END
+    FS_WG_EPILOGUE
 }
 
 // x_hi += x_lo; x_lo = 0  (systems pending a reliable update)
@@ -178,6 +185,7 @@ __global__ void __launch_bounds__(256) k_fold(Work w, Fld xhi, Fld xlo, const Sy
         store_sp<P64, double>(hb, nullptr, gs, slot, h);
         store_sp<P, A>(lb, ln, gs, slot, l);
     FS_SLOT_LOOP_END
+    FS_WG_EPILOGUE
 }
 
 // r = round(r_hi); restart systems also set p = r (their shadow residual is a
@@ -213,6 +221,7 @@ __global__ void __launch_bounds__(256) k_convert(Work w, Fld rhi, Fld r, const N
         }
     FS_SLOT_LOOP_END
     block_partials<3, 4>(acc, w.nr, part, wg_id);
+    FS_WG_EPILOGUE
 }
 
 // x_hi = x_lo = 0, r_hi = b, r = p = round(b).  Partials |b|^2, (rhat, r), |r|^2
@@ -253,6 +262,7 @@ __global__ void __launch_bounds__(256) k_init(Work w, Fld bf, Fld xhi, Fld xlo, 
         }
     FS_SLOT_LOOP_END
     block_partials<4, 4>(acc, w.nr, part, wg_id);
+    FS_WG_EPILOGUE
 }
 
 // ------------------------------------------------------------------ finish
@@ -379,11 +389,14 @@ __global__ void __launch_bounds__(256) k_finish(Work w, SysState* __restrict__ s
     constexpr int ND = STAGE == F_INIT ? 4 : STAGE == F_ALPHA ? 2 : STAGE == F_TRUE ? 1 : 3;
     __shared__ double q[ND * 16];
     __shared__ int any_on, any_rel, any_pend;
-    const int b = blockIdx.x;
     const int nr = w.nr;
+    // blocks of the launch being completed: its list (persistent launches), or
+    // one workgroup per block skipping those whose launch was skipped
+    const int nlist = w.vlist ? *w.vcount : 1;
+    for (int kk = w.vlist ? (int)blockIdx.x : 0; kk < nlist; kk += w.vlist ? (int)gridDim.x : 1) {
+    const int b = w.vlist ? w.vlist[kk] : (int)blockIdx.x;
     const BlockDesc bd = w.blocks[b];
-    // blocks whose launch was skipped have no fresh partial sums
-    if (w.blk_on && !w.blk_on[b] && STAGE != F_INIT) return;
+    if (!w.vlist && w.blk_on && !w.blk_on[b] && STAGE != F_INIT) return;
     reduce_rows(part, ND * nr, w.wg_start[b], w.wg_start[b + 1], q);
     if (threadIdx.x == 0) {
         any_on = 0;
@@ -418,6 +431,7 @@ __global__ void __launch_bounds__(256) k_finish(Work w, SysState* __restrict__ s
         if (blk_on) blk_on[b] = any_on;
         if (blk_pend) blk_pend[b] = any_pend;
     }
+    }
 }
 
 // Per-block mask "has systems in the given class" (sets blk_on for eager launches).
@@ -428,6 +442,58 @@ __global__ void k_blk_mask(Work w, const SysState* __restrict__ st, int mask, in
     int any = 0;
     for (int r = 0; r < w.nr; ++r) any |= mask_ok(mask, st, s0 + r) ? 1 : 0;
     blk_on[b] = any;
+}
+
+// Compact the blocks with flags[b] != 0 into a list (block order) with the
+// prefix sums of their workgroup counts in both mappings.  One workgroup.
+__global__ void __launch_bounds__(256) k_vlist(const int* __restrict__ flags, int nblk, const int* __restrict__ wg_tile,
+                                               const int* __restrict__ wg_sten, VList out) {
+    __shared__ int sc[256], st[256], ss[256];
+    __shared__ int base_n, base_t, base_s;
+    if (threadIdx.x == 0) {
+        base_n = 0;
+        base_t = 0;
+        base_s = 0;
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < nblk; c0 += 256) {
+        const int b = c0 + threadIdx.x;
+        const int on = (b < nblk && flags[b]) ? 1 : 0;
+        const int ct = on ? wg_tile[b + 1] - wg_tile[b] : 0;
+        const int cs = on ? wg_sten[b + 1] - wg_sten[b] : 0;
+        sc[threadIdx.x] = on;
+        st[threadIdx.x] = ct;
+        ss[threadIdx.x] = cs;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {  // inclusive scan (Hillis-Steele)
+            const int a0 = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
+            const int a1 = threadIdx.x >= off ? st[threadIdx.x - off] : 0;
+            const int a2 = threadIdx.x >= off ? ss[threadIdx.x - off] : 0;
+            __syncthreads();
+            sc[threadIdx.x] += a0;
+            st[threadIdx.x] += a1;
+            ss[threadIdx.x] += a2;
+            __syncthreads();
+        }
+        if (on) {
+            const int k = base_n + sc[threadIdx.x] - 1;
+            out.list[k] = b;
+            out.vstart_tile[k] = base_t + st[threadIdx.x] - ct;
+            out.vstart_sten[k] = base_s + ss[threadIdx.x] - cs;
+        }
+        __syncthreads();
+        if (threadIdx.x == 255) {
+            base_n += sc[255];
+            base_t += st[255];
+            base_s += ss[255];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out.vstart_tile[base_n] = base_t;
+        out.vstart_sten[base_n] = base_s;
+        *out.count = base_n;
+    }
 }
 
 // ------------------------------------------------------------------ layout conversion
@@ -452,6 +518,7 @@ __global__ void __launch_bounds__(256) k_pack(Work w, Fld dst, const double* __r
         }
         store_sp<P, A>(fbase_w<P>(dst, bd), nbase(dst, bd), gs, slot, v);
     FS_SLOT_LOOP_END
+    FS_WG_EPILOGUE
 }
 
 template <int P>
@@ -469,6 +536,7 @@ __global__ void __launch_bounds__(256) k_unpack(Work w, double* __restrict__ dst
 #pragma unroll
         for (int k = 0; k < 24; ++k) d[k] = (double)v[k];
     FS_SLOT_LOOP_END
+    FS_WG_EPILOGUE
 }
 
 template <int P>
@@ -515,6 +583,7 @@ __global__ void __launch_bounds__(256) k_noise_block(Work w, Fld dst, const Nois
         for (int j = 0; j < 24; ++j) q[j] = (A)v[j];
         store_sp<P, A>(fbase_w<P>(dst, bd), nbase(dst, bd), gs, slot, q);
     FS_SLOT_LOOP_END
+    FS_WG_EPILOGUE
 }
 
 __global__ void k_noise_canonical(double* __restrict__ dst, int V, NoiseKey k) {
@@ -591,6 +660,7 @@ __global__ void __launch_bounds__(256) k_hop_reduce(Work w, int p, Fld phi_out, 
             }
     FS_SLOT_LOOP_END
     block_partials<32, 4>(acc, w.nr, part, wg_id);
+    FS_WG_EPILOGUE
 }
 
 // M[(sys * M_stride + p) * 32 + k] = reduced partial k of system sys.
@@ -711,7 +781,7 @@ __global__ void __launch_bounds__(256) k_copy(uint4* __restrict__ dst, const uin
 
 // ------------------------------------------------------------------ launchers
 
-static int grid_of(const Work& w) { return (w.total_wg + 7) / 8 * 8; }
+static int grid_of(const Work& w) { return w.vlist ? persistent_grid(w.wg) : (w.total_wg + 7) / 8 * 8; }
 
 #define FS_DISPATCH_P(prec, CALL)          \
     switch (prec) {                         \
@@ -748,18 +818,22 @@ void launch_init(int prec, const Work& w, Fld b, Fld xhi, Fld xlo, Fld rhi, Fld 
 }
 void launch_finish(int stage, const Work& w, SysState* st, const double* part, int* out, int* out2, hipStream_t s) {
     Work wf = w;
+    const int grid = w.vlist ? std::min(w.nblk, 1024) : w.nblk;
     switch (stage) {
-        case F_INIT: wf.blk_on = nullptr; hipLaunchKernelGGL(k_finish<F_INIT>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, out, out2); break;
-        case F_ALPHA: hipLaunchKernelGGL(k_finish<F_ALPHA>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, out, out2); break;
-        case F_OMEGA: hipLaunchKernelGGL(k_finish<F_OMEGA>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, out, out2); break;
-        case F_RHO: hipLaunchKernelGGL(k_finish<F_RHO>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, out, out2); break;
-        case F_TRUE: hipLaunchKernelGGL(k_finish<F_TRUE>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, out, out2); break;
-        case F_RESUME: hipLaunchKernelGGL(k_finish<F_RESUME>, dim3(w.nblk), dim3(256), 0, s, wf, st, part, out, out2); break;
+        case F_INIT: wf.blk_on = nullptr; wf.vlist = nullptr; hipLaunchKernelGGL(k_finish<F_INIT>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
+        case F_ALPHA: hipLaunchKernelGGL(k_finish<F_ALPHA>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
+        case F_OMEGA: hipLaunchKernelGGL(k_finish<F_OMEGA>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
+        case F_RHO: hipLaunchKernelGGL(k_finish<F_RHO>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
+        case F_TRUE: hipLaunchKernelGGL(k_finish<F_TRUE>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
+        case F_RESUME: hipLaunchKernelGGL(k_finish<F_RESUME>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
         default: break;
     }
 }
 void launch_blk_mask(const Work& w, const SysState* st, int mask, int* blk_on, hipStream_t s) {
     hipLaunchKernelGGL(k_blk_mask, dim3((w.nblk + 255) / 256), dim3(256), 0, s, w, st, mask, blk_on);
+}
+void launch_vlist(const int* flags, int nblk, const int* wg_tile, const int* wg_sten, VList out, hipStream_t s) {
+    hipLaunchKernelGGL(k_vlist, dim3(1), dim3(256), 0, s, flags, nblk, wg_tile, wg_sten, out);
 }
 void launch_pack(int prec, const Work& w, Fld dst, const double* src, long long sys_stride, const int* sys_map,
                  hipStream_t s) {

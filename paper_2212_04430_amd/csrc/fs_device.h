@@ -275,6 +275,7 @@ __device__ __forceinline__ void block_partials(double (&v)[ND], int nr, double* 
         for (int w = 0; w < nwave; ++w) s += red[w][q];
         part[(size_t)wg * nq + q] = s;
     }
+    __syncthreads();  // red[] is reused by the next virtual workgroup of a persistent launch
 }
 
 // Reduce part rows [w0, w1) of width nq into out[q] (shared), fixed order.

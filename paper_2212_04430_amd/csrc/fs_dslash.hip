@@ -184,10 +184,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
     using A = typename Tr<P>::acc;
     constexpr int G = Tr<P>::G;
     constexpr int ND = NDots<MODE>::v;
-    const int wg_id = xcd_remap(blockIdx.x, gridDim.x);
-    if (wg_id >= w.total_wg) return;
-    const int b = find_block(w.wg_start, w.nblk, wg_id);
-    if (w.blk_on && !w.blk_on[b]) return;
+    for_each_vwg(w, [&](const int wg_id, const int b) {
     const BlockDesc bd = w.blocks[b];
     const LatDesc ld = w.lats[bd.lat];
     const int wgb = wg_id - w.wg_start[b];
@@ -298,11 +295,12 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
         }
     }
     if constexpr (MODE != D_PLAIN) block_partials<ND, 4>(acc, w.nr, part, wg_id);
+    });
 }
 
 }  // namespace
 
-static int grid_of(const Work& w) { return (w.total_wg + 7) / 8 * 8; }
+static int grid_of(const Work& w) { return w.vlist ? persistent_grid(w.wg) : (w.total_wg + 7) / 8 * 8; }
 
 // Dynamic LDS that caps resident workgroups per CU (160 KiB of LDS per CU):
 // waves = target waves per SIMD (0 = no cap).

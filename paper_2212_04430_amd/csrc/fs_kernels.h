@@ -46,7 +46,49 @@ struct Work {
     int tc;                   // stencil launches: t-slices per workgroup column (0 = tile mapping)
     int ilp;                  // stencil: register-rich variant (one wave per SIMD)
     int occ;                  // stencil: cap on resident waves per SIMD (0 = none)
+    // Persistent launches: when vlist is set, a fixed grid walks the virtual
+    // workgroups of the blocks listed there (vlist[0..*vcount)), vstart being
+    // their prefix sums in this launch's mapping (tile or stencil table).
+    const int* vlist;
+    const int* vstart;
+    const int* vcount;
 };
+
+// Device-side list of active blocks with virtual-workgroup prefix sums for
+// both mappings (built by launch_vlist from a block flag array).
+struct VList {
+    int* list = nullptr;         // [nblk]
+    int* vstart_tile = nullptr;  // [nblk + 1]
+    int* vstart_sten = nullptr;  // [nblk + 1]
+    int* count = nullptr;        // [1]
+};
+
+// Walk the virtual workgroups of a launch: body(wg_id, b) once per workgroup
+// of every listed block (or of every block with its flag set when the launch
+// has no list).  Each XCD walks a contiguous range of virtual workgroups.
+template <typename F>
+__device__ __forceinline__ void for_each_vwg(const Work& w, F&& body) {
+    if (!w.vlist) {
+        const int wg_id = xcd_remap(blockIdx.x, gridDim.x);
+        if (wg_id >= w.total_wg) return;
+        const int b = find_block(w.wg_start, w.nblk, wg_id);
+        if (w.blk_on && !w.blk_on[b]) return;
+        body(wg_id, b);
+        return;
+    }
+    const int n = *w.vcount;
+    if (n <= 0) return;
+    const int T = w.vstart[n];
+    const int nx = 8;
+    const int xcd = (int)(blockIdx.x % nx), slot = (int)(blockIdx.x / nx), nper = (int)(gridDim.x / nx);
+    const int lo = (int)((long long)T * xcd / nx), hi = (int)((long long)T * (xcd + 1) / nx);
+    for (int v = lo + slot; v < hi; v += nper) {
+        const int k = find_block(w.vstart, n, v);
+        const int b = w.vlist[k];
+        body(w.wg_start[b] + (v - w.vstart[k]), b);
+    }
+}
+
 
 struct Fld {
     uint4* v = nullptr;    // block-layout field (16-byte groups)
@@ -189,6 +231,10 @@ void launch_gamma_contract(const double* M, int P1, int nsys, const XMap* xm, co
                            int n_noise, hipStream_t s);
 void launch_level_stats(const double* X, int L1, int n_noise, int P1, double* out, hipStream_t s);
 void launch_blk_mask(const Work& w, const SysState* st, int mask, int* blk_on, hipStream_t s);
+// list of blocks with flags[b] != 0; wg_tile / wg_sten: the two workgroup tables of the plan
+void launch_vlist(const int* flags, int nblk, const int* wg_tile, const int* wg_sten, VList out, hipStream_t s);
+// physical grid of persistent launches
+inline int persistent_grid(int wg) { return 2048 * (256 / wg); }
 
 // copy kernel of known size (bandwidth calibration)
 void launch_copy(uint4* dst, const uint4* src, size_t n16, hipStream_t s);
