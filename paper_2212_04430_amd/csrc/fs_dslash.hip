@@ -171,7 +171,7 @@ template <> struct NDots<D_RESID> { static constexpr int v = 1; };
 // per-XCD L2 holds, so the autotuner measures both, together with a cap on
 // resident waves (dynamic LDS per workgroup, see launch_dslash).
 template <int P, int ILP> struct Wpe {
-    static constexpr int lo = ILP ? 1 : (P == P64 ? 2 : 1);
+    static constexpr int lo = 1;
     static constexpr int hi = ILP ? 1 : 8;
 };
 
@@ -233,6 +233,10 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
                 for (int k = 0; k < 12; ++k) bw[k] = -bw[k];
             }
         }
+        // centre spinor of the current slice, carried in registers: the
+        // forward-t neighbour loaded at slice t is the centre of slice t+1
+        A cv[24];
+        load_sp<P, A>(ib, inn, gs, ((size_t)(xyz + vxyz * t0) << w.lognr) + r, cv);
 #pragma unroll 1
         for (int t = t0; t < t1; ++t) {
             const int site = xyz + vxyz * t;
@@ -241,28 +245,42 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
             A bn[12];  // backward-t term of slice t+1
             {
                 // centre: diagonal term, and with U_t(x,t) the next slice's backward term
-                A v[24], h[12], u[18];
-                load_sp<P, A>(ib, inn, gs, slot, v);
+                A h[12], u[18];
 #pragma unroll
-                for (int k = 0; k < 24; ++k) o[k] = dg * v[k];
+                for (int k = 0; k < 24; ++k) o[k] = dg * cv[k];
                 load_link<P, A>(ld.gauge, ld.V, 3, site, u);
-                PtP::project(v, h);
+                PtP::project(cv, h);
                 mul_udag(u, h, bn);
                 // forward t hop with the same link
                 const bool wrap = (t == Lt - 1);
                 const int sf = wrap ? xyz : site + vxyz;
-                A ww[12];
+                A ww[12], v[24];
                 load_sp<P, A>(ib, inn, gs, ((size_t)sf << w.lognr) + r, v);
                 PtM::project(v, h);
                 mul_u(u, h, ww);
                 PtM::accum(o, ww, (wrap && ld.tsign < 0) ? A(0.5) : A(-0.5));
-            }
-            PtP::accum(o, bw, A(-0.5));
-            hop_dir<P, 0, PxM, PxP>(ld, ib, inn, gs, site, c.x, 1, r, w.lognr, o);
-            hop_dir<P, 1, PyM, PyP>(ld, ib, inn, gs, site, c.y, sy, r, w.lognr, o);
-            hop_dir<P, 2, PzM, PzP>(ld, ib, inn, gs, site, c.z, sz, r, w.lognr, o);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) bw[k] = bn[k];
+                for (int k = 0; k < 24; ++k) {
+                    const A c0 = cv[k];
+                    cv[k] = v[k];      // next slice's centre
+                    v[k] = c0;         // this slice's centre, for the dot below
+                }
+                PtP::accum(o, bw, A(-0.5));
+                hop_dir<P, 0, PxM, PxP>(ld, ib, inn, gs, site, c.x, 1, r, w.lognr, o);
+                hop_dir<P, 1, PyM, PyP>(ld, ib, inn, gs, site, c.y, sy, r, w.lognr, o);
+                hop_dir<P, 2, PzM, PzP>(ld, ib, inn, gs, site, c.z, sz, r, w.lognr, o);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) bw[k] = bn[k];
+                if constexpr (MODE == D_TS) {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) {
+                        const double tr = o[2 * k], ti = o[2 * k + 1], sr = v[2 * k], si = v[2 * k + 1];
+                        acc[0] += tr * sr + ti * si;
+                        acc[1] += tr * si - ti * sr;
+                        acc[2] += tr * tr + ti * ti;
+                    }
+                }
+            }
             if constexpr (MODE == D_RESID) {
                 A bv[24];
                 load_sp<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
@@ -277,16 +295,6 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
                 for (int k = 0; k < 12; ++k) {
                     acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
                     acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
-                }
-            } else if constexpr (MODE == D_TS) {
-                A sv[24];
-                load_sp<P, A>(ib, inn, gs, slot, sv);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    const double tr = o[2 * k], ti = o[2 * k + 1], sr = sv[2 * k], si = sv[2 * k + 1];
-                    acc[0] += tr * sr + ti * si;
-                    acc[1] += tr * si - ti * sr;
-                    acc[2] += tr * tr + ti * ti;
                 }
             } else if constexpr (MODE == D_RESID) {
 #pragma unroll
