@@ -295,7 +295,9 @@ __device__ __forceinline__ void finish_system(SysState& S, const double* q, int 
         if (S.state == S_RUN) {
             const double vr = Q(0), vi = Q(1);
             const double d = vr * vr + vi * vi;
-            if (!(d > 0.0) || !finite_d(d)) {
+            const double rho2 = S.rho[0] * S.rho[0] + S.rho[1] * S.rho[1];
+            if (!(d > 0.0) || !finite_d(d) || rho2 <= 1e-28 * S.rhat2 * S.rr) {
+                // (rhat, v) = 0 or (rhat, r) = 0: the Lanczos recurrence breaks down
                 S.state = S_BRK;
             } else {
                 // alpha = rho / (rhat, v)
