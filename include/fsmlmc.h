@@ -205,10 +205,21 @@ fs_status fs_batch_estimate(fs_batch b, const fs_est_params* prm, const double* 
 fs_status fs_batch_destroy(fs_batch b);
 
 /*
+ * Stencil variants (row a4 of the hot path):
+ *   0  t-columns: a work-group owns wg consecutive (xyz, rhs) slots and walks
+ *      t, carrying the backward-t half spinor and the centre in registers;
+ *      x/y/z neighbours are loaded from memory (cache hits across lanes);
+ *   1  as 0 with one wave per SIMD and the whole register file;
+ *   2  LDS tiles: a work-group owns a TX x TY x TZ tile of sites (powers of
+ *      two >= 2 dividing Lx, Ly, Lz; TX*TY*TZ = wg / rhs_block) and walks t;
+ *      the centre spinors of each slice are staged in LDS, so only the lanes
+ *      on a tile face load their outside neighbour from memory.  Where no
+ *      such tile exists (e.g. an odd extent) variant 0 runs instead.
+ *
  * fs_autotune -- time the stencil over a batch of n_sys systems (batches above
  * 96 are timed at 96: the resident set is bounded by the chip) for every
- * rhs_block in {1,2,4,8,16} (<= n_sys), work-group size in {64,128,256}, both
- * register variants and a cap of {none,1,2,4} resident waves per SIMD, and
+ * rhs_block in {1,2,4,8,16} (<= n_sys), work-group size in {64,128,256}, the
+ * three variants and a cap of {none,1,2,4} resident waves per SIMD, and
  * keep the fastest (per system) in the context for this storage precision;
  * later solves, estimates and stencil calls with rhs_block/wg = 0 use it.
  * cache_path: text file keyed by (arch, dims, precision, batch class), read
@@ -219,11 +230,21 @@ fs_status fs_autotune(fs_ctx ctx, fs_prec storage, int32_t n_sys, const char* ca
                       int32_t* best_rhs_block, int32_t* best_wg);
 
 /*
+ * fs_set_tuning -- set the stencil configuration for one storage precision
+ * by hand (what fs_autotune would store): rhs_block in {1,2,4,8,16}, wg in
+ * {64,128,256}, variant in {0,1,2} (see above), occ = cap on resident waves
+ * per SIMD in 0..8 (0 = none).  FS_E_ARG otherwise, leaving the context
+ * unchanged.  The FP64 reliable-update stencil of a mixed-precision batch
+ * uses the variant of the batch's storage precision.
+ */
+fs_status fs_set_tuning(fs_ctx ctx, fs_prec storage, int32_t rhs_block, int32_t wg, int32_t variant,
+                        int32_t occ);
+
+/*
  * fs_time_dslash -- average duration (ms, HIP events on the context's stream)
  * of n_launch back-to-back stencil launches on n_sys systems at the given
  * storage precision, rhs_block (0 = tuned), work-group size wg (0 = tuned),
- * register variant ilp (1: one wave per SIMD with the whole register file,
- * 0: default allocation, -1: tuned) and residency cap occ (waves per SIMD,
+ * stencil variant ilp (0, 1, 2 as above, -1: tuned) and residency cap occ (waves per SIMD,
  * 0 = none, -1 = tuned); and the algorithmic bytes one launch moves
  * (per site and system 48 stored reals of spinor in and out, plus 72 reals of
  * links per block of rhs_block systems; FP16 adds a 4-byte scale per spinor).

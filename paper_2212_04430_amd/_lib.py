@@ -86,6 +86,7 @@ _sig = {
                                     C.POINTER(fs_est_report)]),
     "fs_batch_destroy": (C.c_int, [_P]),
     "fs_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "fs_set_tuning": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "fs_time_dslash": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "fs_time_copy": (C.c_int, [_P, C.c_uint64, C.c_int32, C.POINTER(C.c_double)]),
@@ -284,6 +285,10 @@ def fs_autotune(ctx, storage, n_sys, cache_path=None):
     _check(_lib.fs_autotune(ctx, _prec(storage), int(n_sys), cache_path.encode() if cache_path else None,
                             C.byref(nr), C.byref(wg)))
     return nr.value, wg.value
+
+
+def fs_set_tuning(ctx, storage, rhs_block, wg, variant, occ=0):
+    _check(_lib.fs_set_tuning(ctx, _prec(storage), int(rhs_block), int(wg), int(variant), int(occ)))
 
 
 def fs_time_dslash(ctx, storage, n_sys, rhs_block=0, wg=0, n_launch=20, ilp=-1, occ=-1):

@@ -273,12 +273,17 @@ int ilog2(int n) {
 
 bool pow2_ok(int n) { return n >= 1 && n <= 16 && (n & (n - 1)) == 0; }
 
+// The kernels address one block's field (V * nr slots of up to 12 16-byte
+// groups, FP64) with 32-bit byte offsets: it must stay below 4 GiB.
+bool block_fits(long long V, int nr) { return 192ll * V * nr < (1ll << 32); }
+
 // ============================================================== plans
 
 // A batch of blocks (each NR systems of one lattice) mapped to workgroups.
 struct Plan {
     int nr = 1, lognr = 0, wg = 256, tpw = 1;
-    int ilp = 0, occ = 0;             // stencil register variant and residency cap
+    int ilp = 0, occ = 0;             // stencil variant and residency cap
+    int tl[3] = {0, 0, 0};            // stencil variant 2: log2 tile extents
     int nsys = 0;                     // nblk * nr
     std::vector<BlockDesc> blocks;
     std::vector<int> wg_start;        // nblk + 1  (tile mapping: vector kernels)
@@ -304,6 +309,7 @@ struct Plan {
         w.total_wg = stencil ? wg_start_d.back() : wg_start.back();
         w.tc = stencil ? tc : 0;
         w.ilp = stencil ? ilp : 0;
+        for (int k = 0; k < 3; ++k) w.tl[k] = tl[k];
         w.occ = stencil ? occ : 0;
         w.vlist = nullptr;
         w.vstart = nullptr;
@@ -325,6 +331,44 @@ constexpr int kTargetWG = 4096;  // workgroups per launch to aim for (256 CUs x 
 #define FS_TC_OVERSUB 8
 #endif
 
+// Tile of the LDS-staged stencil: wg / nr sites as TX x TY x TZ, powers of two,
+// each >= 2 and dividing the x/y/z extents of every lattice of the plan; the
+// shape with the fewest outside neighbours per site (sum over the axes the
+// tile does not span of 2 / T) wins, ties to the longer x extent (contiguous
+// in memory).  Returns false if no such shape exists.
+static bool choose_tile(int sites, const std::vector<fs_ctx_s*>& lats, int tl[3]) {
+    int ls = 0;
+    while ((1 << ls) < sites) ++ls;
+    if ((1 << ls) != sites) return false;
+    double best = 1e30;
+    bool found = false;
+    for (int a = 1; a <= ls; ++a)
+        for (int b = 1; a + b < ls; ++b) {
+            const int cz = ls - a - b;
+            const int e[3] = {a, b, cz};
+            bool ok = true;
+            double cost = 0.0;
+            for (int k = 0; k < 3 && ok; ++k) {
+                bool spans = true;
+                for (auto* c : lats) {
+                    if (c->dims[k] % (1 << e[k]) != 0) ok = false;
+                    if (c->dims[k] != (1 << e[k])) spans = false;
+                }
+                if (!spans) cost += 2.0 / (1 << e[k]);
+            }
+            if (!ok) continue;
+            cost -= 1e-6 * a;
+            if (cost < best) {
+                best = cost;
+                tl[0] = a;
+                tl[1] = b;
+                tl[2] = cz;
+                found = true;
+            }
+        }
+    return found;
+}
+
 // blk_lat[b]: lattice of block b; lats: the contexts of the lattices.
 // Work tables for a given list of blocks (each block keeps its system ids and
 // field offsets, so a plan over a subset of a batch shares the batch's fields).
@@ -335,6 +379,7 @@ std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, con
     pl->ilp = ilp;
     pl->occ = occ;
     pl->lognr = ilog2(nr);
+    if (ilp == 2 && !choose_tile(wg / nr, lats, pl->tl)) pl->ilp = 0;  // no tile fits: column variant
     pl->wg = wg;
     pl->blocks = blocks;
     const int nblk = (int)blocks.size();
@@ -343,6 +388,7 @@ std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, con
     long long tiles_total = 0;
     std::vector<long long> tiles(nblk);
     for (int b = 0; b < nblk; ++b) {
+        if (!block_fits(lats[blocks[b].lat]->V, nr)) fail(FS_E_ARG, "rhs_block too large for this lattice (a block's FP64 field must stay below 4 GiB)");
         const long long slots = (long long)lats[blocks[b].lat]->V * nr;
         tiles[b] = (slots + wg - 1) / wg;
         tiles_total += tiles[b];
@@ -718,7 +764,7 @@ void from_device(void* dst, const DevBuf& d, size_t n, int is_device, hipStream_
 int tuned_nr(fs_ctx c, int P, int n_sys) {
     auto it = c->tune.find(P);
     int nr = it != c->tune.end() ? it->second.nr : (P == P64 ? 4 : 8);
-    while (nr > 1 && nr > n_sys) nr >>= 1;
+    while (nr > 1 && (nr > n_sys || !block_fits(c->V, nr))) nr >>= 1;
     return nr;
 }
 int tuned_wg(fs_ctx c, int P) {
@@ -1137,12 +1183,16 @@ fs_status fs_apply_dirac(fs_ctx c, double m0, double sigma, fs_prec storage, con
         if (n_rhs < 1) fail(FS_E_ARG, "n_rhs must be >= 1");
         DeviceScope ds(c->device);
         hipStream_t s = c->stream;
-        int nr = 1;
-        while (nr < 16 && n_rhs % (nr * 2) == 0) nr *= 2;
-        const int nblk = n_rhs / nr;
+        // the tuned (or set) rhs block and work-group size; a last partial
+        // block is padded with zero systems
+        const int nr = tuned_nr(c, storage, n_rhs);
+        const int nblk = (n_rhs + nr - 1) / nr;
         std::vector<int> blk_lat(nblk, 0);
         std::vector<fs_ctx_s*> lats{c};
-        auto pl = make_plan(blk_lat, lats, nr, 256, s, tuned_ilp(c, storage), tuned_occ(c, storage));
+        auto pl = make_plan(blk_lat, lats, nr, tuned_wg(c, storage), s, tuned_ilp(c, storage), tuned_occ(c, storage));
+        std::vector<int> sys_map(pl->nsys);
+        for (int i = 0; i < pl->nsys; ++i) sys_map[i] = i < n_rhs ? i : -1;
+        DevBuf d_map = to_device(sys_map.data(), sizeof(int) * sys_map.size(), 0, s);
         const size_t nb = sizeof(double) * 24 * (size_t)c->V * n_rhs;
         DevBuf din = to_device(in, nb, is_device, s);
         DevBuf dout(nb);
@@ -1150,12 +1200,12 @@ fs_status fs_apply_dirac(fs_ctx c, double m0, double sigma, fs_prec storage, con
         fi.alloc(storage, pl->total_slots);
         fo.alloc(storage, pl->total_slots);
         const long long stride = 24ll * c->V;
-        launch_pack(storage, pl->work(storage, false), fi.f(), din.as<double>(), stride, nullptr, s);
+        launch_pack(storage, pl->work(storage, false), fi.f(), din.as<double>(), stride, d_map.as<int>(), s);
         std::vector<double> diag(pl->nsys, 4.0 + m0 + sigma);
         DevBuf d_diag = to_device(diag.data(), sizeof(double) * diag.size(), 0, s);
         launch_dslash(storage, D_PLAIN, pl->work(storage, false, true), fo.f(), fi.f(), Fld(), d_diag.as<double>(),
                       nullptr, M_ALL, nullptr, s);
-        launch_unpack(storage, pl->work(storage, false), dout.as<double>(), fo.f(), stride, nullptr, s);
+        launch_unpack(storage, pl->work(storage, false), dout.as<double>(), fo.f(), stride, d_map.as<int>(), s);
         HC(hipGetLastError());
         from_device(out, dout, nb, is_device, s);
     });
@@ -1412,7 +1462,8 @@ fs_status fs_time_dslash(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_b
         if (!pow2_ok(nr)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
         int w = wg ? wg : tuned_wg(c, storage);
         if (w != 64 && w != 128 && w != 256) fail(FS_E_ARG, "wg must be 64, 128 or 256");
-        const int il = ilp < 0 ? tuned_ilp(c, storage) : (ilp ? 1 : 0);
+        if (ilp > 2) fail(FS_E_ARG, "ilp must be -1, 0, 1 or 2");
+        const int il = ilp < 0 ? tuned_ilp(c, storage) : ilp;
         const int oc = occ < 0 ? tuned_occ(c, storage) : occ;
         if (oc > 8) fail(FS_E_ARG, "occ must be <= 8");
         DeviceScope ds(c->device);
@@ -1448,6 +1499,23 @@ fs_status fs_time_copy(fs_ctx c, uint64_t bytes, int32_t n_launch, double* avg_m
     });
 }
 
+fs_status fs_set_tuning(fs_ctx c, fs_prec storage, int32_t rhs_block, int32_t wg, int32_t variant, int32_t occ) {
+    return guard([&] {
+        check_ctx(c, false);
+        check_prec(storage);
+        if (!pow2_ok(rhs_block)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
+        if (wg != 64 && wg != 128 && wg != 256) fail(FS_E_ARG, "wg must be 64, 128 or 256");
+        if (variant < 0 || variant > 2) fail(FS_E_ARG, "variant must be 0, 1 or 2");
+        if (occ < 0 || occ > 8) fail(FS_E_ARG, "occ must be in 0..8");
+        TuneEntry e;
+        e.nr = rhs_block;
+        e.wg = wg;
+        e.ilp = variant;
+        e.occ = occ;
+        c->tune[storage] = e;
+    });
+}
+
 fs_status fs_autotune(fs_ctx c, fs_prec storage, int32_t n_sys, const char* cache_path, int32_t* best_rhs_block,
                       int32_t* best_wg) {
     return guard([&] {
@@ -1475,7 +1543,7 @@ fs_status fs_autotune(fs_ctx c, fs_prec storage, int32_t n_sys, const char* cach
                 if (line.rfind(key.str() + " ", 0) == 0) {
                     std::istringstream ls(line.substr(key.str().size()));
                     TuneEntry e;
-                    if (ls >> e.nr >> e.wg >> e.ilp >> e.occ >> e.ms_per_sys && pow2_ok(e.nr) &&
+                    if (ls >> e.nr >> e.wg >> e.ilp >> e.occ >> e.ms_per_sys && pow2_ok(e.nr) && e.ilp >= 0 && e.ilp <= 2 &&
                         (e.wg == 64 || e.wg == 128 || e.wg == 256) && e.occ >= 0 && e.occ <= 8) {
                         best = e;
                         found = true;
@@ -1486,9 +1554,9 @@ fs_status fs_autotune(fs_ctx c, fs_prec storage, int32_t n_sys, const char* cach
         if (!found) {
             best.ms_per_sys = 1e30;
             for (int nr : {1, 2, 4, 8, 16}) {
-                if (nr > n_tune) break;
+                if (nr > n_tune || !block_fits(c->V, nr)) break;
                 for (int wg : {64, 128, 256})
-                    for (int ilp : {0, 1})
+                    for (int ilp : {0, 1, 2})
                         for (int occ : {0, 1, 2, 4}) {
                             const double ms = time_dslash_impl(c, storage, n_tune, nr, wg, ilp, occ, 8) / n_tune;
                             if (ms < best.ms_per_sys) {

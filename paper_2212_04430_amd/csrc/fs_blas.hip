@@ -208,8 +208,8 @@ __global__ void __launch_bounds__(256) k_convert(Work w, Fld rhi, Fld r, const N
 #pragma unroll
         for (int k = 0; k < 24; ++k) q[k] = (A)h[k];
         store_sp<P, A>(rb, rn, gs, slot, q);
-        load_sp<P, A>(rb, rn, gs, slot, q);  // the rounded value the iteration will see
         if (s == S_RST) store_sp<P, A>(fbase_w<P>(p, bd), nbase(p, bd), gs, slot, q);
+        round_sp<P, A>(q);  // the stored value the iteration will see
         A hv[24];
         rhat_site<A>(rk[sys], st[sys].restarts, (long long)(slot >> w.lognr), hv);
 #pragma unroll
@@ -249,8 +249,8 @@ __global__ void __launch_bounds__(256) k_init(Work w, Fld bf, Fld xhi, Fld xlo, 
         for (int k = 0; k < 24; ++k) zl[k] = A(0);
         store_sp<P, A>(fbase_w<P>(xlo, bd), nbase(xlo, bd), gs, slot, zl);
         store_sp<P, A>(fbase_w<P>(r, bd), nbase(r, bd), gs, slot, q);
-        load_sp<P, A>(fbase<P>(r, bd), nbase(r, bd), gs, slot, q);
         store_sp<P, A>(fbase_w<P>(p, bd), nbase(p, bd), gs, slot, q);
+        round_sp<P, A>(q);  // the stored value
         A hv[24];
         rhat_site<A>(rk[sys], 0, (long long)(slot >> w.lognr), hv);
 #pragma unroll

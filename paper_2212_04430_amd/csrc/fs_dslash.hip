@@ -128,7 +128,7 @@ __device__ __forceinline__ void hop_dir(const LatDesc& ld, const uint4* __restri
     }
     {
         A v[24], h[12], u[18], w[12];
-        load_sp<P, A>(ib, inn, gs, ((size_t)sf << lognr) + r, v);
+        load_spb<P, A>(ib, inn, gs, ((size_t)sf << lognr) + r, v);
         PF::project(v, h);
         load_link<P, A>(ld.gauge, ld.V, MU, site, u);
         mul_u(u, h, w);
@@ -136,7 +136,7 @@ __device__ __forceinline__ void hop_dir(const LatDesc& ld, const uint4* __restri
     }
     {
         A v[24], h[12], u[18], w[12];
-        load_sp<P, A>(ib, inn, gs, ((size_t)sb << lognr) + r, v);
+        load_spb<P, A>(ib, inn, gs, ((size_t)sb << lognr) + r, v);
         PB::project(v, h);
         load_link<P, A>(ld.gauge, ld.V, MU, sb, u);
         mul_udag(u, h, w);
@@ -224,7 +224,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
             const int tb = (t0 == 0) ? Lt - 1 : t0 - 1;
             const int sb = xyz + vxyz * tb;
             A v[24], h[12], u[18];
-            load_sp<P, A>(ib, inn, gs, ((size_t)sb << w.lognr) + r, v);
+            load_spb<P, A>(ib, inn, gs, ((size_t)sb << w.lognr) + r, v);
             PtP::project(v, h);
             load_link<P, A>(ld.gauge, ld.V, 3, sb, u);
             mul_udag(u, h, bw);
@@ -236,7 +236,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
         // centre spinor of the current slice, carried in registers: the
         // forward-t neighbour loaded at slice t is the centre of slice t+1
         A cv[24];
-        load_sp<P, A>(ib, inn, gs, ((size_t)(xyz + vxyz * t0) << w.lognr) + r, cv);
+        load_spb<P, A>(ib, inn, gs, ((size_t)(xyz + vxyz * t0) << w.lognr) + r, cv);
 #pragma unroll 1
         for (int t = t0; t < t1; ++t) {
             const int site = xyz + vxyz * t;
@@ -255,7 +255,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
                 const bool wrap = (t == Lt - 1);
                 const int sf = wrap ? xyz : site + vxyz;
                 A ww[12], v[24];
-                load_sp<P, A>(ib, inn, gs, ((size_t)sf << w.lognr) + r, v);
+                load_spb<P, A>(ib, inn, gs, ((size_t)sf << w.lognr) + r, v);
                 PtM::project(v, h);
                 mul_u(u, h, ww);
                 PtM::accum(o, ww, (wrap && ld.tsign < 0) ? A(0.5) : A(-0.5));
@@ -283,11 +283,11 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
             }
             if constexpr (MODE == D_RESID) {
                 A bv[24];
-                load_sp<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
+                load_spb<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
 #pragma unroll
                 for (int k = 0; k < 24; ++k) o[k] = bv[k] - o[k];
             }
-            store_sp<P, A>(ob, on, gs, slot, o);
+            store_spb<P, A>(ob, on, gs, slot, o);
             if constexpr (MODE == D_RHAT) {
                 A rh[24];
                 rhat_site<A>(rk[sys], st[sys].restarts, site, rh);
@@ -303,6 +303,257 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
         }
     }
     if constexpr (MODE != D_PLAIN) block_partials<ND, 4>(acc, w.nr, part, wg_id);
+    });
+}
+
+// LDS-staged variant.  A workgroup owns a TX x TY x TZ tile of sites times the
+// NR systems of one block (lane = r + NR*(ix + TX*(iy + TY*iz))) and walks t
+// as above.  At every slice the lanes publish their centre spinor in LDS, so
+// a neighbour inside the tile is read from LDS and only the lanes on a tile
+// face load their outside neighbour from memory: per site ~sum_mu 2/T_mu of
+// the six spatial neighbour spinors instead of all six.
+template <typename A> struct LdsVec;
+template <> struct LdsVec<float> { using T = float4; };
+template <> struct LdsVec<double> { using T = double2; };
+
+template <typename A>
+__device__ __forceinline__ void lds_put(typename LdsVec<A>::T* sh, int wg, int lane, const A v[24]) {
+    constexpr int K = 16 / sizeof(A);
+#pragma unroll
+    for (int g = 0; g < 24 / K; ++g) {
+        typename LdsVec<A>::T q;
+        if constexpr (K == 4) q = make_float4(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]);
+        else q = make_double2(v[2 * g], v[2 * g + 1]);
+        sh[g * wg + lane] = q;
+    }
+}
+
+template <typename A>
+__device__ __forceinline__ void lds_get(const typename LdsVec<A>::T* sh, int wg, int lane, A v[24]) {
+    constexpr int K = 16 / sizeof(A);
+#pragma unroll
+    for (int g = 0; g < 24 / K; ++g) {
+        const typename LdsVec<A>::T q = sh[g * wg + lane];
+        if constexpr (K == 4) {
+            v[4 * g] = q.x; v[4 * g + 1] = q.y; v[4 * g + 2] = q.z; v[4 * g + 3] = q.w;
+        } else {
+            v[2 * g] = q.x; v[2 * g + 1] = q.y;
+        }
+    }
+}
+
+// One spatial direction of the tiled stencil: forward and backward hop of
+// slice-t site `site` (tile coordinate i of extent T = 1 << lt, lattice
+// coordinate coord of extent Lm, site stride `stride`, lane stride `ls`).
+// Every lane reads its neighbour's LDS entry and issues the memory load; a
+// lane whose neighbour is inside the tile points that load at slot 0 of the
+// block instead (one address for the whole wave: a broadcast, no traffic),
+// and the projected half spinors are selected without branching.
+template <int P, typename PR>
+__device__ __forceinline__ void fetch_half(bool in_tile, const uint4* __restrict__ ib,
+                                           const float* __restrict__ inn, size_t gs, size_t gslot,
+                                           const typename LdsVec<typename Tr<P>::acc>::T* sh, int wg, int nl,
+                                           typename Tr<P>::acc h[12]) {
+    using A = typename Tr<P>::acc;
+    A hg[12];
+    {
+        A g[24];
+        load_spb<P, A>(ib, inn, gs, in_tile ? (size_t)0 : gslot, g);
+        PR::project(g, hg);
+    }
+    {
+        A l[24];
+        lds_get<A>(sh, wg, nl, l);
+        PR::project(l, h);
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) h[k] = in_tile ? h[k] : hg[k];
+}
+
+template <int P, int MU, typename PF, typename PB>
+__device__ __forceinline__ void hop_tile(const LatDesc& ld, const uint4* __restrict__ ib,
+                                         const float* __restrict__ inn, size_t gs,
+                                         const typename LdsVec<typename Tr<P>::acc>::T* sh, int wg, int lane,
+                                         int site, int coord, int stride, int i, int lt, int ls, int r, int lognr,
+                                         typename Tr<P>::acc o[24]) {
+    using A = typename Tr<P>::acc;
+    const int Lm = ld.L[MU];
+    const int T = 1 << lt;
+    const bool whole = (T == Lm);  // the tile spans the lattice: wrap-around inside it
+    {
+        const int sf = (coord == Lm - 1) ? site - (Lm - 1) * stride : site + stride;
+        A h[12], u[18], w[12];
+        fetch_half<P, PF>(whole || i < T - 1, ib, inn, gs, ((size_t)sf << lognr) + r, sh, wg,
+                          (i < T - 1) ? lane + ls : lane - (T - 1) * ls, h);
+        load_link<P, A>(ld.gauge, ld.V, MU, site, u);
+        mul_u(u, h, w);
+        PF::accum(o, w, A(-0.5));
+    }
+    {
+        const int sb = (coord == 0) ? site + (Lm - 1) * stride : site - stride;
+        A h[12], u[18], w[12];
+        fetch_half<P, PB>(whole || i > 0, ib, inn, gs, ((size_t)sb << lognr) + r, sh, wg,
+                          (i > 0) ? lane - ls : lane + (T - 1) * ls, h);
+        load_link<P, A>(ld.gauge, ld.V, MU, sb, u);
+        mul_udag(u, h, w);
+        PB::accum(o, w, A(-0.5));
+    }
+}
+
+// LDS buffers of the tiled stencil: two for 4-byte arithmetic (one barrier
+// per slice), one for FP64 (two barriers per slice), 16-byte groups.
+// Minimum resident waves per SIMD the tiled stencil is compiled for: 3
+// matches the three 48 KiB workgroups that fit a CU's LDS; variants whose
+// live state does not fit take fewer rather than spill (FP64 arithmetic
+// doubles every register, BF16 needs its rounding temporaries).
+template <int P, int MODE> struct TileW {
+    static constexpr int v = (P == P32 || P == P16) ? (MODE != D_RHAT ? 3 : 2) : 1;
+};
+
+template <int P> constexpr int tile_nbuf() { return sizeof(typename Tr<P>::acc) == 4 ? 2 : 1; }
+
+template <int P, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<P, MODE>::v, 8))) k_dslash_tile(Work w, Fld out, Fld in, Fld aux,
+                                                     const double* __restrict__ diag,
+                                                     const SysState* __restrict__ st, int mask,
+                                                     double* __restrict__ part, const NoiseKey* __restrict__ rk) {
+    using A = typename Tr<P>::acc;
+    using V16 = typename LdsVec<A>::T;
+    constexpr int G = Tr<P>::G;
+    constexpr int ND = NDots<MODE>::v;
+    constexpr int NBUF = tile_nbuf<P>();
+    constexpr int NG = 24 * (int)sizeof(A) / 16;
+    extern __shared__ uint4 lds_dyn[];
+    V16* const shb = reinterpret_cast<V16*>(lds_dyn);
+    for_each_vwg(w, [&](const int wg_id, const int b) {
+    const BlockDesc bd = w.blocks[b];
+    const LatDesc ld = w.lats[bd.lat];
+    const int wgb = wg_id - w.wg_start[b];
+    const size_t gs = (size_t)ld.V << w.lognr;
+    const uint4* ib = in.v + (size_t)bd.slot_off * G;
+    const float* inn = in.n ? in.n + bd.slot_off : nullptr;
+    uint4* ob = out.v + (size_t)bd.slot_off * G;
+    float* on = out.n ? out.n + bd.slot_off : nullptr;
+    const int sy = ld.L[0], sz = ld.L[0] * ld.L[1], vxyz = sz * ld.L[2];
+    const int Lt = ld.L[3];
+    const int tx = w.tl[0], ty = w.tl[1], tz = w.tl[2];
+    const int ntx = ld.L[0] >> tx, nty = ld.L[1] >> ty, ntz = ld.L[2] >> tz;
+    const int ntile3 = ntx * nty * ntz;
+    const int j = wgb % ntile3, ch = wgb / ntile3;
+    const int t0 = ch * w.tc, t1 = min(Lt, t0 + w.tc);
+    const int lane = threadIdx.x;
+    const int r = lane & (w.nr - 1);
+    int q = lane >> w.lognr;
+    const int ix = q & ((1 << tx) - 1);
+    q >>= tx;
+    const int iy = q & ((1 << ty) - 1);
+    const int iz = q >> ty;
+    Coord c;
+    {
+        int jq = j;
+        c.x = ((jq % ntx) << tx) + ix;
+        jq /= ntx;
+        c.y = ((jq % nty) << ty) + iy;
+        c.z = ((jq / nty) << tz) + iz;
+    }
+    const int xyz = c.x + ld.L[0] * (c.y + ld.L[1] * c.z);
+    const int sys = bd.sys0 + r;
+    const bool act = mask_ok(mask, st, sys);
+    const int lsx = w.nr, lsy = w.nr << tx, lsz = w.nr << (tx + ty);
+
+    double acc[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) acc[k] = 0.0;
+    const A dg = act ? (A)diag[sys] : A(0);
+
+    A bw[12], cv[24];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) bw[k] = A(0);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) cv[k] = A(0);
+    if (act) {
+        const int tb = (t0 == 0) ? Lt - 1 : t0 - 1;
+        const int sb = xyz + vxyz * tb;
+        A v[24], h[12], u[18];
+        load_spb<P, A>(ib, inn, gs, ((size_t)sb << w.lognr) + r, v);
+        PtP::project(v, h);
+        load_link<P, A>(ld.gauge, ld.V, 3, sb, u);
+        mul_udag(u, h, bw);
+        if (t0 == 0 && ld.tsign < 0) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) bw[k] = -bw[k];
+        }
+        load_spb<P, A>(ib, inn, gs, ((size_t)(xyz + vxyz * t0) << w.lognr) + r, cv);
+    }
+#pragma unroll 1
+    for (int t = t0; t < t1; ++t) {
+        V16* const sh = shb + (NBUF == 2 ? ((t - t0) & 1) : 0) * NG * w.wg;
+        const int site = xyz + vxyz * t;
+        const size_t slot = ((size_t)site << w.lognr) + r;
+        const bool wrap = (t == Lt - 1);
+        // forward-t neighbour (the next slice's centre), in flight during the
+        // LDS exchange and the spatial hops
+        A nv[24];
+        if (act) load_spb<P, A>(ib, inn, gs, ((size_t)(wrap ? xyz : site + vxyz) << w.lognr) + r, nv);
+        if (NBUF == 1 && t > t0) __syncthreads();  // the previous slice's LDS reads are done
+        lds_put<A>(sh, w.wg, lane, cv);
+        __syncthreads();
+        if (act) {
+            A o[24];
+#pragma unroll
+            for (int k = 0; k < 24; ++k) o[k] = A(0);
+            hop_tile<P, 0, PxM, PxP>(ld, ib, inn, gs, sh, w.wg, lane, site, c.x, 1, ix, tx, lsx, r, w.lognr, o);
+            hop_tile<P, 1, PyM, PyP>(ld, ib, inn, gs, sh, w.wg, lane, site, c.y, sy, iy, ty, lsy, r, w.lognr, o);
+            hop_tile<P, 2, PzM, PzP>(ld, ib, inn, gs, sh, w.wg, lane, site, c.z, sz, iz, tz, lsz, r, w.lognr, o);
+            PtP::accum(o, bw, A(-0.5));
+            {
+                // centre (re-read from LDS): diagonal term, the next slice's
+                // backward term with U_t(x,t), and the forward t hop
+                A v[24], h[12], u[18], ww[12];
+                lds_get<A>(sh, w.wg, lane, v);
+#pragma unroll
+                for (int k = 0; k < 24; ++k) o[k] += dg * v[k];
+                load_link<P, A>(ld.gauge, ld.V, 3, site, u);
+                PtP::project(v, h);
+                mul_udag(u, h, bw);
+                PtM::project(nv, h);
+                mul_u(u, h, ww);
+                PtM::accum(o, ww, (wrap && ld.tsign < 0) ? A(0.5) : A(-0.5));
+                if constexpr (MODE == D_TS) {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) {
+                        const double tr = o[2 * k], ti = o[2 * k + 1], sr = v[2 * k], si = v[2 * k + 1];
+                        acc[0] += tr * sr + ti * si;
+                        acc[1] += tr * si - ti * sr;
+                        acc[2] += tr * tr + ti * ti;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 24; ++k) cv[k] = nv[k];
+            if constexpr (MODE == D_RESID) {
+                A bv[24];
+                load_spb<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
+#pragma unroll
+                for (int k = 0; k < 24; ++k) o[k] = bv[k] - o[k];
+            }
+            store_spb<P, A>(ob, on, gs, slot, o);
+            if constexpr (MODE == D_RHAT) {
+                A rh[24];
+                rhat_site<A>(rk[sys], st[sys].restarts, site, rh);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
+                    acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
+                }
+            } else if constexpr (MODE == D_RESID) {
+#pragma unroll
+                for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
+            }
+        }
+    }
+    if constexpr (MODE != D_PLAIN) block_partials<ND, 4>(acc, w.nr, part, wg_id);
+    else __syncthreads();  // LDS is reused by the next virtual workgroup
     });
 }
 
@@ -329,9 +580,18 @@ static void launch_t(const Work& w, Fld out, Fld in, Fld aux, const double* diag
 }
 
 template <int P, int MODE>
+static void launch_tile(const Work& w, Fld out, Fld in, Fld aux, const double* diag, const SysState* st,
+                        int mask, double* part, hipStream_t s, const NoiseKey* rk) {
+    const size_t need = (size_t)tile_nbuf<P>() * 24 * sizeof(typename Tr<P>::acc) * w.wg;
+    hipLaunchKernelGGL((k_dslash_tile<P, MODE>), dim3(grid_of(w)), dim3(w.wg), std::max(need, lds_cap(w.wg, w.occ)),
+                       s, w, out, in, aux, diag, st, mask, part, rk);
+}
+
+template <int P, int MODE>
 static void launch_v(const Work& w, Fld out, Fld in, Fld aux, const double* diag, const SysState* st,
                      int mask, double* part, hipStream_t s, const NoiseKey* rk) {
-    if (w.ilp) launch_t<P, MODE, 1>(w, out, in, aux, diag, st, mask, part, s, rk);
+    if (w.ilp == 2) launch_tile<P, MODE>(w, out, in, aux, diag, st, mask, part, s, rk);
+    else if (w.ilp) launch_t<P, MODE, 1>(w, out, in, aux, diag, st, mask, part, s, rk);
     else launch_t<P, MODE, 0>(w, out, in, aux, diag, st, mask, part, s, rk);
 }
 

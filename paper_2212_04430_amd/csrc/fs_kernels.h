@@ -44,7 +44,8 @@ struct Work {
     int nr, lognr;            // systems per block
     const int* blk_on;        // device [nblk]: 0 => workgroups of the block exit (may be null)
     int tc;                   // stencil launches: t-slices per workgroup column (0 = tile mapping)
-    int ilp;                  // stencil: register-rich variant (one wave per SIMD)
+    int ilp;                  // stencil variant: 0 default, 1 register-rich (one wave per SIMD), 2 LDS tiles
+    int tl[3];                // stencil variant 2: log2 of the tile extent in x, y, z
     int occ;                  // stencil: cap on resident waves per SIMD (0 = none)
     // Persistent launches: when vlist is set, a fixed grid walks the virtual
     // workgroups of the blocks listed there (vlist[0..*vcount)), vstart being
@@ -68,10 +69,13 @@ struct VList {
 // has no list).  Each XCD walks a contiguous range of virtual workgroups.
 template <typename F>
 __device__ __forceinline__ void for_each_vwg(const Work& w, F&& body) {
+    // The block and workgroup indices are uniform over the workgroup; saying
+    // so (readfirstlane) lets the block and lattice descriptors and the buffer
+    // resources built from them live in scalar registers.
     if (!w.vlist) {
         const int wg_id = xcd_remap(blockIdx.x, gridDim.x);
         if (wg_id >= w.total_wg) return;
-        const int b = find_block(w.wg_start, w.nblk, wg_id);
+        const int b = __builtin_amdgcn_readfirstlane(find_block(w.wg_start, w.nblk, wg_id));
         if (w.blk_on && !w.blk_on[b]) return;
         body(wg_id, b);
         return;
@@ -83,9 +87,9 @@ __device__ __forceinline__ void for_each_vwg(const Work& w, F&& body) {
     const int xcd = (int)(blockIdx.x % nx), slot = (int)(blockIdx.x / nx), nper = (int)(gridDim.x / nx);
     const int lo = (int)((long long)T * xcd / nx), hi = (int)((long long)T * (xcd + 1) / nx);
     for (int v = lo + slot; v < hi; v += nper) {
-        const int k = find_block(w.vstart, n, v);
-        const int b = w.vlist[k];
-        body(w.wg_start[b] + (v - w.vstart[k]), b);
+        const int k = __builtin_amdgcn_readfirstlane(find_block(w.vstart, n, v));
+        const int b = __builtin_amdgcn_readfirstlane(w.vlist[k]);
+        body(__builtin_amdgcn_readfirstlane(w.wg_start[b] + (v - w.vstart[k])), b);
     }
 }
 

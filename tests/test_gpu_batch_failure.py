@@ -7,7 +7,7 @@
   the same instance estimated alone (both solved to 1e-10, so they agree to
   ~kappa * 1e-10 of the sample scale; asserted at 1e-6).
 * Reproducibility: reductions are summed in a fixed order, so two estimates
-  of the same inputs are bit-identical.
+  of the same inputs are bit-identical, in every storage precision.
 * Failure handling, forced from the host: a source orthogonal to the solver's
   shadow residual (BiCGStab breakdown, restart from a fresh shadow residual)
   and a NaN link (no hang, FS_E_NOCONV with the status set).
@@ -69,7 +69,7 @@ def test_estimates_are_bit_reproducible(L):
     c = L.fs_create(dims, 0, 0)
     try:
         L.fs_upload_gauge(c, synth.gauge_field(dims, eps=0.25, seed=0))
-        for storage in ("f64", "f32"):
+        for storage in ("f64", "f32", "f16", "bf16"):
             sp = L.solve_params(0.05, tol=1e-10, storage=storage, batched=1, use_graph=1)
             prm = L.fs_est_params(3, 8, 0, 4, sp)
             s1, X1, _ = L.fs_estimate(c, prm, [0.0, 0.1, 0.4, 1.2], want_samples=True)

@@ -51,7 +51,8 @@ def test_dslash_parity(L, dims, ap, prec):
 
 @pytest.mark.parametrize("n_rhs", [2, 4, 16, 48, 6])
 def test_dslash_multi_rhs(L, n_rhs):
-    """Blocks of NR right-hand sides sharing link loads (NR = 2, 4, 16, 16, 2)."""
+    """Blocks of right-hand sides sharing link loads (default block 4 for FP64, 8
+    otherwise, halved down to n_rhs; a last partial block is zero-padded)."""
     dims = (4, 2, 6, 4)
     print(f"dslash multi-rhs n_rhs={n_rhs}", flush=True)
     ctx, U = _ctx(L, dims, 0.4, seed=3)
