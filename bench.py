@@ -194,6 +194,7 @@ def main():
 
     # ---- plain FP64 single-RHS path on a subset of the same systems and noise
     n64 = args.fp64_noise
+    L.fs_autotune(ctx, "f64", 1, cache)  # the plain path's own best single-system stencil
     prm64 = est_params(L, "f64", 0, n64, graph=0)
     t1 = time.perf_counter()
     stats_a, X_a, rep_a = L.fs_estimate(ctx, prm64, w["sigma"], want_samples=True)

@@ -70,7 +70,8 @@ const char* fs_last_error(void);
 
 /*
  * fs_create -- one lattice instance on one device.
- *   dims[4]        Lx, Ly, Lz, Lt; each >= 2 (FS_E_ARG otherwise).
+ *   dims[4]        Lx, Ly, Lz, Lt; each >= 2, at most 29.8M sites in all
+ *                  (FS_E_ARG otherwise).
  *   t_antiperiodic 0: periodic in t; 1: antiperiodic in t.
  *   device         HIP device ordinal.
  *   hip_stream     hipStream_t to issue work on (borrowed, never destroyed);

@@ -273,9 +273,7 @@ int ilog2(int n) {
 
 bool pow2_ok(int n) { return n >= 1 && n <= 16 && (n & (n - 1)) == 0; }
 
-// The kernels address one block's field (V * nr slots of up to 12 16-byte
-// groups, FP64) with 32-bit byte offsets: it must stay below 4 GiB.
-bool block_fits(long long V, int nr) { return 192ll * V * nr < (1ll << 32); }
+
 
 // ============================================================== plans
 
@@ -388,7 +386,6 @@ std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, con
     long long tiles_total = 0;
     std::vector<long long> tiles(nblk);
     for (int b = 0; b < nblk; ++b) {
-        if (!block_fits(lats[blocks[b].lat]->V, nr)) fail(FS_E_ARG, "rhs_block too large for this lattice (a block's FP64 field must stay below 4 GiB)");
         const long long slots = (long long)lats[blocks[b].lat]->V * nr;
         tiles[b] = (slots + wg - 1) / wg;
         tiles_total += tiles[b];
@@ -764,7 +761,7 @@ void from_device(void* dst, const DevBuf& d, size_t n, int is_device, hipStream_
 int tuned_nr(fs_ctx c, int P, int n_sys) {
     auto it = c->tune.find(P);
     int nr = it != c->tune.end() ? it->second.nr : (P == P64 ? 4 : 8);
-    while (nr > 1 && (nr > n_sys || !block_fits(c->V, nr))) nr >>= 1;
+    while (nr > 1 && nr > n_sys) nr >>= 1;
     return nr;
 }
 int tuned_wg(fs_ctx c, int P) {
@@ -1118,7 +1115,9 @@ fs_status fs_create(fs_ctx* out, const int32_t dims[4], int32_t t_antiperiodic, 
             if (dims[i] < 2) fail(FS_E_ARG, "every lattice extent must be >= 2");
             V *= dims[i];
         }
-        if (V > (1ll << 28)) fail(FS_E_ARG, "lattice too large");
+        // one direction of FP64 links (nine complex planes) is addressed with
+        // 32-bit offsets
+        if (144ll * V >= (1ll << 32)) fail(FS_E_ARG, "lattice too large (over 29.8M sites)");
         int ndev = 0;
         HC(hipGetDeviceCount(&ndev));
         if (device < 0 || device >= ndev) fail(FS_E_ARG, "invalid device ordinal");
@@ -1554,7 +1553,7 @@ fs_status fs_autotune(fs_ctx c, fs_prec storage, int32_t n_sys, const char* cach
         if (!found) {
             best.ms_per_sys = 1e30;
             for (int nr : {1, 2, 4, 8, 16}) {
-                if (nr > n_tune || !block_fits(c->V, nr)) break;
+                if (nr > n_tune) break;
                 for (int wg : {64, 128, 256})
                     for (int ilp : {0, 1, 2})
                         for (int occ : {0, 1, 2, 4}) {

@@ -87,11 +87,13 @@ template <> struct Tr<PBF> {
     static constexpr int SB = 48;
 };
 
-// Memory access through raw buffer instructions: a 128-bit resource holds a
+// Link loads go through raw buffer instructions: a 128-bit resource holds a
 // wave-uniform base address and extent (scalar registers), each lane supplies
-// a 32-bit byte offset, and a uniform offset selects the 16-byte group or link
-// component, so addressing costs no per-lane 64-bit arithmetic.  Lanes whose
-// offset falls outside the extent read zero and drop their writes.
+// a 32-bit byte offset and a uniform offset selects the link component, so the
+// addressing costs no per-lane 64-bit arithmetic and the loads are not
+// generic (flat) accesses.  A lattice's links of one direction (nine complex
+// planes) must stay below 4 GiB, which fs_create checks.  Spinor fields, which
+// the vector kernels update in place, use plain global pointers.
 constexpr int kBufFlags = 0x00020000;  // raw 32-bit data format (gfx9 family)
 
 // Bases and extents come from per-block tables in ordinary memory, which the
@@ -103,89 +105,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uin
     const uint64_t p = reinterpret_cast<uint64_t>(base);
     const uint64_t q = ((uint64_t)uni((uint32_t)(p >> 32)) << 32) | uni((uint32_t)p);
     return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(q), (short)0, (int)uni(bytes), kBufFlags);
-}
-
-// Buffer forms of load_sp / store_sp (below), used by the stencil: gs = group
-// stride in 16-byte units (= V * NR); one block's field (G groups) must stay
-// below 4 GiB, which the host checks when it plans a batch.  `nrm` is the FP16
-// per-slot scale array.  The vector kernels, which update fields in place, use
-// the global-pointer forms: with the buffer forms their solves were not
-// reproducible from run to run (BF16 storage), while the stencil, whose
-// input and output fields never alias, is.
-template <int P, typename A>
-__device__ __forceinline__ void load_spb(const uint4* __restrict__ base, const float* __restrict__ nrm,
-                                         size_t gs, size_t slot, A v[24]) {
-    constexpr int G = P == P64 ? 12 : (P == P32 ? 6 : 3);
-    const uint32_t off = (uint32_t)slot * 16u;
-    const uint32_t ext = uni((uint32_t)gs * 16u);
-    const auto rs = buf_rsrc(base, G * ext);
-    float s = 1.0f;
-    if constexpr (P == P16) s = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(buf_rsrc(nrm, ext >> 2), (uint32_t)slot * 4u, 0, 0));
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, off, g * ext, 0);
-        if constexpr (P == P64) {
-            v[2 * g] = (A)__hiloint2double((int)q[1], (int)q[0]);
-            v[2 * g + 1] = (A)__hiloint2double((int)q[3], (int)q[2]);
-        } else if constexpr (P == P32) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) v[4 * g + k] = (A)__uint_as_float(q[k]);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                float lo, hi;
-                if constexpr (P == P16) {
-                    lo = h_to_f((uint16_t)(q[k] & 0xffff)) * s;
-                    hi = h_to_f((uint16_t)(q[k] >> 16)) * s;
-                } else {
-                    lo = bf16_to_f((uint16_t)(q[k] & 0xffff));
-                    hi = bf16_to_f((uint16_t)(q[k] >> 16));
-                }
-                v[8 * g + 2 * k] = (A)lo;
-                v[8 * g + 2 * k + 1] = (A)hi;
-            }
-        }
-    }
-}
-
-template <int P, typename A>
-__device__ __forceinline__ void store_spb(uint4* __restrict__ base, float* __restrict__ nrm,
-                                          size_t gs, size_t slot, const A v[24]) {
-    constexpr int G = P == P64 ? 12 : (P == P32 ? 6 : 3);
-    const uint32_t off = (uint32_t)slot * 16u;
-    const uint32_t ext = uni((uint32_t)gs * 16u);
-    const auto rs = buf_rsrc(base, G * ext);
-    float inv = 1.0f;
-    if constexpr (P == P16) {
-        float m = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf((float)v[k]));
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(m), buf_rsrc(nrm, ext >> 2),
-                                              (uint32_t)slot * 4u, 0, 0);
-        inv = m > 0.0f ? 1.0f / m : 0.0f;
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-        u32x4 q;
-        if constexpr (P == P64) {
-            q[0] = (uint32_t)__double2loint((double)v[2 * g]);
-            q[1] = (uint32_t)__double2hiint((double)v[2 * g]);
-            q[2] = (uint32_t)__double2loint((double)v[2 * g + 1]);
-            q[3] = (uint32_t)__double2hiint((double)v[2 * g + 1]);
-        } else if constexpr (P == P32) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) q[k] = __float_as_uint((float)v[4 * g + k]);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float lo = (float)v[8 * g + 2 * k], hi = (float)v[8 * g + 2 * k + 1];
-                if constexpr (P == P16) q[k] = (uint32_t)f_to_h(lo * inv) | ((uint32_t)f_to_h(hi * inv) << 16);
-                else q[k] = (uint32_t)f_to_bf16(lo) | ((uint32_t)f_to_bf16(hi) << 16);
-            }
-        }
-        __builtin_amdgcn_raw_buffer_store_b128(q, rs, off, g * ext, 0);
-    }
 }
 
 // Load / store the 24 reals of spinor (slot) from a block base.  gs = group

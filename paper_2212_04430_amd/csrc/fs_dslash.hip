@@ -128,7 +128,7 @@ __device__ __forceinline__ void hop_dir(const LatDesc& ld, const uint4* __restri
     }
     {
         A v[24], h[12], u[18], w[12];
-        load_spb<P, A>(ib, inn, gs, ((size_t)sf << lognr) + r, v);
+        load_sp<P, A>(ib, inn, gs, ((size_t)sf << lognr) + r, v);
         PF::project(v, h);
         load_link<P, A>(ld.gauge, ld.V, MU, site, u);
         mul_u(u, h, w);
@@ -136,7 +136,7 @@ __device__ __forceinline__ void hop_dir(const LatDesc& ld, const uint4* __restri
     }
     {
         A v[24], h[12], u[18], w[12];
-        load_spb<P, A>(ib, inn, gs, ((size_t)sb << lognr) + r, v);
+        load_sp<P, A>(ib, inn, gs, ((size_t)sb << lognr) + r, v);
         PB::project(v, h);
         load_link<P, A>(ld.gauge, ld.V, MU, sb, u);
         mul_udag(u, h, w);
@@ -224,7 +224,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
             const int tb = (t0 == 0) ? Lt - 1 : t0 - 1;
             const int sb = xyz + vxyz * tb;
             A v[24], h[12], u[18];
-            load_spb<P, A>(ib, inn, gs, ((size_t)sb << w.lognr) + r, v);
+            load_sp<P, A>(ib, inn, gs, ((size_t)sb << w.lognr) + r, v);
             PtP::project(v, h);
             load_link<P, A>(ld.gauge, ld.V, 3, sb, u);
             mul_udag(u, h, bw);
@@ -236,7 +236,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
         // centre spinor of the current slice, carried in registers: the
         // forward-t neighbour loaded at slice t is the centre of slice t+1
         A cv[24];
-        load_spb<P, A>(ib, inn, gs, ((size_t)(xyz + vxyz * t0) << w.lognr) + r, cv);
+        load_sp<P, A>(ib, inn, gs, ((size_t)(xyz + vxyz * t0) << w.lognr) + r, cv);
 #pragma unroll 1
         for (int t = t0; t < t1; ++t) {
             const int site = xyz + vxyz * t;
@@ -255,7 +255,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
                 const bool wrap = (t == Lt - 1);
                 const int sf = wrap ? xyz : site + vxyz;
                 A ww[12], v[24];
-                load_spb<P, A>(ib, inn, gs, ((size_t)sf << w.lognr) + r, v);
+                load_sp<P, A>(ib, inn, gs, ((size_t)sf << w.lognr) + r, v);
                 PtM::project(v, h);
                 mul_u(u, h, ww);
                 PtM::accum(o, ww, (wrap && ld.tsign < 0) ? A(0.5) : A(-0.5));
@@ -283,11 +283,11 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
             }
             if constexpr (MODE == D_RESID) {
                 A bv[24];
-                load_spb<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
+                load_sp<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
 #pragma unroll
                 for (int k = 0; k < 24; ++k) o[k] = bv[k] - o[k];
             }
-            store_spb<P, A>(ob, on, gs, slot, o);
+            store_sp<P, A>(ob, on, gs, slot, o);
             if constexpr (MODE == D_RHAT) {
                 A rh[24];
                 rhat_site<A>(rk[sys], st[sys].restarts, site, rh);
@@ -358,7 +358,7 @@ __device__ __forceinline__ void fetch_half(bool in_tile, const uint4* __restrict
     A hg[12];
     {
         A g[24];
-        load_spb<P, A>(ib, inn, gs, in_tile ? (size_t)0 : gslot, g);
+        load_sp<P, A>(ib, inn, gs, in_tile ? (size_t)0 : gslot, g);
         PR::project(g, hg);
     }
     {
@@ -475,7 +475,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
         const int tb = (t0 == 0) ? Lt - 1 : t0 - 1;
         const int sb = xyz + vxyz * tb;
         A v[24], h[12], u[18];
-        load_spb<P, A>(ib, inn, gs, ((size_t)sb << w.lognr) + r, v);
+        load_sp<P, A>(ib, inn, gs, ((size_t)sb << w.lognr) + r, v);
         PtP::project(v, h);
         load_link<P, A>(ld.gauge, ld.V, 3, sb, u);
         mul_udag(u, h, bw);
@@ -483,7 +483,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
 #pragma unroll
             for (int k = 0; k < 12; ++k) bw[k] = -bw[k];
         }
-        load_spb<P, A>(ib, inn, gs, ((size_t)(xyz + vxyz * t0) << w.lognr) + r, cv);
+        load_sp<P, A>(ib, inn, gs, ((size_t)(xyz + vxyz * t0) << w.lognr) + r, cv);
     }
 #pragma unroll 1
     for (int t = t0; t < t1; ++t) {
@@ -494,7 +494,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
         // forward-t neighbour (the next slice's centre), in flight during the
         // LDS exchange and the spatial hops
         A nv[24];
-        if (act) load_spb<P, A>(ib, inn, gs, ((size_t)(wrap ? xyz : site + vxyz) << w.lognr) + r, nv);
+        if (act) load_sp<P, A>(ib, inn, gs, ((size_t)(wrap ? xyz : site + vxyz) << w.lognr) + r, nv);
         if (NBUF == 1 && t > t0) __syncthreads();  // the previous slice's LDS reads are done
         lds_put<A>(sh, w.wg, lane, cv);
         __syncthreads();
@@ -533,11 +533,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
             for (int k = 0; k < 24; ++k) cv[k] = nv[k];
             if constexpr (MODE == D_RESID) {
                 A bv[24];
-                load_spb<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
+                load_sp<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
 #pragma unroll
                 for (int k = 0; k < 24; ++k) o[k] = bv[k] - o[k];
             }
-            store_spb<P, A>(ob, on, gs, slot, o);
+            store_sp<P, A>(ob, on, gs, slot, o);
             if constexpr (MODE == D_RHAT) {
                 A rh[24];
                 rhat_site<A>(rk[sys], st[sys].restarts, site, rh);
