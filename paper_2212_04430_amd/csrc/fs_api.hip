@@ -174,6 +174,7 @@ struct HostBuf {
 
 int prec_group_bytes_spinor(int P) { return P == P64 ? 192 : P == P32 ? 96 : 48; }
 int prec_link_complex_bytes(int P) { return P == P64 ? 16 : P == P32 ? 8 : 4; }
+int prec_link_site_bytes(int P) { return P == P64 ? 144 : P == P32 ? 80 : 48; }  // site-major, 16-byte chunks
 int prec_groups(int P) { return P == P64 ? 12 : P == P32 ? 6 : 3; }
 
 // ============================================================== gamma table
@@ -234,6 +235,7 @@ struct fs_ctx_s {
     uint32_t instance = 0;
     bool has_gauge = false;
     DevBuf gauge[4];                 // [mu][9][site] per precision
+    DevBuf gauge_q[4];               // [mu][site][QC 16-byte chunks] per precision
     std::map<int, TuneEntry> tune;   // per precision
     HostBuf pinned;
 };
@@ -262,6 +264,7 @@ LatDesc lat_desc(const fs_ctx_s* c, int P) {
     d.V = c->V;
     d.tsign = c->tsign;
     d.gauge = c->gauge[P].p;
+    d.gauge_q = c->gauge_q[P].p;
     return d;
 }
 
@@ -1167,6 +1170,8 @@ fs_status fs_upload_gauge(fs_ctx c, const double* links, int32_t is_device) {
         for (int P = 0; P < 4; ++P) {
             c->gauge[P].alloc((size_t)4 * 9 * c->V * prec_link_complex_bytes(P));
             launch_gauge_convert(P, c->gauge[P].p, src.as<double>(), c->V, c->stream);
+            c->gauge_q[P].alloc((size_t)4 * c->V * prec_link_site_bytes(P));
+            launch_gauge_convert_q(P, c->gauge_q[P].p, src.as<double>(), c->V, c->stream);
         }
         HC(hipStreamSynchronize(c->stream));
         c->has_gauge = true;

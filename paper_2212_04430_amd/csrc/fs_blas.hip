@@ -564,6 +564,40 @@ __global__ void k_gauge_convert(void* __restrict__ dst, const double* __restrict
     }
 }
 
+// Site-major copy of the links for quad-shared loads: link (mu, site) is
+// Tr<P>::QC 16-byte chunks at ((mu * V + site) * QC), the 9 complex entries
+// packed in order in the storage precision, the tail padded with zeros.
+template <int P>
+__global__ void k_gauge_convert_q(uint4* __restrict__ dst, const double* __restrict__ src, int V) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)4 * V) return;
+    constexpr int QC = Tr<P>::QC;
+    uint32_t w[4 * QC];
+#pragma unroll
+    for (int k = 0; k < 4 * QC; ++k) w[k] = 0u;
+    const double* s = src + i * 18;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double re = s[2 * k], im = s[2 * k + 1];
+        if constexpr (P == P64) {
+            w[4 * k] = (uint32_t)__double2loint(re);
+            w[4 * k + 1] = (uint32_t)__double2hiint(re);
+            w[4 * k + 2] = (uint32_t)__double2loint(im);
+            w[4 * k + 3] = (uint32_t)__double2hiint(im);
+        } else if constexpr (P == P32) {
+            w[2 * k] = __float_as_uint((float)re);
+            w[2 * k + 1] = __float_as_uint((float)im);
+        } else if constexpr (P == P16) {
+            w[k] = (uint32_t)f_to_h((float)re) | ((uint32_t)f_to_h((float)im) << 16);
+        } else {
+            w[k] = (uint32_t)f_to_bf16((float)re) | ((uint32_t)f_to_bf16((float)im) << 16);
+        }
+    }
+    uint4* d = dst + i * QC;  // i = mu * V + site
+#pragma unroll
+    for (int c = 0; c < QC; ++c) d[c] = make_uint4(w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3]);
+}
+
 // ------------------------------------------------------------------ Z4 noise
 
 template <int P>
@@ -850,6 +884,11 @@ void launch_unpack(int prec, const Work& w, double* dst, Fld src, long long sys_
 void launch_gauge_convert(int prec, void* dst, const double* src, int V, hipStream_t s) {
     const int n = 4 * V;
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_gauge_convert<PP>, dim3((n + 255) / 256), dim3(256), 0, s, dst, src, V))
+}
+void launch_gauge_convert_q(int prec, void* dst, const double* src, int V, hipStream_t s) {
+    const int n = 4 * V;
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_gauge_convert_q<PP>, dim3((n + 255) / 256), dim3(256), 0, s,
+                                           static_cast<uint4*>(dst), src, V))
 }
 void launch_noise_block(int prec, const Work& w, Fld dst, const NoiseKey* keys, hipStream_t s) {
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_noise_block<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, dst, keys))

@@ -27,7 +27,8 @@ struct LatDesc {
     int L[4];          // Lx, Ly, Lz, Lt
     int V;             // sites
     int tsign;         // +1 periodic, -1 antiperiodic in t
-    const void* gauge; // links in the launch's storage precision
+    const void* gauge; // links in the launch's storage precision, [mu][9][site]
+    const void* gauge_q; // the same links site-major, [mu][site][QC 16-byte chunks]
 };
 
 struct BlockDesc {
@@ -67,24 +68,28 @@ template <> struct Tr<P64> {
     static constexpr int G = 12;   // 16-byte groups per spinor
     static constexpr int GB = 16;  // bytes per stored link complex
     static constexpr int SB = 192; // spinor bytes (without scale)
+    static constexpr int QC = 9;   // 16-byte chunks per site-major link (144 B)
 };
 template <> struct Tr<P32> {
     using acc = float;
     static constexpr int G = 6;
     static constexpr int GB = 8;
     static constexpr int SB = 96;
+    static constexpr int QC = 5;   // 72 B padded to 80 B
 };
 template <> struct Tr<P16> {
     using acc = float;
     static constexpr int G = 3;
     static constexpr int GB = 4;
     static constexpr int SB = 48;
+    static constexpr int QC = 3;   // 36 B padded to 48 B
 };
 template <> struct Tr<PBF> {
     using acc = float;
     static constexpr int G = 3;
     static constexpr int GB = 4;
     static constexpr int SB = 48;
+    static constexpr int QC = 3;   // 36 B padded to 48 B
 };
 
 // Link loads go through raw buffer instructions: a 128-bit resource holds a
@@ -243,6 +248,93 @@ __device__ __forceinline__ void load_link(const void* __restrict__ gauge, int V,
             }
         }
     }
+}
+
+// Quad-shared link load.  When the four lanes of a quad hold four systems of
+// the same site (rhs blocks of 4 or more), each lane loads one 16-byte chunk of
+// the site-major link, so a quad reads one contiguous window per instruction,
+// and the chunks are exchanged inside the quad with DPP broadcasts.  All four
+// lanes of the quad must be active.  (With the [mu][9][site] layout every link
+// costs the cache one access per quad for each of its nine components.)  One
+// direction's site-major links must stay below 4 GiB (fs_create's limit).
+template <int J>
+__device__ __forceinline__ uint32_t quad_bcast(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, J * 0x55, 0xF, 0xF, false);
+}
+
+template <int J>
+__device__ __forceinline__ void chunk_bcast(const uint4& c, uint32_t o[4]) {
+    o[0] = quad_bcast<J>(c.x);
+    o[1] = quad_bcast<J>(c.y);
+    o[2] = quad_bcast<J>(c.z);
+    o[3] = quad_bcast<J>(c.w);
+}
+
+template <int P, typename A>
+__device__ __forceinline__ void load_link_q(const void* __restrict__ gauge_q, int V, int mu, int site, A u[18]) {
+    constexpr uint32_t QB = 16u * Tr<P>::QC;  // bytes per site
+    const int qd = threadIdx.x & 3;
+    const uint32_t plane = uni((uint32_t)V * QB);
+    const auto rs = buf_rsrc(reinterpret_cast<const char*>(gauge_q) + (size_t)mu * plane, plane);
+    const uint32_t off = (uint32_t)site * QB;
+    if constexpr (P == P64) {
+        // chunks 0-7 shared (two rounds), chunk 8 loaded by every lane
+        const auto q0 = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16u * qd, 0, 0);
+        const auto q1 = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16u * (4 + qd), 0, 0);
+        const auto q8 = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 128u, 0, 0);
+        const uint4 c0 = make_uint4(q0[0], q0[1], q0[2], q0[3]);
+        const uint4 c1 = make_uint4(q1[0], q1[1], q1[2], q1[3]);
+        uint32_t w[36];
+        chunk_bcast<0>(c0, w + 0);
+        chunk_bcast<1>(c0, w + 4);
+        chunk_bcast<2>(c0, w + 8);
+        chunk_bcast<3>(c0, w + 12);
+        chunk_bcast<0>(c1, w + 16);
+        chunk_bcast<1>(c1, w + 20);
+        chunk_bcast<2>(c1, w + 24);
+        chunk_bcast<3>(c1, w + 28);
+        w[32] = q8[0]; w[33] = q8[1]; w[34] = q8[2]; w[35] = q8[3];
+#pragma unroll
+        for (int k = 0; k < 18; ++k) u[k] = (A)__hiloint2double((int)w[2 * k + 1], (int)w[2 * k]);
+    } else if constexpr (P == P32) {
+        // chunks 0-3 shared, the last complex (chunk 4) loaded by every lane
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16u * qd, 0, 0);
+        const auto t = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 64u, 0, 0);
+        const uint4 c = make_uint4(q[0], q[1], q[2], q[3]);
+        uint32_t w[18];
+        chunk_bcast<0>(c, w + 0);
+        chunk_bcast<1>(c, w + 4);
+        chunk_bcast<2>(c, w + 8);
+        chunk_bcast<3>(c, w + 12);
+        w[16] = t[0]; w[17] = t[1];
+#pragma unroll
+        for (int k = 0; k < 18; ++k) u[k] = (A)__uint_as_float(w[k]);
+    } else {
+        // three chunks: lanes 0-2 load one each (lane 3 repeats chunk 2)
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16u * (qd < 2 ? qd : 2), 0, 0);
+        const uint4 c = make_uint4(q[0], q[1], q[2], q[3]);
+        uint32_t w[12];
+        chunk_bcast<0>(c, w + 0);
+        chunk_bcast<1>(c, w + 4);
+        chunk_bcast<2>(c, w + 8);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            if constexpr (P == P16) {
+                u[2 * k] = (A)h_to_f((uint16_t)(w[k] & 0xffff));
+                u[2 * k + 1] = (A)h_to_f((uint16_t)(w[k] >> 16));
+            } else {
+                u[2 * k] = (A)bf16_to_f((uint16_t)(w[k] & 0xffff));
+                u[2 * k + 1] = (A)bf16_to_f((uint16_t)(w[k] >> 16));
+            }
+        }
+    }
+}
+
+// Link load of the stencil: quad-shared when Q (rhs blocks of 4 or more).
+template <int P, bool Q, typename A>
+__device__ __forceinline__ void link(const LatDesc& ld, int mu, int site, A u[18]) {
+    if constexpr (Q) load_link_q<P, A>(ld.gauge_q, ld.V, mu, site, u);
+    else load_link<P, A>(ld.gauge, ld.V, mu, site, u);
 }
 
 // ----------------------------------------------------------- lattice geometry

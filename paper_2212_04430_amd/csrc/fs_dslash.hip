@@ -113,7 +113,7 @@ __device__ __forceinline__ void mul_udag(const A u[18], const A h[12], A w[12]) 
         }
 }
 
-template <int P, int MU, typename PF, typename PB>
+template <int P, bool Q, int MU, typename PF, typename PB>
 __device__ __forceinline__ void hop_dir(const LatDesc& ld, const uint4* __restrict__ ib,
                                         const float* __restrict__ inn, size_t gs, int site, int coord,
                                         int stride, int r, int lognr, typename Tr<P>::acc o[24]) {
@@ -130,7 +130,7 @@ __device__ __forceinline__ void hop_dir(const LatDesc& ld, const uint4* __restri
         A v[24], h[12], u[18], w[12];
         load_sp<P, A>(ib, inn, gs, ((size_t)sf << lognr) + r, v);
         PF::project(v, h);
-        load_link<P, A>(ld.gauge, ld.V, MU, site, u);
+        link<P, Q, A>(ld, MU, site, u);
         mul_u(u, h, w);
         PF::accum(o, w, cf);
     }
@@ -138,7 +138,7 @@ __device__ __forceinline__ void hop_dir(const LatDesc& ld, const uint4* __restri
         A v[24], h[12], u[18], w[12];
         load_sp<P, A>(ib, inn, gs, ((size_t)sb << lognr) + r, v);
         PB::project(v, h);
-        load_link<P, A>(ld.gauge, ld.V, MU, sb, u);
+        link<P, Q, A>(ld, MU, sb, u);
         mul_udag(u, h, w);
         PB::accum(o, w, cb);
     }
@@ -175,7 +175,7 @@ template <int P, int ILP> struct Wpe {
     static constexpr int hi = ILP ? 1 : 8;
 };
 
-template <int P, int MODE, int ILP>
+template <int P, int MODE, int ILP, bool Q>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Wpe<P, ILP>::lo, Wpe<P, ILP>::hi)))
 k_dslash(Work w, Fld out, Fld in, Fld aux,
                                                 const double* __restrict__ diag,
@@ -208,7 +208,10 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
     const int xyz = s3 >> w.lognr;
     const int r = s3 & (w.nr - 1);
     const int sys = bd.sys0 + r;
-    if (s3 < n3 && mask_ok(mask, st, sys)) {
+    // With quad-shared links every lane of a valid site runs (the quad must be
+    // complete); the system mask then only gates stores and partial sums.
+    const bool act = s3 < n3 && mask_ok(mask, st, sys);
+    if (Q ? s3 < n3 : act) {
         const A dg = (A)diag[sys];
         Coord c;
         {
@@ -226,7 +229,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
             A v[24], h[12], u[18];
             load_sp<P, A>(ib, inn, gs, ((size_t)sb << w.lognr) + r, v);
             PtP::project(v, h);
-            load_link<P, A>(ld.gauge, ld.V, 3, sb, u);
+            link<P, Q, A>(ld, 3, sb, u);
             mul_udag(u, h, bw);
             if (t0 == 0 && ld.tsign < 0) {
 #pragma unroll
@@ -248,7 +251,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
                 A h[12], u[18];
 #pragma unroll
                 for (int k = 0; k < 24; ++k) o[k] = dg * cv[k];
-                load_link<P, A>(ld.gauge, ld.V, 3, site, u);
+                link<P, Q, A>(ld, 3, site, u);
                 PtP::project(cv, h);
                 mul_udag(u, h, bn);
                 // forward t hop with the same link
@@ -266,21 +269,27 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
                     v[k] = c0;         // this slice's centre, for the dot below
                 }
                 PtP::accum(o, bw, A(-0.5));
-                hop_dir<P, 0, PxM, PxP>(ld, ib, inn, gs, site, c.x, 1, r, w.lognr, o);
-                hop_dir<P, 1, PyM, PyP>(ld, ib, inn, gs, site, c.y, sy, r, w.lognr, o);
-                hop_dir<P, 2, PzM, PzP>(ld, ib, inn, gs, site, c.z, sz, r, w.lognr, o);
+                hop_dir<P, Q, 0, PxM, PxP>(ld, ib, inn, gs, site, c.x, 1, r, w.lognr, o);
+                hop_dir<P, Q, 1, PyM, PyP>(ld, ib, inn, gs, site, c.y, sy, r, w.lognr, o);
+                hop_dir<P, Q, 2, PzM, PzP>(ld, ib, inn, gs, site, c.z, sz, r, w.lognr, o);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) bw[k] = bn[k];
                 if constexpr (MODE == D_TS) {
+                    if (act) {
 #pragma unroll
-                    for (int k = 0; k < 12; ++k) {
-                        const double tr = o[2 * k], ti = o[2 * k + 1], sr = v[2 * k], si = v[2 * k + 1];
-                        acc[0] += tr * sr + ti * si;
-                        acc[1] += tr * si - ti * sr;
-                        acc[2] += tr * tr + ti * ti;
+                        for (int k = 0; k < 12; ++k) {
+                            const double tr = o[2 * k], ti = o[2 * k + 1], sr = v[2 * k], si = v[2 * k + 1];
+                            acc[0] += tr * sr + ti * si;
+                            acc[1] += tr * si - ti * sr;
+                            acc[2] += tr * tr + ti * ti;
+                        }
                     }
                 }
             }
+            // A lane whose system is not running (possible only with quad-shared
+            // links) computes and stores its own system's result from that
+            // system's own fields; those outputs (v, t, r_hi) are recomputed
+            // before the system uses them again, so only partial sums are masked.
             if constexpr (MODE == D_RESID) {
                 A bv[24];
                 load_sp<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
@@ -288,17 +297,19 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
                 for (int k = 0; k < 24; ++k) o[k] = bv[k] - o[k];
             }
             store_sp<P, A>(ob, on, gs, slot, o);
-            if constexpr (MODE == D_RHAT) {
-                A rh[24];
-                rhat_site<A>(rk[sys], st[sys].restarts, site, rh);
+            if (act) {
+                if constexpr (MODE == D_RHAT) {
+                    A rh[24];
+                    rhat_site<A>(rk[sys], st[sys].restarts, site, rh);
 #pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
-                    acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
+                    for (int k = 0; k < 12; ++k) {
+                        acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
+                        acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
+                    }
+                } else if constexpr (MODE == D_RESID) {
+#pragma unroll
+                    for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
                 }
-            } else if constexpr (MODE == D_RESID) {
-#pragma unroll
-                for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
             }
         }
     }
@@ -370,7 +381,7 @@ __device__ __forceinline__ void fetch_half(bool in_tile, const uint4* __restrict
     for (int k = 0; k < 12; ++k) h[k] = in_tile ? h[k] : hg[k];
 }
 
-template <int P, int MU, typename PF, typename PB>
+template <int P, bool Q, int MU, typename PF, typename PB>
 __device__ __forceinline__ void hop_tile(const LatDesc& ld, const uint4* __restrict__ ib,
                                          const float* __restrict__ inn, size_t gs,
                                          const typename LdsVec<typename Tr<P>::acc>::T* sh, int wg, int lane,
@@ -385,7 +396,7 @@ __device__ __forceinline__ void hop_tile(const LatDesc& ld, const uint4* __restr
         A h[12], u[18], w[12];
         fetch_half<P, PF>(whole || i < T - 1, ib, inn, gs, ((size_t)sf << lognr) + r, sh, wg,
                           (i < T - 1) ? lane + ls : lane - (T - 1) * ls, h);
-        load_link<P, A>(ld.gauge, ld.V, MU, site, u);
+        link<P, Q, A>(ld, MU, site, u);
         mul_u(u, h, w);
         PF::accum(o, w, A(-0.5));
     }
@@ -394,7 +405,7 @@ __device__ __forceinline__ void hop_tile(const LatDesc& ld, const uint4* __restr
         A h[12], u[18], w[12];
         fetch_half<P, PB>(whole || i > 0, ib, inn, gs, ((size_t)sb << lognr) + r, sh, wg,
                           (i > 0) ? lane - ls : lane + (T - 1) * ls, h);
-        load_link<P, A>(ld.gauge, ld.V, MU, sb, u);
+        link<P, Q, A>(ld, MU, sb, u);
         mul_udag(u, h, w);
         PB::accum(o, w, A(-0.5));
     }
@@ -412,7 +423,7 @@ template <int P, int MODE> struct TileW {
 
 template <int P> constexpr int tile_nbuf() { return sizeof(typename Tr<P>::acc) == 4 ? 2 : 1; }
 
-template <int P, int MODE>
+template <int P, int MODE, bool Q>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<P, MODE>::v, 8))) k_dslash_tile(Work w, Fld out, Fld in, Fld aux,
                                                      const double* __restrict__ diag,
                                                      const SysState* __restrict__ st, int mask,
@@ -459,6 +470,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
     const int xyz = c.x + ld.L[0] * (c.y + ld.L[1] * c.z);
     const int sys = bd.sys0 + r;
     const bool act = mask_ok(mask, st, sys);
+    const bool run = Q || act;  // quad-shared links need every lane of the quad
     const int lsx = w.nr, lsy = w.nr << tx, lsz = w.nr << (tx + ty);
 
     double acc[ND];
@@ -471,13 +483,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
     for (int k = 0; k < 12; ++k) bw[k] = A(0);
 #pragma unroll
     for (int k = 0; k < 24; ++k) cv[k] = A(0);
-    if (act) {
+    if (run) {
         const int tb = (t0 == 0) ? Lt - 1 : t0 - 1;
         const int sb = xyz + vxyz * tb;
         A v[24], h[12], u[18];
         load_sp<P, A>(ib, inn, gs, ((size_t)sb << w.lognr) + r, v);
         PtP::project(v, h);
-        load_link<P, A>(ld.gauge, ld.V, 3, sb, u);
+        link<P, Q, A>(ld, 3, sb, u);
         mul_udag(u, h, bw);
         if (t0 == 0 && ld.tsign < 0) {
 #pragma unroll
@@ -494,17 +506,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
         // forward-t neighbour (the next slice's centre), in flight during the
         // LDS exchange and the spatial hops
         A nv[24];
-        if (act) load_sp<P, A>(ib, inn, gs, ((size_t)(wrap ? xyz : site + vxyz) << w.lognr) + r, nv);
+        if (run) load_sp<P, A>(ib, inn, gs, ((size_t)(wrap ? xyz : site + vxyz) << w.lognr) + r, nv);
         if (NBUF == 1 && t > t0) __syncthreads();  // the previous slice's LDS reads are done
         lds_put<A>(sh, w.wg, lane, cv);
         __syncthreads();
-        if (act) {
+        if (run) {
             A o[24];
 #pragma unroll
             for (int k = 0; k < 24; ++k) o[k] = A(0);
-            hop_tile<P, 0, PxM, PxP>(ld, ib, inn, gs, sh, w.wg, lane, site, c.x, 1, ix, tx, lsx, r, w.lognr, o);
-            hop_tile<P, 1, PyM, PyP>(ld, ib, inn, gs, sh, w.wg, lane, site, c.y, sy, iy, ty, lsy, r, w.lognr, o);
-            hop_tile<P, 2, PzM, PzP>(ld, ib, inn, gs, sh, w.wg, lane, site, c.z, sz, iz, tz, lsz, r, w.lognr, o);
+            hop_tile<P, Q, 0, PxM, PxP>(ld, ib, inn, gs, sh, w.wg, lane, site, c.x, 1, ix, tx, lsx, r, w.lognr, o);
+            hop_tile<P, Q, 1, PyM, PyP>(ld, ib, inn, gs, sh, w.wg, lane, site, c.y, sy, iy, ty, lsy, r, w.lognr, o);
+            hop_tile<P, Q, 2, PzM, PzP>(ld, ib, inn, gs, sh, w.wg, lane, site, c.z, sz, iz, tz, lsz, r, w.lognr, o);
             PtP::accum(o, bw, A(-0.5));
             {
                 // centre (re-read from LDS): diagonal term, the next slice's
@@ -513,24 +525,30 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
                 lds_get<A>(sh, w.wg, lane, v);
 #pragma unroll
                 for (int k = 0; k < 24; ++k) o[k] += dg * v[k];
-                load_link<P, A>(ld.gauge, ld.V, 3, site, u);
+                link<P, Q, A>(ld, 3, site, u);
                 PtP::project(v, h);
                 mul_udag(u, h, bw);
                 PtM::project(nv, h);
                 mul_u(u, h, ww);
                 PtM::accum(o, ww, (wrap && ld.tsign < 0) ? A(0.5) : A(-0.5));
                 if constexpr (MODE == D_TS) {
+                    if (act) {
 #pragma unroll
-                    for (int k = 0; k < 12; ++k) {
-                        const double tr = o[2 * k], ti = o[2 * k + 1], sr = v[2 * k], si = v[2 * k + 1];
-                        acc[0] += tr * sr + ti * si;
-                        acc[1] += tr * si - ti * sr;
-                        acc[2] += tr * tr + ti * ti;
+                        for (int k = 0; k < 12; ++k) {
+                            const double tr = o[2 * k], ti = o[2 * k + 1], sr = v[2 * k], si = v[2 * k + 1];
+                            acc[0] += tr * sr + ti * si;
+                            acc[1] += tr * si - ti * sr;
+                            acc[2] += tr * tr + ti * ti;
+                        }
                     }
                 }
             }
 #pragma unroll
             for (int k = 0; k < 24; ++k) cv[k] = nv[k];
+            // A lane whose system is not running (possible only with quad-shared
+            // links) computes and stores its own system's result from that
+            // system's own fields; those outputs (v, t, r_hi) are recomputed
+            // before the system uses them again, so only partial sums are masked.
             if constexpr (MODE == D_RESID) {
                 A bv[24];
                 load_sp<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
@@ -538,17 +556,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
                 for (int k = 0; k < 24; ++k) o[k] = bv[k] - o[k];
             }
             store_sp<P, A>(ob, on, gs, slot, o);
-            if constexpr (MODE == D_RHAT) {
-                A rh[24];
-                rhat_site<A>(rk[sys], st[sys].restarts, site, rh);
+            if (act) {
+                if constexpr (MODE == D_RHAT) {
+                    A rh[24];
+                    rhat_site<A>(rk[sys], st[sys].restarts, site, rh);
 #pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
-                    acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
+                    for (int k = 0; k < 12; ++k) {
+                        acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
+                        acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
+                    }
+                } else if constexpr (MODE == D_RESID) {
+#pragma unroll
+                    for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
                 }
-            } else if constexpr (MODE == D_RESID) {
-#pragma unroll
-                for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
             }
         }
     }
@@ -575,16 +595,25 @@ static size_t lds_cap(int wg, int waves) {
 template <int P, int MODE, int ILP>
 static void launch_t(const Work& w, Fld out, Fld in, Fld aux, const double* diag, const SysState* st,
                      int mask, double* part, hipStream_t s, const NoiseKey* rk) {
-    hipLaunchKernelGGL((k_dslash<P, MODE, ILP>), dim3(grid_of(w)), dim3(w.wg), lds_cap(w.wg, w.occ), s, w, out, in,
-                       aux, diag, st, mask, part, rk);
+    if (w.nr >= 4)
+        hipLaunchKernelGGL((k_dslash<P, MODE, ILP, true>), dim3(grid_of(w)), dim3(w.wg), lds_cap(w.wg, w.occ), s, w,
+                           out, in, aux, diag, st, mask, part, rk);
+    else
+        hipLaunchKernelGGL((k_dslash<P, MODE, ILP, false>), dim3(grid_of(w)), dim3(w.wg), lds_cap(w.wg, w.occ), s, w,
+                           out, in, aux, diag, st, mask, part, rk);
 }
 
 template <int P, int MODE>
 static void launch_tile(const Work& w, Fld out, Fld in, Fld aux, const double* diag, const SysState* st,
                         int mask, double* part, hipStream_t s, const NoiseKey* rk) {
     const size_t need = (size_t)tile_nbuf<P>() * 24 * sizeof(typename Tr<P>::acc) * w.wg;
-    hipLaunchKernelGGL((k_dslash_tile<P, MODE>), dim3(grid_of(w)), dim3(w.wg), std::max(need, lds_cap(w.wg, w.occ)),
-                       s, w, out, in, aux, diag, st, mask, part, rk);
+    const size_t lds = std::max(need, lds_cap(w.wg, w.occ));
+    if (w.nr >= 4)
+        hipLaunchKernelGGL((k_dslash_tile<P, MODE, true>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, aux, diag,
+                           st, mask, part, rk);
+    else
+        hipLaunchKernelGGL((k_dslash_tile<P, MODE, false>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, aux, diag,
+                           st, mask, part, rk);
 }
 
 template <int P, int MODE>

@@ -203,6 +203,7 @@ void launch_unpack(int prec, const Work& w, double* dst, Fld src, long long sys_
 
 // gauge: canonical complex128 [mu][site][3][3] -> [mu][9][site] in precision prec
 void launch_gauge_convert(int prec, void* dst, const double* src, int V, hipStream_t s);
+void launch_gauge_convert_q(int prec, void* dst, const double* src, int V, hipStream_t s);
 
 void launch_noise_block(int prec, const Work& w, Fld dst, const NoiseKey* keys /* per system */, hipStream_t s);
 void launch_noise_canonical(double* dst, int V, NoiseKey key, hipStream_t s);
