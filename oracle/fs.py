@@ -184,3 +184,63 @@ def exact_trace(solver, sigma, n, p):
     V = lat.volume(solver.dims)
     G = lat.gamma_dense(n, V) @ lat.omega_dense(solver.U, p, solver.dims)
     return np.trace(G @ solver.inverse(sigma))
+
+
+# ---------------------------------------------------------------------------
+# Variance sampling (Sec. 3.1, subsection "Sampling the Variance")
+# ---------------------------------------------------------------------------
+
+# Level field of the noise key used by the sampling phase: one Z4 vector z_k
+# per sample, shared by every sampling shift and independent of the
+# estimation noise (whose level fields are 0..L).
+SAMPLING_LEVEL = 0xFFFFFFFF
+
+
+def sampling_slots(m):
+    """Order of the sampled quantities: V_L(s_i) for i = 0..m-1, then
+    Vbar_l(s_i, s_j) for i = 0..m-1, j = i..m-1."""
+    return [("single", i, i) for i in range(m)] + [("pair", i, j) for i in range(m) for j in range(i, m)]
+
+
+def sampling_samples(U, dims, shifts, n_samples, seed, gammas, p_max, solver, instance=0):
+    """Per-sample values of the sampling algorithm, X[slot, k, n_idx, p].
+
+    For each noise vector z_k and each sampling shift s_i: x_i = (D+s_i)^-1 z_k
+    and y_i = (D+s_i)^-dagger z_k = g5 (D+s_i)^-1 g5 z_k (the second solve
+    for non-diluted noise).  Then V_L(s_i) samples z_k^dagger Gamma Omega_p x_i
+    (A = Gamma Omega_p (D+s_i)^-1) and Vbar_l(s_i, s_j), j >= i, samples
+    y_i^dagger Gamma Omega_p x_j (A = (D+s_i)^-1 Gamma Omega_p (D+s_j)^-1),
+    without the (s_j - s_i)^2 factor of V_l (eq. sampled_prod, eq. bar_vl).
+    """
+    m = len(shifts)
+    V = lat.volume(dims)
+    slots = sampling_slots(m)
+    X = np.zeros((len(slots), n_samples, len(gammas), p_max + 1), dtype=np.complex128)
+    for k in range(n_samples):
+        z = z4_noise(V, seed, instance, SAMPLING_LEVEL, k)
+        xs = [solver.solve(s, z) for s in shifts]
+        ys = [lat.apply_gamma5(solver.solve(s, lat.apply_gamma5(z))) for s in shifts]
+        for q, (kind, i, j) in enumerate(slots):
+            y = z if kind == "single" else ys[i]
+            X[q, k] = bilinears(U, dims, y, xs[j], gammas, p_max)
+    return X
+
+
+def exact_sampling(solver, shifts, gammas, p_list):
+    """Exact traces and one-sample variances of every sampled matrix, per slot."""
+    U, dims = solver.U, solver.dims
+    V = lat.volume(dims)
+    m = len(shifts)
+    invs = [solver.inverse(s) for s in shifts]
+    slots = sampling_slots(m)
+    T = np.zeros((len(slots), len(gammas), len(p_list)), dtype=np.complex128)
+    Var = np.zeros((len(slots), len(gammas), len(p_list)))
+    for ip, p in enumerate(p_list):
+        Om = lat.omega_dense(U, p, dims)
+        for ig, n in enumerate(gammas):
+            G = lat.gamma_dense(n, V) @ Om
+            for q, (kind, i, j) in enumerate(slots):
+                A = level_matrix(None if kind == "single" else invs[i], invs[j], G, 1.0)
+                T[q, ig, ip] = np.trace(A)
+                Var[q, ig, ip] = offdiag_frobenius(A)
+    return T, Var
