@@ -194,6 +194,33 @@ fs_status fs_estimate(fs_ctx ctx, const fs_est_params* prm, const double* sigma,
                       fs_level_stat* out, double* samples_out, fs_est_report* report);
 
 /*
+ * fs_sample_variances -- the variance-sampling phase of shift selection (paper
+ * Sec. 3.1, "Sampling the Variance", and its algorithm).  One Z4 vector z_k per
+ * sample is shared by all sampling shifts: noise key (seed, instance, level
+ * 0xFFFFFFFF, sample k), independent of the estimation noise.  For every shift
+ * s_i: x_i = (D+s_i)^-1 z_k and y_i = (D+s_i)^-dagger z_k = g5 (D+s_i)^-1 g5 z_k
+ * (a second solve: the noise is not spin-diluted).  Then, per (Gamma_n, p):
+ *   single[i]     samples z_k^+ Gamma_n Omega_p x_i          (V_L(s_i), eq. sampled_single)
+ *   pair[i][j]    samples y_i^+ Gamma_n Omega_p x_j, j >= i  (Vbar_l(s_i, s_j), eq. bar_vl;
+ *                 V_l = (s_j - s_i)^2 Vbar_l, eq. sampled_prod)
+ * each reported as mean, eq. practical_variance and the (N-1) form.
+ *   shifts       s[0..m-1] with s[0] = 0, strictly increasing, 1 <= m <= 16
+ *   prm          seed, n_noise (the N_s samples, >= 2), gamma_mask, p_max, solver
+ *   single       [m][16][p_max+1]
+ *   pair         [m][m][16][p_max+1]; entries with j < i are zeroed
+ *   samples_out  NULL or host [m + m(m+1)/2][n_noise][16][p_max+1] complex128: the
+ *                singles i = 0..m-1, then the pairs (i, j), i = 0..m-1, j = i..m-1
+ *   iters_out    NULL or host [m]: mean Krylov iterations of the 2 n_noise systems of
+ *                each shift, the sampled r(s_i) of the solver-cost model (Sec. 3.2)
+ *   report       NULL or totals of the call
+ * FS_E_ARG for invalid arguments (before any device work); FS_E_NOCONV if a
+ * solve missed tol (outputs still filled).  All systems are solved in one batch.
+ */
+fs_status fs_sample_variances(fs_ctx ctx, const fs_est_params* prm, const double* shifts, int32_t m,
+                              fs_level_stat* single, fs_level_stat* pair, double* samples_out,
+                              double* iters_out, fs_est_report* report);
+
+/*
  * Batches of uneven lattice instances that share persistent launches: every
  * stencil, BLAS and reduction launch of fs_batch_estimate covers the systems
  * of all instances.  Contexts must be on the same device and have gauge

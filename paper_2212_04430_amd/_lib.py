@@ -81,6 +81,8 @@ _sig = {
                                    C.c_int32, C.POINTER(fs_solve_stats)]),
     "fs_estimate": (C.c_int, [_P, C.POINTER(fs_est_params), _P, C.c_int32, C.POINTER(fs_level_stat), _P,
                               C.POINTER(fs_est_report)]),
+    "fs_sample_variances": (C.c_int, [_P, C.POINTER(fs_est_params), _P, C.c_int32, C.POINTER(fs_level_stat),
+                                      C.POINTER(fs_level_stat), _P, _P, C.POINTER(fs_est_report)]),
     "fs_batch_create": (C.c_int, [C.POINTER(_P), C.POINTER(_P), C.c_int32]),
     "fs_batch_estimate": (C.c_int, [_P, C.POINTER(fs_est_params), _P, C.c_int32, C.POINTER(fs_level_stat),
                                     C.POINTER(fs_est_report)]),
@@ -255,6 +257,28 @@ def fs_estimate(ctx, params, sigma, want_samples=False, allow_noconv=False):
                             C.c_void_p(samples.ctypes.data) if want_samples else None, C.byref(rep))
     _check(code, allow=(FS_E_NOCONV,) if allow_noconv else ())
     return _stats_array(list(out), (L + 1, 16, P1)), samples, rep
+
+
+def fs_sample_variances(ctx, params, shifts, want_samples=False, allow_noconv=False):
+    """Variance-sampling phase.  Returns the single-shift stats [m, 16, p_max+1, 6],
+    the pair stats [m, m, 16, p_max+1, 6] (zero for j < i), the samples
+    [m + m(m+1)/2, N, 16, p_max+1] (singles, then pairs (i, j >= i); or None),
+    the mean iterations per shift [m] and the report."""
+    sh = np.ascontiguousarray(shifts, dtype=np.float64)
+    m = len(sh)
+    P1 = params.p_max + 1
+    single = (fs_level_stat * (m * 16 * P1))()
+    pair = (fs_level_stat * (m * m * 16 * P1))()
+    n_slot = m + m * (m + 1) // 2
+    samples = np.zeros((n_slot, params.n_noise, 16, P1), dtype=np.complex128) if want_samples else None
+    iters = np.zeros(m)
+    rep = fs_est_report()
+    code = _lib.fs_sample_variances(ctx, C.byref(params), C.c_void_p(sh.ctypes.data), m, single, pair,
+                                    C.c_void_p(samples.ctypes.data) if want_samples else None,
+                                    C.c_void_p(iters.ctypes.data), C.byref(rep))
+    _check(code, allow=(FS_E_NOCONV,) if allow_noconv else ())
+    return (_stats_array(list(single), (m, 16, P1)), _stats_array(list(pair), (m, m, 16, P1)), samples, iters,
+            rep)
 
 
 def fs_batch_create(ctxs):

@@ -940,6 +940,178 @@ void run_units(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm, con
     }
 }
 
+// Variance sampling (paper Sec. 3.1, "Sampling the Variance").  One Z4
+// vector per sample, shared by every sampling shift (noise level field
+// kSamplingLevel); per shift s_i an x-system on z and a y-system on g5 z,
+// solved in one batch.  The hop/bilinear chain then runs once per pairing:
+// pass 0 pairs each x-block with its own source (V_L(s_i)), pass q >= 1 pairs
+// the x-blocks of s_j, j >= q-1, with the y-blocks of s_{q-1} holding the same
+// samples (Vbar_l(s_{q-1}, s_j)).  Slot order: singles i, then pairs (i, j).
+constexpr uint32_t kSamplingLevel = 0xFFFFFFFFu;
+
+void sampling_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sh_in, int m, fs_level_stat* single,
+                   fs_level_stat* pair, double* samples_out, double* iters_out, fs_est_report* report) {
+    if (!prm || !sh_in || !single || !pair) fail(FS_E_ARG, "null argument");
+    if (m < 1 || m > 16) fail(FS_E_ARG, "m must be in 1..16");
+    if (prm->n_noise < 2) fail(FS_E_ARG, "n_noise must be >= 2");
+    if (prm->p_max < 0 || prm->p_max >= c->dims[2]) fail(FS_E_ARG, "p_max must be in [0, Lz)");
+    check_prec(prm->solve.storage);
+    if (!(prm->solve.tol > 0)) fail(FS_E_ARG, "tol must be > 0");
+    if (prm->solve.max_iter < 1) fail(FS_E_ARG, "max_iter must be >= 1");
+    if (prm->solve.rhs_block != 0 && !pow2_ok(prm->solve.rhs_block)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
+    std::vector<double> sh(sh_in, sh_in + m);
+    if (sh[0] != 0.0) fail(FS_E_ARG, "shifts[0] must be 0");
+    for (int i = 0; i + 1 < m; ++i)
+        if (!(sh[i + 1] > sh[i])) fail(FS_E_ARG, "shifts must be strictly increasing");
+    auto t0 = std::chrono::steady_clock::now();
+    DeviceScope ds(c->device);
+    hipStream_t s = c->stream;
+    const int N = prm->n_noise, P1 = prm->p_max + 1, P = prm->solve.storage;
+    const int nr = prm->solve.rhs_block ? prm->solve.rhs_block : tuned_nr(c, P, N);
+    const int nch = (N + nr - 1) / nr;
+    const int nslot = m + m * (m + 1) / 2;
+    auto slot_pair = [&](int i, int j) { return m + i * m - i * (i - 1) / 2 + (j - i); };
+    // blocks: x(i, ch) = 2 (i nch + ch), y(i, ch) = x + 1
+    const int nblk = 2 * m * nch;
+    std::vector<int> blk_lat(nblk, 0);
+    std::vector<fs_ctx_s*> lats{c};
+    auto pl = make_plan(blk_lat, lats, nr, tuned_wg(c, P), s, tuned_ilp(c, P), tuned_occ(c, P));
+    const int nsys = pl->nsys;
+    std::vector<double> diag(nsys);
+    std::vector<char> idle(nsys);
+    std::vector<NoiseKey> keys(nsys);
+    std::vector<int> smp(nsys);
+    for (int b = 0; b < nblk; ++b) {
+        const int i = (b / 2) / nch, ch = (b / 2) % nch;
+        const bool is_y = b & 1;
+        for (int r = 0; r < nr; ++r) {
+            const int sys = b * nr + r;
+            const int k = ch * nr + r;
+            smp[sys] = k < N ? k : -1;
+            diag[sys] = 4.0 + prm->solve.m0 + sh[i];
+            idle[sys] = k >= N;
+            NoiseKey key;
+            std::memset(&key, 0, sizeof(key));
+            key.seed = prm->seed;
+            key.instance = c->instance;
+            key.level = kSamplingLevel;
+            key.sample = (uint64_t)(k < N ? k : 0);
+            key.g5 = is_y ? 1 : 0;
+            key.pad = k < N ? 0 : 1;
+            keys[sys] = key;
+        }
+    }
+    SolveOpts o;
+    o.P = P;
+    o.tol = prm->solve.tol;
+    o.max_iter = prm->solve.max_iter;
+    o.delta = P == P64 ? 0.0 : (prm->solve.reliable_delta > 0 ? prm->solve.reliable_delta : default_delta(P));
+    o.check_every = prm->solve.check_every > 0 ? prm->solve.check_every : 8;
+    o.use_graph = prm->solve.use_graph != 0;
+    BatchSolver bs(*pl, lats, s, o);
+    bs.setup(diag, idle, keys);
+    DevBuf d_keys = to_device(keys.data(), sizeof(NoiseKey) * nsys, 0, s);
+    launch_noise_block(P64, pl->work(P64, false), bs.b.f(), d_keys.as<NoiseKey>(), s);
+    bs.run();
+
+    // bilinears, one pass per pairing
+    static const GammaTab gt = make_gamma_tab();
+    const size_t xsz = (size_t)nslot * N * 16 * P1 * 2;
+    std::vector<double> X(xsz, 0.0);
+    DevBuf d_X = to_device(X.data(), sizeof(double) * xsz, 0, s);
+    DevBuf d_M(sizeof(double) * (size_t)nsys * P1 * 32);
+    Field phi1;
+    phi1.alloc(P64, pl->total_slots);
+    for (int q = 0; q <= m; ++q) {
+        const int iy = q - 1;
+        std::vector<int> yb(2 * nblk, -1), hop_start(nblk + 1, 0);
+        std::vector<XMap> xm(nsys);
+        for (int b = 0; b < nblk; ++b) {
+            const int j = (b / 2) / nch, ch = (b / 2) % nch;
+            const bool part_of = !(b & 1) && (q == 0 || j >= iy);
+            if (part_of && q > 0) {
+                yb[2 * b] = 2 * (iy * nch + ch) + 1;
+                yb[2 * b + 1] = 1;
+            }
+            hop_start[b + 1] = hop_start[b] + (part_of ? pl->wg_start[b + 1] - pl->wg_start[b] : 0);
+            for (int r = 0; r < nr; ++r) {
+                const int sys = b * nr + r;
+                XMap mp;
+                std::memset(&mp, 0, sizeof(mp));
+                mp.level = (part_of && smp[sys] >= 0) ? (q == 0 ? j : slot_pair(iy, j)) : -1;
+                mp.sample = std::max(0, smp[sys]);
+                mp.g5 = q > 0 ? 1 : 0;
+                mp.coef = 1.0;
+                xm[sys] = mp;
+            }
+        }
+        DevBuf d_hop_start = to_device(hop_start.data(), sizeof(int) * (nblk + 1), 0, s);
+        DevBuf d_yb = to_device(yb.data(), sizeof(int) * 2 * nblk, 0, s);
+        DevBuf d_xm = to_device(xm.data(), sizeof(XMap) * nsys, 0, s);
+        Work wh = pl->work(P64, false);
+        wh.wg_start = d_hop_start.as<int>();
+        wh.total_wg = hop_start.back();
+        Fld cur = bs.xhi.f();
+        for (int p = 0; p <= prm->p_max; ++p) {
+            Fld outf = (p % 2 == 1) ? bs.rhi.f() : phi1.f();
+            launch_hop_reduce(wh, p, outf, cur, bs.xhi.f(), bs.b.f(), d_yb.as<int>(), bs.part(), s);
+            launch_hop_finish(wh, bs.part(), d_M.as<double>(), P1, p, s);
+            if (p > 0) cur = outf;
+        }
+        launch_gamma_contract(d_M.as<double>(), P1, nsys, d_xm.as<XMap>(), gt, d_X.as<double>(), N, s);
+        HC(hipStreamSynchronize(s));  // the host tables above die with this scope
+    }
+    // statistics per slot
+    DevBuf d_st(sizeof(double) * (size_t)nslot * 16 * P1 * 4);
+    launch_level_stats(d_X.as<double>(), nslot, N, P1, d_st.as<double>(), s);
+    std::vector<double> stv((size_t)nslot * 16 * P1 * 4);
+    HC(hipMemcpyAsync(stv.data(), d_st.p, sizeof(double) * stv.size(), hipMemcpyDeviceToHost, s));
+    HC(hipMemcpyAsync(X.data(), d_X.p, sizeof(double) * xsz, hipMemcpyDeviceToHost, s));
+    HC(hipGetLastError());
+    HC(hipStreamSynchronize(s));
+    fs_est_report rep;
+    std::memset(&rep, 0, sizeof(rep));
+    bool noconv = false;
+    std::vector<double> it_sum(m, 0.0);
+    for (int i = 0; i < nsys; ++i) {
+        if (smp[i] < 0) continue;
+        const SysState& S = bs.st_host[i];
+        it_sum[(i / nr / 2) / nch] += S.iters;
+        rep.systems += 1;
+        rep.iterations += S.iters;
+        rep.reliable_updates += S.n_rel;
+        const double rel = S.bb > 0 ? std::sqrt(S.rr_true / S.bb) : 0.0;
+        rep.max_rel_residual = std::max(rep.max_rel_residual, rel);
+        if (S.state != S_DONE) noconv = true;
+    }
+    rep.dslash_calls = bs.dslash_calls;
+    const uint16_t mask = prm->gamma_mask ? prm->gamma_mask : 0xffff;
+    auto fill = [&](fs_level_stat& ostat, int slot, int n, int p) {
+        std::memset(&ostat, 0, sizeof(ostat));
+        if (slot < 0 || !((mask >> n) & 1)) return;
+        const double* d = &stv[(((size_t)slot * 16 + n) * P1 + p) * 4];
+        ostat.tr_re = d[0];
+        ostat.tr_im = d[1];
+        ostat.var_paper = d[2];
+        ostat.var_unbiased = d[3];
+        ostat.n = N;
+        ostat.max_rel_residual = rep.max_rel_residual;
+    };
+    for (int i = 0; i < m; ++i)
+        for (int n = 0; n < 16; ++n)
+            for (int p = 0; p < P1; ++p) {
+                fill(single[((size_t)i * 16 + n) * P1 + p], i, n, p);
+                for (int j = 0; j < m; ++j)
+                    fill(pair[(((size_t)i * m + j) * 16 + n) * P1 + p], j >= i ? slot_pair(i, j) : -1, n, p);
+            }
+    if (samples_out) std::memcpy(samples_out, X.data(), sizeof(double) * xsz);
+    if (iters_out)
+        for (int i = 0; i < m; ++i) iters_out[i] = it_sum[i] / (2.0 * N);
+    rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (report) *report = rep;
+    if (noconv) throw FsError(FS_E_NOCONV, "a shifted solve did not reach tol (outputs are filled)");
+}
+
 void estimate_impl(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm, const double* sigma_in, int L,
                    fs_level_stat* out, double* samples_out, fs_est_report* report) {
     if (!prm || !sigma_in || !out) fail(FS_E_ARG, "null argument");
@@ -1426,6 +1598,15 @@ fs_status fs_estimate(fs_ctx c, const fs_est_params* prm, const double* sigma, i
     return guard([&] {
         check_ctx(c);
         estimate_impl({c}, prm, sigma, L, out, samples_out, report);
+    });
+}
+
+fs_status fs_sample_variances(fs_ctx c, const fs_est_params* prm, const double* shifts, int32_t m,
+                              fs_level_stat* single, fs_level_stat* pair, double* samples_out,
+                              double* iters_out, fs_est_report* report) {
+    return guard([&] {
+        check_ctx(c);
+        sampling_impl(c, prm, shifts, m, single, pair, samples_out, iters_out, report);
     });
 }
 
