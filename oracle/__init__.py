@@ -20,7 +20,12 @@ Multilevel Monte Carlo for Disconnected Diagrams in Lattice QCD"):
 * `fs`       -- exact level traces and variances on tiny lattices and the
                 stochastic FS estimator with per-level mean and variance
                 (Sec. 2.2-2.3, eqs. tele_sum_prod_disp, phi_prod, phi_single,
-                fs_trace_est, practical_variance, total_var, tosv).
+                fs_trace_est, practical_variance, total_var, tosv), and the
+                variance-sampling phase with shared noise (Sec. 3.1).
+* `shifts`   -- shift selection: PCHIP interpolation of the sampled variances
+                in log space, the iteration-count cost model and the argmin of
+                the multilevel cost over the evaluation set (Sec. 3.2-3.3,
+                eqs. ml_cost_shifts, opt_shifts).
 
 Parity status of every function is recorded in its docstring: each is pinned
 by a test that does not reuse the oracle's own formula (closed forms, exact
