@@ -22,6 +22,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -52,9 +53,10 @@ def est_params(L, storage, batched, n_noise, nr=0, graph=1):
     return L.fs_est_params(w["seed"], n_noise, 0, w["p_max"], sp)
 
 
-def cpu_baseline(U, dims, avg_iters):
+def cpu_baseline(U, dims, avg_iters, sel_inputs=None):
     """Oracle FP64 BiCGStab iterations on the same lattice, single thread,
-    scaled to solves/s with the mean iteration count of the GPU solves."""
+    scaled to solves/s with the mean iteration count of the GPU solves; and the
+    oracle's shift selection for one (Gamma, p) pair when sampled inputs are given."""
     from threadpoolctl import threadpool_limits
 
     from oracle import lattice as lat
@@ -87,10 +89,20 @@ def cpu_baseline(U, dims, avg_iters):
             p = r + be * (p - om * v)
         dt = time.perf_counter() - t0
     per_iter = dt / n_it
-    return {"value": 1.0 / (per_iter * avg_iters), "unit": "shifted solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_it} oracle BiCGStab iterations (numpy FP64, 1 thread) on the 16^3x32 lattice at "
-                      f"sigma={sigma}, {dt:.1f} s; solves/s = 1/(s per iteration x {avg_iters:.1f} mean GPU "
-                      f"iterations per system)"}
+    out = {"value": 1.0 / (per_iter * avg_iters), "unit": "shifted solves/s", "cores": 1, "kind": "oracle",
+           "sample": f"{n_it} oracle BiCGStab iterations (numpy FP64, 1 thread) on the 16^3x32 lattice at "
+                     f"sigma={sigma}, {dt:.1f} s; solves/s = 1/(s per iteration x {avg_iters:.1f} mean GPU "
+                     f"iterations per system)"}
+    if sel_inputs is not None:
+        from oracle import shifts as osh
+        s_hat, vs, vp, iters, grid = sel_inputs
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            tabs = (osh.interp_pairs(np.array(s_hat), vp, grid), osh.interp_single(np.array(s_hat), vs, grid),
+                    osh.nn_cost(s_hat, iters, grid))
+            osh.select_dp(6, *tabs)
+            out["shift_selection_seconds_one_pair"] = round(time.perf_counter() - t0, 3)
+    return out
 
 
 def kernel_source_hash():
@@ -134,6 +146,45 @@ def roofline_only(L, ctx, nr, wg):
                       "config": f"f32 nsys={ROOFLINE_NSYS} nr={nr} wg={wg}", "hash": kernel_source_hash()}))
 
 
+def sampling_and_selection(L, ctx, nr):
+    """Variance sampling on the paper's sampling set with N_s = 5 (Sec. 3.1), then
+    shift selection with six shifts (Sec. 3.2-3.3) for every (Gamma_n, p) on the
+    paper's evaluation grid: the dynamic program on the host, and the GPU's
+    exhaustive sweep for (Gamma_11, p = 4) checked against it."""
+    s_hat = list(WORKLOAD["sigma"])
+    prm = est_params(L, "f32", 1, 5, nr=nr)
+    t0 = time.perf_counter()
+    single, pair, _, iters, rep = L.fs_sample_variances(ctx, prm, s_hat)
+    dt_s = time.perf_counter() - t0
+    log(f"variance sampling: {rep.systems} systems in {dt_s:.2f} s")
+    grid = L.fs_eval_grid(s_hat)
+    P1 = single.shape[2]
+    chosen = {}
+    t1 = time.perf_counter()
+    for n_g in range(16):
+        for p in range(P1):
+            mdl = L.ShiftModel(s_hat, single[:, n_g, p, 2], pair[:, :, n_g, p, 2], iters, grid)
+            chosen[(n_g, p)] = L.fs_select_shifts(mdl, 6)
+    dt_dp = time.perf_counter() - t1
+    mdl = L.ShiftModel(s_hat, single[:, 11, 4, 2], pair[:, :, 11, 4, 2], iters, grid)
+    L.fs_sweep_shifts(ctx, mdl, 6)  # warm-up
+    idx_g, c_g, ms_g = L.fs_sweep_shifts(ctx, mdl, 6)
+    idx_d, c_d, _, _ = chosen[(11, 4)]
+    n = len(grid)
+    n_paths = math.comb(n - 1, 6)
+    out = {"sampling_shifts": s_hat, "n_samples": 5, "sampling_systems": int(rep.systems),
+           "sampling_seconds": round(dt_s, 3), "sampling_solves_per_s": round(rep.systems / dt_s, 2),
+           "iters_per_shift": [round(float(v), 2) for v in iters],
+           "eval_grid_points": n, "levels": 7,
+           "dp_seconds_all_144_pairs": round(dt_dp, 4),
+           "sigma_gamma11_p4": [round(float(grid[i]), 5) for i in idx_d], "c_fs_gamma11_p4": c_d,
+           "gpu_sweep": {"paths": n_paths, "ms": round(ms_g, 4), "paths_per_s": round(n_paths / (ms_g * 1e-3), 1),
+                         "same_as_dp": bool(idx_g == idx_d and c_g == c_d)}}
+    log(f"shift selection: 144 DP selections in {dt_dp * 1e3:.1f} ms; GPU sweep of {n_paths} paths "
+        f"in {ms_g:.3f} ms, same as DP: {out['gpu_sweep']['same_as_dp']}")
+    return out, (s_hat, single[:, 11, 4, 2].copy(), pair[:, :, 11, 4, 2].copy(), iters, grid)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +195,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-half", action="store_true", help="skip the FP16/BF16 mixed-path steps")
     ap.add_argument("--roofline-only", action="store_true", help="only the copy and stencil launches of the roofline")
+    ap.add_argument("--no-select", action="store_true", help="skip variance sampling and shift selection")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the hot path shards over independent systems "
@@ -237,6 +289,7 @@ def main():
                 "algorithmic_bytes_per_launch": bytes_d, "avg_launch_ms": round(ms_d, 5),
                 "copy_kernel_GBs": round(2 * (1 << 30) / (ms_c * 1e-3) / 1e9, 1)}
     log(f"dslash f32 batched: {ms_d:.4f} ms, {achieved:.0f} GB/s")
+    select, sel_inputs = (None, None) if args.no_select else sampling_and_selection(L, ctx, nr)
     L.fs_destroy(ctx)
 
     # ---- 32^3 x 64 single-RHS dslash (working set >> 256 MB)
@@ -264,7 +317,7 @@ def main():
             log(f"dslash 32^3x64 {prec}: {ms:.4f} ms {gbs:.0f} GB/s")
         L.fs_destroy(ch)
 
-    cpu = None if args.no_cpu else cpu_baseline(U, dims, avg_iters)
+    cpu = None if args.no_cpu else cpu_baseline(U, dims, avg_iters, sel_inputs)
 
     out = {
         "metric": METRIC,
@@ -293,6 +346,7 @@ def main():
         "level_rel_dev_vs_fp64": [float(f"{e:.3e}") for e in lvl_err],
         "dslash_32c64_single_rhs": headline,
         "mixed_half_precision": half or None,
+        "sampling_and_shift_selection": select,
     }
     print(json.dumps(out), flush=True)
 

@@ -288,6 +288,76 @@ fs_status fs_time_dslash(fs_ctx ctx, fs_prec storage, int32_t n_sys, int32_t rhs
  */
 fs_status fs_time_copy(fs_ctx ctx, uint64_t bytes, int32_t n_launch, double* avg_ms);
 
+/* ------------------------------------------------------------------ shift selection
+ * Paper Sec. 3.2-3.3.  The sampled variances and iteration counts of
+ * fs_sample_variances (one Gamma_n, p) are carried to an evaluation set s by
+ * monotone cubic Hermite interpolation (PCHIP, Fritsch-Carlson with
+ * Fritsch-Butland slopes; a line through two points) of their logarithms:
+ * V_L(s_k) from the m samples V_L(s^_i); Vbar_l by the paper's three-stage
+ * 2-D scheme (along the first argument at each sampled second argument s^_j,
+ * along the diagonal, then along the second argument at each s_i through the
+ * diagonal point and the s^_j > s_i); V_l(s_i, s_k) = (s_k - s_i)^2 Vbar_l
+ * (eq. sampled_prod).  Iteration counts: r(s) = r(s^_j) for
+ * s^_{j-1} < s <= s^_j (eq. solver_cost_shift, 12c = 1 for undiluted noise).
+ * Multilevel cost (eq. ml_cost_shifts, eps = 1):
+ *   C_FS = (sum_{l=0}^{L} sqrt(C_l V_l))^2,
+ *   C_l = r(sigma_l) + r(sigma_{l+1}) for l < L (a level-l sample solves at
+ *   both shifts), C_L = r(sigma_L), with V_l = V_l(sigma_l, sigma_{l+1}) and V_L(sigma_L).
+ * All arrays are host memory owned by the caller.
+ */
+typedef struct {
+    int32_t m;              /* sampling shifts, 2..16                                     */
+    const double* s_hat;    /* [m]: s_hat[0] = 0, strictly increasing                      */
+    const double* v_single; /* [m]: sampled V_L(s_hat_i) > 0                               */
+    const double* v_pair;   /* [m][m]: sampled Vbar_l(s_hat_i, s_hat_j) > 0 for j >= i;
+                               entries j < i are not read                                 */
+    const double* iters;    /* [m]: iteration counts r(s_hat_i) > 0                        */
+    int32_t n;              /* evaluation shifts, 2..4096                                  */
+    const double* s;        /* [n]: s[0] = 0, strictly increasing, containing every s_hat_i
+                               exactly, s[n-1] <= s_hat[m-1] (no extrapolation)            */
+} fs_shift_model;
+
+/*
+ * fs_eval_grid -- the paper's evaluation set (Sec. 3.3): 0, 4 log-spaced
+ * shifts from 1e-5 to 1e-2 and 76 from 0.011 to 1, cut at s_hat[m-1], with the
+ * sampling shifts inserted where missing, sorted.  Writes *n_out values to
+ * s_out (capacity cap; FS_E_ARG if too small or the sampling set is invalid).
+ */
+fs_status fs_eval_grid(const double* s_hat, int32_t m, double* s_out, int32_t cap, int32_t* n_out);
+
+/*
+ * fs_shift_tables -- the predicted quantities on the evaluation set:
+ *   v_pair_eval  NULL or [n][n]: V_l(s_i, s_k) for k > i, zero elsewhere
+ *   v_single_eval NULL or [n]: V_L(s_k)
+ *   r_eval       NULL or [n]: r(s_k)
+ * FS_E_ARG for an invalid model (see fs_shift_model).
+ */
+fs_status fs_shift_tables(const fs_shift_model* model, double* v_pair_eval, double* v_single_eval, double* r_eval);
+
+/*
+ * fs_select_shifts -- eq. opt_shifts: the L shifts sigma_l = s[idx[l]],
+ * 0 = idx[0] < idx[1] < ... < idx[L] <= n-1, minimising C_FS, found exactly by
+ * dynamic programming over increasing indices (each level term depends on two
+ * consecutive shifts), O(L n^2), on the host.  0 <= L <= n-1.
+ *   idx       [L+1]
+ *   c_fs      the minimum C_FS
+ *   v_levels  NULL or [L+1]: V_l of the chosen levels;  c_levels NULL or [L+1]: C_l
+ * With tied minima the choice among them is unspecified.
+ */
+fs_status fs_select_shifts(const fs_shift_model* model, int32_t L, int32_t* idx, double* c_fs, double* v_levels,
+                           double* c_levels);
+
+/*
+ * fs_sweep_shifts -- the same argmin by the paper's exhaustive search over all
+ * C(n-1, L) combinations, on the context's GPU (1 <= L <= 8, n <= 88,
+ * C(n-1, L) <= 2^40).  Per-path sums are formed in the same order as in
+ * fs_select_shifts, so equal paths give equal c_fs bit for bit; ties go to
+ * the lexicographically first index tuple.
+ *   idx [L+1], c_fs as above; ms NULL or the sweep kernels' GPU time (HIP events)
+ */
+fs_status fs_sweep_shifts(fs_ctx ctx, const fs_shift_model* model, int32_t L, int32_t* idx, double* c_fs,
+                          double* ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,6 +39,9 @@ class FsError(RuntimeError):
         self.code = code
 
 
+_DP = C.POINTER(C.c_double)
+
+
 class fs_solve_params(C.Structure):
     _fields_ = [("m0", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("storage", C.c_int32), ("rhs_block", C.c_int32), ("use_graph", C.c_int32),
@@ -63,6 +66,11 @@ class fs_level_stat(C.Structure):
 class fs_est_report(C.Structure):
     _fields_ = [("systems", C.c_int64), ("iterations", C.c_int64), ("reliable_updates", C.c_int64),
                 ("dslash_calls", C.c_int64), ("max_rel_residual", C.c_double), ("seconds", C.c_double)]
+
+
+class fs_shift_model(C.Structure):
+    _fields_ = [("m", C.c_int32), ("s_hat", _DP), ("v_single", _DP), ("v_pair", _DP), ("iters", _DP),
+                ("n", C.c_int32), ("s", _DP)]
 
 
 _P = C.c_void_p
@@ -92,6 +100,10 @@ _sig = {
     "fs_time_dslash": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "fs_time_copy": (C.c_int, [_P, C.c_uint64, C.c_int32, C.POINTER(C.c_double)]),
+    "fs_eval_grid": (C.c_int, [_DP, C.c_int32, _DP, C.c_int32, C.POINTER(C.c_int32)]),
+    "fs_shift_tables": (C.c_int, [C.POINTER(fs_shift_model), _DP, _DP, _DP]),
+    "fs_select_shifts": (C.c_int, [C.POINTER(fs_shift_model), C.c_int32, C.POINTER(C.c_int32), _DP, _DP, _DP]),
+    "fs_sweep_shifts": (C.c_int, [_P, C.POINTER(fs_shift_model), C.c_int32, C.POINTER(C.c_int32), _DP, _DP]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -327,3 +339,56 @@ def fs_time_copy(ctx, nbytes, n_launch=20):
     ms = C.c_double()
     _check(_lib.fs_time_copy(ctx, int(nbytes), int(n_launch), C.byref(ms)))
     return ms.value
+
+
+# ---------------------------------------------------------------- shift selection
+
+def _dp(a):
+    return a.ctypes.data_as(_DP)
+
+
+class ShiftModel:
+    """Host arrays of an fs_shift_model, kept alive with the struct."""
+
+    def __init__(self, s_hat, v_single, v_pair, iters, s):
+        self.arrays = [np.ascontiguousarray(a, dtype=np.float64) for a in (s_hat, v_single, v_pair, iters, s)]
+        sh, vs, vp, it, ev = self.arrays
+        m = len(sh)
+        if vs.shape != (m,) or vp.shape != (m, m) or it.shape != (m,):
+            raise ValueError("shift model arrays must be [m], [m], [m][m], [m]")
+        self.n = len(ev)
+        self.c = fs_shift_model(m, _dp(sh), _dp(vs), _dp(vp), _dp(it), self.n, _dp(ev))
+
+
+def fs_eval_grid(s_hat):
+    sh = np.ascontiguousarray(s_hat, dtype=np.float64)
+    out = np.zeros(256)
+    n = C.c_int32()
+    _check(_lib.fs_eval_grid(_dp(sh), len(sh), _dp(out), len(out), C.byref(n)))
+    return out[:n.value].copy()
+
+
+def fs_shift_tables(model):
+    """(V_l(s_i, s_k) [n][n], V_L(s_k) [n], r(s_k) [n]) on the evaluation set."""
+    n = model.n
+    vp, vs, r = np.zeros((n, n)), np.zeros(n), np.zeros(n)
+    _check(_lib.fs_shift_tables(C.byref(model.c), _dp(vp), _dp(vs), _dp(r)))
+    return vp, vs, r
+
+
+def fs_select_shifts(model, L):
+    """(idx [L+1], C_FS, V_l [L+1], C_l [L+1]) of the optimal shifts."""
+    idx = (C.c_int32 * (L + 1))()
+    c = C.c_double()
+    v, cl = np.zeros(L + 1), np.zeros(L + 1)
+    _check(_lib.fs_select_shifts(C.byref(model.c), int(L), idx, C.byref(c), _dp(v), _dp(cl)))
+    return tuple(idx), c.value, v, cl
+
+
+def fs_sweep_shifts(ctx, model, L):
+    """(idx [L+1], C_FS, GPU ms) from the exhaustive sweep on the GPU."""
+    idx = (C.c_int32 * (L + 1))()
+    c = C.c_double()
+    ms = C.c_double()
+    _check(_lib.fs_sweep_shifts(ctx, C.byref(model.c), int(L), idx, C.byref(c), C.byref(ms)))
+    return tuple(idx), c.value, ms.value

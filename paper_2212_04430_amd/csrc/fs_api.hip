@@ -21,6 +21,7 @@
 
 #include "../../include/fsmlmc.h"
 #include "fs_kernels.h"
+#include "fs_shift.h"
 
 using namespace fs;
 
@@ -54,6 +55,9 @@ fs_status guard(F&& f) {
     } catch (const FsError& e) {
         g_err = e.what();
         return e.code;
+    } catch (const ShiftArgError& e) {
+        g_err = e.what();
+        return FS_E_ARG;
     } catch (const std::bad_alloc&) {
         g_err = "host allocation failed";
         return FS_E_OOM;
@@ -1607,6 +1611,126 @@ fs_status fs_sample_variances(fs_ctx c, const fs_est_params* prm, const double* 
     return guard([&] {
         check_ctx(c);
         sampling_impl(c, prm, shifts, m, single, pair, samples_out, iters_out, report);
+    });
+}
+
+// ------------------------------------------------------------------ shift selection
+
+fs_status fs_eval_grid(const double* s_hat, int32_t m, double* s_out, int32_t cap, int32_t* n_out) {
+    return guard([&] {
+        if (!s_hat || !s_out || !n_out) fail(FS_E_ARG, "null argument");
+        if (m < 2 || m > 16) fail(FS_E_ARG, "m must be in 2..16");
+        if (s_hat[0] != 0.0) fail(FS_E_ARG, "s_hat[0] must be 0");
+        for (int i = 0; i + 1 < m; ++i)
+            if (!(s_hat[i + 1] > s_hat[i]) || !std::isfinite(s_hat[i + 1]))
+                fail(FS_E_ARG, "s_hat must be strictly increasing");
+        const std::vector<double> g = paper_eval_grid(s_hat, m);
+        if ((int)g.size() > cap) fail(FS_E_ARG, "output capacity too small");
+        std::copy(g.begin(), g.end(), s_out);
+        *n_out = (int32_t)g.size();
+    });
+}
+
+fs_status fs_shift_tables(const fs_shift_model* model, double* v_pair_eval, double* v_single_eval, double* r_eval) {
+    return guard([&] {
+        if (!model) fail(FS_E_ARG, "null model");
+        const ShiftTables T = shift_tables(*model);
+        if (v_pair_eval) std::copy(T.vp.begin(), T.vp.end(), v_pair_eval);
+        if (v_single_eval) std::copy(T.vs.begin(), T.vs.end(), v_single_eval);
+        if (r_eval) std::copy(T.r.begin(), T.r.end(), r_eval);
+    });
+}
+
+namespace {
+
+void level_terms(const ShiftTables& T, const std::vector<int>& id, double* v_levels, double* c_levels) {
+    const int L = (int)id.size() - 1, n = T.n;
+    for (int l = 0; l <= L; ++l) {
+        const bool last = l == L;
+        if (v_levels) v_levels[l] = last ? T.vs[id[l]] : T.vp[(size_t)id[l] * n + id[l + 1]];
+        if (c_levels) c_levels[l] = last ? T.r[id[l]] : T.r[id[l]] + T.r[id[l + 1]];
+    }
+}
+
+}  // namespace
+
+fs_status fs_select_shifts(const fs_shift_model* model, int32_t L, int32_t* idx, double* c_fs, double* v_levels,
+                           double* c_levels) {
+    return guard([&] {
+        if (!model || !idx || !c_fs) fail(FS_E_ARG, "null argument");
+        const ShiftTables T = shift_tables(*model);
+        if (L < 0 || L > T.n - 1) fail(FS_E_ARG, "L must be in 0..n-1");
+        std::vector<int> id(L + 1);
+        const double c = shift_select_dp(T, L, id.data());
+        for (int l = 0; l <= L; ++l) idx[l] = id[l];
+        *c_fs = c;
+        level_terms(T, id, v_levels, c_levels);
+    });
+}
+
+fs_status fs_sweep_shifts(fs_ctx c, const fs_shift_model* model, int32_t L, int32_t* idx, double* c_fs, double* ms) {
+    return guard([&] {
+        check_ctx(c, false);
+        if (!model || !idx || !c_fs) fail(FS_E_ARG, "null argument");
+        if (L < 1 || L > kSweepMaxL) fail(FS_E_ARG, "L must be in 1..8 for the sweep");
+        if (model->n > kSweepMaxN) fail(FS_E_ARG, "n must be <= 88 for the sweep");
+        const ShiftTables T = shift_tables(*model);
+        const int n = T.n;
+        if (L > n - 1) fail(FS_E_ARG, "L must be <= n-1");
+        constexpr int BW = kSweepMaxL + 1;
+        std::vector<uint64_t> binom((size_t)(kSweepMaxN + 1) * BW, 0);
+        for (int a = 0; a <= kSweepMaxN; ++a) {
+            binom[(size_t)a * BW] = 1;
+            for (int b = 1; b < BW && a > 0; ++b) binom[(size_t)a * BW + b] = binom[(size_t)(a - 1) * BW + b - 1] +
+                                                                             binom[(size_t)(a - 1) * BW + b];
+        }
+        auto C = [&](int a, int b) { return binom[(size_t)a * BW + b]; };
+        if (C(n - 1, L) > (1ull << 40)) fail(FS_E_ARG, "too many combinations for the sweep");
+        const uint64_t n_prefix = C(n - 2, L - 1);  // prefixes from {1..n-2}: each has a last index above it
+        const uint64_t max_threads = 1024ull * 256;
+        const uint64_t per = (n_prefix + max_threads - 1) / max_threads;
+        const int grid = (int)((n_prefix + per * 256 - 1) / (per * 256));
+        DeviceScope ds(c->device);
+        hipStream_t s = c->stream;
+        DevBuf d_w = to_device(T.w.data(), sizeof(double) * n * n, 0, s);
+        DevBuf d_u = to_device(T.u.data(), sizeof(double) * n, 0, s);
+        DevBuf d_b = to_device(binom.data(), sizeof(uint64_t) * binom.size(), 0, s);
+        DevBuf d_pc(sizeof(double) * grid), d_pk(sizeof(uint64_t) * grid), d_oc(sizeof(double)),
+            d_ok(sizeof(uint64_t));
+        hipEvent_t e0, e1;
+        HC(hipEventCreate(&e0));
+        HC(hipEventCreate(&e1));
+        HC(hipEventRecord(e0, s));
+        launch_shift_sweep(L, d_w.as<double>(), d_u.as<double>(), d_b.as<uint64_t>(), n, n_prefix, per, grid,
+                           d_pc.as<double>(), d_pk.as<uint64_t>(), s);
+        launch_sweep_reduce(d_pc.as<double>(), d_pk.as<uint64_t>(), grid, d_oc.as<double>(), d_ok.as<uint64_t>(), s);
+        HC(hipEventRecord(e1, s));
+        HC(hipGetLastError());
+        double best = 0.0;
+        uint64_t key = 0;
+        HC(hipMemcpyAsync(&best, d_oc.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        HC(hipMemcpyAsync(&key, d_ok.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        HC(hipStreamSynchronize(s));
+        float t = 0.f;
+        HC(hipEventElapsedTime(&t, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (!std::isfinite(best)) fail(FS_E_HIP, "sweep found no finite cost");
+        // decode: lexicographic prefix rank, then the last index
+        uint64_t r = key >> 7;
+        const int K = L - 1, M = n - 2;
+        std::vector<int> id(L + 1, 0);
+        for (int p = 0, x = 1; p < K; ++p) {
+            while (r >= C(M - x, K - 1 - p)) {
+                r -= C(M - x, K - 1 - p);
+                ++x;
+            }
+            id[p + 1] = x++;
+        }
+        id[L] = (int)(key & 127);
+        for (int l = 0; l <= L; ++l) idx[l] = id[l];
+        *c_fs = best * best;
+        if (ms) *ms = t;
     });
 }
 
