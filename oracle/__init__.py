@@ -22,6 +22,9 @@ Multilevel Monte Carlo for Disconnected Diagrams in Lattice QCD"):
                 (Sec. 2.2-2.3, eqs. tele_sum_prod_disp, phi_prod, phi_single,
                 fs_trace_est, practical_variance, total_var, tosv), and the
                 variance-sampling phase with shared noise (Sec. 3.1).
+* `probing`  -- displacement-p distance-k probing colourings and the FS
+                estimator with full spin-colour dilution (Background,
+                Probing; Sec. 3.1 and 3.4).
 * `shifts`   -- shift selection: PCHIP interpolation of the sampled variances
                 in log space, the iteration-count cost model and the argmin of
                 the multilevel cost over the evaluation set (Sec. 3.2-3.3,
