@@ -288,6 +288,43 @@ fs_status fs_time_dslash(fs_ctx ctx, fs_prec storage, int32_t n_sys, int32_t rhs
  */
 fs_status fs_time_copy(fs_ctx ctx, uint64_t bytes, int32_t n_launch, double* avg_ms);
 
+/* ------------------------------------------------------------------ probing and dilution
+ * Paper Background (Probing) and Sec. 3.1/3.4: probing vectors from a
+ * displacement-p distance-k colouring, combined with Z4 noise and full
+ * spin-colour dilution.
+ */
+
+/*
+ * fs_probing_colours -- greedy colouring of the symmetric part of Pi_p A^k:
+ * sites x != y conflict when y lies within periodic taxicab distance k of
+ * x + p z^ or of x - p z^; sites are visited in index order
+ * (site = x + Lx (y + Ly (z + Lz t))) and take the smallest colour no earlier
+ * conflicting site holds.  Host only.
+ *   dims       Lx, Ly, Lz, Lt (each >= 2, volume <= 2^26);  0 <= p < Lz;  0 <= k <= 16
+ *   colours    host [volume]: colour per site, 0..n_colours-1
+ */
+fs_status fs_probing_colours(const int32_t dims[4], int32_t p, int32_t k, int32_t* colours, int32_t* n_colours);
+
+/*
+ * fs_estimate_probed -- fs_estimate with probing and full spin-colour
+ * dilution.  Sample s of level l sums over the 12 n_colours sources
+ *   z^(j,a)(x, b) = xi(x, a) if colours[x] = j and b = a, else 0
+ * (a = spin-colour index 3 spin + colour, xi the Z4 vector of key (seed,
+ * instance, l, s)):
+ *   level l < L:  X = sum_{j,a} (sigma_{l+1}-sigma_l) y^+ Gamma_n Omega_p x,
+ *                 x = (D+sigma_{l+1})^-1 z, y = s_a g5 (D+sigma_l)^-1 z
+ *                 (s_a = +1 for spins 0, 1 and -1 for spins 2, 3: g5 z = s_a z)
+ *   level L:      X = sum_{j,a} z^+ Gamma_n Omega_p (D+sigma_L)^-1 z
+ * so each sample costs 12 n_colours (2L+1) solves, all in one batch.
+ *   colours      host [volume], values 0..n_colours-1, every colour used (1 <= n_colours <= 4096)
+ *   out, samples_out, report as for fs_estimate (samples_out holds the per-sample sums)
+ * FS_E_ARG for invalid arguments (before any device work); FS_E_NOCONV if a
+ * solve missed tol (outputs still filled).
+ */
+fs_status fs_estimate_probed(fs_ctx ctx, const fs_est_params* prm, const double* sigma, int32_t L,
+                             const int32_t* colours, int32_t n_colours, fs_level_stat* out, double* samples_out,
+                             fs_est_report* report);
+
 /* ------------------------------------------------------------------ shift selection
  * Paper Sec. 3.2-3.3.  The sampled variances and iteration counts of
  * fs_sample_variances (one Gamma_n, p) are carried to an evaluation set s by

@@ -100,6 +100,10 @@ _sig = {
     "fs_time_dslash": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "fs_time_copy": (C.c_int, [_P, C.c_uint64, C.c_int32, C.POINTER(C.c_double)]),
+    "fs_probing_colours": (C.c_int, [C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32)]),
+    "fs_estimate_probed": (C.c_int, [_P, C.POINTER(fs_est_params), _P, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                                     C.POINTER(fs_level_stat), _P, C.POINTER(fs_est_report)]),
     "fs_eval_grid": (C.c_int, [_DP, C.c_int32, _DP, C.c_int32, C.POINTER(C.c_int32)]),
     "fs_shift_tables": (C.c_int, [C.POINTER(fs_shift_model), _DP, _DP, _DP]),
     "fs_select_shifts": (C.c_int, [C.POINTER(fs_shift_model), C.c_int32, C.POINTER(C.c_int32), _DP, _DP, _DP]),
@@ -392,3 +396,32 @@ def fs_sweep_shifts(ctx, model, L):
     ms = C.c_double()
     _check(_lib.fs_sweep_shifts(ctx, C.byref(model.c), int(L), idx, C.byref(c), C.byref(ms)))
     return tuple(idx), c.value, ms.value
+
+
+# ---------------------------------------------------------------- probing and dilution
+
+def fs_probing_colours(dims, p, k):
+    """(colour per site [V] int32, number of colours)."""
+    d = (C.c_int32 * 4)(*[int(v) for v in dims])
+    V = int(np.prod(dims))
+    col = np.zeros(V, dtype=np.int32)
+    nc = C.c_int32()
+    _check(_lib.fs_probing_colours(d, int(p), int(k), col.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(nc)))
+    return col, nc.value
+
+
+def fs_estimate_probed(ctx, params, sigma, colours, want_samples=False, allow_noconv=False):
+    """As fs_estimate, with probing colours [V] and full spin-colour dilution."""
+    sig = np.ascontiguousarray(sigma, dtype=np.float64)
+    col = np.ascontiguousarray(colours, dtype=np.int32)
+    L = len(sig) - 1
+    P1 = params.p_max + 1
+    out = (fs_level_stat * ((L + 1) * 16 * P1))()
+    samples = np.zeros((L + 1, params.n_noise, 16, P1), dtype=np.complex128) if want_samples else None
+    rep = fs_est_report()
+    n_col = int(col.max()) + 1 if col.size else 0
+    code = _lib.fs_estimate_probed(ctx, C.byref(params), C.c_void_p(sig.ctypes.data), L,
+                                   col.ctypes.data_as(C.POINTER(C.c_int32)), n_col, out,
+                                   C.c_void_p(samples.ctypes.data) if want_samples else None, C.byref(rep))
+    _check(code, allow=(FS_E_NOCONV,) if allow_noconv else ())
+    return _stats_array(list(out), (L + 1, 16, P1)), samples, rep

@@ -21,6 +21,7 @@
 
 #include "../../include/fsmlmc.h"
 #include "fs_kernels.h"
+#include "fs_probe.h"
 #include "fs_shift.h"
 
 using namespace fs;
@@ -944,6 +945,207 @@ void run_units(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm, con
     }
 }
 
+// FS estimate with probing and full spin-colour dilution (paper Background,
+// Probing; Sec. 3.1 and 3.4).  Each sample s of level l uses D = 12 c sources:
+// the Z4 vector of key (seed, instance, l, s) restricted to one probing colour
+// j and one spin-colour component a.  A spin-diluted source is a g5
+// eigenvector (g5 z = s_a z), so y_l = (D + sigma_l)^-dagger z = s_a g5 x' with
+// x' = (D + sigma_l)^-1 z: level l < L solves each source at sigma_l and
+// sigma_{l+1}, level L at sigma_L.  Systems are grouped per (level, role), the
+// D sources of a sample consecutive, so an x-block and its y-block hold the
+// same sources.  The shadow residual of every system is the undiluted Z4
+// vector of its key, whose inner product with the source is the source's norm.
+// Per-system estimates are summed over the D sources in a fixed order.
+void probed_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sigma_in, int L, const int32_t* colours,
+                 int n_col, fs_level_stat* out, double* samples_out, fs_est_report* report) {
+    if (!prm || !sigma_in || !out || !colours) fail(FS_E_ARG, "null argument");
+    if (L < 0) fail(FS_E_ARG, "L must be >= 0");
+    if (prm->n_noise < 1) fail(FS_E_ARG, "n_noise must be >= 1");
+    if (prm->p_max < 0 || prm->p_max >= c->dims[2]) fail(FS_E_ARG, "p_max must be in [0, Lz)");
+    check_prec(prm->solve.storage);
+    if (!(prm->solve.tol > 0)) fail(FS_E_ARG, "tol must be > 0");
+    if (prm->solve.max_iter < 1) fail(FS_E_ARG, "max_iter must be >= 1");
+    if (prm->solve.rhs_block != 0 && !pow2_ok(prm->solve.rhs_block)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
+    if (n_col < 1 || n_col > 4096) fail(FS_E_ARG, "n_colours must be in 1..4096");
+    std::vector<double> sigma(sigma_in, sigma_in + L + 1);
+    if (sigma[0] != 0.0) fail(FS_E_ARG, "sigma[0] must be 0");
+    for (int l = 0; l < L; ++l)
+        if (!(sigma[l + 1] > sigma[l])) fail(FS_E_ARG, "sigma must be strictly increasing");
+    const long long V = (long long)c->dims[0] * c->dims[1] * c->dims[2] * c->dims[3];
+    std::vector<uint16_t> col16(V);
+    std::vector<char> seen(n_col, 0);
+    for (long long i = 0; i < V; ++i) {
+        if (colours[i] < 0 || colours[i] >= n_col) fail(FS_E_ARG, "colour out of range");
+        col16[i] = (uint16_t)colours[i];
+        seen[colours[i]] = 1;
+    }
+    for (int j = 0; j < n_col; ++j)
+        if (!seen[j]) fail(FS_E_ARG, "every colour must hold at least one site");
+    auto t0 = std::chrono::steady_clock::now();
+    DeviceScope ds(c->device);
+    hipStream_t s = c->stream;
+    const int N = prm->n_noise, P1 = prm->p_max + 1, P = prm->solve.storage, D = 12 * n_col;
+    const long long per_group = (long long)N * D;
+    const int nr = prm->solve.rhs_block ? prm->solve.rhs_block : tuned_nr(c, P, (int)std::min<long long>(per_group, 1 << 20));
+    const int nbg = (int)((per_group + nr - 1) / nr);  // blocks per (level, role) group
+    // groups: level l: x (shift sigma_{l+1}, or sigma_L on the last level), then y (sigma_l) for l < L
+    std::vector<int> gx(L + 1), gy(L + 1, -1);
+    int ngroups = 0;
+    for (int l = 0; l <= L; ++l) {
+        gx[l] = ngroups++;
+        if (l < L) gy[l] = ngroups++;
+    }
+    const long long nblk_ll = (long long)ngroups * nbg;
+    if (nblk_ll * nr > (1ll << 24)) fail(FS_E_ARG, "too many diluted systems for one batch");
+    const int nblk = (int)nblk_ll;
+    std::vector<int> blk_lat(nblk, 0);
+    std::vector<fs_ctx_s*> lats{c};
+    auto pl = make_plan(blk_lat, lats, nr, tuned_wg(c, P), s, tuned_ilp(c, P), tuned_occ(c, P));
+    const int nsys = pl->nsys;
+    std::vector<double> diag(nsys);
+    std::vector<char> idle(nsys);
+    std::vector<NoiseKey> keys(nsys), rkeys(nsys);
+    std::vector<XMap> xm(nsys);
+    std::vector<int> sys_level(nsys, -1);
+    for (int l = 0; l <= L; ++l)
+        for (int role = 0; role < 2; ++role) {
+            const int g = role == 0 ? gx[l] : gy[l];
+            if (g < 0) continue;
+            const double shift = role == 0 ? sigma[l < L ? l + 1 : L] : sigma[l];
+            for (long long q = 0; q < (long long)nbg * nr; ++q) {
+                const int sys = (int)((long long)g * nbg * nr + q);
+                const bool real = q < per_group;
+                const int smp = real ? (int)(q / D) : 0, d = real ? (int)(q % D) : 0;
+                diag[sys] = 4.0 + prm->solve.m0 + shift;
+                idle[sys] = !real;
+                NoiseKey k;
+                std::memset(&k, 0, sizeof(k));
+                k.seed = prm->seed;
+                k.instance = c->instance;
+                k.level = (uint32_t)l;
+                k.sample = (uint64_t)smp;
+                k.pad = real ? 0 : 1;
+                rkeys[sys] = k;  // shadow residual: the undiluted Z4 vector
+                k.dil = 1 + d;
+                keys[sys] = k;
+                XMap mp;
+                std::memset(&mp, 0, sizeof(mp));
+                mp.level = -1;
+                if (role == 0 && real) {
+                    const int a = d % 12;
+                    const double sa = (a / 3) < 2 ? 1.0 : -1.0;  // g5 eigenvalue of the source's spin
+                    mp.level = sys;  // one slot per system; summed over the D sources below
+                    mp.sample = 0;
+                    mp.g5 = l < L ? 1 : 0;
+                    mp.coef = l < L ? (sigma[l + 1] - sigma[l]) * sa : 1.0;
+                    sys_level[sys] = l;
+                }
+                xm[sys] = mp;
+            }
+        }
+    SolveOpts o;
+    o.P = P;
+    o.tol = prm->solve.tol;
+    o.max_iter = prm->solve.max_iter;
+    o.delta = P == P64 ? 0.0 : (prm->solve.reliable_delta > 0 ? prm->solve.reliable_delta : default_delta(P));
+    o.check_every = prm->solve.check_every > 0 ? prm->solve.check_every : 8;
+    o.use_graph = prm->solve.use_graph != 0;
+    BatchSolver bs(*pl, lats, s, o);
+    bs.setup(diag, idle, rkeys);
+    DevBuf d_keys = to_device(keys.data(), sizeof(NoiseKey) * nsys, 0, s);
+    DevBuf d_col = to_device(col16.data(), sizeof(uint16_t) * V, 0, s);
+    launch_noise_block(P64, pl->work(P64, false), bs.b.f(), d_keys.as<NoiseKey>(), s, d_col.as<uint16_t>());
+    bs.run();
+
+    // bilinears: x-blocks only, paired with the y-block of the same sources (or their own source on level L)
+    static const GammaTab gt = make_gamma_tab();
+    std::vector<int> yb(2 * nblk, -1), hop_start(nblk + 1, 0);
+    for (int l = 0; l <= L; ++l)
+        for (int b = 0; b < nbg; ++b) {
+            const int xb = gx[l] * nbg + b;
+            if (l < L) {
+                yb[2 * xb] = gy[l] * nbg + b;
+                yb[2 * xb + 1] = 1;
+            }
+        }
+    std::vector<char> is_x_group(ngroups, 0);
+    for (int l = 0; l <= L; ++l) is_x_group[gx[l]] = 1;
+    for (int b = 0; b < nblk; ++b)
+        hop_start[b + 1] = hop_start[b] + (is_x_group[b / nbg] ? pl->wg_start[b + 1] - pl->wg_start[b] : 0);
+    DevBuf d_hop_start = to_device(hop_start.data(), sizeof(int) * (nblk + 1), 0, s);
+    DevBuf d_yb = to_device(yb.data(), sizeof(int) * 2 * nblk, 0, s);
+    DevBuf d_xm = to_device(xm.data(), sizeof(XMap) * nsys, 0, s);
+    Work wh = pl->work(P64, false);
+    wh.wg_start = d_hop_start.as<int>();
+    wh.total_wg = hop_start.back();
+    DevBuf d_M(sizeof(double) * (size_t)nsys * P1 * 32);
+    Field phi1;
+    phi1.alloc(P64, pl->total_slots);
+    Fld cur = bs.xhi.f();
+    for (int p = 0; p <= prm->p_max; ++p) {
+        Fld outf = (p % 2 == 1) ? bs.rhi.f() : phi1.f();
+        launch_hop_reduce(wh, p, outf, cur, bs.xhi.f(), bs.b.f(), d_yb.as<int>(), bs.part(), s);
+        launch_hop_finish(wh, bs.part(), d_M.as<double>(), P1, p, s);
+        if (p > 0) cur = outf;
+    }
+    DevBuf d_Y(sizeof(double) * 2 * (size_t)nsys * 16 * P1);
+    launch_gamma_contract(d_M.as<double>(), P1, nsys, d_xm.as<XMap>(), gt, d_Y.as<double>(), 1, s);
+    std::vector<int> g0((size_t)(L + 1) * N);
+    for (int l = 0; l <= L; ++l)
+        for (int smp = 0; smp < N; ++smp) g0[(size_t)l * N + smp] = gx[l] * nbg * nr + smp * D;
+    DevBuf d_g0 = to_device(g0.data(), sizeof(int) * g0.size(), 0, s);
+    const size_t xsz = (size_t)(L + 1) * N * 16 * P1 * 2;
+    DevBuf d_X(sizeof(double) * xsz);
+    launch_dilution_sum(d_Y.as<double>(), P1, d_g0.as<int>(), (L + 1) * N, D, d_X.as<double>(), s);
+    DevBuf d_st(sizeof(double) * (size_t)(L + 1) * 16 * P1 * 4);
+    launch_level_stats(d_X.as<double>(), L + 1, N, P1, d_st.as<double>(), s);
+    std::vector<double> stv((size_t)(L + 1) * 16 * P1 * 4), X(xsz);
+    HC(hipMemcpyAsync(stv.data(), d_st.p, sizeof(double) * stv.size(), hipMemcpyDeviceToHost, s));
+    HC(hipMemcpyAsync(X.data(), d_X.p, sizeof(double) * xsz, hipMemcpyDeviceToHost, s));
+    HC(hipGetLastError());
+    HC(hipStreamSynchronize(s));
+
+    fs_est_report rep;
+    std::memset(&rep, 0, sizeof(rep));
+    std::vector<double> level_res(L + 1, 0.0);
+    bool noconv = false;
+    for (int l = 0; l <= L; ++l)
+        for (int role = 0; role < 2; ++role) {
+            const int g = role == 0 ? gx[l] : gy[l];
+            if (g < 0) continue;
+            for (long long q = 0; q < per_group; ++q) {
+                const SysState& S = bs.st_host[(size_t)g * nbg * nr + q];
+                rep.systems += 1;
+                rep.iterations += S.iters;
+                rep.reliable_updates += S.n_rel;
+                const double rel = S.bb > 0 ? std::sqrt(S.rr_true / S.bb) : 0.0;
+                level_res[l] = std::max(level_res[l], rel);
+                rep.max_rel_residual = std::max(rep.max_rel_residual, rel);
+                if (S.state != S_DONE) noconv = true;
+            }
+        }
+    rep.dslash_calls = bs.dslash_calls;
+    const uint16_t mask = prm->gamma_mask ? prm->gamma_mask : 0xffff;
+    for (int l = 0; l <= L; ++l)
+        for (int n = 0; n < 16; ++n)
+            for (int p = 0; p < P1; ++p) {
+                fs_level_stat& ostat = out[((size_t)l * 16 + n) * P1 + p];
+                std::memset(&ostat, 0, sizeof(ostat));
+                if (!((mask >> n) & 1)) continue;
+                const double* d = &stv[(((size_t)l * 16 + n) * P1 + p) * 4];
+                ostat.tr_re = d[0];
+                ostat.tr_im = d[1];
+                ostat.var_paper = d[2];
+                ostat.var_unbiased = d[3];
+                ostat.n = N;
+                ostat.max_rel_residual = level_res[l];
+            }
+    if (samples_out) std::memcpy(samples_out, X.data(), sizeof(double) * xsz);
+    rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (report) *report = rep;
+    if (noconv) throw FsError(FS_E_NOCONV, "a shifted solve did not reach tol (outputs are filled)");
+}
+
 // Variance sampling (paper Sec. 3.1, "Sampling the Variance").  One Z4
 // vector per sample, shared by every sampling shift (noise level field
 // kSamplingLevel); per shift s_i an x-system on z and a y-system on g5 z,
@@ -1731,6 +1933,35 @@ fs_status fs_sweep_shifts(fs_ctx c, const fs_shift_model* model, int32_t L, int3
         for (int l = 0; l <= L; ++l) idx[l] = id[l];
         *c_fs = best * best;
         if (ms) *ms = t;
+    });
+}
+
+fs_status fs_probing_colours(const int32_t dims[4], int32_t p, int32_t k, int32_t* colours, int32_t* n_colours) {
+    return guard([&] {
+        if (!dims || !colours || !n_colours) fail(FS_E_ARG, "null argument");
+        int d[4];
+        long long V = 1;
+        for (int i = 0; i < 4; ++i) {
+            if (dims[i] < 2) fail(FS_E_ARG, "every extent must be >= 2");
+            d[i] = dims[i];
+            V *= dims[i];
+        }
+        if (V > (1ll << 26)) fail(FS_E_ARG, "lattice too large for the colouring");
+        if (p < 0 || p >= dims[2]) fail(FS_E_ARG, "p must be in [0, Lz)");
+        if (k < 0 || k > 16) fail(FS_E_ARG, "k must be in 0..16");
+        int nc = 0;
+        const std::vector<int32_t> col = probing_colours(d, p, k, &nc);
+        std::copy(col.begin(), col.end(), colours);
+        *n_colours = nc;
+    });
+}
+
+fs_status fs_estimate_probed(fs_ctx c, const fs_est_params* prm, const double* sigma, int32_t L,
+                             const int32_t* colours, int32_t n_colours, fs_level_stat* out, double* samples_out,
+                             fs_est_report* report) {
+    return guard([&] {
+        check_ctx(c);
+        probed_impl(c, prm, sigma, L, colours, n_colours, out, samples_out, report);
     });
 }
 

@@ -601,7 +601,8 @@ __global__ void k_gauge_convert_q(uint4* __restrict__ dst, const double* __restr
 // ------------------------------------------------------------------ Z4 noise
 
 template <int P>
-__global__ void __launch_bounds__(256) k_noise_block(Work w, Fld dst, const NoiseKey* __restrict__ keys) {
+__global__ void __launch_bounds__(256) k_noise_block(Work w, Fld dst, const NoiseKey* __restrict__ keys,
+                                                     const uint16_t* __restrict__ colour) {
     using A = typename Tr<P>::acc;
     FS_WG_PROLOGUE(w)
     FS_SLOT_LOOP(w)
@@ -613,6 +614,13 @@ __global__ void __launch_bounds__(256) k_noise_block(Work w, Fld dst, const Nois
             for (int j = 0; j < 24; ++j) v[j] = 0.0;
         } else {
             z4_site(k, site, v);
+            if (k.dil > 0) {  // diluted: one probing colour, one spin-colour component
+                const int d = k.dil - 1;
+                const bool on = (int)colour[site] == d / 12;
+#pragma unroll
+                for (int j = 0; j < 12; ++j)
+                    if (!on || j != d % 12) v[2 * j] = v[2 * j + 1] = 0.0;
+            }
         }
         A q[24];
 #pragma unroll
@@ -773,6 +781,23 @@ __global__ void k_gamma_contract(const double* __restrict__ M, int P1, int nsys,
 
 // Per (level, n, p): mean and the variance of eq. practical_variance over the
 // samples, summed in sample order (FP64).
+// Sum of the per-system estimates of the D diluted sources of each sample.
+__global__ void k_dilution_sum(const double* __restrict__ Y, int P1, const int* __restrict__ g0, int G, int D,
+                               double* __restrict__ X) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = 16 * P1;
+    if (i >= G * per) return;
+    const int g = i / per, np = i % per;
+    const double* y = Y + 2 * ((size_t)g0[g] * per + np);
+    double re = 0.0, im = 0.0;
+    for (int d = 0; d < D; ++d) {
+        re += y[2 * (size_t)d * per];
+        im += y[2 * (size_t)d * per + 1];
+    }
+    X[2 * (size_t)i] = re;
+    X[2 * (size_t)i + 1] = im;
+}
+
 __global__ void k_level_stats(const double* __restrict__ X, int L1, int n_noise, int P1, double* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L1 * 16 * P1) return;
@@ -890,8 +915,10 @@ void launch_gauge_convert_q(int prec, void* dst, const double* src, int V, hipSt
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_gauge_convert_q<PP>, dim3((n + 255) / 256), dim3(256), 0, s,
                                            static_cast<uint4*>(dst), src, V))
 }
-void launch_noise_block(int prec, const Work& w, Fld dst, const NoiseKey* keys, hipStream_t s) {
-    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_noise_block<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, dst, keys))
+void launch_noise_block(int prec, const Work& w, Fld dst, const NoiseKey* keys, hipStream_t s,
+                        const uint16_t* colour) {
+    FS_DISPATCH_P(prec,
+                  hipLaunchKernelGGL(k_noise_block<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, dst, keys, colour))
 }
 void launch_noise_canonical(double* dst, int V, NoiseKey key, hipStream_t s) {
     hipLaunchKernelGGL(k_noise_canonical, dim3((V + 255) / 256), dim3(256), 0, s, dst, V, key);
@@ -910,6 +937,10 @@ void launch_gamma_contract(const double* M, int P1, int nsys, const XMap* xm, co
                            int n_noise, hipStream_t s) {
     const int n = nsys * P1 * 16;
     hipLaunchKernelGGL(k_gamma_contract, dim3((n + 255) / 256), dim3(256), 0, s, M, P1, nsys, xm, gt, X, n_noise);
+}
+void launch_dilution_sum(const double* Y, int P1, const int* g0, int G, int D, double* X, hipStream_t s) {
+    const int n = G * 16 * P1;
+    hipLaunchKernelGGL(k_dilution_sum, dim3((n + 255) / 256), dim3(256), 0, s, Y, P1, g0, G, D, X);
 }
 void launch_level_stats(const double* X, int L1, int n_noise, int P1, double* out, hipStream_t s) {
     const int n = L1 * 16 * P1;

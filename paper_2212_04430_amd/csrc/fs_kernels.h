@@ -107,6 +107,9 @@ struct NoiseKey {
     uint64_t sample;
     int g5;        // apply gamma_5 to the vector
     int pad;       // padding system: the zero vector
+    int dil;       // 0: the whole Z4 vector; 1 + 12 j + a: only the sites of probing colour j,
+                   // only spin-colour component a (spin a / 3, colour a % 3)
+    int resv;
 };
 
 // The 12 components of `site` for key k: z_c = i^code(c), optionally times g5
@@ -205,7 +208,9 @@ void launch_unpack(int prec, const Work& w, double* dst, Fld src, long long sys_
 void launch_gauge_convert(int prec, void* dst, const double* src, int V, hipStream_t s);
 void launch_gauge_convert_q(int prec, void* dst, const double* src, int V, hipStream_t s);
 
-void launch_noise_block(int prec, const Work& w, Fld dst, const NoiseKey* keys /* per system */, hipStream_t s);
+// colour: per-site probing colour (only read for diluted keys; may be null otherwise)
+void launch_noise_block(int prec, const Work& w, Fld dst, const NoiseKey* keys /* per system */, hipStream_t s,
+                        const uint16_t* colour = nullptr);
 void launch_noise_canonical(double* dst, int V, NoiseKey key, hipStream_t s);
 
 // Displacement + bilinear (FP64).  For each block b (the "x" block) with
@@ -235,6 +240,8 @@ struct GammaTab {      // Gamma_n row a: single nonzero i^ph[n][a] at column per
 void launch_gamma_contract(const double* M, int P1, int nsys, const XMap* xm, const GammaTab& gt, double* X,
                            int n_noise, hipStream_t s);
 void launch_level_stats(const double* X, int L1, int n_noise, int P1, double* out, hipStream_t s);
+// X[g][16][P1] = sum_{d < D} Y[g0[g] + d][16][P1] (complex), summed in order d = 0..D-1
+void launch_dilution_sum(const double* Y, int P1, const int* g0, int G, int D, double* X, hipStream_t s);
 void launch_blk_mask(const Work& w, const SysState* st, int mask, int* blk_on, hipStream_t s);
 // list of blocks with flags[b] != 0; wg_tile / wg_sten: the two workgroup tables of the plan
 void launch_vlist(const int* flags, int nblk, const int* wg_tile, const int* wg_sten, VList out, hipStream_t s);
