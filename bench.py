@@ -146,6 +146,24 @@ def roofline_only(L, ctx, nr, wg):
                       "config": f"f32 nsys={ROOFLINE_NSYS} nr={nr} wg={wg}", "hash": kernel_source_hash()}))
 
 
+def probed_estimate(L, ctx, nr, dims):
+    """FS estimate with p8k7 probing and full spin-colour dilution (the paper's
+    choice, Sec. 3.4) on the workload lattice: 2 Z4 vectors, shifts {0, 0.25},
+    FP32 storage; 12 x colours x 3 solves per vector."""
+    t0 = time.perf_counter()
+    col, nc = L.fs_probing_colours(dims, 8, 7)
+    dt_c = time.perf_counter() - t0
+    prm = est_params(L, "f32", 1, 2, nr=nr)
+    t1 = time.perf_counter()
+    _, _, rep = L.fs_estimate_probed(ctx, prm, [0.0, 0.25], col)
+    dt = time.perf_counter() - t1
+    log(f"probed estimate: {nc} colours ({dt_c:.2f} s), {rep.systems} systems in {dt:.2f} s")
+    return {"probing": "p8k7", "colours": nc, "colouring_seconds": round(dt_c, 3), "noise_vectors": 2,
+            "shifts": [0.0, 0.25], "systems": int(rep.systems), "seconds": round(dt, 3),
+            "solves_per_s": round(rep.systems / dt, 2), "iters_per_system": round(rep.iterations / rep.systems, 2),
+            "max_true_rel_residual": rep.max_rel_residual}
+
+
 def sampling_and_selection(L, ctx, nr):
     """Variance sampling on the paper's sampling set with N_s = 5 (Sec. 3.1), then
     shift selection with six shifts (Sec. 3.2-3.3) for every (Gamma_n, p) on the
@@ -196,6 +214,7 @@ def main():
     ap.add_argument("--no-half", action="store_true", help="skip the FP16/BF16 mixed-path steps")
     ap.add_argument("--roofline-only", action="store_true", help="only the copy and stencil launches of the roofline")
     ap.add_argument("--no-select", action="store_true", help="skip variance sampling and shift selection")
+    ap.add_argument("--no-probe", action="store_true", help="skip the probed, spin-colour diluted estimate")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the hot path shards over independent systems "
@@ -290,6 +309,7 @@ def main():
                 "copy_kernel_GBs": round(2 * (1 << 30) / (ms_c * 1e-3) / 1e9, 1)}
     log(f"dslash f32 batched: {ms_d:.4f} ms, {achieved:.0f} GB/s")
     select, sel_inputs = (None, None) if args.no_select else sampling_and_selection(L, ctx, nr)
+    probed = None if args.no_probe else probed_estimate(L, ctx, nr, dims)
     L.fs_destroy(ctx)
 
     # ---- 32^3 x 64 single-RHS dslash (working set >> 256 MB)
@@ -347,6 +367,7 @@ def main():
         "dslash_32c64_single_rhs": headline,
         "mixed_half_precision": half or None,
         "sampling_and_shift_selection": select,
+        "probed_diluted_estimate": probed,
     }
     print(json.dumps(out), flush=True)
 
