@@ -46,10 +46,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def est_params(L, storage, batched, n_noise, nr=0, graph=1):
+def est_params(L, storage, batched, n_noise, nr=0, graph=1, eo=0):
     w = WORKLOAD
     sp = L.solve_params(w["m0"], tol=w["tol"], storage=storage, batched=batched, rhs_block=nr, use_graph=graph,
-                        max_iter=20000)
+                        max_iter=20000, even_odd=eo)
     return L.fs_est_params(w["seed"], n_noise, 0, w["p_max"], sp)
 
 

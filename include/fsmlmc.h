@@ -134,6 +134,10 @@ typedef struct {
     double reliable_delta; /* mixed: FP64 reliable update when ||r|| drops by this  */
     int32_t check_every;   /* iterations between host convergence checks (0 = 8)    */
     int32_t batched;       /* 0: one system at a time; 1: all systems in one batch  */
+    int32_t even_odd;      /* 1: even-odd preconditioning (every extent even): the
+                              Krylov solver works on the even-site Schur complement
+                              S = a - D_eo D_oe / a (a = 4 + m0 + sigma) and the
+                              odd sites follow; the stopping rule is unchanged    */
 } fs_solve_params;
 
 typedef struct {

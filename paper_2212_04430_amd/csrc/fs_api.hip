@@ -263,10 +263,12 @@ struct DeviceScope {
     }
 };
 
-LatDesc lat_desc(const fs_ctx_s* c, int P) {
+LatDesc lat_desc(const fs_ctx_s* c, int P, int eo = 0) {
     LatDesc d;
     for (int i = 0; i < 4; ++i) d.L[i] = c->dims[i];
     d.V = c->V;
+    d.Vf = eo ? c->V / 2 : c->V;
+    d.eo = eo;
     d.tsign = c->tsign;
     d.gauge = c->gauge[P].p;
     d.gauge_q = c->gauge_q[P].p;
@@ -288,6 +290,7 @@ bool pow2_ok(int n) { return n >= 1 && n <= 16 && (n & (n - 1)) == 0; }
 // A batch of blocks (each NR systems of one lattice) mapped to workgroups.
 struct Plan {
     int nr = 1, lognr = 0, wg = 256, tpw = 1;
+    int eo = 0;                       // 1: fields of one parity (V/2 sites per system)
     int ilp = 0, occ = 0;             // stencil variant and residency cap
     int tl[3] = {0, 0, 0};            // stencil variant 2: log2 tile extents
     int nsys = 0;                     // nblk * nr
@@ -379,9 +382,10 @@ static bool choose_tile(int sites, const std::vector<fs_ctx_s*>& lats, int tl[3]
 // Work tables for a given list of blocks (each block keeps its system ids and
 // field offsets, so a plan over a subset of a batch shares the batch's fields).
 std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, const std::vector<fs_ctx_s*>& lats,
-                                       int nr, int wg, hipStream_t s, int ilp, int occ) {
+                                       int nr, int wg, hipStream_t s, int ilp, int occ, int eo = 0) {
     auto pl = std::make_unique<Plan>();
     pl->nr = nr;
+    pl->eo = eo;
     pl->ilp = ilp;
     pl->occ = occ;
     pl->lognr = ilog2(nr);
@@ -394,7 +398,7 @@ std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, con
     long long tiles_total = 0;
     std::vector<long long> tiles(nblk);
     for (int b = 0; b < nblk; ++b) {
-        const long long slots = (long long)lats[blocks[b].lat]->V * nr;
+        const long long slots = (long long)(lats[blocks[b].lat]->V >> eo) * nr;
         tiles[b] = (slots + wg - 1) / wg;
         tiles_total += tiles[b];
         pl->total_slots = std::max(pl->total_slots, blocks[b].slot_off + slots);
@@ -443,7 +447,7 @@ std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, con
     HC(hipMemcpyAsync(pl->d_blk_on.p, ones.data(), sizeof(int) * nb1, hipMemcpyHostToDevice, s));
     std::vector<LatDesc> ld[4];
     for (int P = 0; P < 4; ++P) {
-        for (auto* c : lats) ld[P].push_back(lat_desc(c, P));
+        for (auto* c : lats) ld[P].push_back(lat_desc(c, P, eo));
         pl->d_lats[P].alloc(sizeof(LatDesc) * ld[P].size());
         HC(hipMemcpyAsync(pl->d_lats[P].p, ld[P].data(), sizeof(LatDesc) * ld[P].size(), hipMemcpyHostToDevice, s));
     }
@@ -453,16 +457,35 @@ std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, con
 
 // A batch of blocks: block b holds systems b*nr .. b*nr+nr-1 of lattice blk_lat[b].
 std::unique_ptr<Plan> make_plan(const std::vector<int>& blk_lat, const std::vector<fs_ctx_s*>& lats, int nr, int wg,
-                                hipStream_t s, int ilp = 0, int occ = 0) {
+                                hipStream_t s, int ilp = 0, int occ = 0, int eo = 0) {
     std::vector<BlockDesc> blocks(blk_lat.size());
     long long off = 0;
     for (size_t b = 0; b < blk_lat.size(); ++b) {
         blocks[b].lat = blk_lat[b];
         blocks[b].sys0 = (int)b * nr;
         blocks[b].slot_off = off;
-        off += (long long)lats[blk_lat[b]]->V * nr;
+        off += (long long)(lats[blk_lat[b]]->V >> eo) * nr;
     }
-    return plan_from_blocks(blocks, lats, nr, wg, s, ilp, occ);
+    return plan_from_blocks(blocks, lats, nr, wg, s, ilp, occ, eo);
+}
+
+// The one-parity plan of a full-lattice plan: the same blocks and systems, each
+// block holding V/2 sites (even-odd preconditioning).
+std::unique_ptr<Plan> eo_plan_of(const Plan& full, const std::vector<fs_ctx_s*>& lats, hipStream_t s) {
+    std::vector<BlockDesc> blocks = full.blocks;
+    long long off = 0;
+    for (auto& bd : blocks) {
+        bd.slot_off = off;
+        off += (long long)(lats[bd.lat]->V / 2) * full.nr;
+    }
+    return plan_from_blocks(blocks, lats, full.nr, full.wg, s, 0, 0, 1);
+}
+
+// FP64 true residual of a system relative to its source (the full system's
+// source under even-odd preconditioning).
+double true_rel(const SysState& S) {
+    const double d = S.bnorm2 > 0.0 ? S.bnorm2 : S.bb;
+    return d > 0.0 ? std::sqrt(S.rr_true / d) : 0.0;
 }
 
 // A block-layout field over a whole plan.
@@ -497,18 +520,25 @@ struct SolveOpts {
     double delta = 0.0;
     int check_every = 8;
     bool use_graph = false;
+    bool eo = false;  // even-odd preconditioning
 };
 
 // Systems of a plan, with sources in `b` (FP64 block layout) and per-system
 // shifts.  On return xhi holds the solutions and `st_host` the final states.
+// With even-odd preconditioning the Krylov iteration runs on a one-parity plan
+// of the same blocks: sb_ = b_e - D_eo b_o / a, the Schur system S x_e = sb_,
+// then x = (x_e, (b_o - D_oe x_e) / a) in xhi.  b, xhi and rhi stay full-lattice.
 struct BatchSolver {
-    Plan& pl;                    // the whole batch (fields, states, system ids)
+    Plan& full;                  // the caller's plan (layout of b, xhi, rhi)
+    std::unique_ptr<Plan> eo_pl; // its one-parity plan (even-odd only)
+    Plan& pl;                    // the plan the iteration runs on (fields, states, system ids)
     Plan* cur;                   // the blocks still iterating (pl, or a compacted sub-plan)
     std::unique_ptr<Plan> sub;
     std::vector<fs_ctx_s*> lats;
     hipStream_t s;
     SolveOpts o;
     Field b, xhi, rhi, r, p, v, t, xlo;
+    Field sb_, sx_, sr_, tmp, tmp64;  // even-odd: FP64 Schur b, x, r; odd-site scratch
     DevBuf d_diag, d_st, d_part, d_flags, d_rkeys, d_vl;
     VList vl_run, vl_pend, vl_conv;
     std::vector<SysState> st_host;
@@ -516,16 +546,22 @@ struct BatchSolver {
     size_t part_rows = 0;
 
     BatchSolver(Plan& plan, const std::vector<fs_ctx_s*>& l, hipStream_t stream, const SolveOpts& opts)
-        : pl(plan), cur(&plan), lats(l), s(stream), o(opts) {
+        : full(plan), eo_pl(opts.eo ? eo_plan_of(plan, l, stream) : nullptr), pl(opts.eo ? *eo_pl : plan),
+          cur(&pl), lats(l), s(stream), o(opts) {
         const long long S = pl.total_slots;
-        b.alloc(P64, S);
-        xhi.alloc(P64, S);
-        rhi.alloc(P64, S);
+        b.alloc(P64, full.total_slots);
+        xhi.alloc(P64, full.total_slots);
+        rhi.alloc(P64, full.total_slots);
+        if (o.eo) {
+            for (Field* f : {&sb_, &sx_, &sr_, &tmp64}) f->alloc(P64, S);
+            tmp.alloc(o.P, S);
+        }
         for (Field* f : {&r, &p, &v, &t, &xlo}) f->alloc(o.P, S);
         d_diag.alloc(sizeof(double) * pl.nsys);
         d_st.alloc(sizeof(SysState) * pl.nsys);
-        // partial sums: max 4 doubles per rhs per workgroup (32 for hop launches)
-        part_rows = (size_t)pl.max_wg();
+        // partial sums: max 4 doubles per rhs per workgroup (32 for hop launches,
+        // which callers run over the full-lattice plan)
+        part_rows = (size_t)std::max(pl.max_wg(), full.max_wg());
         d_part.alloc(sizeof(double) * part_rows * 32 * pl.nr);
         d_flags.alloc(sizeof(int) * 2 * pl.blocks.size());
         const size_t nb = pl.blocks.size();
@@ -561,6 +597,24 @@ struct BatchSolver {
         HC(hipStreamSynchronize(s));  // the host vectors may go out of scope
     }
     const NoiseKey* rk() const { return d_rkeys.as<NoiseKey>(); }
+    // the FP64 fields of the system the iteration solves
+    Field& fb() { return o.eo ? sb_ : b; }
+    Field& fx() { return o.eo ? sx_ : xhi; }
+    Field& fr() { return o.eo ? sr_ : rhi; }
+
+    // out = A in with the fused partial sums of `mode`; A = D + sigma, or the
+    // even-odd Schur operator (two launches: the odd-site hop, then S).  `ws` is
+    // the stencil mapping the following finish must use.
+    void apply(int prec, int mode, const Work& ws, Fld out, Fld in, Fld aux, int mask, Fld scratch) {
+        const double* dg = d_diag.as<double>();
+        if (!o.eo) {
+            launch_dslash(prec, mode, ws, out, in, aux, dg, st(), mask, part(), s, rk());
+            return;
+        }
+        const int hp = mode == D_RESID ? P64 : prec;
+        launch_dslash_eo(hp, D_HOP, ws, scratch, in, Fld(), Fld(), dg, st(), mask, part(), s, rk(), 1);
+        launch_dslash_eo(hp, mode, ws, out, scratch, in, aux, dg, st(), mask, part(), s, rk(), 0);
+    }
 
     SysState* st() { return d_st.as<SysState>(); }
     double* part() { return d_part.as<double>(); }
@@ -590,12 +644,11 @@ struct BatchSolver {
     // With in_loop_reliable the FP64 reliable update of the blocks that asked
     // for one follows at once (no host round trip).
     void iteration(bool in_loop_reliable) {
-        const double* dg = d_diag.as<double>();
-        const Work wr = listed(vl_run, o.P, false), wd = listed(vl_run, o.P, true);
-        launch_dslash(o.P, D_RHAT, wd, v.f(), p.f(), Fld(), dg, st(), M_RUN, part(), s, rk());
+        const Work wr = listed(vl_run, o.P, false), wd = o.eo ? wr : listed(vl_run, o.P, true);
+        apply(o.P, D_RHAT, wd, v.f(), p.f(), Fld(), M_RUN, tmp.f());
         launch_finish(F_ALPHA, wd, st(), part(), nullptr, nullptr, s);
         launch_axpy_s(o.P, wr, r.f(), v.f(), st(), s);
-        launch_dslash(o.P, D_TS, wd, t.f(), r.f(), Fld(), dg, st(), M_RUN, part(), s);
+        apply(o.P, D_TS, wd, t.f(), r.f(), Fld(), M_RUN, tmp.f());
         launch_finish(F_OMEGA, wd, st(), part(), nullptr, nullptr, s);
         launch_update_xr(o.P, wr, xlo.f(), p.f(), r.f(), t.f(), rk(), st(), part(), s);
         launch_finish(F_RHO, wr, st(), part(), f_run(), f_pend(), s);
@@ -611,14 +664,14 @@ struct BatchSolver {
     // FP64 reliable update of the blocks in vl_pend: x_hi += x_lo,
     // r_hi = b - (D + sigma) x_hi, then either done or resume with r = r_hi.
     void reliable_chain() {
-        const Work wp = listed(vl_pend, o.P, false), wpd = listed(vl_pend, o.P, true);
-        const Work wp64d = listed(vl_pend, P64, true);
-        launch_fold(o.P, wp, xhi.f(), xlo.f(), st(), s);
-        launch_dslash(P64, D_RESID, wp64d, rhi.f(), xhi.f(), b.f(), d_diag.as<double>(), st(), M_PEND, part(), s);
+        const Work wp = listed(vl_pend, o.P, false), wpd = o.eo ? wp : listed(vl_pend, o.P, true);
+        const Work wp64d = listed(vl_pend, P64, !o.eo);
+        launch_fold(o.P, wp, fx().f(), xlo.f(), st(), s);
+        apply(P64, D_RESID, wp64d, fr().f(), fx().f(), fb().f(), M_PEND, tmp64.f());
         launch_finish(F_TRUE, wpd, st(), part(), f_conv(), f_pend(), s);  // clears f_pend
         build_list(f_conv(), vl_conv);
         const Work wc = listed(vl_conv, o.P, false);
-        launch_convert(o.P, wc, rhi.f(), r.f(), rk(), p.f(), st(), part(), s);
+        launch_convert(o.P, wc, fr().f(), r.f(), rk(), p.f(), st(), part(), s);
         launch_finish(F_RESUME, wc, st(), part(), f_run(), f_conv(), s);  // clears f_conv
         build_list(f_run(), vl_run);
     }
@@ -649,7 +702,7 @@ struct BatchSolver {
             if (any) keep.push_back(bd);
         }
         if (keep.empty() || keep.size() == cur->blocks.size()) return false;
-        auto np = plan_from_blocks(keep, lats, pl.nr, pl.wg, s, pl.ilp, pl.occ);
+        auto np = plan_from_blocks(keep, lats, pl.nr, pl.wg, s, pl.ilp, pl.occ, pl.eo);
         if ((size_t)np->max_wg() > part_rows) {
             part_rows = (size_t)np->max_wg();
             d_part.alloc(sizeof(double) * part_rows * 32 * pl.nr);
@@ -667,7 +720,12 @@ struct BatchSolver {
     }
 
     void run() {
-        launch_init(o.P, pl.work(o.P, false), b.f(), xhi.f(), xlo.f(), rhi.f(), r.f(), rk(), p.f(), part(), s);
+        if (o.eo) {  // Schur source and the full |b|^2 the tolerance refers to
+            launch_eo_prep(pl.work(P64, false), full.d_blocks.as<BlockDesc>(), b.f(), sb_.f(), d_diag.as<double>(),
+                           part(), s);
+            launch_finish(F_BNORM, pl.work(P64, false), st(), part(), nullptr, nullptr, s);
+        }
+        launch_init(o.P, pl.work(o.P, false), fb().f(), fx().f(), xlo.f(), fr().f(), r.f(), rk(), p.f(), part(), s);
         launch_finish(F_INIT, pl.work(o.P, false), st(), part(), f_run(), nullptr, s);
         {
             const Work w = cur->work(o.P, false);
@@ -738,6 +796,9 @@ struct BatchSolver {
             throw;
         }
         drop_graph();
+        if (o.eo)
+            launch_eo_post(pl.work(P64, false), full.d_blocks.as<BlockDesc>(), b.f(), sx_.f(), xhi.f(),
+                           d_diag.as<double>(), s);
         HC(hipMemcpyAsync(st_host.data(), d_st.p, sizeof(SysState) * pl.nsys, hipMemcpyDeviceToHost, s));
         HC(hipStreamSynchronize(s));
     }
@@ -752,6 +813,12 @@ void check_ctx(fs_ctx c, bool need_gauge = true) {
 
 void check_prec(int P) {
     if (P < 0 || P > 3) fail(FS_E_ARG, "invalid precision");
+}
+
+void check_eo(bool eo, const fs_ctx_s* c) {
+    if (!eo) return;
+    for (int i = 0; i < 4; ++i)
+        if (c->dims[i] % 2) fail(FS_E_ARG, "even-odd preconditioning needs every extent even");
 }
 
 // Copy n bytes of a user buffer to a fresh device buffer.
@@ -848,6 +915,7 @@ void run_units(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm, con
     o.delta = o.P == P64 ? 0.0 : (prm->solve.reliable_delta > 0 ? prm->solve.reliable_delta : default_delta(o.P));
     o.check_every = prm->solve.check_every > 0 ? prm->solve.check_every : 8;
     o.use_graph = prm->solve.use_graph != 0;
+    o.eo = prm->solve.even_odd != 0;
     BatchSolver bs(*pl, ctxs, s, o);
     const int nsys = pl->nsys;
     std::vector<double> diag(nsys);
@@ -937,7 +1005,7 @@ void run_units(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm, con
         res.rep.systems += 1;
         res.rep.iterations += S.iters;
         res.rep.reliable_updates += S.n_rel;
-        const double rel = S.bb > 0 ? std::sqrt(S.rr_true / S.bb) : 0.0;
+        const double rel = true_rel(S);
         double& lr = res.level_res[(size_t)e.inst * (L + 1) + e.level];
         lr = std::max(lr, rel);
         res.rep.max_rel_residual = std::max(res.rep.max_rel_residual, rel);
@@ -963,6 +1031,7 @@ void probed_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sigma_in, 
     if (prm->n_noise < 1) fail(FS_E_ARG, "n_noise must be >= 1");
     if (prm->p_max < 0 || prm->p_max >= c->dims[2]) fail(FS_E_ARG, "p_max must be in [0, Lz)");
     check_prec(prm->solve.storage);
+    check_eo(prm->solve.even_odd != 0, c);
     if (!(prm->solve.tol > 0)) fail(FS_E_ARG, "tol must be > 0");
     if (prm->solve.max_iter < 1) fail(FS_E_ARG, "max_iter must be >= 1");
     if (prm->solve.rhs_block != 0 && !pow2_ok(prm->solve.rhs_block)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
@@ -1050,6 +1119,7 @@ void probed_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sigma_in, 
     o.delta = P == P64 ? 0.0 : (prm->solve.reliable_delta > 0 ? prm->solve.reliable_delta : default_delta(P));
     o.check_every = prm->solve.check_every > 0 ? prm->solve.check_every : 8;
     o.use_graph = prm->solve.use_graph != 0;
+    o.eo = prm->solve.even_odd != 0;
     BatchSolver bs(*pl, lats, s, o);
     bs.setup(diag, idle, rkeys);
     DevBuf d_keys = to_device(keys.data(), sizeof(NoiseKey) * nsys, 0, s);
@@ -1118,7 +1188,7 @@ void probed_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sigma_in, 
                 rep.systems += 1;
                 rep.iterations += S.iters;
                 rep.reliable_updates += S.n_rel;
-                const double rel = S.bb > 0 ? std::sqrt(S.rr_true / S.bb) : 0.0;
+                const double rel = true_rel(S);
                 level_res[l] = std::max(level_res[l], rel);
                 rep.max_rel_residual = std::max(rep.max_rel_residual, rel);
                 if (S.state != S_DONE) noconv = true;
@@ -1162,6 +1232,7 @@ void sampling_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sh_in, i
     if (prm->n_noise < 2) fail(FS_E_ARG, "n_noise must be >= 2");
     if (prm->p_max < 0 || prm->p_max >= c->dims[2]) fail(FS_E_ARG, "p_max must be in [0, Lz)");
     check_prec(prm->solve.storage);
+    check_eo(prm->solve.even_odd != 0, c);
     if (!(prm->solve.tol > 0)) fail(FS_E_ARG, "tol must be > 0");
     if (prm->solve.max_iter < 1) fail(FS_E_ARG, "max_iter must be >= 1");
     if (prm->solve.rhs_block != 0 && !pow2_ok(prm->solve.rhs_block)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
@@ -1214,6 +1285,7 @@ void sampling_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sh_in, i
     o.delta = P == P64 ? 0.0 : (prm->solve.reliable_delta > 0 ? prm->solve.reliable_delta : default_delta(P));
     o.check_every = prm->solve.check_every > 0 ? prm->solve.check_every : 8;
     o.use_graph = prm->solve.use_graph != 0;
+    o.eo = prm->solve.even_odd != 0;
     BatchSolver bs(*pl, lats, s, o);
     bs.setup(diag, idle, keys);
     DevBuf d_keys = to_device(keys.data(), sizeof(NoiseKey) * nsys, 0, s);
@@ -1286,7 +1358,7 @@ void sampling_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sh_in, i
         rep.systems += 1;
         rep.iterations += S.iters;
         rep.reliable_updates += S.n_rel;
-        const double rel = S.bb > 0 ? std::sqrt(S.rr_true / S.bb) : 0.0;
+        const double rel = true_rel(S);
         rep.max_rel_residual = std::max(rep.max_rel_residual, rel);
         if (S.state != S_DONE) noconv = true;
     }
@@ -1334,6 +1406,7 @@ void estimate_impl(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm,
     for (auto* c : ctxs) {
         check_ctx(c);
         if (prm->p_max >= c->dims[2]) fail(FS_E_ARG, "p_max must be < Lz");
+        check_eo(prm->solve.even_odd != 0, c);
         if (c->device != ctxs[0]->device) fail(FS_E_ARG, "batch contexts must share a device");
     }
     if (prm->solve.rhs_block != 0 && !pow2_ok(prm->solve.rhs_block)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
@@ -1711,6 +1784,7 @@ fs_status fs_solve_shifted(fs_ctx c, const fs_solve_params* prm, const double* s
         if (!(prm->tol > 0)) fail(FS_E_ARG, "tol must be > 0");
         if (prm->max_iter < 1) fail(FS_E_ARG, "max_iter must be >= 1");
         if (prm->rhs_block != 0 && !pow2_ok(prm->rhs_block)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
+        check_eo(prm->even_odd != 0, c);
         DeviceScope ds(c->device);
         hipStream_t s = c->stream;
         const size_t nb1 = sizeof(double) * 24 * (size_t)c->V;
@@ -1724,6 +1798,7 @@ fs_status fs_solve_shifted(fs_ctx c, const fs_solve_params* prm, const double* s
         o.delta = P == P64 ? 0.0 : (prm->reliable_delta > 0 ? prm->reliable_delta : default_delta(P));
         o.check_every = prm->check_every > 0 ? prm->check_every : 8;
         o.use_graph = prm->use_graph != 0;
+        o.eo = prm->even_odd != 0;
         std::vector<fs_ctx_s*> lats{c};
         // groups: (shift, rhs range) solved together
         std::vector<std::vector<std::pair<int, int>>> passes;  // each pass: list of (shift, rhs)
@@ -1788,7 +1863,7 @@ fs_status fs_solve_shifted(fs_ctx c, const fs_solve_params* prm, const double* s
                     o2.reliable_updates = S.n_rel;
                     o2.status = code;
                     o2.restarts = S.restarts;
-                    o2.true_rel_residual = S.bb > 0 ? std::sqrt(S.rr_true / S.bb) : 0.0;
+                    o2.true_rel_residual = true_rel(S);
                 }
             }
         }

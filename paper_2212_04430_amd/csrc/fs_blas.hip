@@ -37,7 +37,7 @@ __device__ __forceinline__ bool mask_ok(int mask, const SysState* __restrict__ s
     const BlockDesc bd = (w).blocks[b];                                     \
     const LatDesc ld = (w).lats[bd.lat];                                    \
     const int wgb = wg_id - (w).wg_start[b];                                \
-    const size_t gs = (size_t)ld.V << (w).lognr;
+    const size_t gs = (size_t)ld.Vf << (w).lognr;
 
 #define FS_WG_EPILOGUE });
 
@@ -282,6 +282,9 @@ __device__ __forceinline__ void finish_system(SysState& S, const double* q, int 
             S.rr_max = S.rr;
             S.rhat2 = 12.0 * V;  // |rhat|^2 of a Z4 vector
             S.rr_true = S.bb;
+            // even-odd: the Schur residual equals the full residual, so measure it
+            // against the full source
+            if (S.bnorm2 > 0.0 && S.bb > 0.0) S.tol2 *= S.bnorm2 / S.bb;
             S.iters = 0;
             S.n_rel = 0;
             S.restarts = 0;
@@ -367,6 +370,8 @@ __device__ __forceinline__ void finish_system(SysState& S, const double* q, int 
                 S.state = S.restarts > 64 ? S_FAIL : S_RST;
             } else S.state = S_CONV;
         }
+    } else if constexpr (STAGE == F_BNORM) {
+        if (S.state != S_IDLE) S.bnorm2 = Q(0);
     } else {  // F_RESUME
         const int s = S.state;
         if (s == S_CONV || s == S_RST) {
@@ -388,7 +393,7 @@ __device__ __forceinline__ void finish_system(SysState& S, const double* q, int 
 template <int STAGE>
 __global__ void __launch_bounds__(256) k_finish(Work w, SysState* __restrict__ st, const double* __restrict__ part,
                                                 int* __restrict__ blk_on, int* __restrict__ blk_pend) {
-    constexpr int ND = STAGE == F_INIT ? 4 : STAGE == F_ALPHA ? 2 : STAGE == F_TRUE ? 1 : 3;
+    constexpr int ND = STAGE == F_INIT ? 4 : STAGE == F_ALPHA ? 2 : (STAGE == F_TRUE || STAGE == F_BNORM) ? 1 : 3;
     __shared__ double q[ND * 16];
     __shared__ int any_on, any_rel, any_pend;
     const int nr = w.nr;
@@ -409,7 +414,7 @@ __global__ void __launch_bounds__(256) k_finish(Work w, SysState* __restrict__ s
     const bool mine = threadIdx.x < nr;
     if (mine) {
         SysState& S = st[bd.sys0 + threadIdx.x];
-        finish_system<STAGE>(S, q, nr, threadIdx.x, (double)w.lats[bd.lat].V);
+        finish_system<STAGE>(S, q, nr, threadIdx.x, (double)w.lats[bd.lat].Vf);
         if (STAGE == F_RHO && S.state == S_REL) atomicOr(&any_rel, 1);
     }
     __syncthreads();
@@ -887,6 +892,7 @@ void launch_finish(int stage, const Work& w, SysState* st, const double* part, i
         case F_RHO: hipLaunchKernelGGL(k_finish<F_RHO>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
         case F_TRUE: hipLaunchKernelGGL(k_finish<F_TRUE>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
         case F_RESUME: hipLaunchKernelGGL(k_finish<F_RESUME>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
+        case F_BNORM: wf.blk_on = nullptr; wf.vlist = nullptr; hipLaunchKernelGGL(k_finish<F_BNORM>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
         default: break;
     }
 }

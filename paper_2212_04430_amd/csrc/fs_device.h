@@ -25,7 +25,9 @@ enum Prec : int { P64 = 0, P32 = 1, P16 = 2, PBF = 3 };
 
 struct LatDesc {
     int L[4];          // Lx, Ly, Lz, Lt
-    int V;             // sites
+    int V;             // sites (links are indexed by site)
+    int Vf;            // sites of a field: V, or V/2 for even-odd (one-parity) fields
+    int eo;            // 1: fields hold one parity, field site = site >> 1
     int tsign;         // +1 periodic, -1 antiperiodic in t
     const void* gauge; // links in the launch's storage precision, [mu][9][site]
     const void* gauge_q; // the same links site-major, [mu][site][QC 16-byte chunks]

@@ -577,6 +577,221 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
     });
 }
 
+// ------------------------------------------------------------------ even-odd
+
+// One hop direction as in hop_dir, reading a one-parity field (HALF: neighbour
+// slot = (site >> 1) * NR + r) or a full-layout field.
+template <int P, bool Q, bool HALF, int MU, typename PF, typename PB>
+__device__ __forceinline__ void hop_dir_h(const LatDesc& ld, const uint4* __restrict__ ib,
+                                          const float* __restrict__ inn, size_t gs, int site, int coord,
+                                          int stride, int r, int lognr, typename Tr<P>::acc o[24]) {
+    using A = typename Tr<P>::acc;
+    const int Lm = ld.L[MU];
+    const int sf = (coord == Lm - 1) ? site - (Lm - 1) * stride : site + stride;
+    const int sb = (coord == 0) ? site + (Lm - 1) * stride : site - stride;
+    A cf = A(-0.5), cb = A(-0.5);
+    if (MU == 3 && ld.tsign < 0) {
+        if (coord == Lm - 1) cf = A(0.5);
+        if (coord == 0) cb = A(0.5);
+    }
+    {
+        A v[24], h[12], u[18], w[12];
+        load_sp<P, A>(ib, inn, gs, ((size_t)(HALF ? (sf >> 1) : sf) << lognr) + r, v);
+        PF::project(v, h);
+        link<P, Q, A>(ld, MU, site, u);
+        mul_u(u, h, w);
+        PF::accum(o, w, cf);
+    }
+    {
+        A v[24], h[12], u[18], w[12];
+        load_sp<P, A>(ib, inn, gs, ((size_t)(HALF ? (sb >> 1) : sb) << lognr) + r, v);
+        PB::project(v, h);
+        link<P, Q, A>(ld, MU, sb, u);
+        mul_udag(u, h, w);
+        PB::accum(o, w, cb);
+    }
+}
+
+// o += hopping term of D at `site`: -1/2 sum_mu [(1-g_mu) U psi(x+mu) + (1+g_mu) U^+ psi(x-mu)]
+template <int P, bool Q, bool HALF>
+__device__ __forceinline__ void hop_all(const LatDesc& ld, const uint4* __restrict__ ib,
+                                        const float* __restrict__ inn, size_t gs, int site, const Coord& c, int r,
+                                        int lognr, typename Tr<P>::acc o[24]) {
+    const int sy = ld.L[0], sz = ld.L[0] * ld.L[1], stt = sz * ld.L[2];
+    hop_dir_h<P, Q, HALF, 0, PxM, PxP>(ld, ib, inn, gs, site, c.x, 1, r, lognr, o);
+    hop_dir_h<P, Q, HALF, 1, PyM, PyP>(ld, ib, inn, gs, site, c.y, sy, r, lognr, o);
+    hop_dir_h<P, Q, HALF, 2, PzM, PzP>(ld, ib, inn, gs, site, c.z, sz, r, lognr, o);
+    hop_dir_h<P, Q, HALF, 3, PtM, PtP>(ld, ib, inn, gs, site, c.t, stt, r, lognr, o);
+}
+
+// Site of parity `par` ((x+y+z+t) mod 2) with field index cb = site >> 1 (Lx even).
+__device__ __forceinline__ int eo_site(const LatDesc& ld, int cb, int par, Coord& c) {
+    const int Lxh = ld.L[0] >> 1;
+    int q = cb / Lxh;
+    const int xh = cb - q * Lxh;
+    c.y = q % ld.L[1];
+    q /= ld.L[1];
+    c.z = q % ld.L[2];
+    c.t = q / ld.L[2];
+    c.x = 2 * xh + ((c.y + c.z + c.t + par) & 1);
+    return c.x + ld.L[0] * (c.y + ld.L[1] * (c.z + ld.L[2] * c.t));
+}
+
+template <int MODE> struct NDotsEo { static constexpr int v = NDots<MODE>::v; };
+
+// One lane per (field site, rhs) slot of one parity; see launch_dslash_eo.
+template <int P, int MODE, bool Q>
+__global__ void __launch_bounds__(256) k_dslash_eo(Work w, Fld out, Fld in, Fld cen, Fld aux,
+                                                   const double* __restrict__ diag,
+                                                   const SysState* __restrict__ st, int mask,
+                                                   double* __restrict__ part, const NoiseKey* __restrict__ rk,
+                                                   int par_out) {
+    using A = typename Tr<P>::acc;
+    constexpr int G = Tr<P>::G;
+    constexpr int ND = NDotsEo<MODE>::v;
+    for_each_vwg(w, [&](const int wg_id, const int b) {
+    const BlockDesc bd = w.blocks[b];
+    const LatDesc ld = w.lats[bd.lat];
+    const int wgb = wg_id - w.wg_start[b];
+    const size_t gs = (size_t)ld.Vf << w.lognr;
+    const uint4* ib = in.v + (size_t)bd.slot_off * G;
+    const float* inn = in.n ? in.n + bd.slot_off : nullptr;
+    uint4* ob = out.v + (size_t)bd.slot_off * G;
+    float* on = out.n ? out.n + bd.slot_off : nullptr;
+    double acc[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) acc[k] = 0.0;
+    for (int it = 0; it < w.tpw; ++it) {
+        const size_t slot = ((size_t)wgb * w.tpw + it) * w.wg + threadIdx.x;
+        if (slot >= gs) break;
+        const int r = (int)(slot & (size_t)(w.nr - 1));
+        const int sys = bd.sys0 + r;
+        // quad-shared links need the whole quad; then the mask gates only the dots
+        const bool act = mask_ok(mask, st, sys);
+        if (!(Q || act)) continue;
+        const int cb = (int)(slot >> w.lognr);
+        Coord c;
+        const int site = eo_site(ld, cb, par_out, c);
+        A o[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) o[k] = A(0);
+        hop_all<P, Q, true>(ld, ib, inn, gs, site, c, r, w.lognr, o);
+        A cv[24];
+        if constexpr (MODE != D_HOP) {
+            load_sp<P, A>(cen.v + (size_t)bd.slot_off * G, cen.n ? cen.n + bd.slot_off : nullptr, gs, slot, cv);
+            const A a = (A)diag[sys];
+            const A ia = A(1) / a;
+#pragma unroll
+            for (int k = 0; k < 24; ++k) o[k] = a * cv[k] - ia * o[k];
+        }
+        if constexpr (MODE == D_RESID) {
+            A bv[24];
+            load_sp<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
+#pragma unroll
+            for (int k = 0; k < 24; ++k) o[k] = bv[k] - o[k];
+        }
+        store_sp<P, A>(ob, on, gs, slot, o);
+        if (act) {
+            if constexpr (MODE == D_RHAT) {
+                A rh[24];
+                rhat_site<A>(rk[sys], st[sys].restarts, cb, rh);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
+                    acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
+                }
+            } else if constexpr (MODE == D_TS) {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    const double tr = o[2 * k], ti = o[2 * k + 1], sr = cv[2 * k], si = cv[2 * k + 1];
+                    acc[0] += tr * sr + ti * si;
+                    acc[1] += tr * si - ti * sr;
+                    acc[2] += tr * tr + ti * ti;
+                }
+            } else if constexpr (MODE == D_RESID) {
+#pragma unroll
+                for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
+            }
+        }
+    }
+    if constexpr (MODE == D_RHAT || MODE == D_TS || MODE == D_RESID) block_partials<ND, 4>(acc, w.nr, part, wg_id);
+    });
+}
+
+// FP64, over a one-parity plan: bh = b_e - D_eo b_o / a; partials |b_e|^2 + |b_o|^2.
+__global__ void __launch_bounds__(256) k_eo_prep(Work w, const BlockDesc* __restrict__ fblocks, Fld bfull, Fld bh,
+                                                 const double* __restrict__ diag, double* __restrict__ part) {
+    for_each_vwg(w, [&](const int wg_id, const int b) {
+    const BlockDesc bd = w.blocks[b];
+    const LatDesc ld = w.lats[bd.lat];
+    const int wgb = wg_id - w.wg_start[b];
+    const size_t gsh = (size_t)ld.Vf << w.lognr, gsf = (size_t)ld.V << w.lognr;
+    const uint4* fb = bfull.v + (size_t)fblocks[b].slot_off * 12;
+    uint4* hb = bh.v + (size_t)bd.slot_off * 12;
+    double acc[1] = {0.0};
+    for (int it = 0; it < w.tpw; ++it) {
+        const size_t slot = ((size_t)wgb * w.tpw + it) * w.wg + threadIdx.x;
+        if (slot >= gsh) break;
+        const int r = (int)(slot & (size_t)(w.nr - 1));
+        const int sys = bd.sys0 + r;
+        const int cb = (int)(slot >> w.lognr);
+        Coord c;
+        const int se = eo_site(ld, cb, 0, c);
+        const int so = se ^ 1;  // the odd site of the same field index (Lx even)
+        double h[24], be[24], bo[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) h[k] = 0.0;
+        hop_all<P64, false, false>(ld, fb, nullptr, gsf, se, c, r, w.lognr, h);
+        load_sp<P64, double>(fb, nullptr, gsf, ((size_t)se << w.lognr) + r, be);
+        load_sp<P64, double>(fb, nullptr, gsf, ((size_t)so << w.lognr) + r, bo);
+        const double ia = 1.0 / diag[sys];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            acc[0] += be[k] * be[k] + bo[k] * bo[k];
+            be[k] -= ia * h[k];
+        }
+        store_sp<P64, double>(hb, nullptr, gsh, slot, be);
+    }
+    block_partials<1, 4>(acc, w.nr, part, wg_id);
+    });
+}
+
+// FP64: x (full layout) = x_e at even sites, (b_o - D_oe x_e) / a at odd sites.
+__global__ void __launch_bounds__(256) k_eo_post(Work w, const BlockDesc* __restrict__ fblocks, Fld bfull, Fld xh,
+                                                 Fld xfull, const double* __restrict__ diag) {
+    for_each_vwg(w, [&](const int wg_id, const int b) {
+    (void)wg_id;
+    const BlockDesc bd = w.blocks[b];
+    const LatDesc ld = w.lats[bd.lat];
+    const int wgb = wg_id - w.wg_start[b];
+    const size_t gsh = (size_t)ld.Vf << w.lognr, gsf = (size_t)ld.V << w.lognr;
+    const uint4* fb = bfull.v + (size_t)fblocks[b].slot_off * 12;
+    uint4* fx = xfull.v + (size_t)fblocks[b].slot_off * 12;
+    const uint4* hx = xh.v + (size_t)bd.slot_off * 12;
+    for (int it = 0; it < w.tpw; ++it) {
+        const size_t slot = ((size_t)wgb * w.tpw + it) * w.wg + threadIdx.x;
+        if (slot >= gsh) break;
+        const int r = (int)(slot & (size_t)(w.nr - 1));
+        const int sys = bd.sys0 + r;
+        const int cb = (int)(slot >> w.lognr);
+        Coord c;
+        const int so = eo_site(ld, cb, 1, c);
+        const int se = so ^ 1;
+        double h[24], bo[24], xe[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) h[k] = 0.0;
+        hop_all<P64, false, true>(ld, hx, nullptr, gsh, so, c, r, w.lognr, h);
+        load_sp<P64, double>(fb, nullptr, gsf, ((size_t)so << w.lognr) + r, bo);
+        load_sp<P64, double>(hx, nullptr, gsh, slot, xe);
+        const double ia = 1.0 / diag[sys];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) bo[k] = ia * (bo[k] - h[k]);
+        store_sp<P64, double>(fx, nullptr, gsf, ((size_t)se << w.lognr) + r, xe);
+        store_sp<P64, double>(fx, nullptr, gsf, ((size_t)so << w.lognr) + r, bo);
+    }
+    });
+}
+
 }  // namespace
 
 static int grid_of(const Work& w) { return w.vlist ? persistent_grid(w.wg) : (w.total_wg + 7) / 8 * 8; }
@@ -648,6 +863,55 @@ void launch_dslash(int prec, int mode, const Work& w, Fld out, Fld in, Fld aux, 
         case PBF: launch_p<PBF>(mode, w, out, in, aux, diag, st, mask, part, s, rk); break;
         default: break;
     }
+}
+
+
+template <int P, int MODE>
+static void launch_eo_q(const Work& w, Fld out, Fld in, Fld cen, Fld aux, const double* diag, const SysState* st,
+                        int mask, double* part, hipStream_t s, const NoiseKey* rk, int par_out) {
+    if (w.nr >= 4)
+        hipLaunchKernelGGL((k_dslash_eo<P, MODE, true>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen, aux,
+                           diag, st, mask, part, rk, par_out);
+    else
+        hipLaunchKernelGGL((k_dslash_eo<P, MODE, false>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen, aux,
+                           diag, st, mask, part, rk, par_out);
+}
+
+template <int P>
+static void launch_eo_p(int mode, const Work& w, Fld out, Fld in, Fld cen, Fld aux, const double* diag,
+                        const SysState* st, int mask, double* part, hipStream_t s, const NoiseKey* rk, int par_out) {
+    switch (mode) {
+        case D_HOP: launch_eo_q<P, D_HOP>(w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out); break;
+        case D_PLAIN: launch_eo_q<P, D_PLAIN>(w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out); break;
+        case D_RHAT: launch_eo_q<P, D_RHAT>(w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out); break;
+        case D_TS: launch_eo_q<P, D_TS>(w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out); break;
+        default: break;
+    }
+}
+
+void launch_dslash_eo(int prec, int mode, const Work& w, Fld out, Fld in, Fld cen, Fld aux, const double* diag,
+                      const SysState* st, int mask, double* part, hipStream_t s, const NoiseKey* rk, int par_out) {
+    if (mode == D_RESID) {
+        launch_eo_q<P64, D_RESID>(w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out);
+        return;
+    }
+    switch (prec) {
+        case P64: launch_eo_p<P64>(mode, w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out); break;
+        case P32: launch_eo_p<P32>(mode, w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out); break;
+        case P16: launch_eo_p<P16>(mode, w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out); break;
+        case PBF: launch_eo_p<PBF>(mode, w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out); break;
+        default: break;
+    }
+}
+
+void launch_eo_prep(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld bh, const double* diag, double* part,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_eo_prep, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, bh, diag, part);
+}
+
+void launch_eo_post(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld xh, Fld xfull, const double* diag,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_eo_post, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, xh, xfull, diag);
 }
 
 }  // namespace fs

@@ -28,6 +28,7 @@ struct SysState {
     double tol2;      // tol^2 (relative)
     double delta2;    // reliable-update trigger (0 = only at convergence)
     double rhat2;     // |rhat|^2 (breakdown test)
+    double bnorm2;    // even-odd: |b|^2 of the full system (0 otherwise); the tolerance is relative to it
     int state, iters, upd_p, n_rel;
     int restarts, max_iter;
 };
@@ -170,8 +171,27 @@ enum DMode : int {
     D_PLAIN = 0,   // out = (D + sigma) in
     D_RHAT = 1,    // + partial (rhat, out)             [2 doubles]
     D_TS = 2,      // + partials (out, in), (out, out)  [3 doubles]
-    D_RESID = 3    // out = b - (D + sigma) in (b FP64 in aux) + |out|^2 [1 double]
+    D_RESID = 3,   // out = b - (D + sigma) in (b FP64 in aux) + |out|^2 [1 double]
+    D_HOP = 4      // even-odd only: out = D_{par_out, other} in, the off-diagonal block
 };
+
+// Even-odd preconditioning.  Fields hold one parity (field site = site >> 1 with
+// Lx even).  With a = 4 + m0 + sigma, D = [[a, D_eo], [D_oe, a]] and the Schur
+// operator on even sites is S = a - D_eo D_oe / a.  launch_dslash_eo:
+//   D_HOP:    out = D_{par_out, 1-par_out} in
+//   other modes (par_out = even): out = a cen - D_eo in / a with in = D_oe cen,
+//   and the partial sums of launch_dslash (D_RESID: out = b - S cen, b in aux).
+// Launched with the tile mapping (one slot per lane); the finish that follows
+// takes the same mapping.
+void launch_dslash_eo(int prec, int mode, const Work& w, Fld out, Fld in, Fld cen, Fld aux, const double* diag,
+                      const SysState* st, int mask, double* part, hipStream_t s, const NoiseKey* rk, int par_out);
+// Over a one-parity plan whose blocks match fblocks (full-lattice layout) one
+// for one, FP64: bh = b_e - D_eo b_o / a, plus partial |b|^2 of both parities
+// (finished by F_BNORM); and x = (x_e, (b_o - D_oe x_e) / a) in full layout.
+void launch_eo_prep(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld bh, const double* diag, double* part,
+                    hipStream_t s);
+void launch_eo_post(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld xh, Fld xfull, const double* diag,
+                    hipStream_t s);
 
 // D_RHAT takes the shadow residual from rk (per-system keys); D_RESID reads b from aux.
 void launch_dslash(int prec, int mode, const Work& w, Fld out, Fld in, Fld aux, const double* diag,
@@ -184,7 +204,7 @@ void launch_update_xr(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, const
 void launch_update_p(int prec, const Work& w, Fld p, Fld r, Fld v, const SysState* st, hipStream_t s);
 
 // finish kernels: one workgroup per block, reduce partials, update state
-enum FStage : int { F_INIT = 0, F_ALPHA = 1, F_OMEGA = 2, F_RHO = 3, F_TRUE = 4, F_RESUME = 5 };
+enum FStage : int { F_INIT = 0, F_ALPHA = 1, F_OMEGA = 2, F_RHO = 3, F_TRUE = 4, F_RESUME = 5, F_BNORM = 6 };
 // w.blk_on: flags of the launch being completed (blocks with 0 are skipped);
 // out: flags for the next launch; out2 (F_RHO only): blocks with systems
 // pending a reliable update.
