@@ -35,7 +35,7 @@ sys.path.insert(0, ROOT)
 METRIC = "dslash GB/s (% HBM peak); shifted solves/sec at 1e-10, mixed+batched vs FP64"
 HBM_PEAK_GBS = 8000.0
 TUNING = os.path.join(ROOT, "paper_2212_04430_amd", "tuning", "gfx950.txt")
-TRAFFIC = os.path.join(ROOT, "profiles", "dslash_f32_batched_16c32_traffic.md")
+TRAFFIC = os.path.join(ROOT, "profiles", "dslash_eo_f32_batched_16c32_traffic.md")
 ROOFLINE_NSYS = 96
 
 WORKLOAD = dict(dims=(16, 16, 16, 32), eps=0.2, m0=0.02, sigma=[0.0, 0.05, 0.25, 0.5, 1.0], n_noise=48,
@@ -141,9 +141,9 @@ def setup_tuning():
 def roofline_only(L, ctx, nr, wg):
     """The launches the roofline reports, alone (for hardware-counter runs)."""
     ms_c = L.fs_time_copy(ctx, 1 << 30, 20)
-    ms_d, by = L.fs_time_dslash(ctx, "f32", ROOFLINE_NSYS, nr, wg, 50)
+    ms_d, by = L.fs_time_dslash_eo(ctx, "f32", ROOFLINE_NSYS, nr, 50)
     print(json.dumps({"copy_bytes": 1 << 30, "copy_ms": ms_c, "dslash_ms": ms_d, "dslash_bytes": by,
-                      "config": f"f32 nsys={ROOFLINE_NSYS} nr={nr} wg={wg}", "hash": kernel_source_hash()}))
+                      "config": f"f32-eo nsys={ROOFLINE_NSYS} nr={nr} wg=256", "hash": kernel_source_hash()}))
 
 
 def probed_estimate(L, ctx, nr, dims):
@@ -153,7 +153,7 @@ def probed_estimate(L, ctx, nr, dims):
     t0 = time.perf_counter()
     col, nc = L.fs_probing_colours(dims, 8, 7)
     dt_c = time.perf_counter() - t0
-    prm = est_params(L, "f32", 1, 2, nr=nr)
+    prm = est_params(L, "f32", 1, 2, nr=nr, eo=1)
     t1 = time.perf_counter()
     _, _, rep = L.fs_estimate_probed(ctx, prm, [0.0, 0.25], col)
     dt = time.perf_counter() - t1
@@ -170,7 +170,7 @@ def sampling_and_selection(L, ctx, nr):
     paper's evaluation grid: the dynamic program on the host, and the GPU's
     exhaustive sweep for (Gamma_11, p = 4) checked against it."""
     s_hat = list(WORKLOAD["sigma"])
-    prm = est_params(L, "f32", 1, 5, nr=nr)
+    prm = est_params(L, "f32", 1, 5, nr=nr, eo=1)
     t0 = time.perf_counter()
     single, pair, _, iters, rep = L.fs_sample_variances(ctx, prm, s_hat)
     dt_s = time.perf_counter() - t0
@@ -241,8 +241,8 @@ def main():
         roofline_only(L, ctx, nr, wg)
         return
 
-    # ---- batched mixed path: warmup + timed steps
-    prm = est_params(L, "f32", 1, w["n_noise"], nr=nr)
+    # ---- batched mixed path, even-odd preconditioned: warmup + timed steps
+    prm = est_params(L, "f32", 1, w["n_noise"], nr=nr, eo=1)
     for i in range(args.warmup):
         t0 = time.perf_counter()
         L.fs_estimate(ctx, prm, w["sigma"])
@@ -264,26 +264,40 @@ def main():
     max_res = max(r.max_rel_residual for r in reps)
 
     # ---- plain FP64 single-RHS path on a subset of the same systems and noise
+    # (even-odd preconditioned, like the batched path)
     n64 = args.fp64_noise
     L.fs_autotune(ctx, "f64", 1, cache)  # the plain path's own best single-system stencil
-    prm64 = est_params(L, "f64", 0, n64, graph=0)
+    prm64 = est_params(L, "f64", 0, n64, graph=0, eo=1)
     t1 = time.perf_counter()
     stats_a, X_a, rep_a = L.fs_estimate(ctx, prm64, w["sigma"], want_samples=True)
     dt_a = time.perf_counter() - t1
     fp64_rate = rep_a.systems / dt_a
     log(f"fp64 plain: {rep_a.systems} systems in {dt_a:.2f} s ({rep_a.iterations / rep_a.systems:.1f} iters/system)")
-    prm_b_sub = est_params(L, "f32", 1, n64, nr=nr)
+    prm_b_sub = est_params(L, "f32", 1, n64, nr=nr, eo=1)
     _, X_b, _ = L.fs_estimate(ctx, prm_b_sub, w["sigma"], want_samples=True)
     scale = np.abs(X_a).mean(axis=1)
     scale = np.where(scale > 0, scale, 1.0)
     lvl_err = (np.abs(X_b - X_a).max(axis=1) / scale).reshape(L_lev + 1, -1).max(axis=1)
 
+    # ---- the same two paths without even-odd preconditioning (context)
+    t3 = time.perf_counter()
+    _, _, rep_n = L.fs_estimate(ctx, est_params(L, "f32", 1, w["n_noise"], nr=nr, eo=0), w["sigma"])
+    dt_n = time.perf_counter() - t3
+    t4 = time.perf_counter()
+    _, _, rep_n64 = L.fs_estimate(ctx, est_params(L, "f64", 0, n64, graph=0, eo=0), w["sigma"])
+    dt_n64 = time.perf_counter() - t4
+    no_eo = {"fp32_batched_solves_per_s": round(rep_n.systems / dt_n, 3),
+             "fp32_batched_iters_per_system": round(rep_n.iterations / rep_n.systems, 2),
+             "fp64_plain_solves_per_s": round(rep_n64.systems / dt_n64, 3),
+             "fp64_plain_iters_per_system": round(rep_n64.iterations / rep_n64.systems, 2)}
+    log(f"without even-odd: f32 batched {no_eo['fp32_batched_solves_per_s']} solves/s, "
+        f"f64 plain {no_eo['fp64_plain_solves_per_s']} solves/s")
+
     # ---- half-precision storage on the same workload (FP64 reliable updates)
     half = {}
     if not args.no_half:
         for prec in ("f16", "bf16"):
-            L.fs_autotune(ctx, prec, systems_per_step, cache)
-            prm_h = est_params(L, prec, 1, w["n_noise"])
+            prm_h = est_params(L, prec, 1, w["n_noise"], nr=4, eo=1)
             t2 = time.perf_counter()
             _, _, rep_h = L.fs_estimate(ctx, prm_h, w["sigma"])
             dt_h = time.perf_counter() - t2
@@ -291,23 +305,30 @@ def main():
                           "speedup_vs_fp64_plain": round(systems_per_step / dt_h / fp64_rate, 3),
                           "iters_per_system": round(rep_h.iterations / rep_h.systems, 2),
                           "reliable_updates_per_system": round(rep_h.reliable_updates / rep_h.systems, 2),
-                          "max_true_rel_residual": rep_h.max_rel_residual}
+                          "max_true_rel_residual": rep_h.max_rel_residual, "rhs_block": 4}
             log(f"mixed {prec}: {systems_per_step / dt_h:.1f} solves/s")
 
-    # ---- dslash roofline: the batched FP32 kernel of the solver, live HIP events
-    ms_d, bytes_d = L.fs_time_dslash(ctx, "f32", ROOFLINE_NSYS, nr, wg, 50)
+    # ---- dslash roofline: the batched FP32 even-odd hop of the solver, live HIP events
+    ms_d, bytes_d = L.fs_time_dslash_eo(ctx, "f32", ROOFLINE_NSYS, nr, 50)
     ms_c = L.fs_time_copy(ctx, 1 << 30, 20)
     achieved = bytes_d / (ms_d * 1e-3) / 1e9
-    cfg_key = f"f32,nsys={ROOFLINE_NSYS},nr={nr},wg={wg}"
+    cfg_key = f"f32-eo,nsys={ROOFLINE_NSYS},nr={nr},wg=256"
+    ms_full, bytes_full = L.fs_time_dslash(ctx, "f32", ROOFLINE_NSYS, nr, wg, 50)
+    full_gbs = bytes_full / (ms_full * 1e-3) / 1e9
     traffic = committed_traffic(cfg_key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / (ms_d * 1e-3) / 1e9, 1),
                 "traffic_bytes_per_launch": traffic,
-                "kernel": f"k_dslash<P32> D_PLAIN, {ROOFLINE_NSYS} systems, rhs_block {nr}, wg {wg}",
+                "kernel": f"k_dslash_eo<P32> D_HOP (one parity out), {ROOFLINE_NSYS} systems, rhs_block {nr}, "
+                          f"wg 256",
+                "full_lattice_dslash": {"kernel": f"k_dslash<P32> D_PLAIN, rhs_block {nr}, wg {wg}",
+                                        "avg_launch_ms": round(ms_full, 5), "achieved": round(full_gbs, 1),
+                                        "frac": round(full_gbs / HBM_PEAK_GBS, 4)},
                 "algorithmic_bytes_per_launch": bytes_d, "avg_launch_ms": round(ms_d, 5),
                 "copy_kernel_GBs": round(2 * (1 << 30) / (ms_c * 1e-3) / 1e9, 1)}
-    log(f"dslash f32 batched: {ms_d:.4f} ms, {achieved:.0f} GB/s")
+    log(f"dslash f32 batched even-odd hop: {ms_d:.4f} ms, {achieved:.0f} GB/s; full lattice {ms_full:.4f} ms, "
+        f"{full_gbs:.0f} GB/s")
     select, sel_inputs = (None, None) if args.no_select else sampling_and_selection(L, ctx, nr)
     probed = None if args.no_probe else probed_estimate(L, ctx, nr, dims)
     L.fs_destroy(ctx)
@@ -353,11 +374,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "16^3x32 Wilson eps=0.2 m0=0.02, shifts {0,.05,.25,.5,1}, 48 Z4/level, "
-                               "16 Gamma, p=0..8, FP32 storage + FP64 reliable updates, batched",
+                               "16 Gamma, p=0..8, FP32 storage + FP64 reliable updates, batched, "
+                               "even-odd preconditioned",
                    "systems_per_step": systems_per_step, "rhs_block": nr, "wg": wg, "tol": w["tol"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_plain_solves_per_s": round(fp64_rate, 3),
+        "without_even_odd": no_eo,
         "fp64_plain_systems": int(rep_a.systems),
         "speedup_vs_fp64_plain": round(value / fp64_rate, 3),
         "iters_per_system": round(avg_iters, 2),

@@ -1550,6 +1550,57 @@ double time_dslash_impl(fs_ctx c, int P, int n_sys, int nr, int wg, int ilp, int
     return (double)ms / n_launch;
 }
 
+// Algorithmic bytes of one even-odd hop launch (one parity out): per output
+// site and system 24 reals in and 24 out (+ FP16 scales); every link of the
+// lattice once per block of nr systems (each link joins an even and an odd site).
+double dslash_eo_bytes(int P, long long V, int n_sys, int nr) {
+    const double w = P == P64 ? 8 : P == P32 ? 4 : 2;
+    const double per_sys = 48.0 * w + (P == P16 ? 8.0 : 0.0);
+    const long long nblk = (n_sys + nr - 1) / nr;
+    return (double)(V / 2) * per_sys * n_sys + (double)V * 72.0 * w * nblk;
+}
+
+double time_dslash_eo_impl(fs_ctx c, int P, int n_sys, int nr, int n_launch) {
+    hipStream_t s = c->stream;
+    const int nblk = (n_sys + nr - 1) / nr;
+    std::vector<int> blk_lat(nblk, 0);
+    std::vector<fs_ctx_s*> lats{c};
+    auto pl = make_plan(blk_lat, lats, nr, 256, s, 0, 0, 1);
+    Field in, out;
+    in.alloc(P, pl->total_slots);
+    out.alloc(P, pl->total_slots);
+    std::vector<NoiseKey> keys(pl->nsys);
+    for (int i = 0; i < pl->nsys; ++i) {
+        std::memset(&keys[i], 0, sizeof(NoiseKey));
+        keys[i].seed = 12345;
+        keys[i].sample = (uint64_t)i;
+    }
+    DevBuf d_keys = to_device(keys.data(), sizeof(NoiseKey) * keys.size(), 0, s);
+    launch_noise_block(P, pl->work(P, false), in.f(), d_keys.as<NoiseKey>(), s);
+    launch_noise_block(P, pl->work(P, false), out.f(), d_keys.as<NoiseKey>(), s);
+    std::vector<double> diag(pl->nsys, 4.1);
+    DevBuf d_diag = to_device(diag.data(), sizeof(double) * diag.size(), 0, s);
+    HC(hipStreamSynchronize(s));
+    const Work w = pl->work(P, false);
+    auto hop = [&](int i) {  // odd sites from even ones, then back
+        launch_dslash_eo(P, D_HOP, w, (i & 1) ? in.f() : out.f(), (i & 1) ? out.f() : in.f(), Fld(), Fld(),
+                         d_diag.as<double>(), nullptr, M_ALL, nullptr, s, nullptr, (i & 1) ? 0 : 1);
+    };
+    for (int i = 0; i < 3; ++i) hop(i);
+    hipEvent_t e0, e1;
+    HC(hipEventCreate(&e0));
+    HC(hipEventCreate(&e1));
+    HC(hipEventRecord(e0, s));
+    for (int i = 0; i < n_launch; ++i) hop(i);
+    HC(hipEventRecord(e1, s));
+    HC(hipEventSynchronize(e1));
+    float ms = 0;
+    HC(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return (double)ms / n_launch;
+}
+
 }  // namespace
 
 // ============================================================== C ABI
@@ -2085,6 +2136,22 @@ fs_status fs_time_dslash(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_b
         const double ms = time_dslash_impl(c, storage, n_sys, nr, w, il, oc, n_launch);
         if (avg_ms) *avg_ms = ms;
         if (bytes) *bytes = dslash_bytes(storage, c->V, n_sys, nr);
+    });
+}
+
+fs_status fs_time_dslash_eo(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_block, int32_t n_launch,
+                            double* avg_ms, double* bytes) {
+    return guard([&] {
+        check_ctx(c);
+        check_prec(storage);
+        check_eo(true, c);
+        if (n_sys < 1 || n_launch < 1) fail(FS_E_ARG, "n_sys and n_launch must be >= 1");
+        const int nr = rhs_block ? rhs_block : tuned_nr(c, storage, n_sys);
+        if (!pow2_ok(nr)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
+        DeviceScope ds(c->device);
+        const double ms = time_dslash_eo_impl(c, storage, n_sys, nr, n_launch);
+        if (avg_ms) *avg_ms = ms;
+        if (bytes) *bytes = dslash_eo_bytes(storage, c->V, n_sys, nr);
     });
 }
 
