@@ -423,16 +423,28 @@ std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, con
         }
         const long long target = (long long)FS_TC_OVERSUB * 256 * 4 * 4 * 64;
         long long nch = std::max<long long>(1, (target + lanes - 1) / std::max<long long>(1, lanes));
-        int tcv = (int)std::max<long long>(2, (Lt_min + nch - 1) / nch);
-        pl->tc = std::min(tcv, Lt_min);
+        if (!eo) {
+            int tcv = (int)std::max<long long>(2, (Lt_min + nch - 1) / nch);
+            pl->tc = std::min(tcv, Lt_min);
+        } else {  // one-parity fields: tc counts output steps of 2 t-slices
+            const int steps = Lt_min / 2;
+            pl->tc = std::max(1, std::min(steps, (int)((steps + nch - 1) / nch)));
+        }
         pl->wg_start_d.assign(nblk + 1, 0);
         for (int b = 0; b < nblk; ++b) {
             const fs_ctx_s* c = lats[blocks[b].lat];
-            const long long n3 = (long long)(c->V / c->dims[3]) * nr;
-            const long long ntile3 = (n3 + wg - 1) / wg;
-            const long long nchunk = (c->dims[3] + pl->tc - 1) / pl->tc;
-            if (pl->wg_start_d[b] + ntile3 * nchunk > (1ll << 30)) fail(FS_E_ARG, "batch too large for one launch");
-            pl->wg_start_d[b + 1] = pl->wg_start_d[b] + (int)(ntile3 * nchunk);
+            long long cnt;
+            if (!eo) {
+                const long long n3 = (long long)(c->V / c->dims[3]) * nr;
+                const long long ntile3 = (n3 + wg - 1) / wg;
+                cnt = ntile3 * ((c->dims[3] + pl->tc - 1) / pl->tc);
+            } else {  // two parity classes of columns, each walking Lt/2 output steps
+                const long long n3 = (long long)(c->V / c->dims[3] / 2) * nr;
+                const long long ntile3 = (n3 + wg - 1) / wg;
+                cnt = 2 * ntile3 * ((c->dims[3] / 2 + pl->tc - 1) / pl->tc);
+            }
+            if (pl->wg_start_d[b] + cnt > (1ll << 30)) fail(FS_E_ARG, "batch too large for one launch");
+            pl->wg_start_d[b + 1] = pl->wg_start_d[b] + (int)cnt;
         }
     }
     const int nb1 = std::max(nblk, 1);
@@ -644,7 +656,7 @@ struct BatchSolver {
     // With in_loop_reliable the FP64 reliable update of the blocks that asked
     // for one follows at once (no host round trip).
     void iteration(bool in_loop_reliable) {
-        const Work wr = listed(vl_run, o.P, false), wd = o.eo ? wr : listed(vl_run, o.P, true);
+        const Work wr = listed(vl_run, o.P, false), wd = listed(vl_run, o.P, true);
         apply(o.P, D_RHAT, wd, v.f(), p.f(), Fld(), M_RUN, tmp.f());
         launch_finish(F_ALPHA, wd, st(), part(), nullptr, nullptr, s);
         launch_axpy_s(o.P, wr, r.f(), v.f(), st(), s);
@@ -664,8 +676,8 @@ struct BatchSolver {
     // FP64 reliable update of the blocks in vl_pend: x_hi += x_lo,
     // r_hi = b - (D + sigma) x_hi, then either done or resume with r = r_hi.
     void reliable_chain() {
-        const Work wp = listed(vl_pend, o.P, false), wpd = o.eo ? wp : listed(vl_pend, o.P, true);
-        const Work wp64d = listed(vl_pend, P64, !o.eo);
+        const Work wp = listed(vl_pend, o.P, false), wpd = listed(vl_pend, o.P, true);
+        const Work wp64d = listed(vl_pend, P64, true);
         launch_fold(o.P, wp, fx().f(), xlo.f(), st(), s);
         apply(P64, D_RESID, wp64d, fr().f(), fx().f(), fb().f(), M_PEND, tmp64.f());
         launch_finish(F_TRUE, wpd, st(), part(), f_conv(), f_pend(), s);  // clears f_pend
@@ -1581,7 +1593,7 @@ double time_dslash_eo_impl(fs_ctx c, int P, int n_sys, int nr, int n_launch) {
     std::vector<double> diag(pl->nsys, 4.1);
     DevBuf d_diag = to_device(diag.data(), sizeof(double) * diag.size(), 0, s);
     HC(hipStreamSynchronize(s));
-    const Work w = pl->work(P, false);
+    const Work w = pl->work(P, false, true);
     auto hop = [&](int i) {  // odd sites from even ones, then back
         launch_dslash_eo(P, D_HOP, w, (i & 1) ? in.f() : out.f(), (i & 1) ? out.f() : in.f(), Fld(), Fld(),
                          d_diag.as<double>(), nullptr, M_ALL, nullptr, s, nullptr, (i & 1) ? 0 : 1);

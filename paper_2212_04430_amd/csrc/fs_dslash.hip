@@ -718,6 +718,150 @@ __global__ void __launch_bounds__(256) k_dslash_eo(Work w, Fld out, Fld in, Fld 
     });
 }
 
+// The same operator streaming over t.  A workgroup owns wg consecutive
+// (column, rhs) slots of one parity class q = (x+y+z) mod 2 of one block and
+// walks the output sites of those columns, t = tq, tq+2, ... with
+// tq = par_out xor q, through a chunk of tc steps.  All its lanes sit on one
+// t-slice at a time, and the forward-t neighbour psi(x, t+1) loaded for output t
+// gives, with U_t(x, t+1), the backward-t term of output t+2, carried in
+// registers.  Workgroup index within a block: (q, chunk, column tile).
+template <int P, int MODE, bool Q>
+__global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fld cen, Fld aux,
+                                                     const double* __restrict__ diag,
+                                                     const SysState* __restrict__ st, int mask,
+                                                     double* __restrict__ part, const NoiseKey* __restrict__ rk,
+                                                     int par_out) {
+    using A = typename Tr<P>::acc;
+    constexpr int G = Tr<P>::G;
+    constexpr int ND = NDotsEo<MODE>::v;
+    for_each_vwg(w, [&](const int wg_id, const int b) {
+    const BlockDesc bd = w.blocks[b];
+    const LatDesc ld = w.lats[bd.lat];
+    const int wgb = wg_id - w.wg_start[b];
+    const size_t gs = (size_t)ld.Vf << w.lognr;
+    const uint4* ib = in.v + (size_t)bd.slot_off * G;
+    const float* inn = in.n ? in.n + bd.slot_off : nullptr;
+    uint4* ob = out.v + (size_t)bd.slot_off * G;
+    float* on = out.n ? out.n + bd.slot_off : nullptr;
+    const int Lx = ld.L[0], Ly = ld.L[1], Lt = ld.L[3];
+    const int Lxh = Lx >> 1;
+    const int sy = Lx, sz = Lx * Ly, vxyz = sz * ld.L[2];
+    const int n3 = (vxyz >> 1) << w.lognr;  // (column, rhs) slots of one class
+    const int ntile3 = (n3 + w.wg - 1) / w.wg;
+    const int nsteps = Lt >> 1;
+    const int nchunk = (nsteps + w.tc - 1) / w.tc;
+    const int q = wgb / (ntile3 * nchunk);
+    const int rem = wgb - q * (ntile3 * nchunk);
+    const int ch = rem / ntile3, jt = rem - ch * ntile3;
+    const int s3 = jt * w.wg + threadIdx.x;
+    const int k0 = ch * w.tc, k1 = min(nsteps, k0 + w.tc);
+    double acc[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) acc[k] = 0.0;
+    const int col = s3 >> w.lognr;
+    const int r = s3 & (w.nr - 1);
+    const int sys = bd.sys0 + r;
+    const bool valid = s3 < n3;
+    const bool act = valid && mask_ok(mask, st, sys);
+    if (Q ? valid : act) {
+        Coord c;
+        {
+            int qq = col / Lxh;
+            const int xh = col - qq * Lxh;
+            c.y = qq % Ly;
+            c.z = qq / Ly;
+            c.x = 2 * xh + ((c.y + c.z + q) & 1);
+        }
+        const int xyz = c.x + Lx * (c.y + Ly * c.z);
+        const int tq = (par_out ^ q) & 1;
+        // backward-t term of the first output
+        A bw[12];
+        {
+            const int tf = tq + 2 * k0;
+            const int tb = (tf == 0) ? Lt - 1 : tf - 1;
+            const int sb = xyz + vxyz * tb;
+            A v[24], h[12], u[18];
+            load_sp<P, A>(ib, inn, gs, ((size_t)(sb >> 1) << w.lognr) + r, v);
+            PtP::project(v, h);
+            link<P, Q, A>(ld, 3, sb, u);
+            mul_udag(u, h, bw);
+            if (tf == 0 && ld.tsign < 0) {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) bw[k] = -bw[k];
+            }
+        }
+#pragma unroll 1
+        for (int k = k0; k < k1; ++k) {
+            const int t = tq + 2 * k;
+            const int site = xyz + vxyz * t;
+            c.t = t;
+            const size_t slot = ((size_t)(site >> 1) << w.lognr) + r;
+            A o[24];
+#pragma unroll
+            for (int j = 0; j < 24; ++j) o[j] = A(0);
+            A bn[12];  // backward-t term of output t + 2
+            {
+                const bool wrap = (t == Lt - 1);
+                const int sf = wrap ? xyz : site + vxyz;
+                A v[24], h[12], u[18], ww[12];
+                load_sp<P, A>(ib, inn, gs, ((size_t)(sf >> 1) << w.lognr) + r, v);
+                PtM::project(v, h);
+                link<P, Q, A>(ld, 3, site, u);
+                mul_u(u, h, ww);
+                PtM::accum(o, ww, (wrap && ld.tsign < 0) ? A(0.5) : A(-0.5));
+                PtP::project(v, h);
+                link<P, Q, A>(ld, 3, sf, u);
+                mul_udag(u, h, bn);
+            }
+            PtP::accum(o, bw, A(-0.5));
+#pragma unroll
+            for (int j = 0; j < 12; ++j) bw[j] = bn[j];
+            hop_dir_h<P, Q, true, 0, PxM, PxP>(ld, ib, inn, gs, site, c.x, 1, r, w.lognr, o);
+            hop_dir_h<P, Q, true, 1, PyM, PyP>(ld, ib, inn, gs, site, c.y, sy, r, w.lognr, o);
+            hop_dir_h<P, Q, true, 2, PzM, PzP>(ld, ib, inn, gs, site, c.z, sz, r, w.lognr, o);
+            A cv[24];
+            if constexpr (MODE != D_HOP) {
+                load_sp<P, A>(cen.v + (size_t)bd.slot_off * G, cen.n ? cen.n + bd.slot_off : nullptr, gs, slot, cv);
+                const A a = (A)diag[sys];
+                const A ia = A(1) / a;
+#pragma unroll
+                for (int j = 0; j < 24; ++j) o[j] = a * cv[j] - ia * o[j];
+            }
+            if constexpr (MODE == D_RESID) {
+                A bv[24];
+                load_sp<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
+#pragma unroll
+                for (int j = 0; j < 24; ++j) o[j] = bv[j] - o[j];
+            }
+            store_sp<P, A>(ob, on, gs, slot, o);
+            if (act) {
+                if constexpr (MODE == D_RHAT) {
+                    A rh[24];
+                    rhat_site<A>(rk[sys], st[sys].restarts, site >> 1, rh);
+#pragma unroll
+                    for (int j = 0; j < 12; ++j) {
+                        acc[0] += (double)rh[2 * j] * (double)o[2 * j] + (double)rh[2 * j + 1] * (double)o[2 * j + 1];
+                        acc[1] += (double)rh[2 * j] * (double)o[2 * j + 1] - (double)rh[2 * j + 1] * (double)o[2 * j];
+                    }
+                } else if constexpr (MODE == D_TS) {
+#pragma unroll
+                    for (int j = 0; j < 12; ++j) {
+                        const double tr = o[2 * j], ti = o[2 * j + 1], sr = cv[2 * j], si = cv[2 * j + 1];
+                        acc[0] += tr * sr + ti * si;
+                        acc[1] += tr * si - ti * sr;
+                        acc[2] += tr * tr + ti * ti;
+                    }
+                } else if constexpr (MODE == D_RESID) {
+#pragma unroll
+                    for (int j = 0; j < 24; ++j) acc[0] += (double)o[j] * (double)o[j];
+                }
+            }
+        }
+    }
+    if constexpr (MODE == D_RHAT || MODE == D_TS || MODE == D_RESID) block_partials<ND, 4>(acc, w.nr, part, wg_id);
+    });
+}
+
 // FP64, over a one-parity plan: bh = b_e - D_eo b_o / a; partials |b_e|^2 + |b_o|^2.
 __global__ void __launch_bounds__(256) k_eo_prep(Work w, const BlockDesc* __restrict__ fblocks, Fld bfull, Fld bh,
                                                  const double* __restrict__ diag, double* __restrict__ part) {
@@ -869,6 +1013,15 @@ void launch_dslash(int prec, int mode, const Work& w, Fld out, Fld in, Fld aux, 
 template <int P, int MODE>
 static void launch_eo_q(const Work& w, Fld out, Fld in, Fld cen, Fld aux, const double* diag, const SysState* st,
                         int mask, double* part, hipStream_t s, const NoiseKey* rk, int par_out) {
+    if (w.tc > 0) {  // stencil mapping: t-streaming
+        if (w.nr >= 4)
+            hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, true>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen,
+                               aux, diag, st, mask, part, rk, par_out);
+        else
+            hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, false>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen,
+                               aux, diag, st, mask, part, rk, par_out);
+        return;
+    }
     if (w.nr >= 4)
         hipLaunchKernelGGL((k_dslash_eo<P, MODE, true>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen, aux,
                            diag, st, mask, part, rk, par_out);

@@ -181,8 +181,9 @@ enum DMode : int {
 //   D_HOP:    out = D_{par_out, 1-par_out} in
 //   other modes (par_out = even): out = a cen - D_eo in / a with in = D_oe cen,
 //   and the partial sums of launch_dslash (D_RESID: out = b - S cen, b in aux).
-// Launched with the tile mapping (one slot per lane); the finish that follows
-// takes the same mapping.
+// With the stencil mapping of a one-parity plan (w.tc > 0) the kernel streams
+// over t; with the tile mapping it takes one slot per lane.  The finish that
+// follows takes the same mapping.
 void launch_dslash_eo(int prec, int mode, const Work& w, Fld out, Fld in, Fld cen, Fld aux, const double* diag,
                       const SysState* st, int mask, double* part, hipStream_t s, const NoiseKey* rk, int par_out);
 // Over a one-parity plan whose blocks match fblocks (full-lattice layout) one
