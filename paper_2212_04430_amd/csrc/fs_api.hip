@@ -79,7 +79,20 @@ fs_status guard(F&& f) {
 struct Pool {
     std::multimap<std::pair<int, size_t>, void*> free_;
     size_t cached = 0;
-    static constexpr size_t kMaxCached = (size_t)8 << 30;
+    size_t cap = 0;
+    // Cache limit: half the device memory, so that the fields of a large batch
+    // (tens of GB) are reused by the next solve of the same shape instead of
+    // being released and allocated again, which costs about as much as the
+    // solve.  Allocation failures release the cache (get), and so does
+    // destroying the last context.
+    size_t limit() {
+        if (!cap) {
+            size_t f = 0, t = 0;
+            cap = (hipMemGetInfo(&f, &t) == hipSuccess && t > 0) ? t / 2 : ((size_t)8 << 30);
+            cap = std::max(cap, (size_t)8 << 30);
+        }
+        return cap;
+    }
     static size_t round(size_t n) {
         if (n <= (1u << 20)) return (n + 255) & ~(size_t)255;
         const size_t g = (size_t)2 << 20;
@@ -109,7 +122,7 @@ struct Pool {
         (void)hipGetDevice(&dev);
         free_.insert({{dev, n}, p});
         cached += n;
-        if (cached > kMaxCached) trim(kMaxCached / 2);
+        if (cached > limit()) trim(limit() / 2);
     }
     void trim(size_t keep) {
         while (cached > keep && !free_.empty()) {
@@ -121,6 +134,8 @@ struct Pool {
         }
     }
 };
+int g_live_ctx = 0;  // contexts alive; the device cache is released with the last
+
 Pool& pool() {
     static Pool* p = new Pool();  // never destroyed: blocks live until process exit
     return *p;
@@ -1651,6 +1666,7 @@ fs_status fs_create(fs_ctx* out, const int32_t dims[4], int32_t t_antiperiodic, 
             c->own_stream = true;
         }
         *out = c.release();
+        ++g_live_ctx;
     });
 }
 
@@ -1664,6 +1680,10 @@ fs_status fs_destroy(fs_ctx c) {
             if (c->own_stream) (void)hipStreamDestroy(c->stream);
         }
         delete c;
+        if (--g_live_ctx <= 0) {
+            g_live_ctx = 0;
+            pool().trim(0);
+        }
     });
 }
 
