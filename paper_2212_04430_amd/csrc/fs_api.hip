@@ -83,8 +83,9 @@ struct Pool {
     // Cache limit: half the device memory, so that the fields of a large batch
     // (tens of GB) are reused by the next solve of the same shape instead of
     // being released and allocated again, which costs about as much as the
-    // solve.  Allocation failures release the cache (get), and so does
-    // destroying the last context.
+    // solve.  An allocation that would leave less than a reserve of free
+    // memory releases the cache first (get), and so does destroying the last
+    // context.
     size_t limit() {
         if (!cap) {
             size_t f = 0, t = 0;
@@ -108,6 +109,15 @@ struct Pool {
             cached -= n;
             *err = hipSuccess;
             return p;
+        }
+        // keep a reserve of free device memory for the runtime (kernel launches,
+        // graphs): cached blocks go first
+        if (cached > 0) {
+            size_t f = 0, t = 0;
+            if (hipMemGetInfo(&f, &t) == hipSuccess) {
+                const size_t reserve = std::max((size_t)16 << 30, t / 12);
+                if (f < n + reserve) trim(0);
+            }
         }
         void* p = nullptr;
         *err = hipMalloc(&p, n);
