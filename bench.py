@@ -106,10 +106,11 @@ def cpu_baseline(U, dims, avg_iters, sel_inputs=None):
 
 
 def kernel_source_hash():
-    """Hash of the stencil's sources: counters taken on other code do not apply."""
+    """Hash of the stencil's sources and of the file holding its launch
+    configuration rules: counters taken on other code do not apply."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("fs_dslash.hip", "fs_device.h", "fs_kernels.h"):
+    for f in ("fs_dslash.hip", "fs_device.h", "fs_kernels.h", "fs_api.hip"):
         with open(os.path.join(ROOT, "paper_2212_04430_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -320,8 +321,8 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / (ms_d * 1e-3) / 1e9, 1),
                 "traffic_bytes_per_launch": traffic,
-                "kernel": f"k_dslash_eo<P32> D_HOP (one parity out), {ROOFLINE_NSYS} systems, rhs_block {nr}, "
-                          f"wg 256",
+                "kernel": f"k_dslash_eo_t<P32> D_HOP (one parity out), {ROOFLINE_NSYS} systems, rhs_block {nr}, "
+                          f"wg 256, the solver's residency cap",
                 "full_lattice_dslash": {"kernel": f"k_dslash<P32> D_PLAIN, rhs_block {nr}, wg {wg}",
                                         "avg_launch_ms": round(ms_full, 5), "achieved": round(full_gbs, 1),
                                         "frac": round(full_gbs / HBM_PEAK_GBS, 4)},

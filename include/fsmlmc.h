@@ -288,12 +288,14 @@ fs_status fs_time_dslash(fs_ctx ctx, fs_prec storage, int32_t n_sys, int32_t rhs
 /*
  * fs_time_dslash_eo -- as fs_time_dslash for the even-odd hop D_oe / D_eo (one
  * parity out, one in; the kernel of the even-odd preconditioned solver), on
- * n_sys systems in blocks of rhs_block (0 = tuned), every extent even.  bytes:
+ * n_sys systems in blocks of rhs_block (0 = tuned), residency cap occ (waves
+ * per SIMD, 0 = none, -1 = the one the even-odd solver uses), every extent
+ * even.  bytes:
  * per output site and system 48 stored reals (+ FP16 scales), plus every link
  * of the lattice (72 reals per site) once per block.
  */
-fs_status fs_time_dslash_eo(fs_ctx ctx, fs_prec storage, int32_t n_sys, int32_t rhs_block, int32_t n_launch,
-                            double* avg_ms, double* bytes);
+fs_status fs_time_dslash_eo(fs_ctx ctx, fs_prec storage, int32_t n_sys, int32_t rhs_block, int32_t occ,
+                            int32_t n_launch, double* avg_ms, double* bytes);
 
 /*
  * fs_time_copy -- average duration (ms, HIP events on the context's stream) of

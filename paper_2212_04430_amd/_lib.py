@@ -101,8 +101,8 @@ _sig = {
     "fs_time_dslash": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "fs_time_copy": (C.c_int, [_P, C.c_uint64, C.c_int32, C.POINTER(C.c_double)]),
-    "fs_time_dslash_eo": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
-                                    C.POINTER(C.c_double)]),
+    "fs_time_dslash_eo": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "fs_probing_colours": (C.c_int, [C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_int32)]),
     "fs_estimate_probed": (C.c_int, [_P, C.POINTER(fs_est_params), _P, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
@@ -334,11 +334,11 @@ def fs_set_tuning(ctx, storage, rhs_block, wg, variant, occ=0):
     _check(_lib.fs_set_tuning(ctx, _prec(storage), int(rhs_block), int(wg), int(variant), int(occ)))
 
 
-def fs_time_dslash_eo(ctx, storage, n_sys, rhs_block=0, n_launch=20):
+def fs_time_dslash_eo(ctx, storage, n_sys, rhs_block=0, n_launch=20, occ=-1):
     ms = C.c_double()
     b = C.c_double()
-    _check(_lib.fs_time_dslash_eo(ctx, _prec(storage), int(n_sys), int(rhs_block), int(n_launch), C.byref(ms),
-                                  C.byref(b)))
+    _check(_lib.fs_time_dslash_eo(ctx, _prec(storage), int(n_sys), int(rhs_block), int(occ), int(n_launch),
+                                  C.byref(ms), C.byref(b)))
     return ms.value, b.value
 
 

@@ -506,16 +506,22 @@ std::unique_ptr<Plan> make_plan(const std::vector<int>& blk_lat, const std::vect
     return plan_from_blocks(blocks, lats, nr, wg, s, ilp, occ, eo);
 }
 
+// Residency cap of the even-odd stencil (waves per SIMD, 0 = none): a sweep of
+// the FP32 hop on the 16^3x32 workload (96 systems) found 3 fastest at rhs
+// block 4 (0.571 against 0.635 ms uncapped) and no gain at other blocks or in
+// FP16.
+int eo_occ(int P, int nr) { return (P == P32 && nr == 4) ? 3 : 0; }
+
 // The one-parity plan of a full-lattice plan: the same blocks and systems, each
 // block holding V/2 sites (even-odd preconditioning).
-std::unique_ptr<Plan> eo_plan_of(const Plan& full, const std::vector<fs_ctx_s*>& lats, hipStream_t s) {
+std::unique_ptr<Plan> eo_plan_of(const Plan& full, const std::vector<fs_ctx_s*>& lats, hipStream_t s, int occ) {
     std::vector<BlockDesc> blocks = full.blocks;
     long long off = 0;
     for (auto& bd : blocks) {
         bd.slot_off = off;
         off += (long long)(lats[bd.lat]->V / 2) * full.nr;
     }
-    return plan_from_blocks(blocks, lats, full.nr, full.wg, s, 0, 0, 1);
+    return plan_from_blocks(blocks, lats, full.nr, full.wg, s, 0, occ, 1);
 }
 
 // FP64 true residual of a system relative to its source (the full system's
@@ -583,7 +589,8 @@ struct BatchSolver {
     size_t part_rows = 0;
 
     BatchSolver(Plan& plan, const std::vector<fs_ctx_s*>& l, hipStream_t stream, const SolveOpts& opts)
-        : full(plan), eo_pl(opts.eo ? eo_plan_of(plan, l, stream) : nullptr), pl(opts.eo ? *eo_pl : plan),
+        : full(plan), eo_pl(opts.eo ? eo_plan_of(plan, l, stream, eo_occ(opts.P, plan.nr)) : nullptr),
+          pl(opts.eo ? *eo_pl : plan),
           cur(&pl), lats(l), s(stream), o(opts) {
         const long long S = pl.total_slots;
         b.alloc(P64, full.total_slots);
@@ -1597,12 +1604,12 @@ double dslash_eo_bytes(int P, long long V, int n_sys, int nr) {
     return (double)(V / 2) * per_sys * n_sys + (double)V * 72.0 * w * nblk;
 }
 
-double time_dslash_eo_impl(fs_ctx c, int P, int n_sys, int nr, int n_launch) {
+double time_dslash_eo_impl(fs_ctx c, int P, int n_sys, int nr, int occ, int n_launch) {
     hipStream_t s = c->stream;
     const int nblk = (n_sys + nr - 1) / nr;
     std::vector<int> blk_lat(nblk, 0);
     std::vector<fs_ctx_s*> lats{c};
-    auto pl = make_plan(blk_lat, lats, nr, 256, s, 0, 0, 1);
+    auto pl = make_plan(blk_lat, lats, nr, 256, s, 0, occ, 1);
     Field in, out;
     in.alloc(P, pl->total_slots);
     out.alloc(P, pl->total_slots);
@@ -2181,8 +2188,8 @@ fs_status fs_time_dslash(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_b
     });
 }
 
-fs_status fs_time_dslash_eo(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_block, int32_t n_launch,
-                            double* avg_ms, double* bytes) {
+fs_status fs_time_dslash_eo(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_block, int32_t occ,
+                            int32_t n_launch, double* avg_ms, double* bytes) {
     return guard([&] {
         check_ctx(c);
         check_prec(storage);
@@ -2191,7 +2198,8 @@ fs_status fs_time_dslash_eo(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rh
         const int nr = rhs_block ? rhs_block : tuned_nr(c, storage, n_sys);
         if (!pow2_ok(nr)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
         DeviceScope ds(c->device);
-        const double ms = time_dslash_eo_impl(c, storage, n_sys, nr, n_launch);
+        if (occ > 8) fail(FS_E_ARG, "occ must be -1 (the solver's choice) or 0..8");
+        const double ms = time_dslash_eo_impl(c, storage, n_sys, nr, occ < 0 ? eo_occ(storage, nr) : occ, n_launch);
         if (avg_ms) *avg_ms = ms;
         if (bytes) *bytes = dslash_eo_bytes(storage, c->V, n_sys, nr);
     });

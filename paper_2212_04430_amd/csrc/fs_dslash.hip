@@ -1013,13 +1013,14 @@ void launch_dslash(int prec, int mode, const Work& w, Fld out, Fld in, Fld aux, 
 template <int P, int MODE>
 static void launch_eo_q(const Work& w, Fld out, Fld in, Fld cen, Fld aux, const double* diag, const SysState* st,
                         int mask, double* part, hipStream_t s, const NoiseKey* rk, int par_out) {
-    if (w.tc > 0) {  // stencil mapping: t-streaming
+    if (w.tc > 0) {  // stencil mapping: t-streaming, with the plan's residency cap
+        const size_t lds = lds_cap(w.wg, w.occ);
         if (w.nr >= 4)
-            hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, true>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen,
+            hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, true>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, cen,
                                aux, diag, st, mask, part, rk, par_out);
         else
-            hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, false>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen,
-                               aux, diag, st, mask, part, rk, par_out);
+            hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, false>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in,
+                               cen, aux, diag, st, mask, part, rk, par_out);
         return;
     }
     if (w.nr >= 4)
