@@ -164,10 +164,14 @@ def test_uneven_batch_matches_single_instances(L):
             L.fs_destroy(c)
 
 
-def test_full_size_cfg4_properties(L):
+@pytest.mark.parametrize("eo,nr", [(0, 16), (1, 4)])
+def test_full_size_cfg4_properties(L, eo, nr):
     """16^3 x 32 at the benchmark's launch configuration (batched, FP32 storage,
-    FP64 reliable updates, graph): sampled solutions verified by the oracle's
-    FP64 residual, and the bilinear of a verified solution against the oracle."""
+    FP64 reliable updates, graph; even-odd preconditioned at rhs block 4 as the
+    benchmark runs it, and unpreconditioned): sampled solutions verified by the
+    oracle's FP64 residual, the bilinear of a verified solution against the
+    oracle, and last-level estimator samples against the oracle's bilinears of
+    verified solutions on the same noise."""
     dims = (16, 16, 16, 32)
     V = lat.volume(dims)
     U = synth.gauge_field(dims, eps=0.2, seed=0)
@@ -177,8 +181,8 @@ def test_full_size_cfg4_properties(L):
         from oracle.philox import z4_noise
         B = np.stack([z4_noise(V, 1, 0, 0, s) for s in range(2)])
         sig = [0.0, 1.0]
-        prm = L.solve_params(0.02, tol=1e-10, storage="f32", batched=1, rhs_block=16, use_graph=1)
-        print("cfg4-size solve", flush=True)
+        prm = L.solve_params(0.02, tol=1e-10, storage="f32", batched=1, rhs_block=nr, use_graph=1, even_odd=eo)
+        print(f"cfg4-size solve even_odd={eo} nr={nr}", flush=True)
         X, stats, code = L.fs_solve_shifted(ctx, prm, sig, B)
         assert code == 0
         for i, s in enumerate(sig):
@@ -189,9 +193,20 @@ def test_full_size_cfg4_properties(L):
         ref = ofs.bilinears(U, dims, B[1], X[0, 0], list(range(16)), 3)
         assert np.abs(got.T - ref).max() <= 1e-12 * np.abs(ref).max()
         # one estimator step at this size: every level's solves meet the FP64 tolerance
+        sig_e = [0.0, 0.05, 0.25, 0.5, 1.0]
         prm_e = L.fs_est_params(1, 2, 0, 2, prm)
-        stats_e, _, rep = L.fs_estimate(ctx, prm_e, [0.0, 0.05, 0.25, 0.5, 1.0])
+        stats_e, X_e, rep = L.fs_estimate(ctx, prm_e, sig_e, want_samples=True)
         assert rep.systems == 2 * 9 and rep.max_rel_residual <= 1e-10
         assert np.all(stats_e[..., 5] <= 1e-10)
+        # last level, sample by sample: z^+ Gamma Omega_p x with x = (D + sigma_L)^-1 z
+        Lv = len(sig_e) - 1
+        Z = np.stack([z4_noise(V, 1, 0, Lv, s) for s in range(2)])
+        Xl, _, code = L.fs_solve_shifted(ctx, prm, [sig_e[Lv]], Z)
+        assert code == 0
+        for s in range(2):
+            rel = np.linalg.norm(Z[s] - lat.wilson_apply(U, Xl[0, s], 0.02, sig_e[Lv], dims)) / np.linalg.norm(Z[s])
+            assert rel <= 1.5e-10
+            ref = ofs.bilinears(U, dims, Z[s], Xl[0, s], list(range(16)), 2)
+            assert np.abs(X_e[Lv, s] - ref).max() <= 1e-7 * np.abs(ref).max(), s
     finally:
         L.fs_destroy(ctx)
