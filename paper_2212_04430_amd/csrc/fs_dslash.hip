@@ -863,6 +863,8 @@ __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fl
 }
 
 // FP64, over a one-parity plan: bh = b_e - D_eo b_o / a; partials |b_e|^2 + |b_o|^2.
+// Q: quad-shared links (rhs blocks of 4 or more; the quads of a slot range are whole).
+template <bool Q>
 __global__ void __launch_bounds__(256) k_eo_prep(Work w, const BlockDesc* __restrict__ fblocks, Fld bfull, Fld bh,
                                                  const double* __restrict__ diag, double* __restrict__ part) {
     for_each_vwg(w, [&](const int wg_id, const int b) {
@@ -885,7 +887,7 @@ __global__ void __launch_bounds__(256) k_eo_prep(Work w, const BlockDesc* __rest
         double h[24], be[24], bo[24];
 #pragma unroll
         for (int k = 0; k < 24; ++k) h[k] = 0.0;
-        hop_all<P64, false, false>(ld, fb, nullptr, gsf, se, c, r, w.lognr, h);
+        hop_all<P64, Q, false>(ld, fb, nullptr, gsf, se, c, r, w.lognr, h);
         load_sp<P64, double>(fb, nullptr, gsf, ((size_t)se << w.lognr) + r, be);
         load_sp<P64, double>(fb, nullptr, gsf, ((size_t)so << w.lognr) + r, bo);
         const double ia = 1.0 / diag[sys];
@@ -901,6 +903,7 @@ __global__ void __launch_bounds__(256) k_eo_prep(Work w, const BlockDesc* __rest
 }
 
 // FP64: x (full layout) = x_e at even sites, (b_o - D_oe x_e) / a at odd sites.
+template <bool Q>
 __global__ void __launch_bounds__(256) k_eo_post(Work w, const BlockDesc* __restrict__ fblocks, Fld bfull, Fld xh,
                                                  Fld xfull, const double* __restrict__ diag) {
     for_each_vwg(w, [&](const int wg_id, const int b) {
@@ -924,7 +927,7 @@ __global__ void __launch_bounds__(256) k_eo_post(Work w, const BlockDesc* __rest
         double h[24], bo[24], xe[24];
 #pragma unroll
         for (int k = 0; k < 24; ++k) h[k] = 0.0;
-        hop_all<P64, false, true>(ld, hx, nullptr, gsh, so, c, r, w.lognr, h);
+        hop_all<P64, Q, true>(ld, hx, nullptr, gsh, so, c, r, w.lognr, h);
         load_sp<P64, double>(fb, nullptr, gsf, ((size_t)so << w.lognr) + r, bo);
         load_sp<P64, double>(hx, nullptr, gsh, slot, xe);
         const double ia = 1.0 / diag[sys];
@@ -1060,12 +1063,18 @@ void launch_dslash_eo(int prec, int mode, const Work& w, Fld out, Fld in, Fld ce
 
 void launch_eo_prep(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld bh, const double* diag, double* part,
                     hipStream_t s) {
-    hipLaunchKernelGGL(k_eo_prep, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, bh, diag, part);
+    if (wh.nr >= 4)
+        hipLaunchKernelGGL(k_eo_prep<true>, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, bh, diag, part);
+    else
+        hipLaunchKernelGGL(k_eo_prep<false>, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, bh, diag, part);
 }
 
 void launch_eo_post(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld xh, Fld xfull, const double* diag,
                     hipStream_t s) {
-    hipLaunchKernelGGL(k_eo_post, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, xh, xfull, diag);
+    if (wh.nr >= 4)
+        hipLaunchKernelGGL(k_eo_post<true>, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, xh, xfull, diag);
+    else
+        hipLaunchKernelGGL(k_eo_post<false>, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, xh, xfull, diag);
 }
 
 }  // namespace fs
