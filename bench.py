@@ -139,12 +139,18 @@ def setup_tuning():
     return path
 
 
+def link_form(L, ctx):
+    """'2row' when the FP32 stencils rebuild row 2 of the links, else 'whole'."""
+    return "2row" if L.fs_gauge_info(ctx)[0] else "whole"
+
+
 def roofline_only(L, ctx, nr, wg):
     """The launches the roofline reports, alone (for hardware-counter runs)."""
     ms_c = L.fs_time_copy(ctx, 1 << 30, 20)
     ms_d, by = L.fs_time_dslash_eo(ctx, "f32", ROOFLINE_NSYS, nr, 50)
     print(json.dumps({"copy_bytes": 1 << 30, "copy_ms": ms_c, "dslash_ms": ms_d, "dslash_bytes": by,
-                      "config": f"f32-eo nsys={ROOFLINE_NSYS} nr={nr} wg=256", "hash": kernel_source_hash()}))
+                      "config": f"f32-eo,nsys={ROOFLINE_NSYS},nr={nr},wg=256,links={link_form(L, ctx)}",
+                      "hash": kernel_source_hash()}))
 
 
 def probed_estimate(L, ctx, nr, dims):
@@ -313,7 +319,8 @@ def main():
     ms_d, bytes_d = L.fs_time_dslash_eo(ctx, "f32", ROOFLINE_NSYS, nr, 50)
     ms_c = L.fs_time_copy(ctx, 1 << 30, 20)
     achieved = bytes_d / (ms_d * 1e-3) / 1e9
-    cfg_key = f"f32-eo,nsys={ROOFLINE_NSYS},nr={nr},wg=256"
+    links = link_form(L, ctx)
+    cfg_key = f"f32-eo,nsys={ROOFLINE_NSYS},nr={nr},wg=256,links={links}"
     ms_full, bytes_full = L.fs_time_dslash(ctx, "f32", ROOFLINE_NSYS, nr, wg, 50)
     full_gbs = bytes_full / (ms_full * 1e-3) / 1e9
     traffic = committed_traffic(cfg_key)
@@ -322,7 +329,9 @@ def main():
                 "traffic": None if traffic is None else round(traffic / (ms_d * 1e-3) / 1e9, 1),
                 "traffic_bytes_per_launch": traffic,
                 "kernel": f"k_dslash_eo_t<P32> D_HOP (one parity out), {ROOFLINE_NSYS} systems, rhs_block {nr}, "
-                          f"wg 256, the solver's residency cap",
+                          f"wg 256, the solver's residency cap, "
+                          + ("links as rows 0-1 with row 2 rebuilt (12 reals)" if links == "2row"
+                             else "whole links (18 reals)"),
                 "full_lattice_dslash": {"kernel": f"k_dslash<P32> D_PLAIN, rhs_block {nr}, wg {wg}",
                                         "avg_launch_ms": round(ms_full, 5), "achieved": round(full_gbs, 1),
                                         "frac": round(full_gbs / HBM_PEAK_GBS, 4)},

@@ -90,8 +90,21 @@ fs_status fs_set_instance(fs_ctx ctx, uint32_t instance);
  * the context, which keeps FP64, FP32, FP16 and BF16 device copies in its
  * internal structure-of-arrays layout.  Links are used as given (no
  * re-unitarisation).  Must precede every operator call (FS_E_STATE).
+ * When every link is special unitary to 1e-9 (its third row equals the
+ * conjugated cross product of the first two, checked on the host), the FP32
+ * stencils of blocks of 4 or more systems read rows 0-1 only and rebuild row 2
+ * (the context also keeps the whole links); other links are read whole.
  */
 fs_status fs_upload_gauge(fs_ctx ctx, const double* links, int32_t is_device);
+
+/*
+ * fs_gauge_info -- how the uploaded links are stored.
+ *   two_rows    1: FP32 stencils rebuild row 2 of each link from rows 0-1
+ *               (the links are special unitary to 1e-9); 0: whole links.
+ *   su3_defect  max over links and columns j of |U_2j - conj(U_0 x U_1)_j|.
+ * Either output may be NULL.  FS_E_STATE before fs_upload_gauge.
+ */
+fs_status fs_gauge_info(fs_ctx ctx, int32_t* two_rows, double* su3_defect);
 
 /*
  * fs_apply_dirac -- out = (D + sigma) in for n_rhs spinors (canonical layout).

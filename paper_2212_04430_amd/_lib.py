@@ -82,6 +82,7 @@ _sig = {
     "fs_destroy": (C.c_int, [_P]),
     "fs_set_instance": (C.c_int, [_P, C.c_uint32]),
     "fs_upload_gauge": (C.c_int, [_P, _P, C.c_int32]),
+    "fs_gauge_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "fs_apply_dirac": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, _P, _P, C.c_int32, C.c_int32]),
     "fs_z4_noise": (C.c_int, [_P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, _P, C.c_int32]),
     "fs_displace": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int32]),
@@ -193,6 +194,14 @@ def fs_upload_gauge(ctx, links):
         links = _host_c128(links)
     p, dev = _ptr(links)
     _check(_lib.fs_upload_gauge(ctx, p, dev))
+
+
+def fs_gauge_info(ctx):
+    """(two_rows, su3_defect): whether the FP32 stencils rebuild row 2 of the links."""
+    tr = C.c_int32(0)
+    d = C.c_double(0.0)
+    _check(_lib.fs_gauge_info(ctx, C.byref(tr), C.byref(d)))
+    return bool(tr.value), d.value
 
 
 def fs_apply_dirac(ctx, m0, sigma, storage, psi):

@@ -204,7 +204,36 @@ struct HostBuf {
 
 int prec_group_bytes_spinor(int P) { return P == P64 ? 192 : P == P32 ? 96 : 48; }
 int prec_link_complex_bytes(int P) { return P == P64 ? 16 : P == P32 ? 8 : 4; }
-int prec_link_site_bytes(int P) { return P == P64 ? 144 : P == P32 ? 80 : 48; }  // site-major, 16-byte chunks
+// Site-major link bytes: 16-byte chunks of the full (9 complex) or, for
+// FP32, the two-row (6 complex) form.
+int prec_link_site_bytes(int P, bool two_rows) {
+    if (two_rows && P == P32) return 48;
+    return P == P64 ? 144 : P == P32 ? 80 : 48;
+}
+
+// Links whose third row equals the conjugated cross product of the first two
+// within this bound are stored in the two-row form: the rebuilt row then
+// differs from the stored one by far less than FP32 rounding (6e-8).
+constexpr double kSu3RowTol = 1e-9;
+
+// max over links and j of |U_2j - conj(U_0k U_1l - U_0l U_1k)|, (j, k, l)
+// cyclic; u is the canonical layout, n_links row-major 3x3 complex matrices.
+double su3_row_defect(const double* u, size_t n_links) {
+    double worst = 0.0;
+    for (size_t i = 0; i < n_links; ++i) {
+        const double* m = u + 18 * i;
+        for (int j = 0; j < 3; ++j) {
+            const int k = (j + 1) % 3, l = (j + 2) % 3;
+            const double akr = m[2 * k], aki = m[2 * k + 1], alr = m[2 * l], ali = m[2 * l + 1];
+            const double bkr = m[6 + 2 * k], bki = m[7 + 2 * k], blr = m[6 + 2 * l], bli = m[7 + 2 * l];
+            const double re = (akr * blr - aki * bli) - (alr * bkr - ali * bki);
+            const double im = (akr * bli + aki * blr) - (alr * bki + ali * bkr);
+            const double d = std::hypot(m[12 + 2 * j] - re, m[13 + 2 * j] + im);
+            if (!(d <= worst)) worst = d;  // NaN propagates as "not special unitary"
+        }
+    }
+    return worst;
+}
 int prec_groups(int P) { return P == P64 ? 12 : P == P32 ? 6 : 3; }
 
 // ============================================================== gamma table
@@ -266,6 +295,9 @@ struct fs_ctx_s {
     bool has_gauge = false;
     DevBuf gauge[4];                 // [mu][9][site] per precision
     DevBuf gauge_q[4];               // [mu][site][QC 16-byte chunks] per precision
+    DevBuf gauge_q2[4];              // rows 0-1 only, [mu][site][QCR chunks] (FP32 entry only)
+    bool two_rows = false;           // gauge_q2 is filled: every link is special unitary
+    double su3_defect = 0.0;         // max |U_2j - conj(U_0 x U_1)_j| over the uploaded links
     std::map<int, TuneEntry> tune;   // per precision
     HostBuf pinned;
 };
@@ -288,7 +320,8 @@ struct DeviceScope {
     }
 };
 
-LatDesc lat_desc(const fs_ctx_s* c, int P, int eo = 0) {
+// two_rows: the plan's FP32 stencils rebuild row 2.
+LatDesc lat_desc(const fs_ctx_s* c, int P, int eo = 0, bool two_rows = false) {
     LatDesc d;
     for (int i = 0; i < 4; ++i) d.L[i] = c->dims[i];
     d.V = c->V;
@@ -296,7 +329,7 @@ LatDesc lat_desc(const fs_ctx_s* c, int P, int eo = 0) {
     d.eo = eo;
     d.tsign = c->tsign;
     d.gauge = c->gauge[P].p;
-    d.gauge_q = c->gauge_q[P].p;
+    d.gauge_q = (two_rows && P == P32) ? c->gauge_q2[P].p : c->gauge_q[P].p;
     return d;
 }
 
@@ -316,6 +349,7 @@ bool pow2_ok(int n) { return n >= 1 && n <= 16 && (n & (n - 1)) == 0; }
 struct Plan {
     int nr = 1, lognr = 0, wg = 256, tpw = 1;
     int eo = 0;                       // 1: fields of one parity (V/2 sites per system)
+    bool two_rows = false;            // every lattice holds special unitary links (two-row loads)
     int ilp = 0, occ = 0;             // stencil variant and residency cap
     int tl[3] = {0, 0, 0};            // stencil variant 2: log2 tile extents
     int nsys = 0;                     // nblk * nr
@@ -345,6 +379,7 @@ struct Plan {
         w.ilp = stencil ? ilp : 0;
         for (int k = 0; k < 3; ++k) w.tl[k] = tl[k];
         w.occ = stencil ? occ : 0;
+        w.two_rows = (P == P32 && two_rows) ? 1 : 0;
         w.vlist = nullptr;
         w.vstart = nullptr;
         w.vcount = nullptr;
@@ -482,9 +517,11 @@ std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, con
     HC(hipMemcpyAsync(pl->d_wg_start.p, pl->wg_start.data(), sizeof(int) * (nblk + 1), hipMemcpyHostToDevice, s));
     HC(hipMemcpyAsync(pl->d_wg_start_d.p, pl->wg_start_d.data(), sizeof(int) * (nblk + 1), hipMemcpyHostToDevice, s));
     HC(hipMemcpyAsync(pl->d_blk_on.p, ones.data(), sizeof(int) * nb1, hipMemcpyHostToDevice, s));
+    pl->two_rows = !lats.empty();
+    for (auto* c : lats) pl->two_rows = pl->two_rows && c->two_rows;
     std::vector<LatDesc> ld[4];
     for (int P = 0; P < 4; ++P) {
-        for (auto* c : lats) ld[P].push_back(lat_desc(c, P, eo));
+        for (auto* c : lats) ld[P].push_back(lat_desc(c, P, eo, pl->two_rows));
         pl->d_lats[P].alloc(sizeof(LatDesc) * ld[P].size());
         HC(hipMemcpyAsync(pl->d_lats[P].p, ld[P].data(), sizeof(LatDesc) * ld[P].size(), hipMemcpyHostToDevice, s));
     }
@@ -1545,12 +1582,18 @@ void estimate_impl(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm,
 
 // ============================================================== dslash timing
 
-double dslash_bytes(int P, long long V, int n_sys, int nr) {
+// Link reals the stencil reads per site (4 directions): 72, or 48 when the
+// FP32 quad-shared loads (rhs blocks of 4 or more) take the two-row form.
+double link_reals_per_site(int P, int nr, bool two_rows) {
+    return (two_rows && P == P32 && nr >= 4) ? 48.0 : 72.0;
+}
+
+double dslash_bytes(int P, long long V, int n_sys, int nr, bool two_rows) {
     const double ws = P == P64 ? 8 : P == P32 ? 4 : 2;
     const double wg = ws;
     double per_sys = 48.0 * ws + (P == P16 ? 8.0 : 0.0);
     const long long nblk = (n_sys + nr - 1) / nr;
-    return (double)V * (per_sys * n_sys + 72.0 * wg * nblk);
+    return (double)V * (per_sys * n_sys + link_reals_per_site(P, nr, two_rows) * wg * nblk);
 }
 
 double time_dslash_impl(fs_ctx c, int P, int n_sys, int nr, int wg, int ilp, int occ, int n_launch) {
@@ -1596,12 +1639,13 @@ double time_dslash_impl(fs_ctx c, int P, int n_sys, int nr, int wg, int ilp, int
 
 // Algorithmic bytes of one even-odd hop launch (one parity out): per output
 // site and system 24 reals in and 24 out (+ FP16 scales); every link of the
-// lattice once per block of nr systems (each link joins an even and an odd site).
-double dslash_eo_bytes(int P, long long V, int n_sys, int nr) {
+// lattice once per block of nr systems (each link joins an even and an odd
+// site), 18 reals, or 12 in the two-row form.
+double dslash_eo_bytes(int P, long long V, int n_sys, int nr, bool two_rows) {
     const double w = P == P64 ? 8 : P == P32 ? 4 : 2;
     const double per_sys = 48.0 * w + (P == P16 ? 8.0 : 0.0);
     const long long nblk = (n_sys + nr - 1) / nr;
-    return (double)(V / 2) * per_sys * n_sys + (double)V * 72.0 * w * nblk;
+    return (double)(V / 2) * per_sys * n_sys + (double)V * link_reals_per_site(P, nr, two_rows) * w * nblk;
 }
 
 double time_dslash_eo_impl(fs_ctx c, int P, int n_sys, int nr, int occ, int n_launch) {
@@ -1694,6 +1738,8 @@ fs_status fs_destroy(fs_ctx c) {
             DeviceScope ds(c->device);
             (void)hipStreamSynchronize(c->stream);
             for (auto& g : c->gauge) g.release();
+            for (auto& g : c->gauge_q) g.release();
+            for (auto& g : c->gauge_q2) g.release();
             if (c->own_stream) (void)hipStreamDestroy(c->stream);
         }
         delete c;
@@ -1718,14 +1764,36 @@ fs_status fs_upload_gauge(fs_ctx c, const double* links, int32_t is_device) {
         DeviceScope ds(c->device);
         const size_t n = sizeof(double) * 18 * 4 * (size_t)c->V;
         DevBuf src = to_device(links, n, is_device, c->stream);
+        if (is_device) {
+            std::vector<double> h(n / sizeof(double));
+            from_device(h.data(), src, n, 0, c->stream);
+            c->su3_defect = su3_row_defect(h.data(), (size_t)4 * c->V);
+        } else {
+            c->su3_defect = su3_row_defect(links, (size_t)4 * c->V);
+        }
+        c->two_rows = c->su3_defect <= kSu3RowTol;
         for (int P = 0; P < 4; ++P) {
             c->gauge[P].alloc((size_t)4 * 9 * c->V * prec_link_complex_bytes(P));
             launch_gauge_convert(P, c->gauge[P].p, src.as<double>(), c->V, c->stream);
-            c->gauge_q[P].alloc((size_t)4 * c->V * prec_link_site_bytes(P));
-            launch_gauge_convert_q(P, c->gauge_q[P].p, src.as<double>(), c->V, c->stream);
+            c->gauge_q[P].alloc((size_t)4 * c->V * prec_link_site_bytes(P, false));
+            launch_gauge_convert_q(P, c->gauge_q[P].p, src.as<double>(), c->V, false, c->stream);
+            if (c->two_rows && P == P32) {
+                c->gauge_q2[P].alloc((size_t)4 * c->V * prec_link_site_bytes(P, true));
+                launch_gauge_convert_q(P, c->gauge_q2[P].p, src.as<double>(), c->V, true, c->stream);
+            } else {
+                c->gauge_q2[P].release();
+            }
         }
         HC(hipStreamSynchronize(c->stream));
         c->has_gauge = true;
+    });
+}
+
+fs_status fs_gauge_info(fs_ctx c, int32_t* two_rows, double* su3_defect) {
+    return guard([&] {
+        check_ctx(c);
+        if (two_rows) *two_rows = c->two_rows ? 1 : 0;
+        if (su3_defect) *su3_defect = c->su3_defect;
     });
 }
 
@@ -2184,7 +2252,7 @@ fs_status fs_time_dslash(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_b
         DeviceScope ds(c->device);
         const double ms = time_dslash_impl(c, storage, n_sys, nr, w, il, oc, n_launch);
         if (avg_ms) *avg_ms = ms;
-        if (bytes) *bytes = dslash_bytes(storage, c->V, n_sys, nr);
+        if (bytes) *bytes = dslash_bytes(storage, c->V, n_sys, nr, c->two_rows);
     });
 }
 
@@ -2201,7 +2269,7 @@ fs_status fs_time_dslash_eo(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rh
         if (occ > 8) fail(FS_E_ARG, "occ must be -1 (the solver's choice) or 0..8");
         const double ms = time_dslash_eo_impl(c, storage, n_sys, nr, occ < 0 ? eo_occ(storage, nr) : occ, n_launch);
         if (avg_ms) *avg_ms = ms;
-        if (bytes) *bytes = dslash_eo_bytes(storage, c->V, n_sys, nr);
+        if (bytes) *bytes = dslash_eo_bytes(storage, c->V, n_sys, nr, c->two_rows);
     });
 }
 

@@ -569,20 +569,25 @@ __global__ void k_gauge_convert(void* __restrict__ dst, const double* __restrict
     }
 }
 
-// Site-major copy of the links for quad-shared loads: link (mu, site) is
-// Tr<P>::QC 16-byte chunks at ((mu * V + site) * QC), the 9 complex entries
-// packed in order in the storage precision, the tail padded with zeros.
-template <int P>
+// Site-major copy of the links for quad-shared loads: link (mu, site) is QC
+// 16-byte chunks at ((mu * V + site) * QC), the complex entries packed
+// row-major in the storage precision, the tail padded with zeros.  The full
+// form (R = false, QC = Tr<P>::QC) keeps all 9 entries; the two-row form
+// (R = true, FP32 only, QC = Tr<P32>::QCR) keeps rows 0 and 1, whose cross
+// product gives row 2 of a special unitary link.
+template <int P, bool R>
 __global__ void k_gauge_convert_q(uint4* __restrict__ dst, const double* __restrict__ src, int V) {
+    static_assert(!R || P == P32, "only FP32 links are kept in the two-row form");
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (size_t)4 * V) return;
-    constexpr int QC = Tr<P>::QC;
+    constexpr int QC = R ? Tr<P32>::QCR : Tr<P>::QC;
+    constexpr int NE = R ? 6 : 9;
     uint32_t w[4 * QC];
 #pragma unroll
     for (int k = 0; k < 4 * QC; ++k) w[k] = 0u;
     const double* s = src + i * 18;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
+    for (int k = 0; k < NE; ++k) {
         const double re = s[2 * k], im = s[2 * k + 1];
         if constexpr (P == P64) {
             w[4 * k] = (uint32_t)__double2loint(re);
@@ -916,10 +921,14 @@ void launch_gauge_convert(int prec, void* dst, const double* src, int V, hipStre
     const int n = 4 * V;
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_gauge_convert<PP>, dim3((n + 255) / 256), dim3(256), 0, s, dst, src, V))
 }
-void launch_gauge_convert_q(int prec, void* dst, const double* src, int V, hipStream_t s) {
+void launch_gauge_convert_q(int prec, void* dst, const double* src, int V, bool two_rows, hipStream_t s) {
     const int n = 4 * V;
-    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_gauge_convert_q<PP>, dim3((n + 255) / 256), dim3(256), 0, s,
-                                           static_cast<uint4*>(dst), src, V))
+    if (two_rows && prec == P32)
+        hipLaunchKernelGGL((k_gauge_convert_q<P32, true>), dim3((n + 255) / 256), dim3(256), 0, s,
+                           static_cast<uint4*>(dst), src, V);
+    else
+        FS_DISPATCH_P(prec, hipLaunchKernelGGL((k_gauge_convert_q<PP, false>), dim3((n + 255) / 256), dim3(256), 0,
+                                               s, static_cast<uint4*>(dst), src, V))
 }
 void launch_noise_block(int prec, const Work& w, Fld dst, const NoiseKey* keys, hipStream_t s,
                         const uint16_t* colour) {

@@ -30,7 +30,8 @@ struct LatDesc {
     int eo;            // 1: fields hold one parity, field site = site >> 1
     int tsign;         // +1 periodic, -1 antiperiodic in t
     const void* gauge; // links in the launch's storage precision, [mu][9][site]
-    const void* gauge_q; // the same links site-major, [mu][site][QC 16-byte chunks]
+    const void* gauge_q; // the same links site-major, [mu][site][QC 16-byte chunks], or
+                         // rows 0-1 only ([mu][site][QCR], FP32) in plans that rebuild row 2
 };
 
 struct BlockDesc {
@@ -78,6 +79,7 @@ template <> struct Tr<P32> {
     static constexpr int GB = 8;
     static constexpr int SB = 96;
     static constexpr int QC = 5;   // 72 B padded to 80 B
+    static constexpr int QCR = 3;  // rows 0-1 only: 48 B
 };
 template <> struct Tr<P16> {
     using acc = float;
@@ -272,6 +274,49 @@ __device__ __forceinline__ void chunk_bcast(const uint4& c, uint32_t o[4]) {
     o[3] = quad_bcast<J>(c.w);
 }
 
+// Row 2 of a special unitary 3x3 matrix from rows 0 and 1: the complex
+// conjugate of their cross product, U_2j = conj(U_0k U_1l - U_0l U_1k) with
+// (j, k, l) a cyclic permutation of (0, 1, 2).  u holds the matrix row-major
+// as (re, im) pairs; u[12..17] is overwritten.
+template <typename A>
+__device__ __forceinline__ void su3_third_row(A u[18]) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int k = (j + 1) % 3, l = (j + 2) % 3;
+        const A akr = u[2 * k], aki = u[2 * k + 1], alr = u[2 * l], ali = u[2 * l + 1];
+        const A bkr = u[6 + 2 * k], bki = u[7 + 2 * k], blr = u[6 + 2 * l], bli = u[7 + 2 * l];
+        const A re = (akr * blr - aki * bli) - (alr * bkr - ali * bki);
+        const A im = (akr * bli + aki * blr) - (alr * bki + ali * bkr);
+        u[12 + 2 * j] = re;
+        u[13 + 2 * j] = -im;
+    }
+}
+
+// Two-row form of the quad-shared load (FP32 storage): rows 0 and 1 are
+// three 16-byte chunks per site, lanes 0-2 of the quad load one each (lane 3
+// repeats chunk 2), and row 2 is rebuilt with su3_third_row.  This trades 24
+// bytes of link traffic per load for about 40 FP32 operations per lane; the
+// FP16 and BF16 stencils, whose links are smaller and whose lanes already
+// spend more instructions on conversions, read whole links.
+template <int P, typename A>
+__device__ __forceinline__ void load_link_q2(const void* __restrict__ gauge_q, int V, int mu, int site, A u[18]) {
+    static_assert(P == P32, "only FP32 links are kept in the two-row form");
+    constexpr uint32_t QB = 16u * Tr<P>::QCR;  // bytes per site
+    const int qd = threadIdx.x & 3;
+    const uint32_t plane = uni((uint32_t)V * QB);
+    const auto rs = buf_rsrc(reinterpret_cast<const char*>(gauge_q) + (size_t)mu * plane, plane);
+    const uint32_t off = (uint32_t)site * QB;
+    const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16u * (qd < 2 ? qd : 2), 0, 0);
+    const uint4 c = make_uint4(q[0], q[1], q[2], q[3]);
+    uint32_t w[12];
+    chunk_bcast<0>(c, w + 0);
+    chunk_bcast<1>(c, w + 4);
+    chunk_bcast<2>(c, w + 8);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) u[k] = (A)__uint_as_float(w[k]);
+    su3_third_row<A>(u);
+}
+
 template <int P, typename A>
 __device__ __forceinline__ void load_link_q(const void* __restrict__ gauge_q, int V, int mu, int site, A u[18]) {
     constexpr uint32_t QB = 16u * Tr<P>::QC;  // bytes per site
@@ -332,10 +377,13 @@ __device__ __forceinline__ void load_link_q(const void* __restrict__ gauge_q, in
     }
 }
 
-// Link load of the stencil: quad-shared when Q (rhs blocks of 4 or more).
-template <int P, bool Q, typename A>
+// Link load of the stencil, by variant Q: 0 one component per load (rhs
+// blocks of 1 or 2), 1 quad-shared whole links, 2 quad-shared rows 0-1 with
+// row 2 rebuilt (FP32; every lattice of the plan holds special unitary links).
+template <int P, int Q, typename A>
 __device__ __forceinline__ void link(const LatDesc& ld, int mu, int site, A u[18]) {
-    if constexpr (Q) load_link_q<P, A>(ld.gauge_q, ld.V, mu, site, u);
+    if constexpr (Q == 2) load_link_q2<P, A>(ld.gauge_q, ld.V, mu, site, u);
+    else if constexpr (Q == 1) load_link_q<P, A>(ld.gauge_q, ld.V, mu, site, u);
     else load_link<P, A>(ld.gauge, ld.V, mu, site, u);
 }
 

@@ -113,7 +113,7 @@ __device__ __forceinline__ void mul_udag(const A u[18], const A h[12], A w[12]) 
         }
 }
 
-template <int P, bool Q, int MU, typename PF, typename PB>
+template <int P, int Q, int MU, typename PF, typename PB>
 __device__ __forceinline__ void hop_dir(const LatDesc& ld, const uint4* __restrict__ ib,
                                         const float* __restrict__ inn, size_t gs, int site, int coord,
                                         int stride, int r, int lognr, typename Tr<P>::acc o[24]) {
@@ -175,7 +175,7 @@ template <int P, int ILP> struct Wpe {
     static constexpr int hi = ILP ? 1 : 8;
 };
 
-template <int P, int MODE, int ILP, bool Q>
+template <int P, int MODE, int ILP, int Q>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Wpe<P, ILP>::lo, Wpe<P, ILP>::hi)))
 k_dslash(Work w, Fld out, Fld in, Fld aux,
                                                 const double* __restrict__ diag,
@@ -381,7 +381,7 @@ __device__ __forceinline__ void fetch_half(bool in_tile, const uint4* __restrict
     for (int k = 0; k < 12; ++k) h[k] = in_tile ? h[k] : hg[k];
 }
 
-template <int P, bool Q, int MU, typename PF, typename PB>
+template <int P, int Q, int MU, typename PF, typename PB>
 __device__ __forceinline__ void hop_tile(const LatDesc& ld, const uint4* __restrict__ ib,
                                          const float* __restrict__ inn, size_t gs,
                                          const typename LdsVec<typename Tr<P>::acc>::T* sh, int wg, int lane,
@@ -423,7 +423,7 @@ template <int P, int MODE> struct TileW {
 
 template <int P> constexpr int tile_nbuf() { return sizeof(typename Tr<P>::acc) == 4 ? 2 : 1; }
 
-template <int P, int MODE, bool Q>
+template <int P, int MODE, int Q>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<P, MODE>::v, 8))) k_dslash_tile(Work w, Fld out, Fld in, Fld aux,
                                                      const double* __restrict__ diag,
                                                      const SysState* __restrict__ st, int mask,
@@ -581,7 +581,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
 
 // One hop direction as in hop_dir, reading a one-parity field (HALF: neighbour
 // slot = (site >> 1) * NR + r) or a full-layout field.
-template <int P, bool Q, bool HALF, int MU, typename PF, typename PB>
+template <int P, int Q, bool HALF, int MU, typename PF, typename PB>
 __device__ __forceinline__ void hop_dir_h(const LatDesc& ld, const uint4* __restrict__ ib,
                                           const float* __restrict__ inn, size_t gs, int site, int coord,
                                           int stride, int r, int lognr, typename Tr<P>::acc o[24]) {
@@ -613,7 +613,7 @@ __device__ __forceinline__ void hop_dir_h(const LatDesc& ld, const uint4* __rest
 }
 
 // o += hopping term of D at `site`: -1/2 sum_mu [(1-g_mu) U psi(x+mu) + (1+g_mu) U^+ psi(x-mu)]
-template <int P, bool Q, bool HALF>
+template <int P, int Q, bool HALF>
 __device__ __forceinline__ void hop_all(const LatDesc& ld, const uint4* __restrict__ ib,
                                         const float* __restrict__ inn, size_t gs, int site, const Coord& c, int r,
                                         int lognr, typename Tr<P>::acc o[24]) {
@@ -640,7 +640,7 @@ __device__ __forceinline__ int eo_site(const LatDesc& ld, int cb, int par, Coord
 template <int MODE> struct NDotsEo { static constexpr int v = NDots<MODE>::v; };
 
 // One lane per (field site, rhs) slot of one parity; see launch_dslash_eo.
-template <int P, int MODE, bool Q>
+template <int P, int MODE, int Q>
 __global__ void __launch_bounds__(256) k_dslash_eo(Work w, Fld out, Fld in, Fld cen, Fld aux,
                                                    const double* __restrict__ diag,
                                                    const SysState* __restrict__ st, int mask,
@@ -725,7 +725,7 @@ __global__ void __launch_bounds__(256) k_dslash_eo(Work w, Fld out, Fld in, Fld 
 // t-slice at a time, and the forward-t neighbour psi(x, t+1) loaded for output t
 // gives, with U_t(x, t+1), the backward-t term of output t+2, carried in
 // registers.  Workgroup index within a block: (q, chunk, column tile).
-template <int P, int MODE, bool Q>
+template <int P, int MODE, int Q>
 __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fld cen, Fld aux,
                                                      const double* __restrict__ diag,
                                                      const SysState* __restrict__ st, int mask,
@@ -864,7 +864,7 @@ __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fl
 
 // FP64, over a one-parity plan: bh = b_e - D_eo b_o / a; partials |b_e|^2 + |b_o|^2.
 // Q: quad-shared links (rhs blocks of 4 or more; the quads of a slot range are whole).
-template <bool Q>
+template <int Q>
 __global__ void __launch_bounds__(256) k_eo_prep(Work w, const BlockDesc* __restrict__ fblocks, Fld bfull, Fld bh,
                                                  const double* __restrict__ diag, double* __restrict__ part) {
     for_each_vwg(w, [&](const int wg_id, const int b) {
@@ -903,7 +903,7 @@ __global__ void __launch_bounds__(256) k_eo_prep(Work w, const BlockDesc* __rest
 }
 
 // FP64: x (full layout) = x_e at even sites, (b_o - D_oe x_e) / a at odd sites.
-template <bool Q>
+template <int Q>
 __global__ void __launch_bounds__(256) k_eo_post(Work w, const BlockDesc* __restrict__ fblocks, Fld bfull, Fld xh,
                                                  Fld xfull, const double* __restrict__ diag) {
     for_each_vwg(w, [&](const int wg_id, const int b) {
@@ -954,15 +954,29 @@ static size_t lds_cap(int wg, int waves) {
     return std::min<size_t>(bytes, 64 * 1024);
 }
 
+// Link-load variant of a launch (the Q of link()): 0 for rhs blocks of 1 or
+// 2, else 1, or 2 where the plan's FP32 links keep two rows.
+template <int P>
+static int qmode(const Work& w) { return w.nr < 4 ? 0 : (P == P32 && w.two_rows) ? 2 : 1; }
+
 template <int P, int MODE, int ILP>
 static void launch_t(const Work& w, Fld out, Fld in, Fld aux, const double* diag, const SysState* st,
                      int mask, double* part, hipStream_t s, const NoiseKey* rk) {
-    if (w.nr >= 4)
-        hipLaunchKernelGGL((k_dslash<P, MODE, ILP, true>), dim3(grid_of(w)), dim3(w.wg), lds_cap(w.wg, w.occ), s, w,
-                           out, in, aux, diag, st, mask, part, rk);
-    else
-        hipLaunchKernelGGL((k_dslash<P, MODE, ILP, false>), dim3(grid_of(w)), dim3(w.wg), lds_cap(w.wg, w.occ), s, w,
-                           out, in, aux, diag, st, mask, part, rk);
+    const size_t lds = lds_cap(w.wg, w.occ);
+    switch (qmode<P>(w)) {
+        case 2:
+            if constexpr (P == P32)
+                hipLaunchKernelGGL((k_dslash<P, MODE, ILP, 2>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, aux,
+                                   diag, st, mask, part, rk);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_dslash<P, MODE, ILP, 1>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, aux,
+                               diag, st, mask, part, rk);
+            break;
+        default:
+            hipLaunchKernelGGL((k_dslash<P, MODE, ILP, 0>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, aux,
+                               diag, st, mask, part, rk);
+    }
 }
 
 template <int P, int MODE>
@@ -970,12 +984,20 @@ static void launch_tile(const Work& w, Fld out, Fld in, Fld aux, const double* d
                         int mask, double* part, hipStream_t s, const NoiseKey* rk) {
     const size_t need = (size_t)tile_nbuf<P>() * 24 * sizeof(typename Tr<P>::acc) * w.wg;
     const size_t lds = std::max(need, lds_cap(w.wg, w.occ));
-    if (w.nr >= 4)
-        hipLaunchKernelGGL((k_dslash_tile<P, MODE, true>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, aux, diag,
-                           st, mask, part, rk);
-    else
-        hipLaunchKernelGGL((k_dslash_tile<P, MODE, false>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, aux, diag,
-                           st, mask, part, rk);
+    switch (qmode<P>(w)) {
+        case 2:
+            if constexpr (P == P32)
+                hipLaunchKernelGGL((k_dslash_tile<P, MODE, 2>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, aux,
+                                   diag, st, mask, part, rk);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_dslash_tile<P, MODE, 1>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, aux,
+                               diag, st, mask, part, rk);
+            break;
+        default:
+            hipLaunchKernelGGL((k_dslash_tile<P, MODE, 0>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, aux,
+                               diag, st, mask, part, rk);
+    }
 }
 
 template <int P, int MODE>
@@ -1016,22 +1038,39 @@ void launch_dslash(int prec, int mode, const Work& w, Fld out, Fld in, Fld aux, 
 template <int P, int MODE>
 static void launch_eo_q(const Work& w, Fld out, Fld in, Fld cen, Fld aux, const double* diag, const SysState* st,
                         int mask, double* part, hipStream_t s, const NoiseKey* rk, int par_out) {
+    const int q = qmode<P>(w);
     if (w.tc > 0) {  // stencil mapping: t-streaming, with the plan's residency cap
         const size_t lds = lds_cap(w.wg, w.occ);
-        if (w.nr >= 4)
-            hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, true>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, cen,
-                               aux, diag, st, mask, part, rk, par_out);
-        else
-            hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, false>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in,
-                               cen, aux, diag, st, mask, part, rk, par_out);
+        switch (q) {
+            case 2:
+                if constexpr (P == P32)
+                    hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, 2>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in,
+                                       cen, aux, diag, st, mask, part, rk, par_out);
+                break;
+            case 1:
+                hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, 1>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, cen,
+                                   aux, diag, st, mask, part, rk, par_out);
+                break;
+            default:
+                hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, 0>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, cen,
+                                   aux, diag, st, mask, part, rk, par_out);
+        }
         return;
     }
-    if (w.nr >= 4)
-        hipLaunchKernelGGL((k_dslash_eo<P, MODE, true>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen, aux,
-                           diag, st, mask, part, rk, par_out);
-    else
-        hipLaunchKernelGGL((k_dslash_eo<P, MODE, false>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen, aux,
-                           diag, st, mask, part, rk, par_out);
+    switch (q) {
+        case 2:
+            if constexpr (P == P32)
+                hipLaunchKernelGGL((k_dslash_eo<P, MODE, 2>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen,
+                                   aux, diag, st, mask, part, rk, par_out);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_dslash_eo<P, MODE, 1>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen, aux,
+                               diag, st, mask, part, rk, par_out);
+            break;
+        default:
+            hipLaunchKernelGGL((k_dslash_eo<P, MODE, 0>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen, aux,
+                               diag, st, mask, part, rk, par_out);
+    }
 }
 
 template <int P>
@@ -1064,17 +1103,17 @@ void launch_dslash_eo(int prec, int mode, const Work& w, Fld out, Fld in, Fld ce
 void launch_eo_prep(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld bh, const double* diag, double* part,
                     hipStream_t s) {
     if (wh.nr >= 4)
-        hipLaunchKernelGGL(k_eo_prep<true>, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, bh, diag, part);
+        hipLaunchKernelGGL(k_eo_prep<1>, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, bh, diag, part);
     else
-        hipLaunchKernelGGL(k_eo_prep<false>, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, bh, diag, part);
+        hipLaunchKernelGGL(k_eo_prep<0>, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, bh, diag, part);
 }
 
 void launch_eo_post(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld xh, Fld xfull, const double* diag,
                     hipStream_t s) {
     if (wh.nr >= 4)
-        hipLaunchKernelGGL(k_eo_post<true>, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, xh, xfull, diag);
+        hipLaunchKernelGGL(k_eo_post<1>, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, xh, xfull, diag);
     else
-        hipLaunchKernelGGL(k_eo_post<false>, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, xh, xfull, diag);
+        hipLaunchKernelGGL(k_eo_post<0>, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, xh, xfull, diag);
 }
 
 }  // namespace fs

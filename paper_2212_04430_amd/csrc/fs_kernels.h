@@ -48,6 +48,7 @@ struct Work {
     int ilp;                  // stencil variant: 0 default, 1 register-rich (one wave per SIMD), 2 LDS tiles
     int tl[3];                // stencil variant 2: log2 of the tile extent in x, y, z
     int occ;                  // stencil: cap on resident waves per SIMD (0 = none)
+    int two_rows;             // FP32 gauge_q of every lattice holds rows 0-1 only
     // Persistent launches: when vlist is set, a fixed grid walks the virtual
     // workgroups of the blocks listed there (vlist[0..*vcount)), vstart being
     // their prefix sums in this launch's mapping (tile or stencil table).
@@ -227,7 +228,7 @@ void launch_unpack(int prec, const Work& w, double* dst, Fld src, long long sys_
 
 // gauge: canonical complex128 [mu][site][3][3] -> [mu][9][site] in precision prec
 void launch_gauge_convert(int prec, void* dst, const double* src, int V, hipStream_t s);
-void launch_gauge_convert_q(int prec, void* dst, const double* src, int V, hipStream_t s);
+void launch_gauge_convert_q(int prec, void* dst, const double* src, int V, bool two_rows, hipStream_t s);
 
 // colour: per-site probing colour (only read for diluted keys; may be null otherwise)
 void launch_noise_block(int prec, const Work& w, Fld dst, const NoiseKey* keys /* per system */, hipStream_t s,
