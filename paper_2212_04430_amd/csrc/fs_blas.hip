@@ -163,6 +163,99 @@ __global__ void __launch_bounds__(256) k_update_p(Work w, Fld p, Fld r, Fld v, c
     FS_WG_EPILOGUE
 }
 
+// ------------------------------------------------ FP32, one thread per group
+//
+// The element-wise FP32 updates without reductions run one thread per 16-byte
+// group of a slot (two complex numbers) instead of one per slot.  The launch
+// holds 6 x (tile-mapping workgroups of the plan) x tpw workgroups, ordered
+// group-major: while one group of every listed block streams through, all
+// resident waves read and write narrow windows of the same few arrays.  With
+// a device list (persistent mapping of the other kernels) the workgroups past
+// the listed blocks' share exit at once.  Loads and stores are non-temporal:
+// each field is touched once per launch.
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4_t ld_nt(const f32x4_t* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_nt(f32x4_t v, f32x4_t* p) { __builtin_nontemporal_store(v, p); }
+
+// body(block, group, slot) for this workgroup's tile, if it has one.
+template <typename F>
+__device__ __forceinline__ void for_group_tile(const Work& w, F&& body) {
+    constexpr int G = Tr<P32>::G;
+    int n = 0, T;
+    if (w.vlist) {
+        n = *w.vcount;
+        if (n <= 0) return;
+        T = w.vstart[n];
+    } else {
+        T = w.total_wg;
+    }
+    const long long per_g = (long long)T * w.tpw;
+    const long long u = blockIdx.x;
+    if (u >= per_g * G) return;
+    const int g = (int)(u / per_g);
+    const long long rem = u - (long long)g * per_g;
+    const int v = (int)(rem / w.tpw), it = (int)(rem - (long long)v * w.tpw);
+    int b, wgb;
+    if (w.vlist) {
+        const int k = __builtin_amdgcn_readfirstlane(find_block(w.vstart, n, v));
+        b = __builtin_amdgcn_readfirstlane(w.vlist[k]);
+        wgb = v - w.vstart[k];
+    } else {
+        b = __builtin_amdgcn_readfirstlane(find_block(w.wg_start, w.nblk, v));
+        if (w.blk_on && !w.blk_on[b]) return;
+        wgb = v - w.wg_start[b];
+    }
+    body(b, g, ((size_t)wgb * w.tpw + it) * w.wg + threadIdx.x);
+}
+
+// s = r - alpha v  (stored in r), FP32 storage
+__global__ void __launch_bounds__(256) k_axpy_s_g(Work w, Fld r, Fld v, const SysState* __restrict__ st) {
+    for_group_tile(w, [&](const int b, const int g, const size_t slot) {
+        const BlockDesc bd = w.blocks[b];
+        const size_t gs = (size_t)w.lats[bd.lat].Vf << w.lognr;
+        if (slot >= gs) return;
+        const int sys = bd.sys0 + (int)(slot & (size_t)(w.nr - 1));
+        if (st[sys].state != S_RUN) return;
+        const float ar = (float)st[sys].alpha[0], ai = (float)st[sys].alpha[1];
+        const size_t e = (size_t)g * gs + slot;
+        f32x4_t* rp = reinterpret_cast<f32x4_t*>(fbase_w<P32>(r, bd)) + e;
+        const f32x4_t y = ld_nt(reinterpret_cast<const f32x4_t*>(fbase<P32>(v, bd)) + e);
+        f32x4_t x = ld_nt(rp);
+        x.x -= ar * y.x - ai * y.y;
+        x.y -= ar * y.y + ai * y.x;
+        x.z -= ar * y.z - ai * y.w;
+        x.w -= ar * y.w + ai * y.z;
+        st_nt(x, rp);
+    });
+}
+
+// p = r + beta (p - omega v), FP32 storage
+__global__ void __launch_bounds__(256) k_update_p_g(Work w, Fld p, Fld r, Fld v, const SysState* __restrict__ st) {
+    for_group_tile(w, [&](const int b, const int g, const size_t slot) {
+        const BlockDesc bd = w.blocks[b];
+        const size_t gs = (size_t)w.lats[bd.lat].Vf << w.lognr;
+        if (slot >= gs) return;
+        const int sys = bd.sys0 + (int)(slot & (size_t)(w.nr - 1));
+        if (!st[sys].upd_p) return;
+        const float br = (float)st[sys].beta[0], bi = (float)st[sys].beta[1];
+        const float wr = (float)st[sys].omega[0], wi = (float)st[sys].omega[1];
+        const size_t e = (size_t)g * gs + slot;
+        f32x4_t* pp = reinterpret_cast<f32x4_t*>(fbase_w<P32>(p, bd)) + e;
+        const f32x4_t rv = ld_nt(reinterpret_cast<const f32x4_t*>(fbase<P32>(r, bd)) + e);
+        const f32x4_t vv = ld_nt(reinterpret_cast<const f32x4_t*>(fbase<P32>(v, bd)) + e);
+        f32x4_t pv = ld_nt(pp);
+        const float q0 = pv.x - (wr * vv.x - wi * vv.y), q1 = pv.y - (wr * vv.y + wi * vv.x);
+        const float q2 = pv.z - (wr * vv.z - wi * vv.w), q3 = pv.w - (wr * vv.w + wi * vv.z);
+        pv.x = rv.x + br * q0 - bi * q1;
+        pv.y = rv.y + br * q1 + bi * q0;
+        pv.z = rv.z + br * q2 - bi * q3;
+        pv.w = rv.w + br * q3 + bi * q2;
+        st_nt(pv, pp);
+    });
+}
+
 // x_hi += x_lo; x_lo = 0  (systems pending a reliable update)
 template <int P>
 __global__ void __launch_bounds__(256) k_fold(Work w, Fld xhi, Fld xlo, const SysState* __restrict__ st) {
@@ -863,7 +956,14 @@ static int grid_of(const Work& w) { return w.vlist ? persistent_grid(w.wg) : (w.
         default: break;                     \
     }
 
+// Workgroups of a one-thread-per-group FP32 launch (every block of the plan).
+static unsigned grid_groups(const Work& w) { return (unsigned)((long long)Tr<P32>::G * w.total_wg * w.tpw); }
+
 void launch_axpy_s(int prec, const Work& w, Fld r, Fld v, const SysState* st, hipStream_t s) {
+    if (prec == P32 && w.wg == 256) {
+        hipLaunchKernelGGL(k_axpy_s_g, dim3(grid_groups(w)), dim3(256), 0, s, w, r, v, st);
+        return;
+    }
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_axpy_s<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, r, v, st))
 }
 void launch_update_xr(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, const NoiseKey* rk, const SysState* st,
@@ -872,6 +972,10 @@ void launch_update_xr(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, const
                                            st, part))
 }
 void launch_update_p(int prec, const Work& w, Fld p, Fld r, Fld v, const SysState* st, hipStream_t s) {
+    if (prec == P32 && w.wg == 256) {
+        hipLaunchKernelGGL(k_update_p_g, dim3(grid_groups(w)), dim3(256), 0, s, w, p, r, v, st);
+        return;
+    }
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_update_p<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, p, r, v, st))
 }
 void launch_fold(int prec, const Work& w, Fld xhi, Fld xlo, const SysState* st, hipStream_t s) {
