@@ -89,7 +89,8 @@ __global__ void __launch_bounds__(256) k_axpy_s(Work w, Fld r, Fld v, const SysS
     FS_WG_EPILOGUE
 }
 
-// x += alpha p + omega s;  r = s - omega t  (s is held in r);  partials (rhat, r), |r|^2
+// x += alpha p + omega s;  r = s - omega t  (s is held in r);  partials (rhat, r), |r|^2.
+// Every field is touched once: non-temporal loads and stores.
 template <int P>
 __global__ void __launch_bounds__(256) k_update_xr(Work w, Fld x, Fld p, Fld r, Fld t, const NoiseKey* __restrict__ rk,
                                                    const SysState* __restrict__ st, double* __restrict__ part) {
@@ -105,23 +106,23 @@ __global__ void __launch_bounds__(256) k_update_xr(Work w, Fld x, Fld p, Fld r, 
         const A ar = (A)st[sys].alpha[0], ai = (A)st[sys].alpha[1];
         const A wr = (A)st[sys].omega[0], wi = (A)st[sys].omega[1];
         A xv[24], pv[24], sv[24];
-        load_sp<P, A>(xb, xn, gs, slot, xv);
-        load_sp<P, A>(fbase<P>(p, bd), nbase(p, bd), gs, slot, pv);
-        load_sp<P, A>(rb, rn, gs, slot, sv);
+        load_sp<P, A, true>(xb, xn, gs, slot, xv);
+        load_sp<P, A, true>(fbase<P>(p, bd), nbase(p, bd), gs, slot, pv);
+        load_sp<P, A, true>(rb, rn, gs, slot, sv);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             xv[2 * k] += ar * pv[2 * k] - ai * pv[2 * k + 1] + wr * sv[2 * k] - wi * sv[2 * k + 1];
             xv[2 * k + 1] += ar * pv[2 * k + 1] + ai * pv[2 * k] + wr * sv[2 * k + 1] + wi * sv[2 * k];
         }
-        store_sp<P, A>(xb, xn, gs, slot, xv);
+        store_sp<P, A, true>(xb, xn, gs, slot, xv);
         A tv[24];
-        load_sp<P, A>(fbase<P>(t, bd), nbase(t, bd), gs, slot, tv);
+        load_sp<P, A, true>(fbase<P>(t, bd), nbase(t, bd), gs, slot, tv);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             sv[2 * k] -= wr * tv[2 * k] - wi * tv[2 * k + 1];
             sv[2 * k + 1] -= wr * tv[2 * k + 1] + wi * tv[2 * k];
         }
-        store_sp<P, A>(rb, rn, gs, slot, sv);
+        store_sp<P, A, true>(rb, rn, gs, slot, sv);
         A hv[24];
         rhat_site<A>(rk[sys], st[sys].restarts, (long long)(slot >> w.lognr), hv);
 #pragma unroll

@@ -116,35 +116,64 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uin
     return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(q), (short)0, (int)uni(bytes), kBufFlags);
 }
 
+// 16-byte group load / store, optionally with the non-temporal hint (data
+// touched once by the launch: it streams through the caches instead of
+// displacing lines that other lanes will read again).
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ uint4 ld16(const uint4* p) {
+    if constexpr (NT) {
+        const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(p));
+        return make_uint4(v.x, v.y, v.z, v.w);
+    } else {
+        return *p;
+    }
+}
+
+template <bool NT>
+__device__ __forceinline__ void st16(uint4* p, uint4 v) {
+    if constexpr (NT) {
+        const u32x4_t u = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(u, reinterpret_cast<u32x4_t*>(p));
+    } else {
+        *p = v;
+    }
+}
+
+__device__ __forceinline__ uint4 pack_d(double re, double im) {
+    return make_uint4((uint32_t)__double2loint(re), (uint32_t)__double2hiint(re), (uint32_t)__double2loint(im),
+                      (uint32_t)__double2hiint(im));
+}
+
 // Load / store the 24 reals of spinor (slot) from a block base.  gs = group
 // stride in 16-byte units (= V * NR).  `nrm` is the FP16 per-slot scale array.
-template <int P, typename A>
+// NT: non-temporal accesses (see ld16).
+template <int P, typename A, bool NT = false>
 __device__ __forceinline__ void load_sp(const uint4* __restrict__ base, const float* __restrict__ nrm,
                                         size_t gs, size_t slot, A v[24]) {
     if constexpr (P == P64) {
-        const double2* b = reinterpret_cast<const double2*>(base);
 #pragma unroll
         for (int g = 0; g < 12; ++g) {
-            double2 d = b[g * gs + slot];
-            v[2 * g] = (A)d.x;
-            v[2 * g + 1] = (A)d.y;
+            const uint4 d = ld16<NT>(base + g * gs + slot);
+            v[2 * g] = (A)__hiloint2double((int)d.y, (int)d.x);
+            v[2 * g + 1] = (A)__hiloint2double((int)d.w, (int)d.z);
         }
     } else if constexpr (P == P32) {
-        const float4* b = reinterpret_cast<const float4*>(base);
 #pragma unroll
         for (int g = 0; g < 6; ++g) {
-            float4 d = b[g * gs + slot];
-            v[4 * g] = (A)d.x;
-            v[4 * g + 1] = (A)d.y;
-            v[4 * g + 2] = (A)d.z;
-            v[4 * g + 3] = (A)d.w;
+            const uint4 d = ld16<NT>(base + g * gs + slot);
+            v[4 * g] = (A)__uint_as_float(d.x);
+            v[4 * g + 1] = (A)__uint_as_float(d.y);
+            v[4 * g + 2] = (A)__uint_as_float(d.z);
+            v[4 * g + 3] = (A)__uint_as_float(d.w);
         }
     } else {
         float s = 1.0f;
         if constexpr (P == P16) s = nrm[slot];
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-            uint4 d = base[g * gs + slot];
+            uint4 d = ld16<NT>(base + g * gs + slot);
             uint32_t w[4] = {d.x, d.y, d.z, d.w};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -163,18 +192,18 @@ __device__ __forceinline__ void load_sp(const uint4* __restrict__ base, const fl
     }
 }
 
-template <int P, typename A>
+template <int P, typename A, bool NT = false>
 __device__ __forceinline__ void store_sp(uint4* __restrict__ base, float* __restrict__ nrm,
                                          size_t gs, size_t slot, const A v[24]) {
     if constexpr (P == P64) {
-        double2* b = reinterpret_cast<double2*>(base);
 #pragma unroll
-        for (int g = 0; g < 12; ++g) b[g * gs + slot] = make_double2((double)v[2 * g], (double)v[2 * g + 1]);
+        for (int g = 0; g < 12; ++g) st16<NT>(base + g * gs + slot, pack_d((double)v[2 * g], (double)v[2 * g + 1]));
     } else if constexpr (P == P32) {
-        float4* b = reinterpret_cast<float4*>(base);
 #pragma unroll
         for (int g = 0; g < 6; ++g)
-            b[g * gs + slot] = make_float4((float)v[4 * g], (float)v[4 * g + 1], (float)v[4 * g + 2], (float)v[4 * g + 3]);
+            st16<NT>(base + g * gs + slot,
+                     make_uint4(__float_as_uint((float)v[4 * g]), __float_as_uint((float)v[4 * g + 1]),
+                                __float_as_uint((float)v[4 * g + 2]), __float_as_uint((float)v[4 * g + 3])));
     } else {
         float inv = 1.0f;
         if constexpr (P == P16) {
@@ -196,7 +225,7 @@ __device__ __forceinline__ void store_sp(uint4* __restrict__ base, float* __rest
                     w[k] = (uint32_t)f_to_bf16(lo) | ((uint32_t)f_to_bf16(hi) << 16);
                 }
             }
-            base[g * gs + slot] = make_uint4(w[0], w[1], w[2], w[3]);
+            st16<NT>(base + g * gs + slot, make_uint4(w[0], w[1], w[2], w[3]));
         }
     }
 }

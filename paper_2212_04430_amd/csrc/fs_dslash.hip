@@ -296,7 +296,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
 #pragma unroll
                 for (int k = 0; k < 24; ++k) o[k] = bv[k] - o[k];
             }
-            store_sp<P, A>(ob, on, gs, slot, o);
+            store_sp<P, A, true>(ob, on, gs, slot, o);
             if (act) {
                 if constexpr (MODE == D_RHAT) {
                     A rh[24];
@@ -555,7 +555,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
 #pragma unroll
                 for (int k = 0; k < 24; ++k) o[k] = bv[k] - o[k];
             }
-            store_sp<P, A>(ob, on, gs, slot, o);
+            store_sp<P, A, true>(ob, on, gs, slot, o);
             if (act) {
                 if constexpr (MODE == D_RHAT) {
                     A rh[24];
@@ -690,7 +690,7 @@ __global__ void __launch_bounds__(256) k_dslash_eo(Work w, Fld out, Fld in, Fld 
 #pragma unroll
             for (int k = 0; k < 24; ++k) o[k] = bv[k] - o[k];
         }
-        store_sp<P, A>(ob, on, gs, slot, o);
+        store_sp<P, A, true>(ob, on, gs, slot, o);
         if (act) {
             if constexpr (MODE == D_RHAT) {
                 A rh[24];
@@ -833,7 +833,9 @@ __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fl
 #pragma unroll
                 for (int j = 0; j < 24; ++j) o[j] = bv[j] - o[j];
             }
-            store_sp<P, A>(ob, on, gs, slot, o);
+            // written once and read by the next launch: non-temporal, so the
+            // output stream does not evict the neighbours other lanes still read
+            store_sp<P, A, true>(ob, on, gs, slot, o);
             if (act) {
                 if constexpr (MODE == D_RHAT) {
                     A rh[24];
