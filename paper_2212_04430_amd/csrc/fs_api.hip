@@ -802,9 +802,10 @@ struct BatchSolver {
 
     void run() {
         if (o.eo) {  // Schur source and the full |b|^2 the tolerance refers to
-            launch_eo_prep(pl.work(P64, false), full.d_blocks.as<BlockDesc>(), b.f(), sb_.f(), d_diag.as<double>(),
-                           part(), s);
-            launch_finish(F_BNORM, pl.work(P64, false), st(), part(), nullptr, nullptr, s);
+            // stencil mapping (streaming over t); the finish reads that mapping's rows
+            const Work wp = pl.work(P64, false, true);
+            launch_eo_prep(wp, full.d_blocks.as<BlockDesc>(), b.f(), sb_.f(), d_diag.as<double>(), part(), s);
+            launch_finish(F_BNORM, wp, st(), part(), nullptr, nullptr, s);
         }
         launch_init(o.P, pl.work(o.P, false), fb().f(), fx().f(), xlo.f(), fr().f(), r.f(), rk(), p.f(), part(), s);
         launch_finish(F_INIT, pl.work(o.P, false), st(), part(), f_run(), nullptr, s);
@@ -878,7 +879,7 @@ struct BatchSolver {
         }
         drop_graph();
         if (o.eo)
-            launch_eo_post(pl.work(P64, false), full.d_blocks.as<BlockDesc>(), b.f(), sx_.f(), xhi.f(),
+            launch_eo_post(pl.work(P64, false, true), full.d_blocks.as<BlockDesc>(), b.f(), sx_.f(), xhi.f(),
                            d_diag.as<double>(), s);
         HC(hipMemcpyAsync(st_host.data(), d_st.p, sizeof(SysState) * pl.nsys, hipMemcpyDeviceToHost, s));
         HC(hipStreamSynchronize(s));

@@ -725,23 +725,33 @@ __global__ void __launch_bounds__(256) k_dslash_eo(Work w, Fld out, Fld in, Fld 
 // t-slice at a time, and the forward-t neighbour psi(x, t+1) loaded for output t
 // gives, with U_t(x, t+1), the backward-t term of output t+2, carried in
 // registers.  Workgroup index within a block: (q, chunk, column tile).
+// D_PREP and D_POST (FP64) read or write full-layout fields, whose block
+// descriptors are fblocks (the same blocks over V sites): D_PREP reads the
+// hop input b and its centres from there, D_POST writes both parities of x
+// there and reads b_o from aux.
 template <int P, int MODE, int Q>
 __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fld cen, Fld aux,
                                                      const double* __restrict__ diag,
                                                      const SysState* __restrict__ st, int mask,
                                                      double* __restrict__ part, const NoiseKey* __restrict__ rk,
-                                                     int par_out) {
+                                                     int par_out, const BlockDesc* __restrict__ fblocks) {
     using A = typename Tr<P>::acc;
     constexpr int G = Tr<P>::G;
     constexpr int ND = NDotsEo<MODE>::v;
+    constexpr bool FULL_IN = MODE == D_PREP;
+    constexpr bool FULL_OUT = MODE == D_POST;
+    static_assert(!(FULL_IN || FULL_OUT) || P == P64, "the even-odd source and reconstruction are FP64");
     for_each_vwg(w, [&](const int wg_id, const int b) {
     const BlockDesc bd = w.blocks[b];
     const LatDesc ld = w.lats[bd.lat];
     const int wgb = wg_id - w.wg_start[b];
     const size_t gs = (size_t)ld.Vf << w.lognr;
-    const uint4* ib = in.v + (size_t)bd.slot_off * G;
+    const size_t gsf = (size_t)ld.V << w.lognr;   // full-layout fields
+    const size_t gsi = FULL_IN ? gsf : gs;         // the hop input
+    const long long foff = (FULL_IN || FULL_OUT) ? fblocks[b].slot_off : 0;
+    const uint4* ib = in.v + (size_t)(FULL_IN ? foff : bd.slot_off) * G;
     const float* inn = in.n ? in.n + bd.slot_off : nullptr;
-    uint4* ob = out.v + (size_t)bd.slot_off * G;
+    uint4* ob = out.v + (size_t)(FULL_OUT ? foff : bd.slot_off) * G;
     float* on = out.n ? out.n + bd.slot_off : nullptr;
     const int Lx = ld.L[0], Ly = ld.L[1], Lt = ld.L[3];
     const int Lxh = Lx >> 1;
@@ -781,7 +791,7 @@ __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fl
             const int tb = (tf == 0) ? Lt - 1 : tf - 1;
             const int sb = xyz + vxyz * tb;
             A v[24], h[12], u[18];
-            load_sp<P, A>(ib, inn, gs, ((size_t)(sb >> 1) << w.lognr) + r, v);
+            load_sp<P, A>(ib, inn, gsi, ((size_t)(FULL_IN ? sb : sb >> 1) << w.lognr) + r, v);
             PtP::project(v, h);
             link<P, Q, A>(ld, 3, sb, u);
             mul_udag(u, h, bw);
@@ -804,7 +814,7 @@ __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fl
                 const bool wrap = (t == Lt - 1);
                 const int sf = wrap ? xyz : site + vxyz;
                 A v[24], h[12], u[18], ww[12];
-                load_sp<P, A>(ib, inn, gs, ((size_t)(sf >> 1) << w.lognr) + r, v);
+                load_sp<P, A>(ib, inn, gsi, ((size_t)(FULL_IN ? sf : sf >> 1) << w.lognr) + r, v);
                 PtM::project(v, h);
                 link<P, Q, A>(ld, 3, site, u);
                 mul_u(u, h, ww);
@@ -816,9 +826,55 @@ __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fl
             PtP::accum(o, bw, A(-0.5));
 #pragma unroll
             for (int j = 0; j < 12; ++j) bw[j] = bn[j];
-            hop_dir_h<P, Q, true, 0, PxM, PxP>(ld, ib, inn, gs, site, c.x, 1, r, w.lognr, o);
-            hop_dir_h<P, Q, true, 1, PyM, PyP>(ld, ib, inn, gs, site, c.y, sy, r, w.lognr, o);
-            hop_dir_h<P, Q, true, 2, PzM, PzP>(ld, ib, inn, gs, site, c.z, sz, r, w.lognr, o);
+            hop_dir_h<P, Q, !FULL_IN, 0, PxM, PxP>(ld, ib, inn, gsi, site, c.x, 1, r, w.lognr, o);
+            hop_dir_h<P, Q, !FULL_IN, 1, PyM, PyP>(ld, ib, inn, gsi, site, c.y, sy, r, w.lognr, o);
+            hop_dir_h<P, Q, !FULL_IN, 2, PzM, PzP>(ld, ib, inn, gsi, site, c.z, sz, r, w.lognr, o);
+            if constexpr (MODE == D_PREP) {
+                // out_e = b_e - D_eo b_o / a; partial |b_e|^2 + |b_o|^2 (b_o at the odd
+                // site of the same field index).  The scheduling barriers keep the
+                // centre loads after the hop: hoisted above it they overflow the
+                // register file.
+                const A ia = A(1) / (A)diag[sys];
+                __builtin_amdgcn_sched_barrier(0);
+                {
+                    A be[24];
+                    load_sp<P, A>(ib, nullptr, gsf, ((size_t)site << w.lognr) + r, be);
+#pragma unroll
+                    for (int j = 0; j < 24; ++j) {
+                        if (act) acc[0] += (double)be[j] * (double)be[j];
+                        o[j] = be[j] - ia * o[j];
+                    }
+                }
+                store_sp<P, A, true>(ob, on, gs, slot, o);
+                __builtin_amdgcn_sched_barrier(0);
+                {
+                    A bo[24];
+                    load_sp<P, A>(ib, nullptr, gsf, ((size_t)(site ^ 1) << w.lognr) + r, bo);
+#pragma unroll
+                    for (int j = 0; j < 24; ++j)
+                        if (act) acc[0] += (double)bo[j] * (double)bo[j];
+                }
+                continue;
+            } else if constexpr (MODE == D_POST) {
+                // x_o = (b_o - D_oe x_e) / a at this odd site; x_e copied to the even
+                // site of the same field index
+                const A ia = A(1) / (A)diag[sys];
+                __builtin_amdgcn_sched_barrier(0);
+                {
+                    A bo[24];
+                    load_sp<P, A>(aux.v + (size_t)foff * G, nullptr, gsf, ((size_t)site << w.lognr) + r, bo);
+#pragma unroll
+                    for (int j = 0; j < 24; ++j) o[j] = ia * (bo[j] - o[j]);
+                }
+                store_sp<P, A, true>(ob, nullptr, gsf, ((size_t)site << w.lognr) + r, o);
+                __builtin_amdgcn_sched_barrier(0);
+                {
+                    A xe[24];
+                    load_sp<P, A>(ib, inn, gs, slot, xe);
+                    store_sp<P, A, true>(ob, nullptr, gsf, ((size_t)(site ^ 1) << w.lognr) + r, xe);
+                }
+                continue;
+            }
             A cv[24];
             if constexpr (MODE != D_HOP) {
                 load_sp<P, A>(cen.v + (size_t)bd.slot_off * G, cen.n ? cen.n + bd.slot_off : nullptr, gs, slot, cv);
@@ -860,7 +916,8 @@ __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fl
             }
         }
     }
-    if constexpr (MODE == D_RHAT || MODE == D_TS || MODE == D_RESID) block_partials<ND, 4>(acc, w.nr, part, wg_id);
+    if constexpr (MODE == D_RHAT || MODE == D_TS || MODE == D_RESID || MODE == D_PREP)
+        block_partials<ND, 4>(acc, w.nr, part, wg_id);
     });
 }
 
@@ -1047,15 +1104,15 @@ static void launch_eo_q(const Work& w, Fld out, Fld in, Fld cen, Fld aux, const 
             case 2:
                 if constexpr (P == P32)
                     hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, 2>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in,
-                                       cen, aux, diag, st, mask, part, rk, par_out);
+                                       cen, aux, diag, st, mask, part, rk, par_out, nullptr);
                 break;
             case 1:
                 hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, 1>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, cen,
-                                   aux, diag, st, mask, part, rk, par_out);
+                                   aux, diag, st, mask, part, rk, par_out, nullptr);
                 break;
             default:
                 hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, 0>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, cen,
-                                   aux, diag, st, mask, part, rk, par_out);
+                                   aux, diag, st, mask, part, rk, par_out, nullptr);
         }
         return;
     }
@@ -1104,6 +1161,16 @@ void launch_dslash_eo(int prec, int mode, const Work& w, Fld out, Fld in, Fld ce
 
 void launch_eo_prep(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld bh, const double* diag, double* part,
                     hipStream_t s) {
+    if (wh.tc > 0) {  // stencil mapping: stream over t
+        const size_t lds = lds_cap(wh.wg, wh.occ);
+        if (wh.nr >= 4)
+            hipLaunchKernelGGL((k_dslash_eo_t<P64, D_PREP, 1>), dim3(grid_of(wh)), dim3(wh.wg), lds, s, wh, bh, bfull,
+                               Fld(), Fld(), diag, nullptr, (int)M_ALL, part, nullptr, 0, fblocks);
+        else
+            hipLaunchKernelGGL((k_dslash_eo_t<P64, D_PREP, 0>), dim3(grid_of(wh)), dim3(wh.wg), lds, s, wh, bh, bfull,
+                               Fld(), Fld(), diag, nullptr, (int)M_ALL, part, nullptr, 0, fblocks);
+        return;
+    }
     if (wh.nr >= 4)
         hipLaunchKernelGGL(k_eo_prep<1>, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, bh, diag, part);
     else
@@ -1112,6 +1179,16 @@ void launch_eo_prep(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld bh,
 
 void launch_eo_post(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld xh, Fld xfull, const double* diag,
                     hipStream_t s) {
+    if (wh.tc > 0) {  // stencil mapping: stream over t
+        const size_t lds = lds_cap(wh.wg, wh.occ);
+        if (wh.nr >= 4)
+            hipLaunchKernelGGL((k_dslash_eo_t<P64, D_POST, 1>), dim3(grid_of(wh)), dim3(wh.wg), lds, s, wh, xfull, xh,
+                               Fld(), bfull, diag, nullptr, (int)M_ALL, nullptr, nullptr, 1, fblocks);
+        else
+            hipLaunchKernelGGL((k_dslash_eo_t<P64, D_POST, 0>), dim3(grid_of(wh)), dim3(wh.wg), lds, s, wh, xfull, xh,
+                               Fld(), bfull, diag, nullptr, (int)M_ALL, nullptr, nullptr, 1, fblocks);
+        return;
+    }
     if (wh.nr >= 4)
         hipLaunchKernelGGL(k_eo_post<1>, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, xh, xfull, diag);
     else

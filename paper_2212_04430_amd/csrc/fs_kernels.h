@@ -173,7 +173,9 @@ enum DMode : int {
     D_RHAT = 1,    // + partial (rhat, out)             [2 doubles]
     D_TS = 2,      // + partials (out, in), (out, out)  [3 doubles]
     D_RESID = 3,   // out = b - (D + sigma) in (b FP64 in aux) + |out|^2 [1 double]
-    D_HOP = 4      // even-odd only: out = D_{par_out, other} in, the off-diagonal block
+    D_HOP = 4,     // even-odd only: out = D_{par_out, other} in, the off-diagonal block
+    D_PREP = 5,    // even-odd, FP64: out_e = b_e - D_eo b_o / a from b in full layout, + |b|^2
+    D_POST = 6     // even-odd, FP64: x (full layout) = (x_e, (b_o - D_oe x_e) / a)
 };
 
 // Even-odd preconditioning.  Fields hold one parity (field site = site >> 1 with
