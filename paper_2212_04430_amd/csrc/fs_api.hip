@@ -380,6 +380,7 @@ struct Plan {
         for (int k = 0; k < 3; ++k) w.tl[k] = tl[k];
         w.occ = stencil ? occ : 0;
         w.two_rows = (P == P32 && two_rows) ? 1 : 0;
+        w.prow = 1;
         w.vlist = nullptr;
         w.vstart = nullptr;
         w.vcount = nullptr;
@@ -623,7 +624,13 @@ struct BatchSolver {
     VList vl_run, vl_pend, vl_conv;
     std::vector<SysState> st_host;
     long long dslash_calls = 0;
-    size_t part_rows = 0;
+    size_t part_doubles = 0;
+    // doubles of partial sums the launches over plan q may write
+    size_t part_need(const Plan& q) const {
+        const Work wq = q.work(o.P, false);
+        const size_t xr = (size_t)wq.total_wg * (size_t)update_xr_rows(o.P, wq) * 3 * q.nr;
+        return std::max((size_t)q.max_wg() * 32 * q.nr, xr);
+    }
 
     BatchSolver(Plan& plan, const std::vector<fs_ctx_s*>& l, hipStream_t stream, const SolveOpts& opts)
         : full(plan), eo_pl(opts.eo ? eo_plan_of(plan, l, stream, eo_occ(opts.P, plan.nr)) : nullptr),
@@ -641,9 +648,10 @@ struct BatchSolver {
         d_diag.alloc(sizeof(double) * pl.nsys);
         d_st.alloc(sizeof(SysState) * pl.nsys);
         // partial sums: max 4 doubles per rhs per workgroup (32 for hop launches,
-        // which callers run over the full-lattice plan)
-        part_rows = (size_t)std::max(pl.max_wg(), full.max_wg());
-        d_part.alloc(sizeof(double) * part_rows * 32 * pl.nr);
+        // which callers run over the full-lattice plan), or 3 per rhs in each of
+        // update_xr_rows rows per workgroup
+        part_doubles = std::max(part_need(pl), part_need(full));
+        d_part.alloc(sizeof(double) * part_doubles);
         d_flags.alloc(sizeof(int) * 2 * pl.blocks.size());
         const size_t nb = pl.blocks.size();
         d_vl.alloc(sizeof(int) * 3 * (3 * nb + 3));
@@ -732,7 +740,9 @@ struct BatchSolver {
         apply(o.P, D_TS, wd, t.f(), r.f(), Fld(), M_RUN, tmp.f());
         launch_finish(F_OMEGA, wd, st(), part(), nullptr, nullptr, s);
         launch_update_xr(o.P, wr, xlo.f(), p.f(), r.f(), t.f(), rk(), st(), part(), s);
-        launch_finish(F_RHO, wr, st(), part(), f_run(), f_pend(), s);
+        Work wrf = wr;
+        wrf.prow = update_xr_rows(o.P, wr);
+        launch_finish(F_RHO, wrf, st(), part(), f_run(), f_pend(), s);
         build_list(f_run(), vl_run);
         launch_update_p(o.P, listed(vl_run, o.P, false), p.f(), r.f(), v.f(), st(), s);
         dslash_calls += 2;
@@ -784,9 +794,9 @@ struct BatchSolver {
         }
         if (keep.empty() || keep.size() == cur->blocks.size()) return false;
         auto np = plan_from_blocks(keep, lats, pl.nr, pl.wg, s, pl.ilp, pl.occ, pl.eo);
-        if ((size_t)np->max_wg() > part_rows) {
-            part_rows = (size_t)np->max_wg();
-            d_part.alloc(sizeof(double) * part_rows * 32 * pl.nr);
+        if (part_need(*np) > part_doubles) {
+            part_doubles = part_need(*np);
+            d_part.alloc(sizeof(double) * part_doubles);
         }
         sub = std::move(np);
         cur = sub.get();

@@ -180,8 +180,11 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ f32x4_t ld_nt(const f32x4_t* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_nt(f32x4_t v, f32x4_t* p) { __builtin_nontemporal_store(v, p); }
 
-// body(block, group, slot) for this workgroup's tile, if it has one.
-template <typename F>
+// body(block, group, workgroup in the block, tile in the workgroup, slot) for
+// this workgroup's tile, if it has one.  PER_TILE: one workgroup per tile
+// (6 x workgroups x tpw); otherwise one per (group, tile-mapping workgroup),
+// walking its tpw tiles (6 x workgroups).
+template <bool PER_TILE = true, typename F>
 __device__ __forceinline__ void for_group_tile(const Work& w, F&& body) {
     constexpr int G = Tr<P32>::G;
     int n = 0, T;
@@ -192,12 +195,13 @@ __device__ __forceinline__ void for_group_tile(const Work& w, F&& body) {
     } else {
         T = w.total_wg;
     }
-    const long long per_g = (long long)T * w.tpw;
+    const int tpu = PER_TILE ? w.tpw : 1;  // units per tile-mapping workgroup
+    const long long per_g = (long long)T * tpu;
     const long long u = blockIdx.x;
     if (u >= per_g * G) return;
     const int g = (int)(u / per_g);
     const long long rem = u - (long long)g * per_g;
-    const int v = (int)(rem / w.tpw), it = (int)(rem - (long long)v * w.tpw);
+    const int v = (int)(rem / tpu), it0 = (int)(rem - (long long)v * tpu);
     int b, wgb;
     if (w.vlist) {
         const int k = __builtin_amdgcn_readfirstlane(find_block(w.vstart, n, v));
@@ -208,12 +212,16 @@ __device__ __forceinline__ void for_group_tile(const Work& w, F&& body) {
         if (w.blk_on && !w.blk_on[b]) return;
         wgb = v - w.wg_start[b];
     }
-    body(b, g, ((size_t)wgb * w.tpw + it) * w.wg + threadIdx.x);
+    if constexpr (PER_TILE) {
+        body(b, g, wgb, it0, ((size_t)wgb * w.tpw + it0) * w.wg + threadIdx.x);
+    } else {
+        for (int it = 0; it < w.tpw; ++it) body(b, g, wgb, it, ((size_t)wgb * w.tpw + it) * w.wg + threadIdx.x);
+    }
 }
 
 // s = r - alpha v  (stored in r), FP32 storage
 __global__ void __launch_bounds__(256) k_axpy_s_g(Work w, Fld r, Fld v, const SysState* __restrict__ st) {
-    for_group_tile(w, [&](const int b, const int g, const size_t slot) {
+    for_group_tile(w, [&](const int b, const int g, const int, const int, const size_t slot) {
         const BlockDesc bd = w.blocks[b];
         const size_t gs = (size_t)w.lats[bd.lat].Vf << w.lognr;
         if (slot >= gs) return;
@@ -234,7 +242,7 @@ __global__ void __launch_bounds__(256) k_axpy_s_g(Work w, Fld r, Fld v, const Sy
 
 // p = r + beta (p - omega v), FP32 storage
 __global__ void __launch_bounds__(256) k_update_p_g(Work w, Fld p, Fld r, Fld v, const SysState* __restrict__ st) {
-    for_group_tile(w, [&](const int b, const int g, const size_t slot) {
+    for_group_tile(w, [&](const int b, const int g, const int, const int, const size_t slot) {
         const BlockDesc bd = w.blocks[b];
         const size_t gs = (size_t)w.lats[bd.lat].Vf << w.lognr;
         if (slot >= gs) return;
@@ -255,6 +263,57 @@ __global__ void __launch_bounds__(256) k_update_p_g(Work w, Fld p, Fld r, Fld v,
         pv.w = rv.w + br * q3 + bi * q2;
         st_nt(pv, pp);
     });
+}
+
+// x += alpha p + omega s;  r = s - omega t  (s is held in r), FP32 storage, one
+// thread per group; partials (rhat, r), |r|^2 over the thread's two complex
+// components, rhat drawn from its Philox block.  A workgroup takes one group
+// of the tpw tiles of a tile-mapping workgroup and writes its own partial row,
+// (tile-mapping workgroup) * 6 + g, so a block's rows stay contiguous and the
+// finish sums 6 rows per workgroup (update_xr_rows) in a fixed order.
+__global__ void __launch_bounds__(256) k_update_xr_g(Work w, Fld x, Fld p, Fld r, Fld t,
+                                                     const NoiseKey* __restrict__ rk, const SysState* __restrict__ st,
+                                                     double* __restrict__ part) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    int row = -1;
+    for_group_tile<false>(w, [&](const int b, const int g, const int wgb, const int, const size_t slot) {
+        const BlockDesc bd = w.blocks[b];
+        row = (w.wg_start[b] + wgb) * Tr<P32>::G + g;
+        const size_t gs = (size_t)w.lats[bd.lat].Vf << w.lognr;
+        if (slot >= gs) return;
+        const int sys = bd.sys0 + (int)(slot & (size_t)(w.nr - 1));
+        if (st[sys].state != S_RUN) return;
+        const float ar = (float)st[sys].alpha[0], ai = (float)st[sys].alpha[1];
+        const float wr = (float)st[sys].omega[0], wi = (float)st[sys].omega[1];
+        const size_t e = (size_t)g * gs + slot;
+        f32x4_t* xp = reinterpret_cast<f32x4_t*>(fbase_w<P32>(x, bd)) + e;
+        f32x4_t* rp = reinterpret_cast<f32x4_t*>(fbase_w<P32>(r, bd)) + e;
+        const f32x4_t pv = ld_nt(reinterpret_cast<const f32x4_t*>(fbase<P32>(p, bd)) + e);
+        const f32x4_t tv = ld_nt(reinterpret_cast<const f32x4_t*>(fbase<P32>(t, bd)) + e);
+        f32x4_t xv = ld_nt(xp), sv = ld_nt(rp);
+        xv.x += ar * pv.x - ai * pv.y + wr * sv.x - wi * sv.y;
+        xv.y += ar * pv.y + ai * pv.x + wr * sv.y + wi * sv.x;
+        xv.z += ar * pv.z - ai * pv.w + wr * sv.z - wi * sv.w;
+        xv.w += ar * pv.w + ai * pv.z + wr * sv.w + wi * sv.z;
+        st_nt(xv, xp);
+        sv.x -= wr * tv.x - wi * tv.y;
+        sv.y -= wr * tv.y + wi * tv.x;
+        sv.z -= wr * tv.z - wi * tv.w;
+        sv.w -= wr * tv.w + wi * tv.z;
+        st_nt(sv, rp);
+        float h[4];
+        rhat_pair(rk[sys], st[sys].restarts, (long long)(slot >> w.lognr), 2 * g, h);
+        const float q[4] = {sv.x, sv.y, sv.z, sv.w};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const double hr = h[2 * k], hi = h[2 * k + 1], qr = q[2 * k], qi = q[2 * k + 1];
+            acc[0] += hr * qr + hi * qi;
+            acc[1] += hr * qi - hi * qr;
+            acc[2] += qr * qr + qi * qi;
+        }
+    });
+    if (row < 0) return;  // no tile: the whole workgroup leaves
+    block_partials<3, 4>(acc, w.nr, part, row);
 }
 
 // x_hi += x_lo; x_lo = 0  (systems pending a reliable update)
@@ -498,7 +557,8 @@ __global__ void __launch_bounds__(256) k_finish(Work w, SysState* __restrict__ s
     const int b = w.vlist ? w.vlist[kk] : (int)blockIdx.x;
     const BlockDesc bd = w.blocks[b];
     if (!w.vlist && w.blk_on && !w.blk_on[b] && STAGE != F_INIT) return;
-    reduce_rows(part, ND * nr, w.wg_start[b], w.wg_start[b + 1], q);
+    const int M = w.prow > 1 ? w.prow : 1;  // partial rows per workgroup of the mapping
+    reduce_rows(part, ND * nr, w.wg_start[b] * M, w.wg_start[b + 1] * M, q);
     if (threadIdx.x == 0) {
         any_on = 0;
         any_rel = 0;
@@ -967,8 +1027,15 @@ void launch_axpy_s(int prec, const Work& w, Fld r, Fld v, const SysState* st, hi
     }
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_axpy_s<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, r, v, st))
 }
+int update_xr_rows(int prec, const Work& w) { return (prec == P32 && w.wg == 256) ? Tr<P32>::G : 1; }
+
 void launch_update_xr(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, const NoiseKey* rk, const SysState* st,
                       double* part, hipStream_t s) {
+    if (update_xr_rows(prec, w) > 1) {
+        hipLaunchKernelGGL(k_update_xr_g, dim3((unsigned)((long long)Tr<P32>::G * w.total_wg)), dim3(256), 0, s, w,
+                           x, p, r, t, rk, st, part);
+        return;
+    }
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_update_xr<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, x, p, r, t, rk,
                                            st, part))
 }

@@ -49,6 +49,7 @@ struct Work {
     int tl[3];                // stencil variant 2: log2 of the tile extent in x, y, z
     int occ;                  // stencil: cap on resident waves per SIMD (0 = none)
     int two_rows;             // FP32 gauge_q of every lattice holds rows 0-1 only
+    int prow;                 // finish stages: partial-sum rows per workgroup of the mapping (<= 1: one)
     // Persistent launches: when vlist is set, a fixed grid walks the virtual
     // workgroups of the blocks listed there (vlist[0..*vcount)), vstart being
     // their prefix sums in this launch's mapping (tile or stencil table).
@@ -145,6 +146,25 @@ __device__ __forceinline__ void z4_site(const NoiseKey& k, long long site, doubl
     }
 }
 
+// Components j0 and j0 + 1 (j0 even) of z4_site: both come from one Philox
+// block, since site*12 + j0 is even.
+__device__ __forceinline__ void z4_pair(const NoiseKey& k, long long site, int j0, double v[4]) {
+    const long long c = site * 12 + j0;
+    const U64x4 o = philox4x64_10((uint64_t)(c >> 7), k.sample, k.level, k.instance, k.seed, 0ull);
+    const int e = (int)(c & 127);  // e and e + 1 share a word (e even)
+    const int wi = e >> 5;
+    const uint64_t w01 = wi == 0 ? o.v[0] : o.v[1];
+    const uint64_t w23 = wi == 2 ? o.v[2] : o.v[3];
+    const uint64_t word = wi < 2 ? w01 : w23;
+    const double sg = (k.g5 && j0 >= 6) ? -1.0 : 1.0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int code = (int)((word >> (2 * ((e + i) & 31))) & 3ull);
+        v[2 * i] = sg * (code == 0 ? 1.0 : code == 2 ? -1.0 : 0.0);
+        v[2 * i + 1] = sg * (code == 1 ? 1.0 : code == 3 ? -1.0 : 0.0);
+    }
+}
+
 // BiCGStab shadow residual of a system: its Z4 source stream (rhat = r0 = b
 // for estimator systems, x0 = 0); after the n-th breakdown restart a fresh Z4
 // stream (instance bit 31 set, level + n).  Padding systems: zero.
@@ -164,6 +184,23 @@ __device__ __forceinline__ void rhat_site(const NoiseKey& k0, int restarts, long
     z4_site(k, site, d);
 #pragma unroll
     for (int j = 0; j < 24; ++j) v[j] = (A)d[j];
+}
+// Components j0, j0 + 1 of rhat_site (j0 even).
+__device__ __forceinline__ void rhat_pair(const NoiseKey& k0, int restarts, long long site, int j0, float v[4]) {
+    if (k0.pad) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = 0.0f;
+        return;
+    }
+    NoiseKey k = k0;
+    if (restarts > 0) {
+        k.instance ^= 0x80000000u;
+        k.level += (uint32_t)restarts;
+    }
+    double d[4];
+    z4_pair(k, site, j0, d);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = (float)d[j];
 }
 enum Mask : int { M_ALL = 0, M_RUN = 1, M_PEND = 2, M_CONVERT = 3, M_UPDP = 4 };
 
@@ -205,6 +242,9 @@ void launch_dslash(int prec, int mode, const Work& w, Fld out, Fld in, Fld aux, 
 void launch_axpy_s(int prec, const Work& w, Fld r, Fld v, const SysState* st, hipStream_t s);
 void launch_update_xr(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, const NoiseKey* rk,
                       const SysState* st, double* part, hipStream_t s);
+// Partial-sum rows per workgroup of w that launch_update_xr writes (the F_RHO
+// finish that follows must be given them in Work::prow).
+int update_xr_rows(int prec, const Work& w);
 void launch_update_p(int prec, const Work& w, Fld p, Fld r, Fld v, const SysState* st, hipStream_t s);
 
 // finish kernels: one workgroup per block, reduce partials, update state
