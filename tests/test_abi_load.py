@@ -60,6 +60,7 @@ def test_argument_errors_before_device_work():
     rc = L._lib.fs_upload_gauge(None, None, 0)
     assert rc == L.FS_E_ARG
     assert L._lib.fs_set_tuning(None, 1, 4, 256, 2, 0) == L.FS_E_ARG
+    assert L._lib.fs_gauge_info(None, None, None) == L.FS_E_ARG
 
 
 def test_plain_library_has_no_oracle_dependency():
