@@ -106,8 +106,11 @@ def level_vectors(solver, sigmas, level, z):
 
 
 def fs_samples(U, dims, sigmas, n_noise, seed, gammas, p_max, solver,
-               instance=0, levels=None, samples=None):
-    """Per-sample estimates X[l, s, n_idx, p] with independent noise per level."""
+               instance=0, levels=None, samples=None, shared_noise=False):
+    """Per-sample estimates X[l, s, n_idx, p] with independent noise per level
+    (eq. fs_trace_est), or with one noise vector z_s for every level
+    (shared_noise: the key of level 0), as the sampling algorithm of Sec. 3.1
+    shares its noise across shifts."""
     L = len(sigmas) - 1
     V = lat.volume(dims)
     levels = range(L + 1) if levels is None else levels
@@ -115,7 +118,7 @@ def fs_samples(U, dims, sigmas, n_noise, seed, gammas, p_max, solver,
     X = np.zeros((L + 1, len(samples), len(gammas), p_max + 1), dtype=np.complex128)
     for l in levels:
         for j, s in enumerate(samples):
-            z = z4_noise(V, seed, instance, l, s)
+            z = z4_noise(V, seed, instance, 0 if shared_noise else l, s)
             coef, y, x = level_vectors(solver, sigmas, l, z)
             X[l, j] = coef * bilinears(U, dims, y, x, gammas, p_max)
     return X
@@ -128,6 +131,16 @@ def level_stats(X, axis=1):
     var_paper = (np.abs(X) ** 2).mean(axis=axis) - np.abs(t) ** 2
     var_unbiased = var_paper * N / (N - 1) if N > 1 else np.full_like(var_paper, np.nan)
     return t, var_paper, var_unbiased
+
+
+def optimal_samples(V, C, eps2):
+    """Eq. num_samples: real-valued N_l = mu sqrt(V_l / C_l) with
+    mu = eps^-2 sum_l sqrt(V_l C_l) (the Lagrange solution of: least
+    sum_l C_l N_l subject to sum_l V_l / N_l = eps^2).  Returns (N, mu)."""
+    V = np.asarray(V, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    mu = np.sum(np.sqrt(V * C)) / eps2
+    return mu * np.sqrt(V / C), mu
 
 
 def fs_combine(t_levels, var_levels, n_levels):

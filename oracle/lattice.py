@@ -199,3 +199,22 @@ def gamma_dense(n, V):
     import scipy.sparse as sp
     blk = np.kron(gamma_n(n), np.eye(3))
     return sp.kron(sp.identity(V, format='csr'), sp.csr_matrix(blk), format='csr')
+
+
+def link_norm_bound(U):
+    """Largest spectral norm of the links, max_x,mu ||U_mu(x)||_2 (from numpy's SVD)."""
+    U = np.asarray(U).reshape(-1, 3, 3)
+    return float(np.linalg.norm(U, ord=2, axis=(1, 2)).max())
+
+
+def smin_lower_bound(U, m0, sigma):
+    """Lower bound on the smallest singular value of D + sigma.
+
+    D + sigma = (4 + m0 + sigma) - sum_mu H_mu with H_mu = P-_mu (U_mu shift_+mu)
+    + P+_mu (shift_-mu U_mu^dagger), P-+_mu = (1 -+ g_mu)/2 complementary
+    orthogonal spin projectors that commute with the colour/site maps, so
+    ||H_mu psi||^2 = ||A P- psi||^2 + ||B P+ psi||^2 <= u^2 ||psi||^2 with u the
+    largest link norm (antiperiodic signs do not change norms).  Hence
+    s_min >= 4 + m0 + sigma - 4 u.  Parity: pinned against dense SVD (tests).
+    """
+    return 4.0 + m0 + sigma - 4.0 * link_norm_bound(U)
