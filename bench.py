@@ -129,10 +129,13 @@ def committed_traffic(config_key):
     return None
 
 
-def setup_tuning():
-    """Copy the committed tuning table to a scratch path the library may append to."""
-    path = os.path.join(ROOT, "gpurun_out", "autotune.txt")
-    os.makedirs(os.path.dirname(path), exist_ok=True)
+def setup_tuning(path=None):
+    """Copy the committed tuning table to a scratch file the library may append to
+    (a temporary file unless --tuning-cache names one)."""
+    if path is None:
+        import tempfile
+        fd, path = tempfile.mkstemp(prefix="fsmlmc_tune_", suffix=".txt")
+        os.close(fd)
     if os.path.exists(TUNING):
         with open(TUNING) as src, open(path, "w") as dst:
             dst.write(src.read())
@@ -222,6 +225,8 @@ def main():
     ap.add_argument("--roofline-only", action="store_true", help="only the copy and stencil launches of the roofline")
     ap.add_argument("--no-select", action="store_true", help="skip variance sampling and shift selection")
     ap.add_argument("--no-probe", action="store_true", help="skip the probed, spin-colour diluted estimate")
+    ap.add_argument("--tuning-cache", default=None, help="autotune cache file (default: a temporary copy of the "
+                                                           "committed table)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the hot path shards over independent systems "
@@ -241,7 +246,7 @@ def main():
     systems_per_step = w["n_noise"] * (2 * L_lev + 1)
 
     # stencil configuration: committed tuning table (tuned on the GPU when missing)
-    cache = setup_tuning()
+    cache = setup_tuning(args.tuning_cache)
     nr, wg = L.fs_autotune(ctx, "f32", systems_per_step, cache)
     log(f"tuning f32: rhs_block={nr} wg={wg}")
     if args.roofline_only:

@@ -33,6 +33,9 @@
  *  * Every call returns fs_status and never aborts or throws across the ABI.
  *    FS_E_ARG is returned before anything is written.  The message of the
  *    last failing call on this thread is returned by fs_last_error().
+ *  * Threads: calls on different contexts may come from different host
+ *    threads (the library's device-memory cache is locked); calls on one
+ *    context, or on a batch and its contexts, must not overlap.
  *  * Work is issued on the context's HIP stream.  Calls that return results
  *    through host pointers synchronise that stream before returning; calls
  *    whose outputs are device pointers also synchronise (the ABI is
@@ -173,10 +176,19 @@ fs_status fs_solve_shifted(fs_ctx ctx, const fs_solve_params* prm, const double*
 
 typedef struct {
     uint64_t seed;           /* noise seed                                          */
-    int32_t n_noise;         /* Z4 vectors per level (>= 2 for a variance)          */
+    int32_t n_noise;         /* Z4 vectors per level (>= 2 for a variance), unless
+                                n_level is given                                    */
     uint16_t gamma_mask;     /* bit n -> report Gamma_n (0 = all 16)                */
     int32_t p_max;           /* displacements p = 0..p_max, p_max < Lz              */
     fs_solve_params solve;   /* solver settings (storage FS_F64 = plain path)       */
+    const int32_t* n_level;  /* NULL, or host [L+1]: N_l samples of level l, each in
+                                1..2^24 (eq. fs_trace_est; e.g. from eq. num_samples
+                                via fs_optimal_samples); n_noise is then ignored     */
+    int32_t shared_noise;    /* 0: independent noise z_{s,l} per level (eq.
+                                fs_trace_est); 1: one vector z_s for every level,
+                                the Z4 vector of key (seed, instance, 0, s), as in the
+                                sampling algorithm of Sec. 3.1 (levels then correlate) */
+    int32_t report_fp64_error; /* 1: fill fp64_rel_err and err_bound of every level */
 } fs_est_params;
 
 typedef struct {
@@ -185,7 +197,57 @@ typedef struct {
     double var_unbiased;     /* var_paper * N/(N-1)                                 */
     int64_t n;               /* samples                                             */
     double max_rel_residual; /* worst FP64 true residual of this level's solves     */
+    /* With report_fp64_error (else 0):
+     * fp64_rel_err  |mean - mean_64| / ((1/N) sum_s |X64_s|): deviation of this
+     *               level's mean from the same estimate (same noise) solved on the
+     *               plain FP64 path, which the call runs for this purpose when the
+     *               storage is not FS_F64 (0 for FS_F64 storage);
+     * err_bound     an upper bound on |X_s - X_s^exact| for every sample s of the
+     *               level, X_s^exact being the sample with exact solves:
+     *               |c| (||y~|| e_x + e_y (||x~|| + e_x)) ||Gamma_n Omega_p||, with
+     *               e = ||b - (D+sigma)v~|| / s_lo(sigma) for each solve v~ (FP64
+     *               true residual), c = sigma_{l+1} - sigma_l (l < L, y from the
+     *               sigma_l solve) or c = 1 and e_y = 0 with y = z (l = L).
+     *               s_lo(sigma) = 4 + m0 + sigma - 4 u is a lower bound on the
+     *               smallest singular value of D + sigma, u the largest spectral
+     *               norm of a link (each direction's hopping term is a pair of
+     *               orthogonal spin projectors times maps of norm <= u), and
+     *               ||Gamma_n Omega_p|| <= u^p.  +Inf when s_lo <= 0.          */
+    double fp64_rel_err;
+    double err_bound;
 } fs_level_stat;
+
+/*
+ * fs_level_totals -- per (Gamma_n, p), the combination of the levels of an
+ * estimate (paper Sec. 2.3): the FS trace estimate sum_l mean_l (eq.
+ * fs_trace_est), V_FS = sum_l V_l / N_l (eq. total_var) and V_total = sum_l V_l
+ * (eq. tosv), with V_l the level's eq. practical_variance and, beside them, the
+ * same with the (N-1)-normalised variances; err_bound = sum_l err_bound_l.
+ * Host arithmetic over the output of fs_estimate / fs_batch_estimate /
+ * fs_estimate_probed for one instance: levels [(L+1)][16][p_max+1], out
+ * [16][p_max+1] (Gamma_n with n_l = 0 on every level are zeroed).
+ */
+typedef struct {
+    double tr_re, tr_im;     /* sum_l mean_l                                        */
+    double v_fs;             /* sum_l var_paper_l / n_l      (eq. total_var)        */
+    double v_fs_unbiased;    /* sum_l var_unbiased_l / n_l                          */
+    double v_total;          /* sum_l var_paper_l            (eq. tosv)             */
+    double v_total_unbiased; /* sum_l var_unbiased_l                                */
+    double err_bound;        /* sum_l err_bound_l                                   */
+} fs_total_stat;
+fs_status fs_level_totals(const fs_level_stat* levels, int32_t L, int32_t p_max, fs_total_stat* out);
+
+/*
+ * fs_optimal_samples -- eq. num_samples: N_l = mu sqrt(V_l / C_l) with
+ * mu = eps^-2 sum_l sqrt(V_l C_l), the sample counts that reach the target
+ * variance V_FS = eps^2 at the least total cost sum_l C_l N_l (eq. ml_cost_shifts).
+ * Each N_l is rounded up, and raised to n_min (>= 1; 2 gives every level a
+ * variance), so that V_FS <= eps^2.  v_levels, c_levels: host [L+1], V_l >= 0,
+ * C_l > 0 (e.g. from fs_select_shifts); eps2 > 0.  n_out: host [L+1];
+ * FS_E_ARG if a count exceeds 2^24.  mu_out (nullable): mu.
+ */
+fs_status fs_optimal_samples(const double* v_levels, const double* c_levels, int32_t L, double eps2,
+                             int32_t n_min, int32_t* n_out, double* mu_out);
 
 typedef struct {
     int64_t systems;         /* shifted systems solved                              */
@@ -202,9 +264,11 @@ typedef struct {
  * strictly increasing (FS_E_ARG otherwise).  Level l < L uses
  * X = (sigma_{l+1}-sigma_l) y^+ Gamma_n Omega_p x with x = (D+sigma_{l+1})^-1 z,
  * y = g5 (D+sigma_l)^-1 g5 z; level L uses X = z^+ Gamma_n Omega_p (D+sigma_L)^-1 z;
- * z is the Z4 vector (seed, instance, level, sample), samples 0..n_noise-1.
+ * z is the Z4 vector (seed, instance, level, sample) -- level 0 for every level
+ * with shared_noise -- for samples s = 0..N_l-1 (N_l = n_level[l], or n_noise).
  *   out          [(L+1)][16][p_max+1] fs_level_stat (unrequested Gamma zeroed)
- *   samples_out  NULL or host [(L+1)][n_noise][16][p_max+1] complex128: every X_s
+ *   samples_out  NULL or host [(L+1)][N][16][p_max+1] complex128 with N = max_l N_l:
+ *                every X_s (entries s >= N_l of level l are zero)
  *   report       NULL or totals of the call
  */
 fs_status fs_estimate(fs_ctx ctx, const fs_est_params* prm, const double* sigma, int32_t L,
@@ -232,6 +296,8 @@ fs_status fs_estimate(fs_ctx ctx, const fs_est_params* prm, const double* sigma,
  *   report       NULL or totals of the call
  * FS_E_ARG for invalid arguments (before any device work); FS_E_NOCONV if a
  * solve missed tol (outputs still filled).  All systems are solved in one batch.
+ * n_level, shared_noise and report_fp64_error of prm are not used here (the
+ * sampling noise is always shared; the error fields are zero).
  */
 fs_status fs_sample_variances(fs_ctx ctx, const fs_est_params* prm, const double* shifts, int32_t m,
                               fs_level_stat* single, fs_level_stat* pair, double* samples_out,
@@ -242,11 +308,13 @@ fs_status fs_sample_variances(fs_ctx ctx, const fs_est_params* prm, const double
  * stencil, BLAS and reduction launch of fs_batch_estimate covers the systems
  * of all instances.  Contexts must be on the same device and have gauge
  * uploaded; instance k uses noise instance index (its fs_set_instance value).
- *   out [n][(L+1)][16][p_max+1]
+ *   out          [n][(L+1)][16][p_max+1]
+ *   samples_out  NULL or host [n][(L+1)][N][16][p_max+1] complex128 (as fs_estimate)
  */
 fs_status fs_batch_create(fs_batch* out, const fs_ctx* ctxs, int32_t n);
 fs_status fs_batch_estimate(fs_batch b, const fs_est_params* prm, const double* sigma,
-                            int32_t L, fs_level_stat* out, fs_est_report* report);
+                            int32_t L, fs_level_stat* out, double* samples_out,
+                            fs_est_report* report);
 fs_status fs_batch_destroy(fs_batch b);
 
 /*
@@ -305,7 +373,8 @@ fs_status fs_time_dslash(fs_ctx ctx, fs_prec storage, int32_t n_sys, int32_t rhs
  * per SIMD, 0 = none, -1 = the one the even-odd solver uses), every extent
  * even.  bytes:
  * per output site and system 48 stored reals (+ FP16 scales), plus every link
- * of the lattice (72 reals per site) once per block.
+ * of the lattice once per block: 4 links of 18 reals per site, or 12 reals per
+ * link where the FP32 stencils read two rows (fs_gauge_info, rhs blocks >= 4).
  */
 fs_status fs_time_dslash_eo(fs_ctx ctx, fs_prec storage, int32_t n_sys, int32_t rhs_block, int32_t occ,
                             int32_t n_launch, double* avg_ms, double* bytes);
@@ -345,6 +414,8 @@ fs_status fs_probing_colours(const int32_t dims[4], int32_t p, int32_t k, int32_
  *                 (s_a = +1 for spins 0, 1 and -1 for spins 2, 3: g5 z = s_a z)
  *   level L:      X = sum_{j,a} z^+ Gamma_n Omega_p (D+sigma_L)^-1 z
  * so each sample costs 12 n_colours (2L+1) solves, all in one batch.
+ * n_noise samples per level; n_level, shared_noise and report_fp64_error of prm
+ * are not used here (the error fields are zero).
  *   colours      host [volume], values 0..n_colours-1, every colour used (1 <= n_colours <= 4096)
  *   out, samples_out, report as for fs_estimate (samples_out holds the per-sample sums)
  * FS_E_ARG for invalid arguments (before any device work); FS_E_NOCONV if a

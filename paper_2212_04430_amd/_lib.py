@@ -56,12 +56,34 @@ class fs_solve_stats(C.Structure):
 
 class fs_est_params(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_noise", C.c_int32), ("gamma_mask", C.c_uint16),
-                ("p_max", C.c_int32), ("solve", fs_solve_params)]
+                ("p_max", C.c_int32), ("solve", fs_solve_params), ("n_level", C.POINTER(C.c_int32)),
+                ("shared_noise", C.c_int32), ("report_fp64_error", C.c_int32)]
+
+    def set_n_level(self, counts):
+        """Per-level sample counts N_l (None: n_noise on every level); the array is kept alive here."""
+        if counts is None:
+            self._n_level = None
+            self.n_level = C.POINTER(C.c_int32)()
+        else:
+            self._n_level = np.ascontiguousarray(counts, dtype=np.int32)
+            self.n_level = self._n_level.ctypes.data_as(C.POINTER(C.c_int32))
+        return self
+
+    def n_slots(self, n_levels):
+        """Sample slots per level of the samples array (max N_l)."""
+        nl = getattr(self, "_n_level", None)
+        return int(max(nl)) if nl is not None else int(self.n_noise)
 
 
 class fs_level_stat(C.Structure):
     _fields_ = [("tr_re", C.c_double), ("tr_im", C.c_double), ("var_paper", C.c_double),
-                ("var_unbiased", C.c_double), ("n", C.c_int64), ("max_rel_residual", C.c_double)]
+                ("var_unbiased", C.c_double), ("n", C.c_int64), ("max_rel_residual", C.c_double),
+                ("fp64_rel_err", C.c_double), ("err_bound", C.c_double)]
+
+
+class fs_total_stat(C.Structure):
+    _fields_ = [("tr_re", C.c_double), ("tr_im", C.c_double), ("v_fs", C.c_double), ("v_fs_unbiased", C.c_double),
+                ("v_total", C.c_double), ("v_total_unbiased", C.c_double), ("err_bound", C.c_double)]
 
 
 class fs_est_report(C.Structure):
@@ -94,8 +116,10 @@ _sig = {
     "fs_sample_variances": (C.c_int, [_P, C.POINTER(fs_est_params), _P, C.c_int32, C.POINTER(fs_level_stat),
                                       C.POINTER(fs_level_stat), _P, _P, C.POINTER(fs_est_report)]),
     "fs_batch_create": (C.c_int, [C.POINTER(_P), C.POINTER(_P), C.c_int32]),
-    "fs_batch_estimate": (C.c_int, [_P, C.POINTER(fs_est_params), _P, C.c_int32, C.POINTER(fs_level_stat),
+    "fs_batch_estimate": (C.c_int, [_P, C.POINTER(fs_est_params), _P, C.c_int32, C.POINTER(fs_level_stat), _P,
                                     C.POINTER(fs_est_report)]),
+    "fs_level_totals": (C.c_int, [C.POINTER(fs_level_stat), C.c_int32, C.c_int32, C.POINTER(fs_total_stat)]),
+    "fs_optimal_samples": (C.c_int, [_DP, _DP, C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_int32), _DP]),
     "fs_batch_destroy": (C.c_int, [_P]),
     "fs_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "fs_set_tuning": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
@@ -263,28 +287,56 @@ def fs_solve_shifted(ctx, params, sigma, B, allow_noconv=False):
     return X, [st[i] for i in range(len(st))], code
 
 
+STAT_FIELDS = ("tr_re", "tr_im", "var_paper", "var_unbiased", "n", "max_rel_residual", "fp64_rel_err", "err_bound")
+
+
 def _stats_array(stats, shape):
-    a = np.zeros(shape + (6,))
-    flat = a.reshape(-1, 6)
+    a = np.zeros(shape + (len(STAT_FIELDS),))
+    flat = a.reshape(-1, len(STAT_FIELDS))
     for i, s in enumerate(stats):
-        flat[i] = (s.tr_re, s.tr_im, s.var_paper, s.var_unbiased, s.n, s.max_rel_residual)
+        flat[i] = tuple(getattr(s, f) for f in STAT_FIELDS)
     return a
 
 
-def fs_estimate(ctx, params, sigma, want_samples=False, allow_noconv=False):
-    """Per-level stats as an array [L+1, 16, p_max+1, 6] (tr_re, tr_im, var_paper,
-    var_unbiased, n, max_rel_residual), the per-sample X [L+1, N, 16, p_max+1]
-    (or None) and the report."""
+def fs_estimate(ctx, params, sigma, want_samples=False, allow_noconv=False, raw=False):
+    """Per-level stats as an array [L+1, 16, p_max+1, 8] (STAT_FIELDS: tr_re, tr_im,
+    var_paper, var_unbiased, n, max_rel_residual, fp64_rel_err, err_bound), the
+    per-sample X [L+1, N, 16, p_max+1] (N = max_l N_l; or None) and the report.
+    raw=True also returns the fs_level_stat array (for fs_level_totals)."""
     sig = np.ascontiguousarray(sigma, dtype=np.float64)
     L = len(sig) - 1
     P1 = params.p_max + 1
     out = (fs_level_stat * ((L + 1) * 16 * P1))()
-    samples = np.zeros((L + 1, params.n_noise, 16, P1), dtype=np.complex128) if want_samples else None
+    N = params.n_slots(L + 1)
+    samples = np.zeros((L + 1, N, 16, P1), dtype=np.complex128) if want_samples else None
     rep = fs_est_report()
     code = _lib.fs_estimate(ctx, C.byref(params), C.c_void_p(sig.ctypes.data), L, out,
                             C.c_void_p(samples.ctypes.data) if want_samples else None, C.byref(rep))
     _check(code, allow=(FS_E_NOCONV,) if allow_noconv else ())
-    return _stats_array(list(out), (L + 1, 16, P1)), samples, rep
+    st = _stats_array(list(out), (L + 1, 16, P1))
+    return (st, samples, rep, out) if raw else (st, samples, rep)
+
+
+def fs_level_totals(levels, L, p_max):
+    """Totals per (Gamma_n, p) from an fs_level_stat array: dict of [16, p_max+1] arrays
+    (tr (complex), v_fs, v_fs_unbiased, v_total, v_total_unbiased, err_bound)."""
+    P1 = p_max + 1
+    out = (fs_total_stat * (16 * P1))()
+    _check(_lib.fs_level_totals(levels, int(L), int(p_max), out))
+    g = lambda f: np.array([getattr(o, f) for o in out]).reshape(16, P1)
+    return {"tr": g("tr_re") + 1j * g("tr_im"), "v_fs": g("v_fs"), "v_fs_unbiased": g("v_fs_unbiased"),
+            "v_total": g("v_total"), "v_total_unbiased": g("v_total_unbiased"), "err_bound": g("err_bound")}
+
+
+def fs_optimal_samples(v_levels, c_levels, eps2, n_min=2):
+    """(N_l [L+1] int array, mu) of eq. num_samples."""
+    v = np.ascontiguousarray(v_levels, dtype=np.float64)
+    c = np.ascontiguousarray(c_levels, dtype=np.float64)
+    n = np.zeros(len(v), dtype=np.int32)
+    mu = C.c_double()
+    _check(_lib.fs_optimal_samples(_dp(v), _dp(c), len(v) - 1, float(eps2), int(n_min),
+                                   n.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(mu)))
+    return n, mu.value
 
 
 def fs_sample_variances(ctx, params, shifts, want_samples=False, allow_noconv=False):
@@ -316,15 +368,21 @@ def fs_batch_create(ctxs):
     return h
 
 
-def fs_batch_estimate(batch, n_inst, params, sigma, allow_noconv=False):
+def fs_batch_estimate(batch, n_inst, params, sigma, allow_noconv=False, want_samples=False):
+    """Stats [n_inst, L+1, 16, p_max+1, 8] and the report; with want_samples also the
+    per-sample X [n_inst, L+1, N, 16, p_max+1] (returned between them)."""
     sig = np.ascontiguousarray(sigma, dtype=np.float64)
     L = len(sig) - 1
     P1 = params.p_max + 1
     out = (fs_level_stat * (n_inst * (L + 1) * 16 * P1))()
+    N = params.n_slots(L + 1)
+    samples = np.zeros((n_inst, L + 1, N, 16, P1), dtype=np.complex128) if want_samples else None
     rep = fs_est_report()
-    code = _lib.fs_batch_estimate(batch, C.byref(params), C.c_void_p(sig.ctypes.data), L, out, C.byref(rep))
+    code = _lib.fs_batch_estimate(batch, C.byref(params), C.c_void_p(sig.ctypes.data), L, out,
+                                  C.c_void_p(samples.ctypes.data) if want_samples else None, C.byref(rep))
     _check(code, allow=(FS_E_NOCONV,) if allow_noconv else ())
-    return _stats_array(list(out), (n_inst, L + 1, 16, P1)), rep
+    st = _stats_array(list(out), (n_inst, L + 1, 16, P1))
+    return (st, samples, rep) if want_samples else (st, rep)
 
 
 def fs_batch_destroy(batch):

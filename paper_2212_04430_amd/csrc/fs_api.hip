@@ -12,8 +12,10 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <limits>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <stdexcept>
 #include <string>
@@ -77,6 +79,7 @@ fs_status guard(F&& f) {
 // reused, so repeated solves and estimates do not call hipMalloc/hipFree in
 // their loops.  Sizes are rounded up to 2 MiB above 1 MiB.
 struct Pool {
+    std::recursive_mutex mu;  // several host threads may drive contexts at once
     std::multimap<std::pair<int, size_t>, void*> free_;
     size_t cached = 0;
     size_t cap = 0;
@@ -100,6 +103,7 @@ struct Pool {
         return (n + g - 1) / g * g;
     }
     void* get(size_t n, hipError_t* err) {
+        std::lock_guard<std::recursive_mutex> lk(mu);
         int dev = 0;
         (void)hipGetDevice(&dev);
         auto it = free_.find({dev, n});
@@ -128,6 +132,7 @@ struct Pool {
         return *err == hipSuccess ? p : nullptr;
     }
     void put(void* p, size_t n) {
+        std::lock_guard<std::recursive_mutex> lk(mu);
         int dev = 0;
         (void)hipGetDevice(&dev);
         free_.insert({{dev, n}, p});
@@ -135,6 +140,7 @@ struct Pool {
         if (cached > limit()) trim(limit() / 2);
     }
     void trim(size_t keep) {
+        std::lock_guard<std::recursive_mutex> lk(mu);
         while (cached > keep && !free_.empty()) {
             auto it = std::prev(free_.end());  // largest first
             (void)hipDeviceSynchronize();
@@ -145,6 +151,7 @@ struct Pool {
     }
 };
 int g_live_ctx = 0;  // contexts alive; the device cache is released with the last
+std::mutex g_ctx_mu;  // guards g_live_ctx
 
 Pool& pool() {
     static Pool* p = new Pool();  // never destroyed: blocks live until process exit
@@ -229,12 +236,39 @@ double su3_row_defect(const double* u, size_t n_links) {
             const double re = (akr * blr - aki * bli) - (alr * bkr - ali * bki);
             const double im = (akr * bli + aki * blr) - (alr * bki + ali * bkr);
             const double d = std::hypot(m[12 + 2 * j] - re, m[13 + 2 * j] + im);
-            if (!(d <= worst)) worst = d;  // NaN propagates as "not special unitary"
+            if (std::isnan(d)) return d;  // a non-finite entry: "not special unitary"
+            if (d > worst) worst = d;
         }
     }
     return worst;
 }
 int prec_groups(int P) { return P == P64 ? 12 : P == P32 ? 6 : 3; }
+
+// Upper bound on max_links ||U||_2: ||U||_2^2 is the largest eigenvalue of the
+// Hermitian U^+ U, which Gershgorin's theorem bounds by its largest absolute
+// row sum.  1 up to rounding for unitary links; NaN/Inf propagate.
+double link_norm_bound(const double* u, size_t n_links) {
+    double worst = 0.0;
+    for (size_t i = 0; i < n_links; ++i) {
+        const double* m = u + 18 * i;
+        for (int a = 0; a < 3; ++a) {
+            double row = 0.0;
+            for (int b = 0; b < 3; ++b) {
+                double re = 0.0, im = 0.0;  // (U^+ U)_ab = sum_k conj(U_ka) U_kb
+                for (int k = 0; k < 3; ++k) {
+                    const double xr = m[2 * (3 * k + a)], xi = m[2 * (3 * k + a) + 1];
+                    const double yr = m[2 * (3 * k + b)], yi = m[2 * (3 * k + b) + 1];
+                    re += xr * yr + xi * yi;
+                    im += xr * yi - xi * yr;
+                }
+                row += std::hypot(re, im);
+            }
+            if (std::isnan(row)) return row;
+            if (row > worst) worst = row;
+        }
+    }
+    return std::sqrt(worst);
+}
 
 // ============================================================== gamma table
 
@@ -298,6 +332,7 @@ struct fs_ctx_s {
     DevBuf gauge_q2[4];              // rows 0-1 only, [mu][site][QCR chunks] (FP32 entry only)
     bool two_rows = false;           // gauge_q2 is filled: every link is special unitary
     double su3_defect = 0.0;         // max |U_2j - conj(U_0 x U_1)_j| over the uploaded links
+    double link_norm = 1.0;          // upper bound on the spectral norm of every uploaded link
     std::map<int, TuneEntry> tune;   // per precision
     HostBuf pinned;
 };
@@ -368,11 +403,18 @@ struct Plan {
 
     // stencil = true: the t-column mapping of the dslash launches (and of the
     // finish kernels that reduce their partial sums).
+    // device tables held outside the plan (the allocation-free entry point), or null
+    const LatDesc* x_lats = nullptr;
+    const BlockDesc* x_blocks = nullptr;
+    const int* x_wg_start = nullptr;
+    const int* x_wg_start_d = nullptr;
+
     Work work(int P, bool use_blk_on, bool stencil = false) const {
         Work w;
-        w.lats = d_lats[P].as<LatDesc>();
-        w.blocks = d_blocks.as<BlockDesc>();
-        w.wg_start = stencil ? d_wg_start_d.as<int>() : d_wg_start.as<int>();
+        w.lats = x_lats ? x_lats : d_lats[P].as<LatDesc>();
+        w.blocks = x_blocks ? x_blocks : d_blocks.as<BlockDesc>();
+        if (x_wg_start) w.wg_start = stencil ? x_wg_start_d : x_wg_start;
+        else w.wg_start = stencil ? d_wg_start_d.as<int>() : d_wg_start.as<int>();
         w.nblk = (int)blocks.size();
         w.total_wg = stencil ? wg_start_d.back() : wg_start.back();
         w.tc = stencil ? tc : 0;
@@ -442,9 +484,9 @@ static bool choose_tile(int sites, const std::vector<fs_ctx_s*>& lats, int tl[3]
 // blk_lat[b]: lattice of block b; lats: the contexts of the lattices.
 // Work tables for a given list of blocks (each block keeps its system ids and
 // field offsets, so a plan over a subset of a batch shares the batch's fields).
-std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, const std::vector<fs_ctx_s*>& lats,
-                                       int nr, int wg, hipStream_t s, int ilp, int occ, int eo = 0) {
-    auto pl = std::make_unique<Plan>();
+// The host side of a plan (no device tables): mappings and workgroup counts.
+void plan_host(Plan* pl, const std::vector<BlockDesc>& blocks, const std::vector<fs_ctx_s*>& lats, int nr, int wg,
+               int ilp, int occ, int eo) {
     pl->nr = nr;
     pl->eo = eo;
     pl->ilp = ilp;
@@ -508,6 +550,15 @@ std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, con
             pl->wg_start_d[b + 1] = pl->wg_start_d[b] + (int)cnt;
         }
     }
+    pl->two_rows = !lats.empty();
+    for (auto* c : lats) pl->two_rows = pl->two_rows && c->two_rows;
+}
+
+std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, const std::vector<fs_ctx_s*>& lats,
+                                       int nr, int wg, hipStream_t s, int ilp, int occ, int eo = 0) {
+    auto pl = std::make_unique<Plan>();
+    plan_host(pl.get(), blocks, lats, nr, wg, ilp, occ, eo);
+    const int nblk = (int)blocks.size();
     const int nb1 = std::max(nblk, 1);
     pl->d_blocks.alloc(sizeof(BlockDesc) * nb1);
     pl->d_wg_start.alloc(sizeof(int) * (nblk + 1));
@@ -518,8 +569,6 @@ std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, con
     HC(hipMemcpyAsync(pl->d_wg_start.p, pl->wg_start.data(), sizeof(int) * (nblk + 1), hipMemcpyHostToDevice, s));
     HC(hipMemcpyAsync(pl->d_wg_start_d.p, pl->wg_start_d.data(), sizeof(int) * (nblk + 1), hipMemcpyHostToDevice, s));
     HC(hipMemcpyAsync(pl->d_blk_on.p, ones.data(), sizeof(int) * nb1, hipMemcpyHostToDevice, s));
-    pl->two_rows = !lats.empty();
-    for (auto* c : lats) pl->two_rows = pl->two_rows && c->two_rows;
     std::vector<LatDesc> ld[4];
     for (int P = 0; P < 4; ++P) {
         for (auto* c : lats) ld[P].push_back(lat_desc(c, P, eo, pl->two_rows));
@@ -956,9 +1005,19 @@ struct EstResult {
     std::vector<double> stats;   // per instance [L+1][16][P+1][4]
     std::vector<double> samples; // per instance [L+1][N][16][P+1][2]
     std::vector<double> level_res;  // per instance [L+1] worst relative true residual
+    std::vector<double> bound;   // per instance [L+1][N]: bound on |X_s - X_s^exact| / ||Gamma Omega_p||
     fs_est_report rep;
     bool noconv = false;
 };
+
+// Lower bound on the smallest singular value of D + sigma: D + sigma =
+// (4 + m0 + sigma) - H with H = sum_mu H_mu, and H_mu psi = P_- U_mu Pi_mu psi
+// + P_+ Pi_mu^-1 U_mu^+ psi with P_-+ = (1 -+ g_mu)/2 orthogonal projectors
+// commuting with the colour and site maps, so ||H_mu psi||^2 <= u^2
+// (||P_- psi||^2 + ||P_+ psi||^2) = u^2 ||psi||^2 for links of norm <= u.
+double smin_lower(const fs_ctx_s* c, double m0, double sigma) {
+    return 4.0 + m0 + sigma - 4.0 * c->link_norm;
+}
 
 // One batched pass over a set of (instance, level, sample) units.  For each
 // unit level l < L: an x-system at sigma_{l+1} and a y-system at sigma_l on
@@ -966,6 +1025,7 @@ struct EstResult {
 void run_units(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm, const std::vector<double>& sigma,
                const std::vector<std::array<int, 3>>& units, int nr, int wg, hipStream_t s, EstResult& res,
                int n_noise) {
+    const bool want_bound = prm->report_fp64_error != 0;
     const int L = (int)sigma.size() - 1;
     const int P1 = prm->p_max + 1;
     // group units by (inst, level) into blocks of nr samples
@@ -1021,7 +1081,7 @@ void run_units(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm, con
         std::memset(&k, 0, sizeof(k));
         k.seed = prm->seed;
         k.instance = ctxs[e.inst]->instance;
-        k.level = (uint32_t)e.level;
+        k.level = prm->shared_noise ? 0u : (uint32_t)e.level;  // shared: z_s of level 0 on every level
         k.sample = (uint64_t)std::max(0, e.sample);
         k.g5 = e.g5 ? 1 : 0;
         k.pad = e.sample < 0 ? 1 : 0;
@@ -1032,9 +1092,53 @@ void run_units(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm, con
     launch_noise_block(P64, pl->work(P64, false), bs.b.f(), d_keys.as<NoiseKey>(), s);
     bs.run();
     res.rep.dslash_calls += bs.dslash_calls;
+    const int nblk = (int)blk_lat.size();
+
+    // error bound of every sample: ||x~||^2 of every system from the spin
+    // correlation of the solution with itself (p = 0, each block paired with
+    // itself; the trace over spins is the squared norm), FP64 true residuals
+    // from the solver states
+    if (want_bound) {
+        std::vector<int> ys(2 * nblk, 0);
+        for (int b2 = 0; b2 < nblk; ++b2) ys[2 * b2] = b2;
+        DevBuf d_ys = to_device(ys.data(), sizeof(int) * 2 * nblk, 0, s);
+        const Work wn = pl->work(P64, false);
+        DevBuf d_N(sizeof(double) * (size_t)nsys * 32);
+        launch_hop_reduce(wn, 0, Fld(), bs.xhi.f(), bs.xhi.f(), Fld(), d_ys.as<int>(), bs.part(), s);
+        launch_hop_finish(wn, bs.part(), d_N.as<double>(), 1, 0, s);
+        std::vector<double> hN((size_t)nsys * 32);
+        HC(hipMemcpyAsync(hN.data(), d_N.p, sizeof(double) * hN.size(), hipMemcpyDeviceToHost, s));
+        HC(hipStreamSynchronize(s));
+        auto norm = [&](int sys) {
+            const double* m = &hN[(size_t)sys * 32];
+            return std::sqrt(std::max(0.0, m[0] + m[10] + m[20] + m[30]));  // sum_a M_aa
+        };
+        auto err = [&](int sys, int inst, double sg) {
+            const double lo = smin_lower(ctxs[inst], prm->solve.m0, sg);
+            const double r = std::sqrt(std::max(0.0, bs.st_host[sys].rr_true));
+            return lo > 0.0 ? r / lo : std::numeric_limits<double>::infinity();
+        };
+        for (auto& pr : pairs)
+            for (int r = 0; r < nr; ++r) {
+                const int sx = pr.first * nr + r;
+                const EstSys& e = sysv[sx];
+                if (e.sample < 0) continue;
+                const double ex = err(sx, e.inst, e.sigma);
+                double bnd;
+                if (pr.second < 0) {  // last level: y = z exactly
+                    const SysState& S = bs.st_host[sx];
+                    bnd = std::sqrt(S.bnorm2 > 0.0 ? S.bnorm2 : S.bb) * ex;
+                } else {
+                    const int sy = pr.second * nr + r;
+                    const double ey = err(sy, e.inst, sigma[e.level]);
+                    const double c = std::fabs(sigma[e.level + 1] - sigma[e.level]);
+                    bnd = c * (norm(sy) * ex + ey * (norm(sx) + ex));
+                }
+                res.bound[((size_t)e.inst * (L + 1) + e.level) * n_noise + e.sample] = bnd;
+            }
+    }
 
     // bilinears: hop launches over x-blocks only (y-blocks get no workgroups)
-    const int nblk = (int)blk_lat.size();
     std::vector<int> yb(2 * nblk, -1), hop_start(nblk + 1, 0);
     std::vector<char> is_x(nblk, 0);
     for (auto& pr : pairs) {
@@ -1486,8 +1590,14 @@ void estimate_impl(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm,
                    fs_level_stat* out, double* samples_out, fs_est_report* report) {
     if (!prm || !sigma_in || !out) fail(FS_E_ARG, "null argument");
     if (L < 0) fail(FS_E_ARG, "L must be >= 0");
-    if (prm->n_noise < 1) fail(FS_E_ARG, "n_noise must be >= 1");
     if (prm->p_max < 0) fail(FS_E_ARG, "p_max must be >= 0");
+    // samples per level: n_level[l], or n_noise for every level
+    std::vector<int> Nl(L + 1);
+    for (int l = 0; l <= L; ++l) {
+        const int n = prm->n_level ? prm->n_level[l] : prm->n_noise;
+        if (n < 1 || n > (1 << 24)) fail(FS_E_ARG, prm->n_level ? "n_level[l] must be in 1..2^24" : "n_noise must be >= 1");
+        Nl[l] = n;
+    }
     check_prec(prm->solve.storage);
     if (!(prm->solve.tol > 0)) fail(FS_E_ARG, "tol must be > 0");
     if (prm->solve.max_iter < 1) fail(FS_E_ARG, "max_iter must be >= 1");
@@ -1506,26 +1616,30 @@ void estimate_impl(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm,
     fs_ctx_s* c0 = ctxs[0];
     DeviceScope ds(c0->device);
     hipStream_t s = c0->stream;
-    const int N = prm->n_noise;
+    const int N = *std::max_element(Nl.begin(), Nl.end());  // sample slots per level
     const int P1 = prm->p_max + 1;
+    const bool report_err = prm->report_fp64_error != 0;
     EstResult res;
     std::memset(&res.rep, 0, sizeof(res.rep));
     const size_t xsz = (size_t)(L + 1) * N * 16 * P1 * 2;
     res.samples.assign(xsz * ctxs.size(), 0.0);
     res.level_res.assign((size_t)(L + 1) * ctxs.size(), 0.0);
+    if (report_err) res.bound.assign((size_t)(L + 1) * N * ctxs.size(), 0.0);
     const int P = prm->solve.storage;
     if (!prm->solve.batched) {
         // plain path: one system at a time, NR = 1
         for (size_t i = 0; i < ctxs.size(); ++i)
             for (int l = 0; l <= L; ++l)
-                for (int smp = 0; smp < N; ++smp) {
+                for (int smp = 0; smp < Nl[l]; ++smp) {
                     std::vector<fs_ctx_s*> one{ctxs[i]};
                     EstResult r1;
                     std::memset(&r1.rep, 0, sizeof(r1.rep));
                     r1.samples.assign(xsz, 0.0);
                     r1.level_res.assign(L + 1, 0.0);
+                    if (report_err) r1.bound.assign((size_t)(L + 1) * N, 0.0);
                     run_units(one, prm, sigma, {{0, l, smp}}, 1, tuned_wg(ctxs[i], P), s, r1, N);
                     for (size_t k = 0; k < xsz; ++k) res.samples[i * xsz + k] += r1.samples[k];
+                    for (size_t k = 0; k < r1.bound.size(); ++k) res.bound[i * (L + 1) * N + k] += r1.bound[k];
                     for (int k = 0; k <= L; ++k)
                         res.level_res[i * (L + 1) + k] = std::max(res.level_res[i * (L + 1) + k], r1.level_res[k]);
                     res.rep.systems += r1.rep.systems;
@@ -1552,7 +1666,7 @@ void estimate_impl(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm,
             used = 0;
         };
         for (int l = 0; l <= L; ++l)
-            for (int smp = 0; smp < N; ++smp)
+            for (int smp = 0; smp < Nl[l]; ++smp)
                 for (size_t i = 0; i < ctxs.size(); ++i) {
                     const size_t need = (size_t)ctxs[i]->V * bytes_per_site_sys * (l < L ? 2 : 1);
                     if (used + need > budget && !units.empty()) flush();
@@ -1561,19 +1675,55 @@ void estimate_impl(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm,
                 }
         flush();
     }
+    // deviation from the plain FP64 path: the same estimate (same noise) solved in FP64
+    std::vector<double> t64, scale64;
+    if (report_err && P != P64) {
+        fs_est_params p64 = *prm;
+        p64.solve.storage = FS_F64;
+        p64.solve.batched = 1;
+        p64.report_fp64_error = 0;
+        std::vector<fs_level_stat> o64((size_t)ctxs.size() * (L + 1) * 16 * P1);
+        std::vector<double> x64(xsz * ctxs.size());
+        estimate_impl(ctxs, &p64, sigma_in, L, o64.data(), x64.data(), nullptr);
+        t64.assign((size_t)ctxs.size() * (L + 1) * 16 * P1 * 2, 0.0);
+        scale64.assign((size_t)ctxs.size() * (L + 1) * 16 * P1, 0.0);
+        for (size_t i = 0; i < ctxs.size(); ++i)
+            for (int l = 0; l <= L; ++l)
+                for (int n = 0; n < 16; ++n)
+                    for (int p = 0; p < P1; ++p) {
+                        const size_t q = (((size_t)i * (L + 1) + l) * 16 + n) * P1 + p;
+                        t64[2 * q] = o64[q].tr_re;
+                        t64[2 * q + 1] = o64[q].tr_im;
+                        double a = 0.0;
+                        for (int smp = 0; smp < Nl[l]; ++smp) {
+                            const size_t o = i * xsz + 2 * ((((size_t)l * N + smp) * 16 + n) * P1 + p);
+                            a += std::hypot(x64[o], x64[o + 1]);
+                        }
+                        scale64[q] = a / Nl[l];
+                    }
+    }
     // level statistics from the per-sample estimates (device, FP64, fixed order)
+    DevBuf d_nl = to_device(Nl.data(), sizeof(int) * (L + 1), 0, s);
     for (size_t i = 0; i < ctxs.size(); ++i) {
         DevBuf d_X = to_device(res.samples.data() + i * xsz, sizeof(double) * xsz, 0, s);
         DevBuf d_st(sizeof(double) * (size_t)(L + 1) * 16 * P1 * 4);
-        launch_level_stats(d_X.as<double>(), L + 1, N, P1, d_st.as<double>(), s);
+        launch_level_stats(d_X.as<double>(), L + 1, N, P1, d_st.as<double>(), s, d_nl.as<int>());
         std::vector<double> stv((size_t)(L + 1) * 16 * P1 * 4);
         HC(hipMemcpyAsync(stv.data(), d_st.p, sizeof(double) * stv.size(), hipMemcpyDeviceToHost, s));
         HC(hipStreamSynchronize(s));
         const uint16_t mask = prm->gamma_mask ? prm->gamma_mask : 0xffff;
-        for (int l = 0; l <= L; ++l)
+        const double u = ctxs[i]->link_norm;
+        for (int l = 0; l <= L; ++l) {
+            double bmax = 0.0;
+            if (report_err)
+                for (int smp = 0; smp < Nl[l]; ++smp) {
+                    const double bv = res.bound[((size_t)i * (L + 1) + l) * N + smp];
+                    bmax = (std::isnan(bv) || bv > bmax) ? bv : bmax;
+                }
             for (int n = 0; n < 16; ++n)
                 for (int p = 0; p < P1; ++p) {
-                    fs_level_stat& o = out[i * (size_t)(L + 1) * 16 * P1 + ((size_t)l * 16 + n) * P1 + p];
+                    const size_t q = ((size_t)i * (L + 1) + l) * 16 * P1 + (size_t)n * P1 + p;
+                    fs_level_stat& o = out[q];
                     std::memset(&o, 0, sizeof(o));
                     if (!((mask >> n) & 1)) continue;
                     const double* d = &stv[(((size_t)l * 16 + n) * P1 + p) * 4];
@@ -1581,9 +1731,18 @@ void estimate_impl(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm,
                     o.tr_im = d[1];
                     o.var_paper = d[2];
                     o.var_unbiased = d[3];
-                    o.n = N;
+                    o.n = Nl[l];
                     o.max_rel_residual = res.level_res[i * (L + 1) + l];
+                    if (report_err) {
+                        o.err_bound = bmax * std::pow(std::max(u, 1.0), p);  // ||Gamma_n Omega_p|| <= u^p
+                        if (!t64.empty()) {
+                            const double dr = o.tr_re - t64[2 * q], di = o.tr_im - t64[2 * q + 1];
+                            const double sc = scale64[q] > 0.0 ? scale64[q] : 1.0;
+                            o.fp64_rel_err = std::hypot(dr, di) / sc;
+                        }
+                    }
                 }
+        }
         if (samples_out) std::memcpy(samples_out + i * xsz, res.samples.data() + i * xsz, sizeof(double) * xsz);
     }
     res.rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1738,6 +1897,7 @@ fs_status fs_create(fs_ctx* out, const int32_t dims[4], int32_t t_antiperiodic, 
             c->own_stream = true;
         }
         *out = c.release();
+        std::lock_guard<std::mutex> lk(g_ctx_mu);
         ++g_live_ctx;
     });
 }
@@ -1754,6 +1914,7 @@ fs_status fs_destroy(fs_ctx c) {
             if (c->own_stream) (void)hipStreamDestroy(c->stream);
         }
         delete c;
+        std::lock_guard<std::mutex> lk(g_ctx_mu);
         if (--g_live_ctx <= 0) {
             g_live_ctx = 0;
             pool().trim(0);
@@ -1779,8 +1940,10 @@ fs_status fs_upload_gauge(fs_ctx c, const double* links, int32_t is_device) {
             std::vector<double> h(n / sizeof(double));
             from_device(h.data(), src, n, 0, c->stream);
             c->su3_defect = su3_row_defect(h.data(), (size_t)4 * c->V);
+            c->link_norm = link_norm_bound(h.data(), (size_t)4 * c->V);
         } else {
             c->su3_defect = su3_row_defect(links, (size_t)4 * c->V);
+            c->link_norm = link_norm_bound(links, (size_t)4 * c->V);
         }
         c->two_rows = c->su3_defect <= kSu3RowTol;
         for (int P = 0; P < 4; ++P) {
@@ -2234,11 +2397,61 @@ fs_status fs_batch_create(fs_batch* out, const fs_ctx* ctxs, int32_t n) {
 }
 
 fs_status fs_batch_estimate(fs_batch b, const fs_est_params* prm, const double* sigma, int32_t L, fs_level_stat* out,
-                            fs_est_report* report) {
+                            double* samples_out, fs_est_report* report) {
     return guard([&] {
         if (!b) fail(FS_E_ARG, "null batch");
         std::vector<fs_ctx_s*> v(b->ctxs.begin(), b->ctxs.end());
-        estimate_impl(v, prm, sigma, L, out, nullptr, report);
+        estimate_impl(v, prm, sigma, L, out, samples_out, report);
+    });
+}
+
+fs_status fs_level_totals(const fs_level_stat* levels, int32_t L, int32_t p_max, fs_total_stat* out) {
+    return guard([&] {
+        if (!levels || !out) fail(FS_E_ARG, "null argument");
+        if (L < 0 || p_max < 0) fail(FS_E_ARG, "L and p_max must be >= 0");
+        const int P1 = p_max + 1;
+        for (int n = 0; n < 16; ++n)
+            for (int p = 0; p < P1; ++p) {
+                fs_total_stat t;
+                std::memset(&t, 0, sizeof(t));
+                for (int l = 0; l <= L; ++l) {
+                    const fs_level_stat& v = levels[((size_t)l * 16 + n) * P1 + p];
+                    if (v.n <= 0) continue;  // Gamma_n not requested
+                    t.tr_re += v.tr_re;
+                    t.tr_im += v.tr_im;
+                    t.v_fs += v.var_paper / (double)v.n;
+                    t.v_fs_unbiased += v.var_unbiased / (double)v.n;
+                    t.v_total += v.var_paper;
+                    t.v_total_unbiased += v.var_unbiased;
+                    t.err_bound += v.err_bound;
+                }
+                out[(size_t)n * P1 + p] = t;
+            }
+    });
+}
+
+fs_status fs_optimal_samples(const double* v_levels, const double* c_levels, int32_t L, double eps2, int32_t n_min,
+                             int32_t* n_out, double* mu_out) {
+    return guard([&] {
+        if (!v_levels || !c_levels || !n_out) fail(FS_E_ARG, "null argument");
+        if (L < 0) fail(FS_E_ARG, "L must be >= 0");
+        if (!(eps2 > 0) || !std::isfinite(eps2)) fail(FS_E_ARG, "eps2 must be > 0");
+        if (n_min < 1) fail(FS_E_ARG, "n_min must be >= 1");
+        double sum = 0.0;
+        for (int l = 0; l <= L; ++l) {
+            if (!(v_levels[l] >= 0) || !std::isfinite(v_levels[l])) fail(FS_E_ARG, "V_l must be finite and >= 0");
+            if (!(c_levels[l] > 0) || !std::isfinite(c_levels[l])) fail(FS_E_ARG, "C_l must be finite and > 0");
+            sum += std::sqrt(v_levels[l] * c_levels[l]);
+        }
+        const double mu = sum / eps2;  // Lagrange multiplier of eq. num_samples
+        std::vector<int32_t> n(L + 1);
+        for (int l = 0; l <= L; ++l) {
+            const double x = std::ceil(mu * std::sqrt(v_levels[l] / c_levels[l]));
+            if (!(x <= (double)(1 << 24))) fail(FS_E_ARG, "a sample count exceeds 2^24");
+            n[l] = std::max<int32_t>(n_min, (int32_t)x);
+        }
+        std::copy(n.begin(), n.end(), n_out);
+        if (mu_out) *mu_out = mu;
     });
 }
 

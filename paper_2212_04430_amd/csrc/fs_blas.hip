@@ -962,28 +962,32 @@ __global__ void k_dilution_sum(const double* __restrict__ Y, int P1, const int* 
     X[2 * (size_t)i + 1] = im;
 }
 
-__global__ void k_level_stats(const double* __restrict__ X, int L1, int n_noise, int P1, double* __restrict__ out) {
+// Samples s < N_l of level l (N_l = n_level[l], or n_noise without a table);
+// X holds n_noise sample slots per level.
+__global__ void k_level_stats(const double* __restrict__ X, int L1, int n_noise, int P1,
+                              const int* __restrict__ n_level, double* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L1 * 16 * P1) return;
     const int p = i % P1;
     const int n = (i / P1) % 16;
     const int l = i / (16 * P1);
+    const int nl = n_level ? n_level[l] : n_noise;
     double sr = 0.0, si = 0.0, s2 = 0.0;
-    for (int s = 0; s < n_noise; ++s) {
+    for (int s = 0; s < nl; ++s) {
         const size_t o = (((size_t)l * n_noise + s) * 16 + n) * P1 + p;
         const double xr = X[2 * o], xi = X[2 * o + 1];
         sr += xr;
         si += xi;
         s2 += xr * xr + xi * xi;
     }
-    const double N = (double)n_noise;
-    const double tr = sr / N, ti = si / N;
-    const double vp = s2 / N - (tr * tr + ti * ti);
+    const double N = (double)nl;
+    const double tr = nl > 0 ? sr / N : 0.0, ti = nl > 0 ? si / N : 0.0;
+    const double vp = nl > 0 ? s2 / N - (tr * tr + ti * ti) : 0.0;
     double* d = out + (size_t)i * 4;
     d[0] = tr;
     d[1] = ti;
     d[2] = vp;
-    d[3] = n_noise > 1 ? vp * N / (N - 1.0) : 0.0;
+    d[3] = nl > 1 ? vp * N / (N - 1.0) : 0.0;
 }
 
 // Streaming copy: each lane moves 4 x 16 bytes with all loads issued first.
@@ -1129,9 +1133,10 @@ void launch_dilution_sum(const double* Y, int P1, const int* g0, int G, int D, d
     const int n = G * 16 * P1;
     hipLaunchKernelGGL(k_dilution_sum, dim3((n + 255) / 256), dim3(256), 0, s, Y, P1, g0, G, D, X);
 }
-void launch_level_stats(const double* X, int L1, int n_noise, int P1, double* out, hipStream_t s) {
+void launch_level_stats(const double* X, int L1, int n_noise, int P1, double* out, hipStream_t s,
+                        const int* n_level) {
     const int n = L1 * 16 * P1;
-    hipLaunchKernelGGL(k_level_stats, dim3((n + 255) / 256), dim3(256), 0, s, X, L1, n_noise, P1, out);
+    hipLaunchKernelGGL(k_level_stats, dim3((n + 255) / 256), dim3(256), 0, s, X, L1, n_noise, P1, n_level, out);
 }
 void launch_copy(uint4* dst, const uint4* src, size_t n16, hipStream_t s) {
     const size_t blocks = (n16 + 1023) / 1024;

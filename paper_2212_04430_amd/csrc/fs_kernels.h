@@ -303,7 +303,9 @@ struct GammaTab {      // Gamma_n row a: single nonzero i^ph[n][a] at column per
 };
 void launch_gamma_contract(const double* M, int P1, int nsys, const XMap* xm, const GammaTab& gt, double* X,
                            int n_noise, hipStream_t s);
-void launch_level_stats(const double* X, int L1, int n_noise, int P1, double* out, hipStream_t s);
+// n_level: NULL or device [L1] sample counts per level (each <= n_noise, the slot stride)
+void launch_level_stats(const double* X, int L1, int n_noise, int P1, double* out, hipStream_t s,
+                        const int* n_level = nullptr);
 // X[g][16][P1] = sum_{d < D} Y[g0[g] + d][16][P1] (complex), summed in order d = 0..D-1
 void launch_dilution_sum(const double* Y, int P1, const int* g0, int G, int D, double* X, hipStream_t s);
 void launch_blk_mask(const Work& w, const SysState* st, int mask, int* blk_on, hipStream_t s);

@@ -120,11 +120,11 @@ def test_cfg2_mini_dense(L):
     ctx = L.fs_create(dims, 0, 0)
     try:
         L.fs_upload_gauge(ctx, U)
-        for storage, tol, ts in (("f64", 1e-12, 1e-9), ("f32", 1e-10, 1e-7)):
+        for storage, tol, ts, tm in (("f64", 1e-12, 1e-9, 1e-10), ("f32", 1e-10, 1e-7, 1e-7)):
             print(f"cfg2-mini {storage}", flush=True)
             prm = _est_params(L, 0.05, 8, 4, storage=storage, tol=tol, nr=8, graph=1)
             stats, X, rep = L.fs_estimate(ctx, prm, sig, want_samples=True)
-            _compare(X, X_ref, stats, ts, ts)
+            _compare(X, X_ref, stats, ts, tm)
     finally:
         L.fs_destroy(ctx)
 

@@ -139,6 +139,11 @@ def test_eo_estimate_matches_oracle(L, cfg1_ref, storage, tol, ts, batched):
         scale = np.abs(X_ref).mean(axis=1)
         scale = np.where(scale > 0, scale, 1.0)
         assert (np.abs(X - X_ref).max(axis=1) / scale).max() <= ts
+        # level means: 1e-10 of mean |X| on the FP64 paths, the stated tolerance otherwise
+        t_ref, vp_ref, _ = ofs.level_stats(X_ref, axis=1)
+        t_gpu = stats[..., 0] + 1j * stats[..., 1]
+        assert (np.abs(t_gpu - t_ref) / scale).max() <= (1e-10 if storage == "f64" else ts)
+        assert np.allclose(stats[..., 2], vp_ref, rtol=1e-6, atol=1e-12 * scale.max() ** 2)
     finally:
         L.fs_destroy(ctx)
 

@@ -1,0 +1,242 @@
+"""Full-size parity against the oracle (GPU), at the sizes the benchmark runs.
+
+The oracle cannot invert these operators densely, so it checks properties that
+hold at any size: it recomputes the FP64 true residual of GPU solutions with
+its own operator, and forms the bilinears of eq. fs_trace_est from those
+verified solutions itself.
+
+* 16^3 x 32, the benchmark's configurations (even-odd, FP32 storage, rhs block
+  4, graph; and the plain FP64 single-system path): every level's samples
+  (2 per level, all 5 levels, all 16 Gamma, p <= 8) against oracle bilinears
+  of verified solutions (FP64, residual 1e-13) on the same noise.  For l < L
+  that covers the gamma_5 partner solve at sigma_l.  At the benchmark's
+  tolerance (residual 1e-10) the deviation is set by the tolerance, not the
+  precision (m0 = 0.02 and sigma_0 = 0 make the operator ill-conditioned:
+  4.6e-8 of mean |X| on the FP64 path), so there each sample must lie within
+  the library's own a-posteriori bound, and the mixed path within 1e-7 of mean
+  |X|; solved to 1e-12, the FP64 path meets 1e-9 of mean |X|.
+* 32^3 x 64: the stencil in f64/f32/f16 for every work-group size, variant and
+  residency cap the benchmark sweeps, against the oracle's operator; and one
+  even-odd FP32 solve to 1e-10 verified by the oracle.
+* uneven batches with even-odd preconditioning: small lattices with different
+  Lt against the dense oracle sample by sample, and the full-size uneven batch
+  (8^3x16 ... 24^3x48) with its residuals recomputed by the oracle and one
+  instance's last-level samples against oracle bilinears.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fs as ofs, lattice as lat
+from oracle.philox import z4_noise
+
+pytestmark = pytest.mark.gpu
+
+SIG_BENCH = [0.0, 0.05, 0.25, 0.5, 1.0]
+SIGMA_PAPER = [0.0, 1e-5, 0.053, 0.146, 0.360, 0.618, 1.0]
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2212_04430_amd import _lib
+    return _lib
+
+
+def _rel_res(U, dims, m0, sigma, x, b):
+    return np.linalg.norm(b - lat.wilson_apply(U, x, m0, sigma, dims)) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def bench_lattice(L):
+    dims = (16, 16, 16, 32)
+    U = synth.gauge_field(dims, eps=0.2, seed=0)
+    ctx = L.fs_create(dims, 0, 0)
+    L.fs_upload_gauge(ctx, U)
+    yield dims, U, ctx
+    L.fs_destroy(ctx)
+
+
+@pytest.fixture(scope="module")
+def bench_reference(L, bench_lattice):
+    """Oracle bilinears of GPU solutions (FP64, tol 1e-13) verified by the oracle:
+    X_ref[l, s] for s = 0, 1, with the estimator's noise keys."""
+    dims, U, ctx = bench_lattice
+    V = lat.volume(dims)
+    Lv = len(SIG_BENCH) - 1
+    sp = L.solve_params(0.02, tol=1e-13, storage="f64", batched=1, rhs_block=2, use_graph=0, even_odd=1,
+                        max_iter=20000)
+    X_ref = np.zeros((Lv + 1, 2, 16, 9), dtype=np.complex128)
+    for l in range(Lv + 1):
+        Z = np.stack([z4_noise(V, 1, 0, l, s) for s in range(2)])
+        hi = SIG_BENCH[l + 1] if l < Lv else SIG_BENCH[Lv]
+        print(f"reference level {l}", flush=True)
+        Xs, _, code = L.fs_solve_shifted(ctx, sp, [hi], Z)
+        assert code == 0
+        if l < Lv:
+            Ws, _, code = L.fs_solve_shifted(ctx, sp, [SIG_BENCH[l]], lat.apply_gamma5(Z))
+            assert code == 0
+        for s in range(2):
+            assert _rel_res(U, dims, 0.02, hi, Xs[0, s], Z[s]) <= 1.5e-13
+            if l < Lv:
+                assert _rel_res(U, dims, 0.02, SIG_BENCH[l], Ws[0, s], lat.apply_gamma5(Z[s])) <= 1.5e-13
+                y = lat.apply_gamma5(Ws[0, s])
+                coef = SIG_BENCH[l + 1] - SIG_BENCH[l]
+            else:
+                y, coef = Z[s], 1.0
+            X_ref[l, s] = coef * ofs.bilinears(U, dims, y, Xs[0, s], list(range(16)), 8)
+    return X_ref
+
+
+@pytest.mark.parametrize("storage,batched,nr,tol,tol_x", [("f32", 1, 4, 1e-10, 1e-7), ("f64", 0, 0, 1e-10, None),
+                                                           ("f64", 0, 0, 1e-12, 1e-9)])
+def test_bench_lattice_every_level(L, bench_lattice, bench_reference, storage, batched, nr, tol, tol_x):
+    dims, U, ctx = bench_lattice
+    print(f"bench lattice estimate {storage} batched={batched} tol={tol}", flush=True)
+    sp = L.solve_params(0.02, tol=tol, storage=storage, batched=batched, rhs_block=nr, use_graph=batched,
+                        even_odd=1, max_iter=20000)
+    prm = L.fs_est_params(1, 2, 0, 8, sp)
+    prm.report_fp64_error = 1
+    stats, X, rep = L.fs_estimate(ctx, prm, SIG_BENCH, want_samples=True)
+    assert rep.max_rel_residual <= tol
+    dev_abs = np.abs(X - bench_reference)  # [L+1, 2, 16, 9]
+    bound = stats[..., 7]  # [L+1, 16, 9], holds for every sample of the level
+    print("worst deviation / bound per level:",
+          [f"{d:.2e}" for d in (dev_abs.max(axis=1) / bound).reshape(len(SIG_BENCH), -1).max(axis=1)], flush=True)
+    assert np.all(dev_abs <= 1.01 * bound[:, None])
+    scale = np.abs(bench_reference).mean(axis=1)
+    scale = np.where(scale > 0, scale, 1.0)
+    dev = dev_abs.max(axis=1) / scale  # [L+1, 16, 9]
+    print("worst deviation per level:", [f"{d:.2e}" for d in dev.reshape(len(SIG_BENCH), -1).max(axis=1)],
+          flush=True)
+    if tol_x is not None:
+        assert dev.max() <= tol_x
+    if storage != "f64":  # deviation of the level means from the FP64 path, as reported
+        assert stats[..., 6].max() <= 1e-7
+
+
+@pytest.fixture(scope="module")
+def big_lattice(L):
+    dims = (32, 32, 32, 64)
+    print("gauge 32^3x64", flush=True)
+    U = synth.gauge_field(dims, eps=0.2, seed=0)
+    ctx = L.fs_create(dims, 0, 0)
+    L.fs_upload_gauge(ctx, U)
+    yield dims, U, ctx
+    L.fs_destroy(ctx)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 2e-6), ("f16", 4e-3)])
+def test_32c64_stencil_every_benchmarked_configuration(L, big_lattice, prec, tol):
+    """The configurations the benchmark's 32^3x64 single-RHS sweep times."""
+    dims, U, ctx = big_lattice
+    psi = synth.random_spinor(dims, seed=11)
+    ref = lat.wilson_apply(U, psi, 0.02, 0.3, dims)
+    scale = np.abs(ref).max()
+    try:
+        for wg in (64, 256):
+            for ilp in (0, 1):
+                for occ in (0, 1, 2, 4):
+                    L.fs_set_tuning(ctx, prec, 1, wg, ilp, occ)
+                    out = L.fs_apply_dirac(ctx, 0.02, 0.3, prec, psi)
+                    err = np.abs(out - ref).max() / scale
+                    assert err <= tol, (prec, wg, ilp, occ, err)
+            print(f"32^3x64 {prec}: 16 configurations ok", flush=True)
+    finally:
+        L.fs_set_tuning(ctx, prec, 1, 256, 1, 0)
+
+
+def test_32c64_even_odd_fp32_solve(L, big_lattice):
+    dims, U, ctx = big_lattice
+    V = lat.volume(dims)
+    b = z4_noise(V, 1, 0, 0, 0)
+    sp = L.solve_params(0.02, tol=1e-10, storage="f32", batched=1, rhs_block=1, use_graph=1, even_odd=1,
+                        max_iter=20000)
+    print("32^3x64 even-odd FP32 solve", flush=True)
+    X, st, code = L.fs_solve_shifted(ctx, sp, [0.05], b[None])
+    assert code == 0 and st[0].true_rel_residual <= 1e-10
+    assert _rel_res(U, dims, 0.02, 0.05, X[0, 0], b) <= 1.5e-10
+
+
+@pytest.mark.parametrize("storage,tol,ts", [("f64", 1e-12, 1e-9), ("f32", 1e-10, 1e-7)])
+def test_uneven_even_odd_batch_matches_oracle(L, storage, tol, ts):
+    """Even-odd preconditioning over lattices of different Lt (the t-chunking
+    follows the smallest) in shared launches, sample by sample vs dense LU."""
+    shapes = [(4, 4, 4, 4), (4, 4, 4, 8), (6, 4, 4, 2)]
+    sig = [0.0, 0.3, 1.0]
+    n = 4
+    ctxs, Us = [], []
+    try:
+        for k, d in enumerate(shapes):
+            c = L.fs_create(d, 0, 0)
+            L.fs_set_instance(c, k)
+            U = synth.gauge_field(d, eps=0.2, seed=k)
+            L.fs_upload_gauge(c, U)
+            ctxs.append(c)
+            Us.append(U)
+        sp = L.solve_params(0.02, tol=tol, storage=storage, batched=1, rhs_block=4, use_graph=1, even_odd=1)
+        prm = L.fs_est_params(1, n, 0, 1, sp)
+        batch = L.fs_batch_create(ctxs)
+        try:
+            print(f"uneven even-odd batch {storage}", flush=True)
+            stats, X, rep = L.fs_batch_estimate(batch, len(ctxs), prm, sig, want_samples=True)
+        finally:
+            L.fs_batch_destroy(batch)
+        assert rep.max_rel_residual <= tol
+        for k, d in enumerate(shapes):
+            Xr = ofs.fs_samples(Us[k], d, sig, n, seed=1, gammas=list(range(16)), p_max=1,
+                                solver=ofs.DenseSolver(Us[k], d, 0.02), instance=k)
+            scale = np.abs(Xr).mean(axis=1)
+            scale = np.where(scale > 0, scale, 1.0)
+            assert (np.abs(X[k] - Xr).max(axis=1) / scale).max() <= ts, k
+    finally:
+        for c in ctxs:
+            L.fs_destroy(c)
+
+
+@pytest.mark.parametrize("eo", [0, 1])
+def test_uneven_full_size_batch_against_oracle(L, eo):
+    """The full-size uneven batch (FP16 storage, FP64 reliable updates, the
+    paper's six shifts): per instance one system re-solved alone and verified
+    by the oracle's operator, its last-level samples against oracle bilinears
+    of that verified solution; with even-odd preconditioning each instance also
+    against its single-instance even-odd estimate."""
+    shapes = [(8, 8, 8, 16), (12, 12, 12, 24), (16, 16, 16, 32), (24, 24, 24, 48)]
+    Lv = len(SIGMA_PAPER) - 1
+    ctxs, Us = [], []
+    try:
+        for k, d in enumerate(shapes):
+            print(f"instance {k}: {d}", flush=True)
+            c = L.fs_create(d, 0, 0)
+            L.fs_set_instance(c, k)
+            U = synth.gauge_field(d, eps=0.2, seed=k)
+            L.fs_upload_gauge(c, U)
+            ctxs.append(c)
+            Us.append(U)
+        sp = L.solve_params(0.02, tol=1e-10, storage="f16", batched=1, use_graph=1, max_iter=20000, even_odd=eo)
+        prm = L.fs_est_params(1, 2, 0, 2, sp)
+        batch = L.fs_batch_create(ctxs)
+        try:
+            print(f"batch estimate even_odd={eo}", flush=True)
+            stats, X, rep = L.fs_batch_estimate(batch, len(ctxs), prm, SIGMA_PAPER, want_samples=True)
+        finally:
+            L.fs_batch_destroy(batch)
+        assert rep.max_rel_residual <= 1e-10
+        sp1 = L.solve_params(0.02, tol=1e-12, storage="f64", batched=1, rhs_block=1, even_odd=eo, max_iter=20000)
+        for k, d in enumerate(shapes):
+            V = lat.volume(d)
+            z = z4_noise(V, 1, k, Lv, 0)
+            print(f"instance {k}: oracle residual and bilinears", flush=True)
+            x, _, code = L.fs_solve_shifted(ctxs[k], sp1, [SIGMA_PAPER[Lv]], z[None])
+            assert code == 0
+            assert _rel_res(Us[k], d, 0.02, SIGMA_PAPER[Lv], x[0, 0], z) <= 1.5e-12
+            ref = ofs.bilinears(Us[k], d, z, x[0, 0], list(range(16)), 2)
+            assert np.abs(X[k, Lv, 0] - ref).max() <= 1e-7 * np.abs(ref).max(), k
+            if eo:
+                single, Xs, _ = L.fs_estimate(ctxs[k], prm, SIGMA_PAPER, want_samples=True)
+                scale = np.abs(Xs).mean(axis=1)
+                scale = np.where(scale > 0, scale, 1.0)
+                assert (np.abs(X[k] - Xs).max(axis=1) / scale).max() <= 1e-7, k
+    finally:
+        for c in ctxs:
+            L.fs_destroy(c)
