@@ -119,6 +119,26 @@ fs_status fs_apply_dirac(fs_ctx ctx, double m0, double sigma, fs_prec storage,
                          const double* in, double* out, int32_t n_rhs, int32_t is_device);
 
 /*
+ * fs_apply_dirac_noalloc -- fs_apply_dirac for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same operator, kernels and launch configuration as
+ * fs_apply_dirac (equal results bit for bit).
+ *   in, out   device pointers on the context's device, n_rhs canonical spinors
+ *             each (the caller owns them; nothing is copied to host).
+ * The staged block-layout fields and work tables live in a fixed 64 MiB
+ * device scratch area that the library holds on every GPU it runs on until the
+ * process ends; the call allocates nothing (no hipMalloc, no allocating
+ * library routine).  Limit: about 64 MiB / (2 x 192 B) = 174k site-systems in
+ * FP64 storage (349k FP32, 699k FP16/BF16) per call; larger inputs return
+ * FS_E_ARG before anything runs.  Every call on a GPU shares that GPU's
+ * scratch area: calls that overlap on one GPU (other host threads, other
+ * streams) race and must be serialised by the caller.  Work is issued on the
+ * context's stream, which the call synchronises unless it is capturing a graph.
+ */
+fs_status fs_apply_dirac_noalloc(fs_ctx ctx, double m0, double sigma, fs_prec storage,
+                                 const double* in, double* out, int32_t n_rhs);
+
+/*
  * fs_z4_noise -- the Z4 noise vector for (seed, instance, level, sample) in
  * canonical layout: component c = (site*4+spin)*3+colour takes the 2-bit code
  * k = bits [2(c%32), 2(c%32)+1] of word (c%128)/32 of the Philox4x64-10 block

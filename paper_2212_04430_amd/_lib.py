@@ -106,6 +106,7 @@ _sig = {
     "fs_upload_gauge": (C.c_int, [_P, _P, C.c_int32]),
     "fs_gauge_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "fs_apply_dirac": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, _P, _P, C.c_int32, C.c_int32]),
+    "fs_apply_dirac_noalloc": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, _P, _P, C.c_int32]),
     "fs_z4_noise": (C.c_int, [_P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, _P, C.c_int32]),
     "fs_displace": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int32]),
     "fs_bilinear": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int32]),
@@ -237,6 +238,20 @@ def fs_apply_dirac(ctx, m0, sigma, storage, psi):
     pi, dev = _ptr(psi)
     po, _ = _ptr(out)
     _check(_lib.fs_apply_dirac(ctx, float(m0), float(sigma), _prec(storage), pi, po, n, dev))
+    return out
+
+
+def fs_apply_dirac_noalloc(ctx, m0, sigma, storage, psi, out):
+    """(D + sigma) psi into out, both CUDA/HIP torch tensors (V,4,3) or (n,V,4,3) complex128,
+    through the allocation-free entry point."""
+    if not (_is_torch(psi) and psi.is_cuda and _is_torch(out) and out.is_cuda):
+        raise ValueError("fs_apply_dirac_noalloc takes device tensors")
+    if psi.shape != out.shape:
+        raise ValueError("in and out must have the same shape")
+    n = 1 if psi.ndim == 3 else psi.shape[0]
+    pi, _ = _ptr(psi)
+    po, _ = _ptr(out)
+    _check(_lib.fs_apply_dirac_noalloc(ctx, float(m0), float(sigma), _prec(storage), pi, po, n))
     return out
 
 

@@ -158,6 +158,38 @@ Pool& pool() {
     return *p;
 }
 
+// Device scratch of the allocation-free entry point (fs_apply_dirac_noalloc):
+// a fixed array in the code object, one copy per GPU, held until the process
+// ends.  Host code never passes `scratch` itself to a kernel (its name is a
+// host-side stand-in); it uses the device address that hipGetSymbolAddress
+// returns for the current device, looked up once per device when the first
+// context is created there.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// With the device current: find this device's copy of the scratch array.
+void scratch_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return;  // no scratch: the entry point reports FS_E_STATE
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return;
+    }
+    g_scratch_ptr[dev] = p;
+}
+
+void* scratch_of(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
 struct DevBuf {
     void* p = nullptr;
     size_t n = 0;
@@ -1859,6 +1891,98 @@ double time_dslash_eo_impl(fs_ctx c, int P, int n_sys, int nr, int occ, int n_la
     return (double)ms / n_launch;
 }
 
+// Work tables of a plan of nblk equal blocks of one lattice, written on the
+// device (the allocation-free entry point keeps them in its scratch area).
+__global__ void k_uniform_tables(BlockDesc* blocks, int* wg_start, int* wg_start_d, LatDesc* lats, double* diag,
+                                 int* sys_map, int nblk, int nr, long long slots_per_block, int nwg_tile,
+                                 int nwg_sten, LatDesc ld, double dg, int n_rhs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) lats[0] = ld;
+    if (i <= nblk) {
+        wg_start[i] = i * nwg_tile;
+        wg_start_d[i] = i * nwg_sten;
+    }
+    if (i < nblk) {
+        BlockDesc b;
+        b.lat = 0;
+        b.sys0 = i * nr;
+        b.slot_off = (long long)i * slots_per_block;
+        blocks[i] = b;
+    }
+    if (i < nblk * nr) {
+        diag[i] = dg;
+        sys_map[i] = i < n_rhs ? i : -1;
+    }
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// fs_apply_dirac with every device buffer carved out of the scratch area.
+void apply_dirac_noalloc(fs_ctx c, double m0, double sigma, int storage, const double* in, double* out, int n_rhs) {
+    check_ctx(c);
+    check_prec(storage);
+    if (!in || !out) fail(FS_E_ARG, "null buffer");
+    if (n_rhs < 1) fail(FS_E_ARG, "n_rhs must be >= 1");
+    DeviceScope ds(c->device);
+    char* base = static_cast<char*>(scratch_of(c->device));
+    if (!base) fail(FS_E_STATE, "no scratch area on this device");
+    hipStream_t s = c->stream;
+    const int nr = tuned_nr(c, storage, n_rhs);
+    const int nblk = (n_rhs + nr - 1) / nr;
+    std::vector<fs_ctx_s*> lats{c};
+    std::vector<BlockDesc> blocks(nblk);
+    for (int b = 0; b < nblk; ++b) {
+        blocks[b].lat = 0;
+        blocks[b].sys0 = b * nr;
+        blocks[b].slot_off = (long long)b * c->V * nr;
+    }
+    Plan pl;
+    plan_host(&pl, blocks, lats, nr, tuned_wg(c, storage), tuned_ilp(c, storage), tuned_occ(c, storage), 0);
+    // scratch layout: tables, then the two block-layout fields (and FP16 scales)
+    const int nsys = pl.nsys;
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        const size_t o = off;
+        off += align256(n);
+        return o;
+    };
+    const size_t o_blocks = take(sizeof(BlockDesc) * nblk), o_ws = take(sizeof(int) * (nblk + 1)),
+                 o_wsd = take(sizeof(int) * (nblk + 1)), o_lat = take(sizeof(LatDesc)),
+                 o_diag = take(sizeof(double) * nsys), o_map = take(sizeof(int) * nsys);
+    const size_t fbytes = (size_t)pl.total_slots * prec_group_bytes_spinor(storage);
+    const size_t nbytes = storage == P16 ? (size_t)pl.total_slots * sizeof(float) : 0;
+    const size_t o_fi = take(fbytes), o_fo = take(fbytes), o_ni = take(nbytes), o_no = take(nbytes);
+    if (off > kScratchBytes)
+        fail(FS_E_ARG, "input too large for the allocation-free scratch (" + std::to_string(off >> 20) +
+                           " MiB needed, 64 MiB available)");
+    pl.x_blocks = reinterpret_cast<const BlockDesc*>(base + o_blocks);
+    pl.x_wg_start = reinterpret_cast<const int*>(base + o_ws);
+    pl.x_wg_start_d = reinterpret_cast<const int*>(base + o_wsd);
+    pl.x_lats = reinterpret_cast<const LatDesc*>(base + o_lat);
+    const double* diag = reinterpret_cast<const double*>(base + o_diag);
+    const int* sys_map = reinterpret_cast<const int*>(base + o_map);
+    Fld fi, fo;
+    fi.v = reinterpret_cast<uint4*>(base + o_fi);
+    fo.v = reinterpret_cast<uint4*>(base + o_fo);
+    if (storage == P16) {
+        fi.n = reinterpret_cast<float*>(base + o_ni);
+        fo.n = reinterpret_cast<float*>(base + o_no);
+    }
+    const int n_items = std::max(nblk + 1, nsys);
+    hipLaunchKernelGGL(k_uniform_tables, dim3((n_items + 255) / 256), dim3(256), 0, s, (BlockDesc*)(base + o_blocks),
+                       (int*)(base + o_ws), (int*)(base + o_wsd), (LatDesc*)(base + o_lat), (double*)(base + o_diag),
+                       (int*)(base + o_map), nblk, nr, (long long)c->V * nr, pl.wg_start[1], pl.wg_start_d[1],
+                       lat_desc(c, storage, 0, pl.two_rows), 4.0 + m0 + sigma, n_rhs);
+    const long long stride = 24ll * c->V;
+    launch_pack(storage, pl.work(storage, false), fi, in, stride, sys_map, s);
+    launch_dslash(storage, D_PLAIN, pl.work(storage, false, true), fo, fi, Fld(), diag, nullptr, M_ALL, nullptr, s);
+    launch_unpack(storage, pl.work(storage, false), out, fo, stride, sys_map, s);
+    HC(hipGetLastError());
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HC(hipStreamIsCapturing(s, &cs));
+    if (cs == hipStreamCaptureStatusNone) HC(hipStreamSynchronize(s));
+}
+
 }  // namespace
 
 // ============================================================== C ABI
@@ -1890,6 +2014,7 @@ fs_status fs_create(fs_ctx* out, const int32_t dims[4], int32_t t_antiperiodic, 
         c->tsign = t_antiperiodic ? -1 : 1;
         c->device = device;
         DeviceScope ds(device);
+        scratch_init(device);
         if (hip_stream) {
             c->stream = (hipStream_t)hip_stream;
         } else {
@@ -2006,6 +2131,11 @@ fs_status fs_apply_dirac(fs_ctx c, double m0, double sigma, fs_prec storage, con
         HC(hipGetLastError());
         from_device(out, dout, nb, is_device, s);
     });
+}
+
+fs_status fs_apply_dirac_noalloc(fs_ctx c, double m0, double sigma, fs_prec storage, const double* in, double* out,
+                                 int32_t n_rhs) {
+    return guard([&] { apply_dirac_noalloc(c, m0, sigma, storage, in, out, n_rhs); });
 }
 
 fs_status fs_z4_noise(fs_ctx c, uint64_t seed, uint32_t instance, uint32_t level, uint64_t sample, double* out,
