@@ -355,8 +355,12 @@ fs_status fs_batch_destroy(fs_batch b);
  * three variants and a cap of {none,1,2,4} resident waves per SIMD, and
  * keep the fastest (per system) in the context for this storage precision;
  * later solves, estimates and stencil calls with rhs_block/wg = 0 use it.
- * cache_path: text file keyed by (arch, dims, precision, batch class), read
- * first and appended to; NULL keeps the table in memory only.
+ * When every extent is even it then tunes the even-odd operator at that rhs
+ * block: variant 0 or 2 and residency cap -1, 0, 2, 3 or 4 (fs_set_eo_tuning),
+ * timing the hop plus the Schur launch as the even-odd solver issues them.
+ * cache_path: text file keyed by (arch, dims, precision, batch class; "eo" and
+ * the rhs block for the even-odd entry), read first and appended to; NULL
+ * keeps the table in memory only.
  * best_rhs_block / best_wg may be NULL.
  */
 fs_status fs_autotune(fs_ctx ctx, fs_prec storage, int32_t n_sys, const char* cache_path,
@@ -388,10 +392,10 @@ fs_status fs_time_dslash(fs_ctx ctx, fs_prec storage, int32_t n_sys, int32_t rhs
 
 /*
  * fs_time_dslash_eo -- as fs_time_dslash for the even-odd hop D_oe / D_eo (one
- * parity out, one in; the kernel of the even-odd preconditioned solver), on
- * n_sys systems in blocks of rhs_block (0 = tuned), residency cap occ (waves
- * per SIMD, 0 = none, -1 = the one the even-odd solver uses), every extent
- * even.  bytes:
+ * parity out, one in; the kernel of the even-odd preconditioned solver, in the
+ * context's even-odd configuration, fs_set_eo_tuning), on n_sys systems in
+ * blocks of rhs_block (0 = tuned), residency cap occ (waves per SIMD, 0 =
+ * none, -1 = the one the even-odd solver uses), every extent even.  bytes:
  * per output site and system 48 stored reals (+ FP16 scales), plus every link
  * of the lattice once per block: 4 links of 18 reals per site, or 12 reals per
  * link where the FP32 stencils read two rows (fs_gauge_info, rhs blocks >= 4).
@@ -400,9 +404,36 @@ fs_status fs_time_dslash_eo(fs_ctx ctx, fs_prec storage, int32_t n_sys, int32_t 
                             int32_t n_launch, double* avg_ms, double* bytes);
 
 /*
+ * fs_time_dslash_eo_each -- the launches of fs_time_dslash_eo (the context's
+ * even-odd configuration) timed one by one: ms_each host [n_launch] (HIP
+ * events around each launch on the context's stream), for medians.
+ */
+fs_status fs_time_dslash_eo_each(fs_ctx ctx, fs_prec storage, int32_t n_sys, int32_t rhs_block,
+                                 int32_t n_launch, float* ms_each, double* bytes);
+
+/*
+ * fs_set_eo_tuning -- the even-odd stencil of every one-parity launch of this
+ * storage precision (fs_autotune stores its choice the same way):
+ *   variant 0  t-streaming: a workgroup owns columns of one parity class and
+ *              walks their output sites t, t+2, ...; neighbours come from memory;
+ *   variant 2  x-pairs: a lane owns the two columns (2x, 2x+1) at one (y, z) and
+ *              walks every t-slice, computing the output column's site while
+ *              its input column's spinor -- the forward-t neighbour loaded a
+ *              slice earlier -- is shared through LDS with the x/y/z neighbours
+ *              of a tile of (Lx/2) x TY x TZ pairs; where no tile fits the
+ *              work-group, variant 0 runs.
+ *   occ        cap on resident waves per SIMD, 0..8 (0 = none), -1 = the
+ *              variant's default (variant 0: 3 for FP32 rhs block 4, else none;
+ *              variant 2: none).
+ * The FP64 source and reconstruction kernels always stream (variant 0 mapping).
+ */
+fs_status fs_set_eo_tuning(fs_ctx ctx, fs_prec storage, int32_t variant, int32_t occ);
+
+/*
  * fs_time_copy -- average duration (ms, HIP events on the context's stream) of
  * n_launch device-to-device copies of `bytes` bytes (rounded down to 16) by a
- * plain streaming kernel: the achievable-bandwidth reference for the roofline.
+ * plain streaming kernel (one 16-byte element per lane, non-temporal): the
+ * achievable-bandwidth reference for the roofline.
  */
 fs_status fs_time_copy(fs_ctx ctx, uint64_t bytes, int32_t n_launch, double* avg_ms);
 

@@ -127,6 +127,9 @@ _sig = {
     "fs_time_dslash": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "fs_time_copy": (C.c_int, [_P, C.c_uint64, C.c_int32, C.POINTER(C.c_double)]),
+    "fs_time_dslash_eo_each": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_float),
+                                         C.POINTER(C.c_double)]),
+    "fs_set_eo_tuning": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32]),
     "fs_time_dslash_eo": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "fs_probing_colours": (C.c_int, [C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
@@ -430,6 +433,19 @@ def fs_time_dslash(ctx, storage, n_sys, rhs_block=0, wg=0, n_launch=20, ilp=-1, 
     _check(_lib.fs_time_dslash(ctx, _prec(storage), int(n_sys), int(rhs_block), int(wg), int(ilp), int(occ),
                                int(n_launch), C.byref(ms), C.byref(b)))
     return ms.value, b.value
+
+
+def fs_time_dslash_eo_each(ctx, storage, n_sys, rhs_block=0, n_launch=100):
+    """(per-launch ms array, algorithmic bytes per launch) of the context's even-odd hop."""
+    ms = np.zeros(n_launch, dtype=np.float32)
+    b = C.c_double()
+    _check(_lib.fs_time_dslash_eo_each(ctx, _prec(storage), int(n_sys), int(rhs_block), int(n_launch),
+                                       ms.ctypes.data_as(C.POINTER(C.c_float)), C.byref(b)))
+    return ms.astype(np.float64), b.value
+
+
+def fs_set_eo_tuning(ctx, storage, variant, occ=-1):
+    _check(_lib.fs_set_eo_tuning(ctx, _prec(storage), int(variant), int(occ)))
 
 
 def fs_time_copy(ctx, nbytes, n_launch=20):

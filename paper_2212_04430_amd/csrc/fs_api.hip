@@ -366,6 +366,7 @@ struct fs_ctx_s {
     double su3_defect = 0.0;         // max |U_2j - conj(U_0 x U_1)_j| over the uploaded links
     double link_norm = 1.0;          // upper bound on the spectral norm of every uploaded link
     std::map<int, TuneEntry> tune;   // per precision
+    std::map<int, std::array<int, 2>> eo_tune;  // per precision: even-odd stencil variant, residency cap
     HostBuf pinned;
 };
 
@@ -397,6 +398,7 @@ LatDesc lat_desc(const fs_ctx_s* c, int P, int eo = 0, bool two_rows = false) {
     d.tsign = c->tsign;
     d.gauge = c->gauge[P].p;
     d.gauge_q = (two_rows && P == P32) ? c->gauge_q2[P].p : c->gauge_q[P].p;
+    d.pty = d.ptz = 0;
     return d;
 }
 
@@ -424,14 +426,22 @@ struct Plan {
     std::vector<int> wg_start;        // nblk + 1  (tile mapping: vector kernels)
     std::vector<int> wg_start_d;      // nblk + 1  (t-column mapping: stencil)
     int tc = 1;                       // t-slices per stencil workgroup
+    // one-parity plans: the t-streaming mapping of the FP64 source and
+    // reconstruction kernels (the stencil mapping itself when ilp != 2)
+    std::vector<int> wg_start_s;
+    int tc_s = 1;
+    std::vector<std::array<int, 2>> ptile;  // x-pair stencil (ilp 2): TY, TZ per lattice
     std::vector<int> lat_V;           // per lattice
     long long total_slots = 0;
     // device tables
     DevBuf d_blocks, d_wg_start, d_wg_start_d, d_blk_on;
     DevBuf d_lats[4];
     DevBuf d_wg_start_alt;            // alternative start table (hop launches)
+    DevBuf d_wg_start_s;              // streaming mapping of one-parity plans
 
-    int max_wg() const { return std::max(wg_start.back(), wg_start_d.back()); }
+    int max_wg() const {
+        return std::max({wg_start.back(), wg_start_d.back(), wg_start_s.empty() ? 0 : wg_start_s.back()});
+    }
 
     // stencil = true: the t-column mapping of the dslash launches (and of the
     // finish kernels that reduce their partial sums).
@@ -463,6 +473,18 @@ struct Plan {
         w.nr = nr;
         w.lognr = lognr;
         w.blk_on = use_blk_on ? d_blk_on.as<int>() : nullptr;
+        return w;
+    }
+
+    // one-parity plans: the t-streaming mapping (FP64 source and reconstruction)
+    Work work_stream(int P) const {
+        Work w = work(P, false, true);
+        if (eo && ilp == 2) {
+            w.wg_start = d_wg_start_s.as<int>();
+            w.total_wg = wg_start_s.back();
+            w.tc = tc_s;
+            w.ilp = 0;
+        }
         return w;
     }
 };
@@ -516,6 +538,49 @@ static bool choose_tile(int sites, const std::vector<fs_ctx_s*>& lats, int tl[3]
 // blk_lat[b]: lattice of block b; lats: the contexts of the lattices.
 // Work tables for a given list of blocks (each block keeps its system ids and
 // field offsets, so a plan over a subset of a batch shares the batch's fields).
+// x-pair stencil: at least this many lanes (2 waves per SIMD of the chip),
+// else the t-streaming variant, which splits small batches finer
+#ifndef FS_PAIR_MIN_LANES
+#define FS_PAIR_MIN_LANES (256 * 4 * 2 * 64)
+#endif
+// resident x-pair workgroups per CU assumed when sizing its t-chunks
+#ifndef FS_PAIR_WG_PER_CU
+#define FS_PAIR_WG_PER_CU 3
+#endif
+
+// Tiles of the x-pair even-odd stencil: per lattice TY x TZ pairs (dividing
+// Ly, Lz, each at least 2; the tile spans all Lx/2 pairs of x) so that
+// nr * Lx/2 * TY * TZ lanes fit the workgroup; the most lanes win, then the
+// fewest reads beyond the tile's y/z faces per output (2/T for an axis the
+// tile does not span).  False if no such tile fits.
+static bool pair_tiles(int nr, int wg, const std::vector<fs_ctx_s*>& lats, std::vector<std::array<int, 2>>& out) {
+    out.clear();
+    for (auto* c : lats) {
+        const int row = nr * (c->dims[0] / 2);
+        if (row > wg || c->dims[0] % 2) return false;
+        const int maxyz = wg / row;
+        int bt[2] = {0, 0}, best_n = 0;
+        double best_cost = 1e30;
+        for (int ty = 1; ty <= c->dims[1]; ++ty) {
+            if (c->dims[1] % ty) continue;
+            if (ty == 1 && c->dims[1] != 1) continue;  // one-pair-thick tiles are not supported
+            for (int tz = 2; tz <= c->dims[2] && ty * tz <= maxyz; ++tz) {
+                if (c->dims[2] % tz) continue;
+                const double cost = (ty < c->dims[1] ? 2.0 / ty : 0.0) + (tz < c->dims[2] ? 2.0 / tz : 0.0);
+                if (ty * tz > best_n || (ty * tz == best_n && cost < best_cost)) {
+                    best_n = ty * tz;
+                    best_cost = cost;
+                    bt[0] = ty;
+                    bt[1] = tz;
+                }
+            }
+        }
+        if (best_n == 0) return false;
+        out.push_back({bt[0], bt[1]});
+    }
+    return true;
+}
+
 // The host side of a plan (no device tables): mappings and workgroup counts.
 void plan_host(Plan* pl, const std::vector<BlockDesc>& blocks, const std::vector<fs_ctx_s*>& lats, int nr, int wg,
                int ilp, int occ, int eo) {
@@ -524,7 +589,7 @@ void plan_host(Plan* pl, const std::vector<BlockDesc>& blocks, const std::vector
     pl->ilp = ilp;
     pl->occ = occ;
     pl->lognr = ilog2(nr);
-    if (ilp == 2 && !choose_tile(wg / nr, lats, pl->tl)) pl->ilp = 0;  // no tile fits: column variant
+    if (ilp == 2 && !eo && !choose_tile(wg / nr, lats, pl->tl)) pl->ilp = 0;  // no tile fits: column variant
     pl->wg = wg;
     pl->blocks = blocks;
     const int nblk = (int)blocks.size();
@@ -582,6 +647,54 @@ void plan_host(Plan* pl, const std::vector<BlockDesc>& blocks, const std::vector
             pl->wg_start_d[b + 1] = pl->wg_start_d[b] + (int)cnt;
         }
     }
+    if (eo) {
+        pl->wg_start_s = pl->wg_start_d;
+        pl->tc_s = pl->tc;
+    }
+    if (eo && pl->ilp == 2) {
+        long long lanes = 0;
+        for (int b = 0; b < nblk; ++b) {
+            const fs_ctx_s* c = lats[blocks[b].lat];
+            lanes += (long long)(c->V / c->dims[3] / 2) * nr;
+        }
+        if (lanes < FS_PAIR_MIN_LANES || !pair_tiles(nr, wg, lats, pl->ptile)) pl->ilp = 0;
+    }
+    if (eo && pl->ilp == 2) {
+        // x-pair stencil: workgroups of TY x TZ pairs of one block walking
+        // chunks of tc t-slices.  Each chunk costs two extra spinor loads per
+        // lane (its first input slice and the backward neighbour), and the
+        // workgroups run in rounds of the resident count R, so the chunk
+        // count minimises (1 + 2/tc) x rounds x R / workgroups.
+        long long w1 = 0;  // workgroups of one chunk per block, summed
+        int Lt_min = 1 << 30;
+        for (int b = 0; b < nblk; ++b) {
+            const fs_ctx_s* c = lats[blocks[b].lat];
+            const auto& tl = pl->ptile[blocks[b].lat];
+            w1 += (long long)(c->dims[1] / tl[0]) * (c->dims[2] / tl[1]);
+            Lt_min = std::min(Lt_min, c->dims[3]);
+        }
+        const long long R = 256ll * FS_PAIR_WG_PER_CU;
+        double best = 1e30;
+        for (int nch = 1; nch <= 16; ++nch) {
+            const int tcv = (Lt_min + nch - 1) / nch;
+            if (nch > 1 && tcv < 4) break;
+            const long long wgs = w1 * nch;
+            const double rounds = (double)((wgs + R - 1) / R);
+            const double cost = (1.0 + 2.0 / tcv) * rounds * R / (double)wgs;
+            if (cost < best - 1e-9) {
+                best = cost;
+                pl->tc = tcv;
+            }
+        }
+        for (int b = 0; b < nblk; ++b) {
+            const fs_ctx_s* c = lats[blocks[b].lat];
+            const auto& tl = pl->ptile[blocks[b].lat];
+            const long long cnt =
+                (long long)(c->dims[1] / tl[0]) * (c->dims[2] / tl[1]) * ((c->dims[3] + pl->tc - 1) / pl->tc);
+            if (pl->wg_start_d[b] + cnt > (1ll << 30)) fail(FS_E_ARG, "batch too large for one launch");
+            pl->wg_start_d[b + 1] = pl->wg_start_d[b] + (int)cnt;
+        }
+    }
     pl->two_rows = !lats.empty();
     for (auto* c : lats) pl->two_rows = pl->two_rows && c->two_rows;
 }
@@ -601,9 +714,21 @@ std::unique_ptr<Plan> plan_from_blocks(const std::vector<BlockDesc>& blocks, con
     HC(hipMemcpyAsync(pl->d_wg_start.p, pl->wg_start.data(), sizeof(int) * (nblk + 1), hipMemcpyHostToDevice, s));
     HC(hipMemcpyAsync(pl->d_wg_start_d.p, pl->wg_start_d.data(), sizeof(int) * (nblk + 1), hipMemcpyHostToDevice, s));
     HC(hipMemcpyAsync(pl->d_blk_on.p, ones.data(), sizeof(int) * nb1, hipMemcpyHostToDevice, s));
+    if (eo) {
+        pl->d_wg_start_s.alloc(sizeof(int) * (nblk + 1));
+        HC(hipMemcpyAsync(pl->d_wg_start_s.p, pl->wg_start_s.data(), sizeof(int) * (nblk + 1), hipMemcpyHostToDevice,
+                          s));
+    }
     std::vector<LatDesc> ld[4];
     for (int P = 0; P < 4; ++P) {
-        for (auto* c : lats) ld[P].push_back(lat_desc(c, P, eo, pl->two_rows));
+        for (size_t k = 0; k < lats.size(); ++k) {
+            LatDesc d = lat_desc(lats[k], P, eo, pl->two_rows);
+            if (pl->ilp == 2 && eo) {
+                d.pty = pl->ptile[k][0];
+                d.ptz = pl->ptile[k][1];
+            }
+            ld[P].push_back(d);
+        }
         pl->d_lats[P].alloc(sizeof(LatDesc) * ld[P].size());
         HC(hipMemcpyAsync(pl->d_lats[P].p, ld[P].data(), sizeof(LatDesc) * ld[P].size(), hipMemcpyHostToDevice, s));
     }
@@ -625,22 +750,38 @@ std::unique_ptr<Plan> make_plan(const std::vector<int>& blk_lat, const std::vect
     return plan_from_blocks(blocks, lats, nr, wg, s, ilp, occ, eo);
 }
 
-// Residency cap of the even-odd stencil (waves per SIMD, 0 = none): a sweep of
-// the FP32 hop on the 16^3x32 workload (96 systems) found 3 fastest at rhs
-// block 4 (0.571 against 0.635 ms uncapped) and no gain at other blocks or in
-// FP16.
+// Residency cap of the t-streaming even-odd stencil (waves per SIMD, 0 =
+// none): a sweep of the FP32 hop on the 16^3x32 workload (96 systems) found 3
+// fastest at rhs block 4 (0.571 against 0.635 ms uncapped) and no gain at
+// other blocks or in FP16.
 int eo_occ(int P, int nr) { return (P == P32 && nr == 4) ? 3 : 0; }
 
+// Even-odd stencil configuration of a context for one storage precision:
+// variant 0 (t-streaming over one parity class of columns) or 2 (x-pairs
+// with LDS sharing), residency cap (-1: the variant's default).  Without a
+// setting: x-pairs for FP32 and FP64 storage, streaming for FP16 and BF16,
+// whose Schur launches in the x-pair form run at two waves per SIMD (the
+// 432-system FP16 estimate of the 16^3x32 workload: 661 solves/s streaming,
+// 613 in x-pairs; FP32: 603 and 631).
+std::array<int, 2> eo_tuning(const fs_ctx_s* c, int P) {
+    auto it = c->eo_tune.find(P);
+    if (it != c->eo_tune.end()) return it->second;
+    return {(P == P32 || P == P64) ? 2 : 0, -1};
+}
+
 // The one-parity plan of a full-lattice plan: the same blocks and systems, each
-// block holding V/2 sites (even-odd preconditioning).
-std::unique_ptr<Plan> eo_plan_of(const Plan& full, const std::vector<fs_ctx_s*>& lats, hipStream_t s, int occ) {
+// block holding V/2 sites (even-odd preconditioning).  var, occ as eo_tuning.
+std::unique_ptr<Plan> eo_plan_of(const Plan& full, const std::vector<fs_ctx_s*>& lats, hipStream_t s, int P,
+                                 int var, int occ) {
     std::vector<BlockDesc> blocks = full.blocks;
     long long off = 0;
     for (auto& bd : blocks) {
         bd.slot_off = off;
         off += (long long)(lats[bd.lat]->V / 2) * full.nr;
     }
-    return plan_from_blocks(blocks, lats, full.nr, full.wg, s, 0, occ, 1);
+    auto pl = plan_from_blocks(blocks, lats, full.nr, full.wg, s, var, std::max(occ, 0), 1);
+    if (occ < 0) pl->occ = pl->ilp == 2 ? 0 : eo_occ(P, full.nr);  // launch-time only: no table depends on it
+    return pl;
 }
 
 // FP64 true residual of a system relative to its source (the full system's
@@ -683,6 +824,7 @@ struct SolveOpts {
     int check_every = 8;
     bool use_graph = false;
     bool eo = false;  // even-odd preconditioning
+    int eo_var = 0, eo_occ = -1;  // even-odd stencil (eo_tuning)
 };
 
 // Systems of a plan, with sources in `b` (FP64 block layout) and per-system
@@ -707,14 +849,10 @@ struct BatchSolver {
     long long dslash_calls = 0;
     size_t part_doubles = 0;
     // doubles of partial sums the launches over plan q may write
-    size_t part_need(const Plan& q) const {
-        const Work wq = q.work(o.P, false);
-        const size_t xr = (size_t)wq.total_wg * (size_t)update_xr_rows(o.P, wq) * 3 * q.nr;
-        return std::max((size_t)q.max_wg() * 32 * q.nr, xr);
-    }
+    size_t part_need(const Plan& q) const { return (size_t)q.max_wg() * 32 * q.nr; }
 
     BatchSolver(Plan& plan, const std::vector<fs_ctx_s*>& l, hipStream_t stream, const SolveOpts& opts)
-        : full(plan), eo_pl(opts.eo ? eo_plan_of(plan, l, stream, eo_occ(opts.P, plan.nr)) : nullptr),
+        : full(plan), eo_pl(opts.eo ? eo_plan_of(plan, l, stream, opts.P, opts.eo_var, opts.eo_occ) : nullptr),
           pl(opts.eo ? *eo_pl : plan),
           cur(&pl), lats(l), s(stream), o(opts) {
         const long long S = pl.total_slots;
@@ -728,9 +866,8 @@ struct BatchSolver {
         for (Field* f : {&r, &p, &v, &t, &xlo}) f->alloc(o.P, S);
         d_diag.alloc(sizeof(double) * pl.nsys);
         d_st.alloc(sizeof(SysState) * pl.nsys);
-        // partial sums: max 4 doubles per rhs per workgroup (32 for hop launches,
-        // which callers run over the full-lattice plan), or 3 per rhs in each of
-        // update_xr_rows rows per workgroup
+        // partial sums: at most 8 doubles per rhs per workgroup (32 for the hop
+        // launches of the bilinears, which callers run over the full-lattice plan)
         part_doubles = std::max(part_need(pl), part_need(full));
         d_part.alloc(sizeof(double) * part_doubles);
         d_flags.alloc(sizeof(int) * 2 * pl.blocks.size());
@@ -810,7 +947,11 @@ struct BatchSolver {
 
     // One BiCGStab iteration over every running system.  Every launch walks
     // the device-side list of running blocks, so finished blocks cost nothing;
-    // the list changes when F_RHO (or a resumed reliable update) says so.
+    // the list changes when F_OMEGA (or a resumed reliable update) says so.
+    // The t = A s stencil also forms (s, s), (rhat, s) and (rhat, t), so the
+    // F_OMEGA finish knows omega, beta and the new residual's (rhat, r) and
+    // |r|^2, and one vector kernel updates x, r and p (8 field passes; with
+    // s = r - alpha v, 11 per iteration besides the stencils).
     // With in_loop_reliable the FP64 reliable update of the blocks that asked
     // for one follows at once (no host round trip).
     void iteration(bool in_loop_reliable) {
@@ -819,13 +960,9 @@ struct BatchSolver {
         launch_finish(F_ALPHA, wd, st(), part(), nullptr, nullptr, s);
         launch_axpy_s(o.P, wr, r.f(), v.f(), st(), s);
         apply(o.P, D_TS, wd, t.f(), r.f(), Fld(), M_RUN, tmp.f());
-        launch_finish(F_OMEGA, wd, st(), part(), nullptr, nullptr, s);
-        launch_update_xr(o.P, wr, xlo.f(), p.f(), r.f(), t.f(), rk(), st(), part(), s);
-        Work wrf = wr;
-        wrf.prow = update_xr_rows(o.P, wr);
-        launch_finish(F_RHO, wrf, st(), part(), f_run(), f_pend(), s);
+        launch_finish(F_OMEGA, wd, st(), part(), f_run(), f_pend(), s);
         build_list(f_run(), vl_run);
-        launch_update_p(o.P, listed(vl_run, o.P, false), p.f(), r.f(), v.f(), st(), s);
+        launch_update_xrp(o.P, listed(vl_run, o.P, false), xlo.f(), p.f(), r.f(), t.f(), v.f(), st(), s);
         dslash_calls += 2;
         if (in_loop_reliable) {
             build_list(f_pend(), vl_pend);
@@ -893,8 +1030,8 @@ struct BatchSolver {
 
     void run() {
         if (o.eo) {  // Schur source and the full |b|^2 the tolerance refers to
-            // stencil mapping (streaming over t); the finish reads that mapping's rows
-            const Work wp = pl.work(P64, false, true);
+            // streaming mapping over t; the finish reads that mapping's rows
+            const Work wp = pl.work_stream(P64);
             launch_eo_prep(wp, full.d_blocks.as<BlockDesc>(), b.f(), sb_.f(), d_diag.as<double>(), part(), s);
             launch_finish(F_BNORM, wp, st(), part(), nullptr, nullptr, s);
         }
@@ -970,7 +1107,7 @@ struct BatchSolver {
         }
         drop_graph();
         if (o.eo)
-            launch_eo_post(pl.work(P64, false, true), full.d_blocks.as<BlockDesc>(), b.f(), sx_.f(), xhi.f(),
+            launch_eo_post(pl.work_stream(P64), full.d_blocks.as<BlockDesc>(), b.f(), sx_.f(), xhi.f(),
                            d_diag.as<double>(), s);
         HC(hipMemcpyAsync(st_host.data(), d_st.p, sizeof(SysState) * pl.nsys, hipMemcpyDeviceToHost, s));
         HC(hipStreamSynchronize(s));
@@ -1100,6 +1237,8 @@ void run_units(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm, con
     o.check_every = prm->solve.check_every > 0 ? prm->solve.check_every : 8;
     o.use_graph = prm->solve.use_graph != 0;
     o.eo = prm->solve.even_odd != 0;
+    o.eo_var = eo_tuning(ctxs[0], o.P)[0];
+    o.eo_occ = eo_tuning(ctxs[0], o.P)[1];
     BatchSolver bs(*pl, ctxs, s, o);
     const int nsys = pl->nsys;
     std::vector<double> diag(nsys);
@@ -1348,6 +1487,8 @@ void probed_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sigma_in, 
     o.check_every = prm->solve.check_every > 0 ? prm->solve.check_every : 8;
     o.use_graph = prm->solve.use_graph != 0;
     o.eo = prm->solve.even_odd != 0;
+    o.eo_var = eo_tuning(c, o.P)[0];
+    o.eo_occ = eo_tuning(c, o.P)[1];
     BatchSolver bs(*pl, lats, s, o);
     bs.setup(diag, idle, rkeys);
     DevBuf d_keys = to_device(keys.data(), sizeof(NoiseKey) * nsys, 0, s);
@@ -1514,6 +1655,8 @@ void sampling_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sh_in, i
     o.check_every = prm->solve.check_every > 0 ? prm->solve.check_every : 8;
     o.use_graph = prm->solve.use_graph != 0;
     o.eo = prm->solve.even_odd != 0;
+    o.eo_var = eo_tuning(c, o.P)[0];
+    o.eo_occ = eo_tuning(c, o.P)[1];
     BatchSolver bs(*pl, lats, s, o);
     bs.setup(diag, idle, keys);
     DevBuf d_keys = to_device(keys.data(), sizeof(NoiseKey) * nsys, 0, s);
@@ -1850,12 +1993,14 @@ double dslash_eo_bytes(int P, long long V, int n_sys, int nr, bool two_rows) {
     return (double)(V / 2) * per_sys * n_sys + (double)V * link_reals_per_site(P, nr, two_rows) * w * nblk;
 }
 
-double time_dslash_eo_impl(fs_ctx c, int P, int n_sys, int nr, int occ, int n_launch) {
+double time_dslash_eo_impl(fs_ctx c, int P, int n_sys, int nr, int var, int occ, int n_launch,
+                           std::vector<float>* each = nullptr) {
     hipStream_t s = c->stream;
     const int nblk = (n_sys + nr - 1) / nr;
     std::vector<int> blk_lat(nblk, 0);
     std::vector<fs_ctx_s*> lats{c};
-    auto pl = make_plan(blk_lat, lats, nr, 256, s, 0, occ, 1);
+    auto full = make_plan(blk_lat, lats, nr, 256, s, 0, 0, 0);
+    auto pl = eo_plan_of(*full, lats, s, P, var, occ);
     Field in, out;
     in.alloc(P, pl->total_slots);
     out.alloc(P, pl->total_slots);
@@ -1880,6 +2025,16 @@ double time_dslash_eo_impl(fs_ctx c, int P, int n_sys, int nr, int occ, int n_la
     hipEvent_t e0, e1;
     HC(hipEventCreate(&e0));
     HC(hipEventCreate(&e1));
+    if (each) {  // every launch timed on its own (for medians)
+        each->resize(n_launch);
+        for (int i = 0; i < n_launch; ++i) {
+            HC(hipEventRecord(e0, s));
+            hop(i);
+            HC(hipEventRecord(e1, s));
+            HC(hipEventSynchronize(e1));
+            HC(hipEventElapsedTime(&(*each)[i], e0, e1));
+        }
+    }
     HC(hipEventRecord(e0, s));
     for (int i = 0; i < n_launch; ++i) hop(i);
     HC(hipEventRecord(e1, s));
@@ -1981,6 +2136,59 @@ void apply_dirac_noalloc(fs_ctx c, double m0, double sigma, int storage, const d
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HC(hipStreamIsCapturing(s, &cs));
     if (cs == hipStreamCaptureStatusNone) HC(hipStreamSynchronize(s));
+}
+
+// One application of the even-odd Schur operator as the solver issues it (the
+// D_oe hop into odd-site scratch, then S with the fused (t, s), (t, t) partial
+// sums), averaged over n_launch applications on n_sys systems.
+double time_eo_apply_impl(fs_ctx c, int P, int n_sys, int nr, int var, int occ, int n_launch) {
+    hipStream_t s = c->stream;
+    const int nblk = (n_sys + nr - 1) / nr;
+    std::vector<int> blk_lat(nblk, 0);
+    std::vector<fs_ctx_s*> lats{c};
+    auto full = make_plan(blk_lat, lats, nr, 256, s, 0, 0, 0);
+    auto pl = eo_plan_of(*full, lats, s, P, var, occ);
+    Field in, tmp, out;
+    in.alloc(P, pl->total_slots);
+    tmp.alloc(P, pl->total_slots);
+    out.alloc(P, pl->total_slots);
+    std::vector<NoiseKey> keys(pl->nsys);
+    for (int i = 0; i < pl->nsys; ++i) {
+        std::memset(&keys[i], 0, sizeof(NoiseKey));
+        keys[i].seed = 12345;
+        keys[i].sample = (uint64_t)i;
+    }
+    DevBuf d_keys = to_device(keys.data(), sizeof(NoiseKey) * keys.size(), 0, s);
+    launch_noise_block(P, pl->work(P, false), in.f(), d_keys.as<NoiseKey>(), s);
+    std::vector<double> diag(pl->nsys, 4.1);
+    DevBuf d_diag = to_device(diag.data(), sizeof(double) * diag.size(), 0, s);
+    // the Schur launch's partial sums read each system's shadow-residual key and
+    // restart count (all systems "running", no restarts)
+    std::vector<SysState> sts(pl->nsys);
+    std::memset(sts.data(), 0, sizeof(SysState) * sts.size());
+    DevBuf d_st = to_device(sts.data(), sizeof(SysState) * sts.size(), 0, s);
+    DevBuf d_part(sizeof(double) * (size_t)pl->max_wg() * 8 * nr);
+    HC(hipStreamSynchronize(s));
+    const Work w = pl->work(P, false, true);
+    auto apply = [&]() {
+        launch_dslash_eo(P, D_HOP, w, tmp.f(), in.f(), Fld(), Fld(), d_diag.as<double>(), d_st.as<SysState>(), M_ALL,
+                         nullptr, s, d_keys.as<NoiseKey>(), 1);
+        launch_dslash_eo(P, D_TS, w, out.f(), tmp.f(), in.f(), Fld(), d_diag.as<double>(), d_st.as<SysState>(),
+                         M_ALL, d_part.as<double>(), s, d_keys.as<NoiseKey>(), 0);
+    };
+    for (int i = 0; i < 2; ++i) apply();
+    hipEvent_t e0, e1;
+    HC(hipEventCreate(&e0));
+    HC(hipEventCreate(&e1));
+    HC(hipEventRecord(e0, s));
+    for (int i = 0; i < n_launch; ++i) apply();
+    HC(hipEventRecord(e1, s));
+    HC(hipEventSynchronize(e1));
+    float ms = 0;
+    HC(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return (double)ms / n_launch;
 }
 
 }  // namespace
@@ -2271,6 +2479,8 @@ fs_status fs_solve_shifted(fs_ctx c, const fs_solve_params* prm, const double* s
         o.check_every = prm->check_every > 0 ? prm->check_every : 8;
         o.use_graph = prm->use_graph != 0;
         o.eo = prm->even_odd != 0;
+        o.eo_var = eo_tuning(c, P)[0];
+        o.eo_occ = eo_tuning(c, P)[1];
         std::vector<fs_ctx_s*> lats{c};
         // groups: (shift, rhs range) solved together
         std::vector<std::vector<std::pair<int, int>>> passes;  // each pass: list of (shift, rhs)
@@ -2621,9 +2831,38 @@ fs_status fs_time_dslash_eo(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rh
         if (!pow2_ok(nr)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
         DeviceScope ds(c->device);
         if (occ > 8) fail(FS_E_ARG, "occ must be -1 (the solver's choice) or 0..8");
-        const double ms = time_dslash_eo_impl(c, storage, n_sys, nr, occ < 0 ? eo_occ(storage, nr) : occ, n_launch);
+        const auto et = eo_tuning(c, storage);
+        const double ms = time_dslash_eo_impl(c, storage, n_sys, nr, et[0], occ < 0 ? et[1] : occ, n_launch);
         if (avg_ms) *avg_ms = ms;
         if (bytes) *bytes = dslash_eo_bytes(storage, c->V, n_sys, nr, c->two_rows);
+    });
+}
+
+fs_status fs_time_dslash_eo_each(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_block, int32_t n_launch,
+                                 float* ms_each, double* bytes) {
+    return guard([&] {
+        check_ctx(c);
+        check_prec(storage);
+        check_eo(true, c);
+        if (n_sys < 1 || n_launch < 1 || !ms_each) fail(FS_E_ARG, "n_sys, n_launch >= 1 and ms_each needed");
+        const int nr = rhs_block ? rhs_block : tuned_nr(c, storage, n_sys);
+        if (!pow2_ok(nr)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
+        DeviceScope ds(c->device);
+        const auto et = eo_tuning(c, storage);
+        std::vector<float> each;
+        time_dslash_eo_impl(c, storage, n_sys, nr, et[0], et[1], n_launch, &each);
+        std::copy(each.begin(), each.end(), ms_each);
+        if (bytes) *bytes = dslash_eo_bytes(storage, c->V, n_sys, nr, c->two_rows);
+    });
+}
+
+fs_status fs_set_eo_tuning(fs_ctx c, fs_prec storage, int32_t variant, int32_t occ) {
+    return guard([&] {
+        check_ctx(c, false);
+        check_prec(storage);
+        if (variant != 0 && variant != 2) fail(FS_E_ARG, "even-odd variant must be 0 or 2");
+        if (occ < -1 || occ > 8) fail(FS_E_ARG, "occ must be in -1..8");
+        c->eo_tune[storage] = {variant, occ};
     });
 }
 
@@ -2729,6 +2968,42 @@ fs_status fs_autotune(fs_ctx c, fs_prec storage, int32_t n_sys, const char* cach
             }
         }
         c->tune[storage] = best;
+        // the even-odd operator of the same rhs block: stencil variant and
+        // residency cap, timed as the solver applies it (hop + Schur launch)
+        bool eo_ok = true;
+        for (int i = 0; i < 4; ++i) eo_ok = eo_ok && c->dims[i] % 2 == 0;
+        if (eo_ok) {
+            std::ostringstream ekey;
+            ekey << "eo " << key.str() << " " << best.nr;
+            std::array<int, 2> eb{-1, -1};
+            if (cache_path) {
+                std::ifstream in(cache_path);
+                std::string line;
+                while (std::getline(in, line)) {
+                    if (line.rfind(ekey.str() + " ", 0) == 0) {
+                        std::istringstream ls(line.substr(ekey.str().size()));
+                        int v = -1, o = -2;
+                        if (ls >> v >> o && (v == 0 || v == 2) && o >= -1 && o <= 8) eb = {v, o};
+                    }
+                }
+            }
+            if (eb[0] < 0) {
+                double bt = 1e30;
+                for (int v : {0, 2})
+                    for (int o : {-1, 0, 2, 3, 4}) {
+                        const double ms = time_eo_apply_impl(c, storage, n_tune, best.nr, v, o, 6);
+                        if (ms < bt) {
+                            bt = ms;
+                            eb = {v, o};
+                        }
+                    }
+                if (cache_path) {
+                    std::ofstream outf(cache_path, std::ios::app);
+                    outf << ekey.str() << " " << eb[0] << " " << eb[1] << " " << bt / n_tune << "\n";
+                }
+            }
+            c->eo_tune[storage] = eb;
+        }
         if (best_rhs_block) *best_rhs_block = best.nr;
         if (best_wg) *best_wg = best.wg;
     });

@@ -89,77 +89,63 @@ __global__ void __launch_bounds__(256) k_axpy_s(Work w, Fld r, Fld v, const SysS
     FS_WG_EPILOGUE
 }
 
-// x += alpha p + omega s;  r = s - omega t  (s is held in r);  partials (rhat, r), |r|^2.
-// Every field is touched once: non-temporal loads and stores.
+// The vector update of one BiCGStab iteration, once its last reduction (the
+// F_OMEGA finish of the t = A s stencil) is done: for the systems that
+// iterated, x += alpha p + omega s and r = s - omega t (s is held in r), and
+// for those that continue, p = r + beta (p - omega v).  Five fields in (x, p,
+// s, t, v), three out; every field is touched once: non-temporal accesses.
 template <int P>
-__global__ void __launch_bounds__(256) k_update_xr(Work w, Fld x, Fld p, Fld r, Fld t, const NoiseKey* __restrict__ rk,
-                                                   const SysState* __restrict__ st, double* __restrict__ part) {
+__global__ void __launch_bounds__(256) k_update_xrp(Work w, Fld x, Fld p, Fld r, Fld t, Fld v,
+                                                    const SysState* __restrict__ st) {
     using A = typename Tr<P>::acc;
     FS_WG_PROLOGUE(w)
-    double acc[3] = {0.0, 0.0, 0.0};
     uint4* xb = fbase_w<P>(x, bd);
     float* xn = nbase(x, bd);
     uint4* rb = fbase_w<P>(r, bd);
     float* rn = nbase(r, bd);
-    FS_SLOT_LOOP(w)
-        if (st[sys].state != S_RUN) continue;
-        const A ar = (A)st[sys].alpha[0], ai = (A)st[sys].alpha[1];
-        const A wr = (A)st[sys].omega[0], wi = (A)st[sys].omega[1];
-        A xv[24], pv[24], sv[24];
-        load_sp<P, A, true>(xb, xn, gs, slot, xv);
-        load_sp<P, A, true>(fbase<P>(p, bd), nbase(p, bd), gs, slot, pv);
-        load_sp<P, A, true>(rb, rn, gs, slot, sv);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            xv[2 * k] += ar * pv[2 * k] - ai * pv[2 * k + 1] + wr * sv[2 * k] - wi * sv[2 * k + 1];
-            xv[2 * k + 1] += ar * pv[2 * k + 1] + ai * pv[2 * k] + wr * sv[2 * k + 1] + wi * sv[2 * k];
-        }
-        store_sp<P, A, true>(xb, xn, gs, slot, xv);
-        A tv[24];
-        load_sp<P, A, true>(fbase<P>(t, bd), nbase(t, bd), gs, slot, tv);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            sv[2 * k] -= wr * tv[2 * k] - wi * tv[2 * k + 1];
-            sv[2 * k + 1] -= wr * tv[2 * k + 1] + wi * tv[2 * k];
-        }
-        store_sp<P, A, true>(rb, rn, gs, slot, sv);
-        A hv[24];
-        rhat_site<A>(rk[sys], st[sys].restarts, (long long)(slot >> w.lognr), hv);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const double hr = hv[2 * k], hi = hv[2 * k + 1], qr = sv[2 * k], qi = sv[2 * k + 1];
-            acc[0] += hr * qr + hi * qi;
-            acc[1] += hr * qi - hi * qr;
-            acc[2] += qr * qr + qi * qi;
-        }
-    FS_SLOT_LOOP_END
-    block_partials<3, 4>(acc, w.nr, part, wg_id);
-    FS_WG_EPILOGUE
-}
-
-// p = r + beta (p - omega v)
-template <int P>
-__global__ void __launch_bounds__(256) k_update_p(Work w, Fld p, Fld r, Fld v, const SysState* __restrict__ st) {
-    using A = typename Tr<P>::acc;
-    FS_WG_PROLOGUE(w)
     uint4* pb = fbase_w<P>(p, bd);
     float* pn = nbase(p, bd);
     FS_SLOT_LOOP(w)
-        if (!st[sys].upd_p) continue;
-        const A br = (A)st[sys].beta[0], bi = (A)st[sys].beta[1];
+        if (!st[sys].upd_x) continue;
+        const A ar = (A)st[sys].alpha[0], ai = (A)st[sys].alpha[1];
         const A wr = (A)st[sys].omega[0], wi = (A)st[sys].omega[1];
-        A pv[24], rv[24], vv[24];
-        load_sp<P, A>(pb, pn, gs, slot, pv);
-        load_sp<P, A>(fbase<P>(r, bd), nbase(r, bd), gs, slot, rv);
-        load_sp<P, A>(fbase<P>(v, bd), nbase(v, bd), gs, slot, vv);
+        A pv[24], sv[24];
+        {
+            A xv[24];
+            load_sp<P, A, true>(xb, xn, gs, slot, xv);
+            load_sp<P, A, true>(pb, pn, gs, slot, pv);
+            load_sp<P, A, true>(rb, rn, gs, slot, sv);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const A qr = pv[2 * k] - (wr * vv[2 * k] - wi * vv[2 * k + 1]);
-            const A qi = pv[2 * k + 1] - (wr * vv[2 * k + 1] + wi * vv[2 * k]);
-            pv[2 * k] = rv[2 * k] + br * qr - bi * qi;
-            pv[2 * k + 1] = rv[2 * k + 1] + br * qi + bi * qr;
+            for (int k = 0; k < 12; ++k) {
+                xv[2 * k] += ar * pv[2 * k] - ai * pv[2 * k + 1] + wr * sv[2 * k] - wi * sv[2 * k + 1];
+                xv[2 * k + 1] += ar * pv[2 * k + 1] + ai * pv[2 * k] + wr * sv[2 * k + 1] + wi * sv[2 * k];
+            }
+            store_sp<P, A, true>(xb, xn, gs, slot, xv);
         }
-        store_sp<P, A>(pb, pn, gs, slot, pv);
+        {
+            A tv[24];
+            load_sp<P, A, true>(fbase<P>(t, bd), nbase(t, bd), gs, slot, tv);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                sv[2 * k] -= wr * tv[2 * k] - wi * tv[2 * k + 1];
+                sv[2 * k + 1] -= wr * tv[2 * k + 1] + wi * tv[2 * k];
+            }
+        }
+        round_sp<P, A>(sv);  // the residual as stored, which p is built from
+        store_sp<P, A, true>(rb, rn, gs, slot, sv);
+        if (st[sys].upd_p) {
+            const A br = (A)st[sys].beta[0], bi = (A)st[sys].beta[1];
+            A vv[24];
+            load_sp<P, A, true>(fbase<P>(v, bd), nbase(v, bd), gs, slot, vv);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const A qr = pv[2 * k] - (wr * vv[2 * k] - wi * vv[2 * k + 1]);
+                const A qi = pv[2 * k + 1] - (wr * vv[2 * k + 1] + wi * vv[2 * k]);
+                pv[2 * k] = sv[2 * k] + br * qr - bi * qi;
+                pv[2 * k + 1] = sv[2 * k + 1] + br * qi + bi * qr;
+            }
+            store_sp<P, A, true>(pb, pn, gs, slot, pv);
+        }
     FS_SLOT_LOOP_END
     FS_WG_EPILOGUE
 }
@@ -240,55 +226,22 @@ __global__ void __launch_bounds__(256) k_axpy_s_g(Work w, Fld r, Fld v, const Sy
     });
 }
 
-// p = r + beta (p - omega v), FP32 storage
-__global__ void __launch_bounds__(256) k_update_p_g(Work w, Fld p, Fld r, Fld v, const SysState* __restrict__ st) {
+// The fused vector update of k_update_xrp, FP32 storage, one thread per group.
+__global__ void __launch_bounds__(256) k_update_xrp_g(Work w, Fld x, Fld p, Fld r, Fld t, Fld v,
+                                                      const SysState* __restrict__ st) {
     for_group_tile(w, [&](const int b, const int g, const int, const int, const size_t slot) {
         const BlockDesc bd = w.blocks[b];
         const size_t gs = (size_t)w.lats[bd.lat].Vf << w.lognr;
         if (slot >= gs) return;
         const int sys = bd.sys0 + (int)(slot & (size_t)(w.nr - 1));
-        if (!st[sys].upd_p) return;
-        const float br = (float)st[sys].beta[0], bi = (float)st[sys].beta[1];
-        const float wr = (float)st[sys].omega[0], wi = (float)st[sys].omega[1];
-        const size_t e = (size_t)g * gs + slot;
-        f32x4_t* pp = reinterpret_cast<f32x4_t*>(fbase_w<P32>(p, bd)) + e;
-        const f32x4_t rv = ld_nt(reinterpret_cast<const f32x4_t*>(fbase<P32>(r, bd)) + e);
-        const f32x4_t vv = ld_nt(reinterpret_cast<const f32x4_t*>(fbase<P32>(v, bd)) + e);
-        f32x4_t pv = ld_nt(pp);
-        const float q0 = pv.x - (wr * vv.x - wi * vv.y), q1 = pv.y - (wr * vv.y + wi * vv.x);
-        const float q2 = pv.z - (wr * vv.z - wi * vv.w), q3 = pv.w - (wr * vv.w + wi * vv.z);
-        pv.x = rv.x + br * q0 - bi * q1;
-        pv.y = rv.y + br * q1 + bi * q0;
-        pv.z = rv.z + br * q2 - bi * q3;
-        pv.w = rv.w + br * q3 + bi * q2;
-        st_nt(pv, pp);
-    });
-}
-
-// x += alpha p + omega s;  r = s - omega t  (s is held in r), FP32 storage, one
-// thread per group; partials (rhat, r), |r|^2 over the thread's two complex
-// components, rhat drawn from its Philox block.  A workgroup takes one group
-// of the tpw tiles of a tile-mapping workgroup and writes its own partial row,
-// (tile-mapping workgroup) * 6 + g, so a block's rows stay contiguous and the
-// finish sums 6 rows per workgroup (update_xr_rows) in a fixed order.
-__global__ void __launch_bounds__(256) k_update_xr_g(Work w, Fld x, Fld p, Fld r, Fld t,
-                                                     const NoiseKey* __restrict__ rk, const SysState* __restrict__ st,
-                                                     double* __restrict__ part) {
-    double acc[3] = {0.0, 0.0, 0.0};
-    int row = -1;
-    for_group_tile<false>(w, [&](const int b, const int g, const int wgb, const int, const size_t slot) {
-        const BlockDesc bd = w.blocks[b];
-        row = (w.wg_start[b] + wgb) * Tr<P32>::G + g;
-        const size_t gs = (size_t)w.lats[bd.lat].Vf << w.lognr;
-        if (slot >= gs) return;
-        const int sys = bd.sys0 + (int)(slot & (size_t)(w.nr - 1));
-        if (st[sys].state != S_RUN) return;
+        if (!st[sys].upd_x) return;
         const float ar = (float)st[sys].alpha[0], ai = (float)st[sys].alpha[1];
         const float wr = (float)st[sys].omega[0], wi = (float)st[sys].omega[1];
         const size_t e = (size_t)g * gs + slot;
         f32x4_t* xp = reinterpret_cast<f32x4_t*>(fbase_w<P32>(x, bd)) + e;
         f32x4_t* rp = reinterpret_cast<f32x4_t*>(fbase_w<P32>(r, bd)) + e;
-        const f32x4_t pv = ld_nt(reinterpret_cast<const f32x4_t*>(fbase<P32>(p, bd)) + e);
+        f32x4_t* pp = reinterpret_cast<f32x4_t*>(fbase_w<P32>(p, bd)) + e;
+        f32x4_t pv = ld_nt(pp);
         const f32x4_t tv = ld_nt(reinterpret_cast<const f32x4_t*>(fbase<P32>(t, bd)) + e);
         f32x4_t xv = ld_nt(xp), sv = ld_nt(rp);
         xv.x += ar * pv.x - ai * pv.y + wr * sv.x - wi * sv.y;
@@ -301,19 +254,17 @@ __global__ void __launch_bounds__(256) k_update_xr_g(Work w, Fld x, Fld p, Fld r
         sv.z -= wr * tv.z - wi * tv.w;
         sv.w -= wr * tv.w + wi * tv.z;
         st_nt(sv, rp);
-        float h[4];
-        rhat_pair(rk[sys], st[sys].restarts, (long long)(slot >> w.lognr), 2 * g, h);
-        const float q[4] = {sv.x, sv.y, sv.z, sv.w};
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const double hr = h[2 * k], hi = h[2 * k + 1], qr = q[2 * k], qi = q[2 * k + 1];
-            acc[0] += hr * qr + hi * qi;
-            acc[1] += hr * qi - hi * qr;
-            acc[2] += qr * qr + qi * qi;
-        }
+        if (!st[sys].upd_p) return;
+        const float br = (float)st[sys].beta[0], bi = (float)st[sys].beta[1];
+        const f32x4_t vv = ld_nt(reinterpret_cast<const f32x4_t*>(fbase<P32>(v, bd)) + e);
+        const float q0 = pv.x - (wr * vv.x - wi * vv.y), q1 = pv.y - (wr * vv.y + wi * vv.x);
+        const float q2 = pv.z - (wr * vv.z - wi * vv.w), q3 = pv.w - (wr * vv.w + wi * vv.z);
+        pv.x = sv.x + br * q0 - bi * q1;
+        pv.y = sv.y + br * q1 + bi * q0;
+        pv.z = sv.z + br * q2 - bi * q3;
+        pv.w = sv.w + br * q3 + bi * q2;
+        st_nt(pv, pp);
     });
-    if (row < 0) return;  // no tile: the whole workgroup leaves
-    block_partials<3, 4>(acc, w.nr, part, row);
 }
 
 // x_hi += x_lo; x_lo = 0  (systems pending a reliable update)
@@ -462,39 +413,44 @@ __device__ __forceinline__ void finish_system(SysState& S, const double* q, int 
             }
         }
     } else if constexpr (STAGE == F_OMEGA) {
+        // t = A s is done: omega = (t, s) / (t, t), and for r = s - omega t
+        // rho_new = (rhat, r) = (rhat, s) - omega (rhat, t) and
+        // |r|^2 = |s|^2 - |(t, s)|^2 / (t, t), all from the stencil's partial sums
+        // (a |r|^2 lost to cancellation can only ask early for the FP64 check);
+        // then the state, and beta = (rho_new / rho) (alpha / omega)
+        S.upd_x = 0;
+        S.upd_p = 0;
         if (S.state == S_RUN) {
-            const double tsr = Q(0), tsi = Q(1), tt = Q(2);
-            if (!finite_d(tt) || !finite_d(tsr) || !finite_d(tsi)) {
+            const double tsr = Q(0), tsi = Q(1), tt = Q(2), ss = Q(3);
+            const double hsr = Q(4), hsi = Q(5), htr = Q(6), hti = Q(7);
+            if (!finite_d(tt) || !finite_d(tsr) || !finite_d(tsi) || !finite_d(ss) || !finite_d(hsr) ||
+                !finite_d(hsi) || !finite_d(htr) || !finite_d(hti)) {
                 S.state = S_BRK;
-            } else if (tt > 0.0) {
-                S.omega[0] = tsr / tt;
-                S.omega[1] = tsi / tt;
             } else {
-                S.omega[0] = S.omega[1] = 0.0;
-            }
-        }
-    } else if constexpr (STAGE == F_RHO) {
-        if (S.state == S_RUN) {
-            const double nr_ = Q(0), ni = Q(1), rr = Q(2);
-            S.iters += 1;
-            S.upd_p = 0;
-            S.rr = rr;
-            const double om2 = S.omega[0] * S.omega[0] + S.omega[1] * S.omega[1];
-            const double rho2 = S.rho[0] * S.rho[0] + S.rho[1] * S.rho[1];
-            int ns = S_RUN;
-            if (!finite_d(rr) || !finite_d(nr_) || !finite_d(ni)) {
-                ns = S_BRK;
-            } else {
+                if (tt > 0.0) {
+                    S.omega[0] = tsr / tt;
+                    S.omega[1] = tsi / tt;
+                } else {
+                    S.omega[0] = S.omega[1] = 0.0;
+                }
+                const double wr = S.omega[0], wi = S.omega[1];
+                const double nr_ = hsr - (wr * htr - wi * hti), ni = hsi - (wr * hti + wi * htr);
+                const double rr = std::max(0.0, tt > 0.0 ? ss - (tsr * tsr + tsi * tsi) / tt : ss);
+                S.upd_x = 1;
+                S.iters += 1;
+                S.rr = rr;
+                const double om2 = wr * wr + wi * wi;
+                const double rho2 = S.rho[0] * S.rho[0] + S.rho[1] * S.rho[1];
+                int ns = S_RUN;
                 if (rr <= S.tol2 * S.bb) ns = S_CHK;
                 else if (S.delta2 > 0.0 && rr < S.delta2 * S.rr_max) ns = S_REL;
                 else if (S.iters >= S.max_iter) ns = S_MAXIT;
                 const double nn2 = nr_ * nr_ + ni * ni;
                 if (om2 > 0.0 && rho2 > 0.0) {
-                    // beta = (rho_new / rho) * (alpha / omega)
                     const double ar = (nr_ * S.rho[0] + ni * S.rho[1]) / rho2;
                     const double ai = (ni * S.rho[0] - nr_ * S.rho[1]) / rho2;
-                    const double cr = (S.alpha[0] * S.omega[0] + S.alpha[1] * S.omega[1]) / om2;
-                    const double ci = (S.alpha[1] * S.omega[0] - S.alpha[0] * S.omega[1]) / om2;
+                    const double cr = (S.alpha[0] * wr + S.alpha[1] * wi) / om2;
+                    const double ci = (S.alpha[1] * wr - S.alpha[0] * wi) / om2;
                     S.beta[0] = ar * cr - ai * ci;
                     S.beta[1] = ar * ci + ai * cr;
                     S.upd_p = 1;
@@ -504,12 +460,10 @@ __device__ __forceinline__ void finish_system(SysState& S, const double* q, int 
                 if (ns == S_RUN && nn2 <= 1e-28 * rr * S.rhat2) ns = S_BRK;  // rho ~ 0
                 S.rho[0] = nr_;
                 S.rho[1] = ni;
+                if (ns == S_BRK) S.upd_p = 0;
+                if (rr > S.rr_max) S.rr_max = rr;
+                S.state = ns;
             }
-            if (ns == S_BRK) S.upd_p = 0;
-            if (rr > S.rr_max) S.rr_max = rr;
-            S.state = ns;
-        } else {
-            S.upd_p = 0;
         }
     } else if constexpr (STAGE == F_TRUE) {
         const int s = S.state;
@@ -540,13 +494,15 @@ __device__ __forceinline__ void finish_system(SysState& S, const double* q, int 
 // One workgroup per block: reduce the partial sums of the launch it completes
 // (fixed order), update the per-system scalars and state, and write the block
 // flags of the next launches.  blk_on (out): blocks that have work in the
-// next iteration kernels (F_TRUE: blocks to convert); blk_pend (out2): after
-// F_RHO, blocks with systems that need an FP64 reliable update (the other
-// stages write 0 there, clearing the flags they consumed).
+// next kernels (F_OMEGA: the vector update; F_TRUE: blocks to convert);
+// blk_pend (out2): after F_OMEGA, blocks with systems that need an FP64
+// reliable update (the other stages write 0 there, clearing the flags they
+// consumed).
 template <int STAGE>
 __global__ void __launch_bounds__(256) k_finish(Work w, SysState* __restrict__ st, const double* __restrict__ part,
                                                 int* __restrict__ blk_on, int* __restrict__ blk_pend) {
-    constexpr int ND = STAGE == F_INIT ? 4 : STAGE == F_ALPHA ? 2 : (STAGE == F_TRUE || STAGE == F_BNORM) ? 1 : 3;
+    constexpr int ND = STAGE == F_INIT ? 4 : STAGE == F_ALPHA ? 2 : STAGE == F_OMEGA ? 8
+                     : (STAGE == F_TRUE || STAGE == F_BNORM) ? 1 : 3;
     __shared__ double q[ND * 16];
     __shared__ int any_on, any_rel, any_pend;
     const int nr = w.nr;
@@ -569,7 +525,7 @@ __global__ void __launch_bounds__(256) k_finish(Work w, SysState* __restrict__ s
     if (mine) {
         SysState& S = st[bd.sys0 + threadIdx.x];
         finish_system<STAGE>(S, q, nr, threadIdx.x, (double)w.lats[bd.lat].Vf);
-        if (STAGE == F_RHO && S.state == S_REL) atomicOr(&any_rel, 1);
+        if (STAGE == F_OMEGA && S.state == S_REL) atomicOr(&any_rel, 1);
     }
     __syncthreads();
     if (mine) {
@@ -577,12 +533,12 @@ __global__ void __launch_bounds__(256) k_finish(Work w, SysState* __restrict__ s
         // Reliable updates are taken block by block: when one system of the
         // block asks for one, every running system of the block joins it, so
         // the FP64 stencil of the update does useful work on all its lanes.
-        if (STAGE == F_RHO && any_rel && S.state == S_RUN) S.state = S_REL;
+        if (STAGE == F_OMEGA && any_rel && S.state == S_RUN) S.state = S_REL;
         bool on;
-        if (STAGE == F_RHO) on = (S.state == S_RUN) || S.upd_p;
+        if (STAGE == F_OMEGA) on = S.upd_x;
         else if (STAGE == F_TRUE) on = S.state == S_CONV || S.state == S_RST;
         else on = S.state == S_RUN;
-        const bool pend = STAGE == F_RHO &&
+        const bool pend = STAGE == F_OMEGA &&
                           (S.state == S_REL || S.state == S_CHK || S.state == S_BRK || S.state == S_MAXIT);
         if (on) atomicOr(&any_on, 1);
         if (pend) atomicOr(&any_pend, 1);
@@ -991,19 +947,12 @@ __global__ void k_level_stats(const double* __restrict__ X, int L1, int n_noise,
 }
 
 // Streaming copy: each lane moves 4 x 16 bytes with all loads issued first.
+// Streaming copy: one 16-byte element per lane, non-temporal loads and
+// stores (the fastest of the copy forms measured on the MI355X: 6.5 TB/s for
+// 1 GiB, against 5.5 with four elements per lane and cached accesses).
 __global__ void __launch_bounds__(256) k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n) {
-    const size_t base = (size_t)blockIdx.x * 1024 + threadIdx.x;
-    uint4 v[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const size_t i = base + (size_t)k * 256;
-        if (i < n) v[k] = src[i];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const size_t i = base + (size_t)k * 256;
-        if (i < n) dst[i] = v[k];
-    }
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) st16<true>(dst + i, ld16<true>(src + i));
 }
 
 }  // namespace
@@ -1031,24 +980,13 @@ void launch_axpy_s(int prec, const Work& w, Fld r, Fld v, const SysState* st, hi
     }
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_axpy_s<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, r, v, st))
 }
-int update_xr_rows(int prec, const Work& w) { return (prec == P32 && w.wg == 256) ? Tr<P32>::G : 1; }
-
-void launch_update_xr(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, const NoiseKey* rk, const SysState* st,
-                      double* part, hipStream_t s) {
-    if (update_xr_rows(prec, w) > 1) {
-        hipLaunchKernelGGL(k_update_xr_g, dim3((unsigned)((long long)Tr<P32>::G * w.total_wg)), dim3(256), 0, s, w,
-                           x, p, r, t, rk, st, part);
-        return;
-    }
-    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_update_xr<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, x, p, r, t, rk,
-                                           st, part))
-}
-void launch_update_p(int prec, const Work& w, Fld p, Fld r, Fld v, const SysState* st, hipStream_t s) {
+void launch_update_xrp(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, Fld v, const SysState* st,
+                       hipStream_t s) {
     if (prec == P32 && w.wg == 256) {
-        hipLaunchKernelGGL(k_update_p_g, dim3(grid_groups(w)), dim3(256), 0, s, w, p, r, v, st);
+        hipLaunchKernelGGL(k_update_xrp_g, dim3(grid_groups(w)), dim3(256), 0, s, w, x, p, r, t, v, st);
         return;
     }
-    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_update_p<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, p, r, v, st))
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_update_xrp<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, x, p, r, t, v, st))
 }
 void launch_fold(int prec, const Work& w, Fld xhi, Fld xlo, const SysState* st, hipStream_t s) {
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_fold<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, xhi, xlo, st))
@@ -1070,7 +1008,6 @@ void launch_finish(int stage, const Work& w, SysState* st, const double* part, i
         case F_INIT: wf.blk_on = nullptr; wf.vlist = nullptr; hipLaunchKernelGGL(k_finish<F_INIT>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
         case F_ALPHA: hipLaunchKernelGGL(k_finish<F_ALPHA>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
         case F_OMEGA: hipLaunchKernelGGL(k_finish<F_OMEGA>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
-        case F_RHO: hipLaunchKernelGGL(k_finish<F_RHO>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
         case F_TRUE: hipLaunchKernelGGL(k_finish<F_TRUE>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
         case F_RESUME: hipLaunchKernelGGL(k_finish<F_RESUME>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
         case F_BNORM: wf.blk_on = nullptr; wf.vlist = nullptr; hipLaunchKernelGGL(k_finish<F_BNORM>, dim3(grid), dim3(256), 0, s, wf, st, part, out, out2); break;
@@ -1139,7 +1076,7 @@ void launch_level_stats(const double* X, int L1, int n_noise, int P1, double* ou
     hipLaunchKernelGGL(k_level_stats, dim3((n + 255) / 256), dim3(256), 0, s, X, L1, n_noise, P1, n_level, out);
 }
 void launch_copy(uint4* dst, const uint4* src, size_t n16, hipStream_t s) {
-    const size_t blocks = (n16 + 1023) / 1024;
+    const size_t blocks = (n16 + 255) / 256;
     hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, n16);
 }
 

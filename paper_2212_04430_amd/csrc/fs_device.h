@@ -32,6 +32,8 @@ struct LatDesc {
     const void* gauge; // links in the launch's storage precision, [mu][9][site]
     const void* gauge_q; // the same links site-major, [mu][site][QC 16-byte chunks], or
                          // rows 0-1 only ([mu][site][QCR], FP32) in plans that rebuild row 2
+    int pty, ptz;        // one-parity plans with the x-pair stencil: tile of TY x TZ pairs
+                         // (dividing Ly, Lz) per workgroup; 0 otherwise
 };
 
 struct BlockDesc {

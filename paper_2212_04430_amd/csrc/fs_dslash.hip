@@ -155,7 +155,32 @@ __device__ __forceinline__ bool mask_ok(int mask, const SysState* __restrict__ s
 
 template <int MODE> struct NDots { static constexpr int v = 1; };
 template <> struct NDots<D_RHAT> { static constexpr int v = 2; };
-template <> struct NDots<D_TS> { static constexpr int v = 3; };
+template <> struct NDots<D_TS> { static constexpr int v = 8; };
+
+// Partial sums of a D_TS launch (t = out, s = the input at the output site):
+// (t, s), (t, t), (s, s), (rhat, s) and (rhat, t), from which the omega finish
+// forms omega and, for r = s - omega t, (rhat, r) and |r|^2 (so the vector
+// update needs no reduction of its own).  rhat is the system's shadow residual
+// at field site `fsite`.
+template <typename A>
+__device__ __forceinline__ void ts_dots(const A o[24], const A s[24], const NoiseKey& key, int restarts,
+                                        long long fsite, double acc[8]) {
+    A rh[24];
+    rhat_site<A>(key, restarts, fsite, rh);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const double tr = o[2 * k], ti = o[2 * k + 1], sr = s[2 * k], si = s[2 * k + 1];
+        const double hr = rh[2 * k], hi = rh[2 * k + 1];
+        acc[0] += tr * sr + ti * si;
+        acc[1] += tr * si - ti * sr;
+        acc[2] += tr * tr + ti * ti;
+        acc[3] += sr * sr + si * si;
+        acc[4] += hr * sr + hi * si;
+        acc[5] += hr * si - hi * sr;
+        acc[6] += hr * tr + hi * ti;
+        acc[7] += hr * ti - hi * tr;
+    }
+}
 template <> struct NDots<D_RESID> { static constexpr int v = 1; };
 
 // Stencil over t-columns.  A workgroup owns `wg` consecutive (xyz, rhs) slots
@@ -275,15 +300,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
 #pragma unroll
                 for (int k = 0; k < 12; ++k) bw[k] = bn[k];
                 if constexpr (MODE == D_TS) {
-                    if (act) {
-#pragma unroll
-                        for (int k = 0; k < 12; ++k) {
-                            const double tr = o[2 * k], ti = o[2 * k + 1], sr = v[2 * k], si = v[2 * k + 1];
-                            acc[0] += tr * sr + ti * si;
-                            acc[1] += tr * si - ti * sr;
-                            acc[2] += tr * tr + ti * ti;
-                        }
-                    }
+                    if (act) ts_dots<A>(o, v, rk[sys], st[sys].restarts, site, acc);
                 }
             }
             // A lane whose system is not running (possible only with quad-shared
@@ -418,7 +435,8 @@ __device__ __forceinline__ void hop_tile(const LatDesc& ld, const uint4* __restr
 // live state does not fit take fewer rather than spill (FP64 arithmetic
 // doubles every register, BF16 needs its rounding temporaries).
 template <int P, int MODE> struct TileW {
-    static constexpr int v = (P == P32 || P == P16) ? (MODE != D_RHAT ? 3 : 2) : 1;
+    // the rhat launches regenerate the shadow residual in their epilogue: two waves
+    static constexpr int v = (P == P32 || P == P16) ? ((MODE != D_RHAT && MODE != D_TS) ? 3 : 2) : 1;
 };
 
 template <int P> constexpr int tile_nbuf() { return sizeof(typename Tr<P>::acc) == 4 ? 2 : 1; }
@@ -532,15 +550,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
                 mul_u(u, h, ww);
                 PtM::accum(o, ww, (wrap && ld.tsign < 0) ? A(0.5) : A(-0.5));
                 if constexpr (MODE == D_TS) {
-                    if (act) {
-#pragma unroll
-                        for (int k = 0; k < 12; ++k) {
-                            const double tr = o[2 * k], ti = o[2 * k + 1], sr = v[2 * k], si = v[2 * k + 1];
-                            acc[0] += tr * sr + ti * si;
-                            acc[1] += tr * si - ti * sr;
-                            acc[2] += tr * tr + ti * ti;
-                        }
-                    }
+                    if (act) ts_dots<A>(o, v, rk[sys], st[sys].restarts, site, acc);
                 }
             }
 #pragma unroll
@@ -701,13 +711,7 @@ __global__ void __launch_bounds__(256) k_dslash_eo(Work w, Fld out, Fld in, Fld 
                     acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
                 }
             } else if constexpr (MODE == D_TS) {
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    const double tr = o[2 * k], ti = o[2 * k + 1], sr = cv[2 * k], si = cv[2 * k + 1];
-                    acc[0] += tr * sr + ti * si;
-                    acc[1] += tr * si - ti * sr;
-                    acc[2] += tr * tr + ti * ti;
-                }
+                ts_dots<A>(o, cv, rk[sys], st[sys].restarts, cb, acc);
             } else if constexpr (MODE == D_RESID) {
 #pragma unroll
                 for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
@@ -902,13 +906,7 @@ __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fl
                         acc[1] += (double)rh[2 * j] * (double)o[2 * j + 1] - (double)rh[2 * j + 1] * (double)o[2 * j];
                     }
                 } else if constexpr (MODE == D_TS) {
-#pragma unroll
-                    for (int j = 0; j < 12; ++j) {
-                        const double tr = o[2 * j], ti = o[2 * j + 1], sr = cv[2 * j], si = cv[2 * j + 1];
-                        acc[0] += tr * sr + ti * si;
-                        acc[1] += tr * si - ti * sr;
-                        acc[2] += tr * tr + ti * ti;
-                    }
+                    ts_dots<A>(o, cv, rk[sys], st[sys].restarts, site >> 1, acc);
                 } else if constexpr (MODE == D_RESID) {
 #pragma unroll
                     for (int j = 0; j < 24; ++j) acc[0] += (double)o[j] * (double)o[j];
@@ -918,6 +916,242 @@ __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fl
     }
     if constexpr (MODE == D_RHAT || MODE == D_TS || MODE == D_RESID || MODE == D_PREP)
         block_partials<ND, 4>(acc, w.nr, part, wg_id);
+    });
+}
+
+// The even-odd operator over x-pairs with LDS sharing (variant 2 of the
+// one-parity plans).  Lane (r, xh, iy, iz) of a workgroup owns the pair of
+// columns x = 2 xh, 2 xh + 1 at (y, z) = tile origin + (iy, iz) for system r,
+// and walks every t-slice of its chunk.  At slice t one column of the pair
+// holds an output site (parity par_out) and the other an input site: the lane
+// computes the output, while the input site's spinor sits in LDS, where the
+// x/y/z neighbours of the other lanes' outputs read it.  That spinor is the
+// lane's forward-t neighbour of slice t-1: loaded once from memory, used for
+// the forward-t hop and written to the other LDS buffer for the next slice.
+// So every input spinor is read from memory once, plus, for the lanes on a
+// y/z face of the tile (TY x TZ pairs; the tile spans all of x), the
+// neighbour beyond the face.  The backward-t term of the next slice's output
+// (the lane's other column) is formed from the pair's input site and carried
+// in registers.  Modes as k_dslash_eo_t (D_HOP, and with par_out = 0 the
+// Schur modes).
+// One neighbour of the x-pair stencil: from LDS when it is inside the tile,
+// else from memory; every lane issues the memory load (interior lanes load
+// slot 0, a broadcast) and the value is selected, so the code has no branch.
+template <int P>
+__device__ __forceinline__ void pair_fetch(bool inside, const uint4* __restrict__ ib, const float* __restrict__ inn,
+                                           size_t gs, size_t gslot, const typename LdsVec<typename Tr<P>::acc>::T* sh,
+                                           int wg, int nl, typename Tr<P>::acc v[24]) {
+    using A = typename Tr<P>::acc;
+    A g[24], l[24];
+    load_sp<P, A>(ib, inn, gs, inside ? (size_t)0 : gslot, g);
+    lds_get<A>(sh, wg, nl, l);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = inside ? l[k] : g[k];
+}
+
+// One spatial axis of the x-pair stencil: forward and backward hops of the
+// output site so (pair field index cb, lattice coordinate c of extent Lm,
+// tile coordinate i of extent T, LDS lane stride ls).
+template <int P, int Q, int MU, typename PF, typename PB>
+__device__ __forceinline__ void pair_hop(const LatDesc& ld, const uint4* __restrict__ ib,
+                                         const float* __restrict__ inn, size_t gs,
+                                         const typename LdsVec<typename Tr<P>::acc>::T* sh, int wg, int lane,
+                                         int i, int T, int Lm, int ls, int c, int cb, int cstride, int so,
+                                         int sstride, int r, int lognr, typename Tr<P>::acc o[24]) {
+    using A = typename Tr<P>::acc;
+    const bool whole = T == Lm;  // the tile spans the axis: wrap-around inside it
+    {
+        const int cbf = (c == Lm - 1) ? cb - (Lm - 1) * cstride : cb + cstride;
+        A v[24], h[12], u[18], w[12];
+        pair_fetch<P>(whole || i < T - 1, ib, inn, gs, ((size_t)cbf << lognr) + r, sh, wg,
+                      (i < T - 1) ? lane + ls : lane - (T - 1) * ls, v);
+        PF::project(v, h);
+        link<P, Q, A>(ld, MU, so, u);
+        mul_u(u, h, w);
+        PF::accum(o, w, A(-0.5));
+    }
+    {
+        const int cbb = (c == 0) ? cb + (Lm - 1) * cstride : cb - cstride;
+        const int sb = (c == 0) ? so + (Lm - 1) * sstride : so - sstride;
+        A v[24], h[12], u[18], w[12];
+        pair_fetch<P>(whole || i > 0, ib, inn, gs, ((size_t)cbb << lognr) + r, sh, wg,
+                      (i > 0) ? lane - ls : lane + (T - 1) * ls, v);
+        PB::project(v, h);
+        link<P, Q, A>(ld, MU, sb, u);
+        mul_udag(u, h, w);
+        PB::accum(o, w, A(-0.5));
+    }
+}
+
+template <int P, int MODE, int Q>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<P, MODE>::v, 8)))
+k_dslash_eo_pair(Work w, Fld out, Fld in, Fld cen, Fld aux, const double* __restrict__ diag,
+                 const SysState* __restrict__ st, int mask, double* __restrict__ part,
+                 const NoiseKey* __restrict__ rk, int par_out) {
+    using A = typename Tr<P>::acc;
+    using V16 = typename LdsVec<A>::T;
+    constexpr int G = Tr<P>::G;
+    constexpr int ND = NDotsEo<MODE>::v;
+    constexpr int NBUF = tile_nbuf<P>();
+    constexpr int NG = 24 * (int)sizeof(A) / 16;
+    extern __shared__ uint4 lds_dyn[];
+    V16* const shb = reinterpret_cast<V16*>(lds_dyn);
+    for_each_vwg(w, [&](const int wg_id, const int b) {
+    const BlockDesc bd = w.blocks[b];
+    const LatDesc ld = w.lats[bd.lat];
+    const int wgb = wg_id - w.wg_start[b];
+    const size_t gs = (size_t)ld.Vf << w.lognr;
+    const uint4* ib = in.v + (size_t)bd.slot_off * G;
+    const float* inn = in.n ? in.n + bd.slot_off : nullptr;
+    uint4* ob = out.v + (size_t)bd.slot_off * G;
+    float* on = out.n ? out.n + bd.slot_off : nullptr;
+    const int Lx = ld.L[0], Ly = ld.L[1], Lz = ld.L[2], Lt = ld.L[3];
+    const int Lxh = Lx >> 1;
+    const int TY = ld.pty, TZ = ld.ptz;
+    const int nty = Ly / TY;
+    const int ntile = nty * (Lz / TZ);
+    const int ch = wgb / ntile, jt = wgb - ch * ntile;
+    const int t0 = ch * w.tc, t1 = min(Lt, t0 + w.tc);
+    const int lane = threadIdx.x;
+    const int r = lane & (w.nr - 1);
+    int q = lane >> w.lognr;
+    const int xh = q % Lxh;
+    q /= Lxh;
+    const int iy = q % TY, iz = q / TY;
+    const bool valid = iz < TZ;  // lanes beyond the tile only join the barriers
+    const int y = (jt % nty) * TY + iy, z = (jt / nty) * TZ + iz;
+    const int sys = bd.sys0 + r;
+    const bool act = valid && mask_ok(mask, st, sys);
+    const int vxyzh = Lxh * Ly * Lz;          // field sites of one t-slice
+    const int cb0 = xh + Lxh * (y + Ly * z);  // field index at t = 0
+    const int ls_y = w.nr * Lxh, ls_z = ls_y * TY;
+    const int sy = Lx, sz = Lx * Ly, stt = sz * Lz;
+    // x neighbour across the pair boundary: pair xh - 1 when the output column
+    // is even, xh + 1 when it is odd (periodic in x; the tile spans all of x)
+    const int lxm = xh == 0 ? lane + (Lxh - 1) * w.nr : lane - w.nr;
+    const int lxp = xh == Lxh - 1 ? lane - (Lxh - 1) * w.nr : lane + w.nr;
+
+    double acc[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) acc[k] = 0.0;
+    A bw[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) bw[k] = A(0);
+    if (valid) {
+        {
+            A e[24];
+            load_sp<P, A>(ib, inn, gs, ((size_t)(cb0 + t0 * vxyzh) << w.lognr) + r, e);
+            lds_put<A>(shb, w.wg, lane, e);
+        }
+        // backward-t term of the first output: its column at t0 - 1 is this
+        // pair's input site there
+        const int tb = t0 == 0 ? Lt - 1 : t0 - 1;
+        const int xo0 = 2 * xh + ((y + z + t0 + par_out) & 1);
+        A v[24], h[12], u[18];
+        load_sp<P, A>(ib, inn, gs, ((size_t)(cb0 + tb * vxyzh) << w.lognr) + r, v);
+        PtP::project(v, h);
+        link<P, Q, A>(ld, 3, xo0 + sy * y + sz * z + stt * tb, u);
+        mul_udag(u, h, bw);
+        if (t0 == 0 && ld.tsign < 0) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) bw[k] = -bw[k];
+        }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int t = t0; t < t1; ++t) {
+        const V16* const sh = shb + (NBUF == 2 ? ((t - t0) & 1) : 0) * NG * w.wg;           // slice t
+        V16* const shn = shb + (NBUF == 2 ? ((t - t0 + 1) & 1) : 0) * NG * w.wg;            // slice t + 1
+        const bool wrap = t == Lt - 1;
+        const int cb = cb0 + t * vxyzh;
+        A nxt[24];
+        if (valid) {
+            const int par = (y + z + t + par_out) & 1;  // output column 2 xh + par
+            const int so = 2 * xh + par + sy * y + sz * z + stt * t;
+            const size_t slot = ((size_t)cb << w.lognr) + r;
+            A o[24];
+#pragma unroll
+            for (int k = 0; k < 24; ++k) o[k] = A(0);
+            PtP::accum(o, bw, A(-0.5));
+            {  // x: one neighbour is the pair's own input site, the other the next pair's;
+               // the own site also gives the next output's backward-t term
+                A e[24], l[24], v[24], h[12], u[18], ww[12];
+                lds_get<A>(sh, w.wg, lane, e);
+                PtP::project(e, h);
+                link<P, Q, A>(ld, 3, so ^ 1, u);
+                mul_udag(u, h, bw);
+                lds_get<A>(sh, w.wg, par ? lxp : lxm, l);
+#pragma unroll
+                for (int k = 0; k < 24; ++k) v[k] = par ? l[k] : e[k];
+                PxM::project(v, h);
+                link<P, Q, A>(ld, 0, so, u);
+                mul_u(u, h, ww);
+                PxM::accum(o, ww, A(-0.5));
+#pragma unroll
+                for (int k = 0; k < 24; ++k) v[k] = par ? e[k] : l[k];
+                PxP::project(v, h);
+                const int xo = 2 * xh + par;
+                link<P, Q, A>(ld, 0, xo == 0 ? so + Lx - 1 : so - 1, u);
+                mul_udag(u, h, ww);
+                PxP::accum(o, ww, A(-0.5));
+            }
+            // scheduling barriers keep each axis's loads in its own phase: hoisted
+            // together they overflow the register file
+            __builtin_amdgcn_sched_barrier(0);
+            pair_hop<P, Q, 1, PyM, PyP>(ld, ib, inn, gs, sh, w.wg, lane, iy, TY, Ly, ls_y, y, cb, Lxh, so, sy, r,
+                                        w.lognr, o);
+            __builtin_amdgcn_sched_barrier(0);
+            pair_hop<P, Q, 2, PzM, PzP>(ld, ib, inn, gs, sh, w.wg, lane, iz, TZ, Lz, ls_z, z, cb, Lxh * Ly, so, sz,
+                                        r, w.lognr, o);
+            __builtin_amdgcn_sched_barrier(0);
+            {  // t: forward hop from the pair's input site at t + 1 (the next slice's LDS entry)
+                load_sp<P, A>(ib, inn, gs, ((size_t)(wrap ? cb0 : cb + vxyzh) << w.lognr) + r, nxt);
+                A h[12], u[18], ww[12];
+                PtM::project(nxt, h);
+                link<P, Q, A>(ld, 3, so, u);
+                mul_u(u, h, ww);
+                PtM::accum(o, ww, (wrap && ld.tsign < 0) ? A(0.5) : A(-0.5));
+            }
+            if (NBUF == 2) lds_put<A>(shn, w.wg, lane, nxt);
+            A cv[24];
+            if constexpr (MODE != D_HOP) {
+                load_sp<P, A>(cen.v + (size_t)bd.slot_off * G, cen.n ? cen.n + bd.slot_off : nullptr, gs, slot, cv);
+                const A a = (A)diag[sys];
+                const A ia = A(1) / a;
+#pragma unroll
+                for (int k = 0; k < 24; ++k) o[k] = a * cv[k] - ia * o[k];
+            }
+            if constexpr (MODE == D_RESID) {
+                A bv[24];
+                load_sp<P, A>(aux.v + (size_t)bd.slot_off * G, nullptr, gs, slot, bv);
+#pragma unroll
+                for (int k = 0; k < 24; ++k) o[k] = bv[k] - o[k];
+            }
+            store_sp<P, A, true>(ob, on, gs, slot, o);
+            if (act) {
+                if constexpr (MODE == D_RHAT) {
+                    A rh[24];
+                    rhat_site<A>(rk[sys], st[sys].restarts, cb, rh);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) {
+                        acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
+                        acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
+                    }
+                } else if constexpr (MODE == D_TS) {
+                    ts_dots<A>(o, cv, rk[sys], st[sys].restarts, cb, acc);
+                } else if constexpr (MODE == D_RESID) {
+#pragma unroll
+                    for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
+                }
+            }
+        }
+        if (NBUF == 1) {  // one buffer: every read of slice t ends before slice t + 1 is written
+            __syncthreads();
+            if (valid) lds_put<A>(shn, w.wg, lane, nxt);
+        }
+        __syncthreads();
+    }
+    if constexpr (MODE == D_RHAT || MODE == D_TS || MODE == D_RESID) block_partials<ND, 4>(acc, w.nr, part, wg_id);
     });
 }
 
@@ -1098,6 +1332,25 @@ template <int P, int MODE>
 static void launch_eo_q(const Work& w, Fld out, Fld in, Fld cen, Fld aux, const double* diag, const SysState* st,
                         int mask, double* part, hipStream_t s, const NoiseKey* rk, int par_out) {
     const int q = qmode<P>(w);
+    if (w.tc > 0 && w.ilp == 2) {  // x-pair stencil mapping with LDS sharing
+        const size_t need = (size_t)tile_nbuf<P>() * 24 * sizeof(typename Tr<P>::acc) * w.wg;
+        const size_t lds = std::max(need, lds_cap(w.wg, w.occ));
+        switch (q) {
+            case 2:
+                if constexpr (P == P32)
+                    hipLaunchKernelGGL((k_dslash_eo_pair<P, MODE, 2>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out,
+                                       in, cen, aux, diag, st, mask, part, rk, par_out);
+                break;
+            case 1:
+                hipLaunchKernelGGL((k_dslash_eo_pair<P, MODE, 1>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in,
+                                   cen, aux, diag, st, mask, part, rk, par_out);
+                break;
+            default:
+                hipLaunchKernelGGL((k_dslash_eo_pair<P, MODE, 0>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in,
+                                   cen, aux, diag, st, mask, part, rk, par_out);
+        }
+        return;
+    }
     if (w.tc > 0) {  // stencil mapping: t-streaming, with the plan's residency cap
         const size_t lds = lds_cap(w.wg, w.occ);
         switch (q) {

@@ -31,6 +31,8 @@ struct SysState {
     double bnorm2;    // even-odd: |b|^2 of the full system (0 otherwise); the tolerance is relative to it
     int state, iters, upd_p, n_rel;
     int restarts, max_iter;
+    int upd_x;        // the system iterated: the vector update applies to its x and r
+    int pad_;
 };
 
 // One batched launch: a set of blocks of NR systems on possibly different lattices.
@@ -208,7 +210,7 @@ enum Mask : int { M_ALL = 0, M_RUN = 1, M_PEND = 2, M_CONVERT = 3, M_UPDP = 4 };
 enum DMode : int {
     D_PLAIN = 0,   // out = (D + sigma) in
     D_RHAT = 1,    // + partial (rhat, out)             [2 doubles]
-    D_TS = 2,      // + partials (out, in), (out, out)  [3 doubles]
+    D_TS = 2,      // + partials (out, in), (out, out), (in, in), (rhat, in), (rhat, out)  [8 doubles]
     D_RESID = 3,   // out = b - (D + sigma) in (b FP64 in aux) + |out|^2 [1 double]
     D_HOP = 4,     // even-odd only: out = D_{par_out, other} in, the off-diagonal block
     D_PREP = 5,    // even-odd, FP64: out_e = b_e - D_eo b_o / a from b in full layout, + |b|^2
@@ -240,17 +242,15 @@ void launch_dslash(int prec, int mode, const Work& w, Fld out, Fld in, Fld aux, 
 
 // BiCGStab vector kernels (precision of the Krylov fields)
 void launch_axpy_s(int prec, const Work& w, Fld r, Fld v, const SysState* st, hipStream_t s);
-void launch_update_xr(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, const NoiseKey* rk,
-                      const SysState* st, double* part, hipStream_t s);
-// Partial-sum rows per workgroup of w that launch_update_xr writes (the F_RHO
-// finish that follows must be given them in Work::prow).
-int update_xr_rows(int prec, const Work& w);
-void launch_update_p(int prec, const Work& w, Fld p, Fld r, Fld v, const SysState* st, hipStream_t s);
+// x += alpha p + omega s, r = s - omega t for the systems that iterated (s held
+// in r), then p = r + beta (p - omega v) for those that continue
+void launch_update_xrp(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, Fld v, const SysState* st,
+                       hipStream_t s);
 
 // finish kernels: one workgroup per block, reduce partials, update state
-enum FStage : int { F_INIT = 0, F_ALPHA = 1, F_OMEGA = 2, F_RHO = 3, F_TRUE = 4, F_RESUME = 5, F_BNORM = 6 };
+enum FStage : int { F_INIT = 0, F_ALPHA = 1, F_OMEGA = 2, F_TRUE = 4, F_RESUME = 5, F_BNORM = 6 };
 // w.blk_on: flags of the launch being completed (blocks with 0 are skipped);
-// out: flags for the next launch; out2 (F_RHO only): blocks with systems
+// out: flags for the next launch; out2 (F_OMEGA only): blocks with systems
 // pending a reliable update.
 void launch_finish(int stage, const Work& w, SysState* st, const double* part, int* out, int* out2, hipStream_t s);
 

@@ -215,6 +215,7 @@ def test_uneven_full_size_batch_against_oracle(L, eo):
             Us.append(U)
         sp = L.solve_params(0.02, tol=1e-10, storage="f16", batched=1, use_graph=1, max_iter=20000, even_odd=eo)
         prm = L.fs_est_params(1, 2, 0, 2, sp)
+        prm.report_fp64_error = eo  # the a-posteriori bounds of both runs set the comparison below
         batch = L.fs_batch_create(ctxs)
         try:
             print(f"batch estimate even_odd={eo}", flush=True)
@@ -233,10 +234,13 @@ def test_uneven_full_size_batch_against_oracle(L, eo):
             ref = ofs.bilinears(Us[k], d, z, x[0, 0], list(range(16)), 2)
             assert np.abs(X[k, Lv, 0] - ref).max() <= 1e-7 * np.abs(ref).max(), k
             if eo:
+                # two solves to residual 1e-10 each: at sigma_1 = 1e-5 with m0 = 0.02
+                # they differ by more than 1e-7 of mean |X| (1.9e-7 seen at 16^3x32),
+                # within the sum of the two a-posteriori bounds
                 single, Xs, _ = L.fs_estimate(ctxs[k], prm, SIGMA_PAPER, want_samples=True)
-                scale = np.abs(Xs).mean(axis=1)
-                scale = np.where(scale > 0, scale, 1.0)
-                assert (np.abs(X[k] - Xs).max(axis=1) / scale).max() <= 1e-7, k
+                allow = stats[k][..., 7] + single[..., 7]  # [L+1, 16, 3]
+                assert np.all(np.abs(X[k] - Xs) <= allow[:, None]), k
+                assert stats[k][..., 6].max() <= 1e-6 and single[..., 6].max() <= 1e-6
     finally:
         for c in ctxs:
             L.fs_destroy(c)
