@@ -165,21 +165,15 @@ template <> struct NDots<D_TS> { static constexpr int v = 8; };
 template <typename A>
 __device__ __forceinline__ void ts_dots(const A o[24], const A s[24], const NoiseKey& key, int restarts,
                                         long long fsite, double acc[8]) {
-    A rh[24];
-    rhat_site<A>(key, restarts, fsite, rh);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
         const double tr = o[2 * k], ti = o[2 * k + 1], sr = s[2 * k], si = s[2 * k + 1];
-        const double hr = rh[2 * k], hi = rh[2 * k + 1];
         acc[0] += tr * sr + ti * si;
         acc[1] += tr * si - ti * sr;
         acc[2] += tr * tr + ti * ti;
         acc[3] += sr * sr + si * si;
-        acc[4] += hr * sr + hi * si;
-        acc[5] += hr * si - hi * sr;
-        acc[6] += hr * tr + hi * ti;
-        acc[7] += hr * ti - hi * tr;
     }
+    rhat_dots<2, A>(key, restarts, fsite, s, o, acc + 4, acc + 6);
 }
 template <> struct NDots<D_RESID> { static constexpr int v = 1; };
 
@@ -316,13 +310,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
             store_sp<P, A, true>(ob, on, gs, slot, o);
             if (act) {
                 if constexpr (MODE == D_RHAT) {
-                    A rh[24];
-                    rhat_site<A>(rk[sys], st[sys].restarts, site, rh);
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) {
-                        acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
-                        acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
-                    }
+                    rhat_dots<1, A>(rk[sys], st[sys].restarts, site, o, o, acc, acc);
                 } else if constexpr (MODE == D_RESID) {
 #pragma unroll
                     for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
@@ -568,13 +556,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
             store_sp<P, A, true>(ob, on, gs, slot, o);
             if (act) {
                 if constexpr (MODE == D_RHAT) {
-                    A rh[24];
-                    rhat_site<A>(rk[sys], st[sys].restarts, site, rh);
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) {
-                        acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
-                        acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
-                    }
+                    rhat_dots<1, A>(rk[sys], st[sys].restarts, site, o, o, acc, acc);
                 } else if constexpr (MODE == D_RESID) {
 #pragma unroll
                     for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
@@ -703,13 +685,7 @@ __global__ void __launch_bounds__(256) k_dslash_eo(Work w, Fld out, Fld in, Fld 
         store_sp<P, A, true>(ob, on, gs, slot, o);
         if (act) {
             if constexpr (MODE == D_RHAT) {
-                A rh[24];
-                rhat_site<A>(rk[sys], st[sys].restarts, cb, rh);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
-                    acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
-                }
+                rhat_dots<1, A>(rk[sys], st[sys].restarts, cb, o, o, acc, acc);
             } else if constexpr (MODE == D_TS) {
                 ts_dots<A>(o, cv, rk[sys], st[sys].restarts, cb, acc);
             } else if constexpr (MODE == D_RESID) {
@@ -898,13 +874,7 @@ __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fl
             store_sp<P, A, true>(ob, on, gs, slot, o);
             if (act) {
                 if constexpr (MODE == D_RHAT) {
-                    A rh[24];
-                    rhat_site<A>(rk[sys], st[sys].restarts, site >> 1, rh);
-#pragma unroll
-                    for (int j = 0; j < 12; ++j) {
-                        acc[0] += (double)rh[2 * j] * (double)o[2 * j] + (double)rh[2 * j + 1] * (double)o[2 * j + 1];
-                        acc[1] += (double)rh[2 * j] * (double)o[2 * j + 1] - (double)rh[2 * j + 1] * (double)o[2 * j];
-                    }
+                    rhat_dots<1, A>(rk[sys], st[sys].restarts, site >> 1, o, o, acc, acc);
                 } else if constexpr (MODE == D_TS) {
                     ts_dots<A>(o, cv, rk[sys], st[sys].restarts, site >> 1, acc);
                 } else if constexpr (MODE == D_RESID) {
@@ -1130,13 +1100,7 @@ k_dslash_eo_pair(Work w, Fld out, Fld in, Fld cen, Fld aux, const double* __rest
             store_sp<P, A, true>(ob, on, gs, slot, o);
             if (act) {
                 if constexpr (MODE == D_RHAT) {
-                    A rh[24];
-                    rhat_site<A>(rk[sys], st[sys].restarts, cb, rh);
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) {
-                        acc[0] += (double)rh[2 * k] * (double)o[2 * k] + (double)rh[2 * k + 1] * (double)o[2 * k + 1];
-                        acc[1] += (double)rh[2 * k] * (double)o[2 * k + 1] - (double)rh[2 * k + 1] * (double)o[2 * k];
-                    }
+                    rhat_dots<1, A>(rk[sys], st[sys].restarts, cb, o, o, acc, acc);
                 } else if constexpr (MODE == D_TS) {
                     ts_dots<A>(o, cv, rk[sys], st[sys].restarts, cb, acc);
                 } else if constexpr (MODE == D_RESID) {

@@ -187,6 +187,51 @@ __device__ __forceinline__ void rhat_site(const NoiseKey& k0, int restarts, long
 #pragma unroll
     for (int j = 0; j < 24; ++j) v[j] = (A)d[j];
 }
+// sum_j conj(rhat_j) v_j and sum_j conj(rhat_j) w_j over the 12 components of
+// `site` (NW = 1: v only), rhat as rhat_site, without forming rhat: every
+// component is a power of i, so conj(i^k) v is v with its parts swapped and
+// negated (k = 1: (vi, -vr); 2: -v; 3: (-vi, vr)).  The sums equal those of
+// the products with rhat_site's values exactly.  Padding systems add nothing.
+template <int NW, typename A>
+__device__ __forceinline__ void rhat_dots(const NoiseKey& k0, int restarts, long long site, const A v[24],
+                                          const A w[24], double acc_v[2], double acc_w[2]) {
+    if (k0.pad) return;
+    NoiseKey k = k0;
+    if (restarts > 0) {
+        k.instance ^= 0x80000000u;
+        k.level += (uint32_t)restarts;
+    }
+    const long long c0 = site * 12;
+    const long long b0 = c0 >> 7, b1 = (c0 + 11) >> 7;
+    U64x4 o0 = philox4x64_10((uint64_t)b0, k.sample, k.level, k.instance, k.seed, 0ull);
+    U64x4 o1 = o0;
+    if (b1 != b0) o1 = philox4x64_10((uint64_t)b1, k.sample, k.level, k.instance, k.seed, 0ull);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        const long long c = c0 + j;
+        const int e = (int)(c & 127);
+        const bool first = (c >> 7) == b0;
+        const int wi = e >> 5;
+        const uint64_t w01 = wi == 0 ? (first ? o0.v[0] : o1.v[0]) : (first ? o0.v[1] : o1.v[1]);
+        const uint64_t w23 = wi == 2 ? (first ? o0.v[2] : o1.v[2]) : (first ? o0.v[3] : o1.v[3]);
+        const int code = (int)(((wi < 2 ? w01 : w23) >> (2 * (e & 31))) & 3ull);
+        const double sg = (k.g5 && j >= 6) ? -1.0 : 1.0;
+        const bool sw = code & 1;                                   // parts swapped (odd powers)
+        const double s_re = (code == 2 || code == 3) ? -sg : sg;    // sign of the new real part
+        const double s_im = (code == 1 || code == 2) ? -sg : sg;    // sign of the new imaginary part
+        {
+            const double xr = (double)v[2 * j], xi = (double)v[2 * j + 1];
+            acc_v[0] += s_re * (sw ? xi : xr);
+            acc_v[1] += s_im * (sw ? xr : xi);
+        }
+        if constexpr (NW == 2) {
+            const double xr = (double)w[2 * j], xi = (double)w[2 * j + 1];
+            acc_w[0] += s_re * (sw ? xi : xr);
+            acc_w[1] += s_im * (sw ? xr : xi);
+        }
+    }
+}
+
 // Components j0, j0 + 1 of rhat_site (j0 even).
 __device__ __forceinline__ void rhat_pair(const NoiseKey& k0, int restarts, long long site, int j0, float v[4]) {
     if (k0.pad) {
