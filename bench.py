@@ -12,10 +12,14 @@ on the batched mixed-precision path (FP32 storage, FP32 stencil arithmetic,
 FP64 reliable updates and FP64 reductions; RHS blocks sharing link loads;
 hipGraph-captured iterations; autotuned RHS block and work-group size).
 `value` is shifted solves per second over the timed steps.  Also reported:
-the plain FP64 single-RHS path on a subset of the same systems and noise, the
-per-level deviation of the mixed path from it, the dslash roofline of the
-batched kernel timed live with HIP events, a single-RHS dslash at 32^3 x 64
-(working set far above the 256 MB last-level cache) and the CPU oracle.
+the plain FP64 single-RHS path on a subset of the same systems and noise
+(warmed up, median of 3 runs), the per-level deviation of the mixed path from
+it with the library's a-posteriori error bounds, the dslash roofline of the
+batched kernel (median of 100 launches timed with HIP events), the uneven
+half-precision batch (8^3x16, 12^3x24, 16^3x32, 24^3x48, the paper's six
+shifts, 24 Z4 vectors each) against the FP64 plain path, a 32^3 x 64 solve rate
+and single-RHS dslash (working set far above the 256 MB last-level cache), and
+the CPU oracle.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -40,6 +44,10 @@ ROOFLINE_NSYS = 96
 
 WORKLOAD = dict(dims=(16, 16, 16, 32), eps=0.2, m0=0.02, sigma=[0.0, 0.05, 0.25, 0.5, 1.0], n_noise=48,
                 p_max=8, seed=1, gauge_seed=0, tol=1e-10)
+# the uneven half-precision batch: four lattices, the six shifts the paper
+# selects (Results, comparison to multigrid deflation), 24 Z4 vectors each
+UNEVEN = dict(shapes=[(8, 8, 8, 16), (12, 12, 12, 24), (16, 16, 16, 32), (24, 24, 24, 48)], eps=0.2, m0=0.02,
+              sigma=[0.0, 1e-5, 0.053, 0.146, 0.360, 0.618, 1.0], n_noise=24, p_max=4, fp64_noise=2)
 
 
 def log(*a):
@@ -92,7 +100,9 @@ def cpu_baseline(U, dims, avg_iters, sel_inputs=None):
     out = {"value": 1.0 / (per_iter * avg_iters), "unit": "shifted solves/s", "cores": 1, "kind": "oracle",
            "sample": f"{n_it} oracle BiCGStab iterations (numpy FP64, 1 thread) on the 16^3x32 lattice at "
                      f"sigma={sigma}, {dt:.1f} s; solves/s = 1/(s per iteration x {avg_iters:.1f} mean "
-                     f"iterations per system of the unpreconditioned GPU solver)"}
+                     f"iterations per system of the unpreconditioned GPU solver); the other keys: the oracle on "
+                     f"the small workloads (one thread)"}
+    out.update(cpu_oracle_items())
     if sel_inputs is not None:
         from oracle import shifts as osh
         s_hat, vs, vp, iters, grid = sel_inputs
@@ -103,6 +113,62 @@ def cpu_baseline(U, dims, avg_iters, sel_inputs=None):
             osh.select_dp(6, *tabs)
             out["shift_selection_seconds_one_pair"] = round(time.perf_counter() - t0, 3)
     return out
+
+
+def cpu_oracle_items():
+    """The oracle's own throughput on the small configurations (one thread):
+    matrix-free FP64 dslash GB/s (960 algorithmic bytes per site), FP64
+    BiCGStab solves/s to 1e-10 on the 4^4, 4x4x8x4 and 8^3x16 workloads, dense
+    LU times for N = 3072 and 6144, and the host's CPU model and core count."""
+    import platform
+
+    import scipy.linalg as sla
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import lattice as lat
+    from oracle.philox import z4_noise
+    from oracle.solver import bicgstab
+    model = platform.processor()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    items = {"host_cpu": model, "host_nproc": os.cpu_count(),
+             "host_affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+    with threadpool_limits(1):
+        dims = WORKLOAD["dims"]
+        U = synth.gauge_field(dims, eps=WORKLOAD["eps"], seed=0)
+        psi = synth.random_spinor(dims, seed=3)
+        t0 = time.perf_counter()
+        lat.wilson_apply(U, psi, WORKLOAD["m0"], 0.0, dims)
+        dt = time.perf_counter() - t0
+        items["dslash_16c32_GBs"] = round(960 * lat.volume(dims) / dt / 1e9, 4)
+        del U, psi
+        solves = {}
+        for name, d, eps, m0, sg in (("cfg1_4^4", (4, 4, 4, 4), 0.3, 0.1, 0.5),
+                                     ("cfg2mini_4x4x8x4", (4, 4, 8, 4), 0.25, 0.05, 0.1),
+                                     ("cfg2_8^3x16", (8, 8, 8, 16), 0.25, 0.05, 0.1)):
+            Ud = synth.gauge_field(d, eps=eps, seed=0)
+            b = z4_noise(lat.volume(d), 1, 0, 0, 0)
+            t0 = time.perf_counter()
+            _, info = bicgstab(lambda v: lat.wilson_apply(Ud, v, m0, sg, d), b, tol=1e-10)
+            dt = time.perf_counter() - t0
+            solves[name] = {"solves_per_s": round(1.0 / dt, 4), "sigma": sg, "iters": info["iters"]}
+        items["bicgstab_1e-10"] = solves
+        lu = {}
+        for d in ((4, 4, 4, 4), (4, 4, 8, 4)):
+            Ud = synth.gauge_field(d, eps=0.3, seed=0)
+            D = lat.wilson_dense(Ud, 0.1, 0.0, d)
+            t0 = time.perf_counter()
+            sla.lu_factor(D)
+            lu[f"N={D.shape[0]}"] = round(time.perf_counter() - t0, 3)
+            del D
+        items["dense_lu_seconds"] = lu
+    return items
 
 
 def kernel_source_hash():
@@ -150,8 +216,9 @@ def link_form(L, ctx):
 def roofline_only(L, ctx, nr, wg):
     """The launches the roofline reports, alone (for hardware-counter runs)."""
     ms_c = L.fs_time_copy(ctx, 1 << 30, 20)
-    ms_d, by = L.fs_time_dslash_eo(ctx, "f32", ROOFLINE_NSYS, nr, 50)
-    print(json.dumps({"copy_bytes": 1 << 30, "copy_ms": ms_c, "dslash_ms": ms_d, "dslash_bytes": by,
+    each, by = L.fs_time_dslash_eo_each(ctx, "f32", ROOFLINE_NSYS, nr, 100)
+    print(json.dumps({"copy_bytes": 1 << 30, "copy_ms": ms_c, "dslash_ms": float(np.median(each)),
+                      "dslash_bytes": by,
                       "config": f"f32-eo,nsys={ROOFLINE_NSYS},nr={nr},wg=256,links={link_form(L, ctx)}",
                       "hash": kernel_source_hash()}))
 
@@ -213,12 +280,81 @@ def sampling_and_selection(L, ctx, nr):
     return out, (s_hat, single[:, 11, 4, 2].copy(), pair[:, :, 11, 4, 2].copy(), iters, grid)
 
 
+def big_lattice_estimate(L, ch):
+    """FS estimate on the 32^3x64 lattice: the workload's five shifts, 4 Z4
+    vectors per level (36 shifted systems), FP32 storage, even-odd, batched."""
+    L.fs_estimate(ch, est_params(L, "f32", 1, 1, eo=1), WORKLOAD["sigma"])  # warm-up
+    t0 = time.perf_counter()
+    _, _, rep = L.fs_estimate(ch, est_params(L, "f32", 1, 4, eo=1), WORKLOAD["sigma"])
+    dt = time.perf_counter() - t0
+    log(f"32^3x64 estimate: {rep.systems} systems in {dt:.2f} s")
+    return {"systems": int(rep.systems), "seconds": round(dt, 3), "solves_per_s": round(rep.systems / dt, 3),
+            "iters_per_system": round(rep.iterations / rep.systems, 2), "max_true_rel_residual": rep.max_rel_residual}
+
+
+def uneven_batch(L, args):
+    """The uneven half-precision batch in shared launches (FP16 storage, FP64
+    reliable updates, even-odd, graph), timed after a warm-up; and the plain
+    FP64 single-RHS path on a subset of the same systems (the first
+    fp64_noise vectors of every level and instance), with the per-level
+    deviation of the half-precision samples from it."""
+    import synth
+    u = UNEVEN
+    ctxs = []
+    try:
+        for k, d in enumerate(u["shapes"]):
+            c = L.fs_create(d, 0, 0)
+            L.fs_set_instance(c, k)
+            L.fs_upload_gauge(c, synth.gauge_field(d, eps=u["eps"], seed=k))
+            ctxs.append(c)
+        batch = L.fs_batch_create(ctxs)
+        n_inst, L_lev = len(ctxs), len(u["sigma"]) - 1
+
+        def prm(storage, batched, n):
+            sp = L.solve_params(u["m0"], tol=1e-10, storage=storage, batched=batched, use_graph=batched,
+                                max_iter=20000, even_odd=1)
+            return L.fs_est_params(1, n, 0, u["p_max"], sp)
+
+        L.fs_batch_estimate(batch, n_inst, prm("f16", 1, 2), u["sigma"])  # warm-up
+        t0 = time.perf_counter()
+        st16, X16, rep = L.fs_batch_estimate(batch, n_inst, prm("f16", 1, u["n_noise"]), u["sigma"],
+                                             want_samples=True)
+        dt = time.perf_counter() - t0
+        log(f"uneven FP16 batch: {rep.systems} systems in {dt:.2f} s")
+        n64 = u["fp64_noise"]
+        L.fs_batch_estimate(batch, n_inst, prm("f64", 0, 1), u["sigma"])  # warm-up
+        t1 = time.perf_counter()
+        _, X64, rep64 = L.fs_batch_estimate(batch, n_inst, prm("f64", 0, n64), u["sigma"], want_samples=True)
+        dt64 = time.perf_counter() - t1
+        log(f"uneven FP64 plain subset: {rep64.systems} systems in {dt64:.2f} s")
+        L.fs_batch_destroy(batch)
+    finally:
+        for c in ctxs:
+            L.fs_destroy(c)
+    sub = X16[:, :, :n64]
+    scale = np.abs(X64).mean(axis=2)
+    scale = np.where(scale > 0, scale, 1.0)
+    dev = (np.abs(sub - X64).max(axis=2) / scale)  # [inst, L+1, 16, P1]
+    rate, rate64 = rep.systems / dt, rep64.systems / dt64
+    return {"workload": "8^3x16 + 12^3x24 + 16^3x32 + 24^3x48, eps=0.2, m0=0.02, shifts "
+                        "{0,1e-5,.053,.146,.360,.618,1}, 24 Z4/level each, 16 Gamma, p=0..4, FP16 storage + FP64 "
+                        "reliable updates, batched in shared launches, even-odd",
+            "systems": int(rep.systems), "seconds": round(dt, 3), "solves_per_s": round(rate, 3),
+            "iters_per_system": round(rep.iterations / rep.systems, 2),
+            "reliable_updates_per_system": round(rep.reliable_updates / rep.systems, 2),
+            "max_true_rel_residual": rep.max_rel_residual,
+            "fp64_plain_systems": int(rep64.systems), "fp64_plain_solves_per_s": round(rate64, 3),
+            "speedup_vs_fp64_plain": round(rate / rate64, 3),
+            "level_rel_dev_vs_fp64": [float(f"{e:.3e}") for e in dev.max(axis=(0, 2, 3))]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--fp64-noise", type=int, default=4, help="noise vectors per level for the FP64 plain path")
+    ap.add_argument("--fp64-noise", type=int, default=8, help="noise vectors per level for the FP64 plain path")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven half-precision batch")
     ap.add_argument("--no-headline", action="store_true", help="skip the 32^3x64 dslash measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-half", action="store_true", help="skip the FP16/BF16 mixed-path steps")
@@ -276,20 +412,33 @@ def main():
     max_res = max(r.max_rel_residual for r in reps)
 
     # ---- plain FP64 single-RHS path on a subset of the same systems and noise
-    # (even-odd preconditioned, like the batched path)
+    # (even-odd preconditioned, like the batched path): one untimed warm-up on
+    # the same shapes, then the median of three timed runs
     n64 = args.fp64_noise
     L.fs_autotune(ctx, "f64", 1, cache)  # the plain path's own best single-system stencil
     prm64 = est_params(L, "f64", 0, n64, graph=0, eo=1)
-    t1 = time.perf_counter()
-    stats_a, X_a, rep_a = L.fs_estimate(ctx, prm64, w["sigma"], want_samples=True)
-    dt_a = time.perf_counter() - t1
+    L.fs_estimate(ctx, est_params(L, "f64", 0, 1, graph=0, eo=1), w["sigma"])
+    runs64 = []
+    for _ in range(3):
+        t1 = time.perf_counter()
+        stats_a, X_a, rep_a = L.fs_estimate(ctx, prm64, w["sigma"], want_samples=True)
+        runs64.append(time.perf_counter() - t1)
+    dt_a = float(np.median(runs64))
     fp64_rate = rep_a.systems / dt_a
-    log(f"fp64 plain: {rep_a.systems} systems in {dt_a:.2f} s ({rep_a.iterations / rep_a.systems:.1f} iters/system)")
+    log(f"fp64 plain: {rep_a.systems} systems in {dt_a:.2f} s (median of {runs64}), "
+        f"{rep_a.iterations / rep_a.systems:.1f} iters/system")
+    # the mixed path on the same subset, with the library's FP64-deviation and error-bound report
     prm_b_sub = est_params(L, "f32", 1, n64, nr=nr, eo=1)
-    _, X_b, _ = L.fs_estimate(ctx, prm_b_sub, w["sigma"], want_samples=True)
+    prm_b_sub.report_fp64_error = 1
+    stats_bs, X_b, _ = L.fs_estimate(ctx, prm_b_sub, w["sigma"], want_samples=True)
     scale = np.abs(X_a).mean(axis=1)
     scale = np.where(scale > 0, scale, 1.0)
     lvl_err = (np.abs(X_b - X_a).max(axis=1) / scale).reshape(L_lev + 1, -1).max(axis=1)
+    per_level = [{"level": l, "sigma": [w["sigma"][l], w["sigma"][min(l + 1, L_lev)]],
+                  "dev_vs_fp64_plain_max_rel": float(f"{lvl_err[l]:.3e}"),
+                  "fp64_rel_err_reported_max": float(f"{stats_bs[l, ..., 6].max():.3e}"),
+                  "err_bound_rel_max": float(f"{(stats_bs[l, ..., 7] / scale[l]).max():.3e}")}
+                 for l in range(L_lev + 1)]
 
     # ---- the same two paths without even-odd preconditioning (context)
     t3 = time.perf_counter()
@@ -320,8 +469,10 @@ def main():
                           "max_true_rel_residual": rep_h.max_rel_residual, "rhs_block": 4}
             log(f"mixed {prec}: {systems_per_step / dt_h:.1f} solves/s")
 
-    # ---- dslash roofline: the batched FP32 even-odd hop of the solver, live HIP events
-    ms_d, bytes_d = L.fs_time_dslash_eo(ctx, "f32", ROOFLINE_NSYS, nr, 50)
+    # ---- dslash roofline: the batched FP32 even-odd hop of the solver, live HIP
+    # events around each of 100 launches (median)
+    each_d, bytes_d = L.fs_time_dslash_eo_each(ctx, "f32", ROOFLINE_NSYS, nr, 100)
+    ms_d = float(np.median(each_d))
     ms_c = L.fs_time_copy(ctx, 1 << 30, 20)
     achieved = bytes_d / (ms_d * 1e-3) / 1e9
     links = link_form(L, ctx)
@@ -333,10 +484,12 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / (ms_d * 1e-3) / 1e9, 1),
                 "traffic_bytes_per_launch": traffic,
-                "kernel": f"k_dslash_eo_t<P32> D_HOP (one parity out), {ROOFLINE_NSYS} systems, rhs_block {nr}, "
-                          f"wg 256, the solver's residency cap, "
+                "kernel": f"k_dslash_eo_pair<P32> D_HOP (one parity out, x-pairs sharing input spinors through "
+                          f"LDS), {ROOFLINE_NSYS} systems, rhs_block {nr}, wg 256, "
                           + ("links as rows 0-1 with row 2 rebuilt (12 reals)" if links == "2row"
                              else "whole links (18 reals)"),
+                "timing": "median of 100 launches, HIP events around each on the library's stream",
+                "mean_launch_ms": round(float(np.mean(each_d)), 5),
                 "full_lattice_dslash": {"kernel": f"k_dslash<P32> D_PLAIN, rhs_block {nr}, wg {wg}",
                                         "avg_launch_ms": round(ms_full, 5), "achieved": round(full_gbs, 1),
                                         "frac": round(full_gbs / HBM_PEAK_GBS, 4)},
@@ -345,6 +498,7 @@ def main():
     log(f"dslash f32 batched even-odd hop: {ms_d:.4f} ms, {achieved:.0f} GB/s; full lattice {ms_full:.4f} ms, "
         f"{full_gbs:.0f} GB/s")
     select, sel_inputs = (None, None) if args.no_select else sampling_and_selection(L, ctx, nr)
+    uneven = None if args.no_uneven else uneven_batch(L, args)
     probed = None if args.no_probe else probed_estimate(L, ctx, nr, dims)
     L.fs_destroy(ctx)
 
@@ -371,6 +525,7 @@ def main():
             headline[prec] = {"ms": round(ms, 4), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                               "bytes": by, "wg": wgs}
             log(f"dslash 32^3x64 {prec}: {ms:.4f} ms {gbs:.0f} GB/s")
+        headline["estimate_fp32_eo"] = big_lattice_estimate(L, ch)
         L.fs_destroy(ch)
 
     # the oracle's BiCGStab works on the unpreconditioned operator: scale its
@@ -404,6 +559,9 @@ def main():
         "fp64_plain_iters_per_system": round(rep_a.iterations / rep_a.systems, 2),
         "max_true_rel_residual": max_res,
         "level_rel_dev_vs_fp64": [float(f"{e:.3e}") for e in lvl_err],
+        "fp64_plain_timing": f"median of 3 runs after a warm-up: {[round(t, 3) for t in runs64]} s",
+        "per_level": per_level,
+        "uneven_half_precision_batch": uneven,
         "dslash_32c64_single_rhs": headline,
         "mixed_half_precision": half or None,
         "sampling_and_shift_selection": select,
