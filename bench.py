@@ -213,13 +213,14 @@ def link_form(L, ctx):
     return "2row" if L.fs_gauge_info(ctx)[0] else "whole"
 
 
-def roofline_only(L, ctx, nr, wg):
-    """The launches the roofline reports, alone (for hardware-counter runs)."""
+def roofline_only(L, ctx, nr, wg, storage="f32"):
+    """The launches the roofline reports, alone (for hardware-counter runs);
+    another storage times the same hop in that precision."""
     ms_c = L.fs_time_copy(ctx, 1 << 30, 20)
-    each, by = L.fs_time_dslash_eo_each(ctx, "f32", ROOFLINE_NSYS, nr, 100)
+    each, by = L.fs_time_dslash_eo_each(ctx, storage, ROOFLINE_NSYS, nr, 100)
     print(json.dumps({"copy_bytes": 1 << 30, "copy_ms": ms_c, "dslash_ms": float(np.median(each)),
                       "dslash_bytes": by,
-                      "config": f"f32-eo,nsys={ROOFLINE_NSYS},nr={nr},wg=256,links={link_form(L, ctx)}",
+                      "config": f"{storage}-eo,nsys={ROOFLINE_NSYS},nr={nr},wg=256,links={link_form(L, ctx)}",
                       "hash": kernel_source_hash()}))
 
 
@@ -359,6 +360,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-half", action="store_true", help="skip the FP16/BF16 mixed-path steps")
     ap.add_argument("--roofline-only", action="store_true", help="only the copy and stencil launches of the roofline")
+    ap.add_argument("--roofline-storage", default="f32", choices=["f64", "f32", "f16", "bf16"],
+                    help="precision of the stencil timed by --roofline-only")
     ap.add_argument("--no-select", action="store_true", help="skip variance sampling and shift selection")
     ap.add_argument("--no-probe", action="store_true", help="skip the probed, spin-colour diluted estimate")
     ap.add_argument("--tuning-cache", default=None, help="autotune cache file (default: a temporary copy of the "
@@ -386,7 +389,9 @@ def main():
     nr, wg = L.fs_autotune(ctx, "f32", systems_per_step, cache)
     log(f"tuning f32: rhs_block={nr} wg={wg}")
     if args.roofline_only:
-        roofline_only(L, ctx, nr, wg)
+        if args.roofline_storage != "f32":
+            nr, wg = L.fs_autotune(ctx, args.roofline_storage, systems_per_step, cache)
+        roofline_only(L, ctx, nr, wg, args.roofline_storage)
         return
 
     # ---- batched mixed path, even-odd preconditioned: warmup + timed steps

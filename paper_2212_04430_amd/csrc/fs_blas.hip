@@ -797,8 +797,10 @@ __global__ void __launch_bounds__(256) k_hop_reduce(Work w, int p, Fld phi_out, 
                     for (int j = 0; j < 3; ++j) {
                         const double ur = u[2 * (3 * i + j)], ui = u[2 * (3 * i + j) + 1];
                         const double hr = v[2 * (3 * s + j)], hi = v[2 * (3 * s + j) + 1];
-                        re += ur * hr - ui * hi;
-                        im += ur * hi + ui * hr;
+                        re = fma_(ur, hr, re);
+                        re = fma_(-ui, hi, re);
+                        im = fma_(ur, hi, im);
+                        im = fma_(ui, hr, im);
                     }
                     f[2 * (3 * s + i)] = re;
                     f[2 * (3 * s + i) + 1] = im;
@@ -811,16 +813,18 @@ __global__ void __launch_bounds__(256) k_hop_reduce(Work w, int p, Fld phi_out, 
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int bb = 0; bb < 4; ++bb) {
-                double re = 0.0, im = 0.0;
+                double re = acc[2 * (4 * a + bb)], im = acc[2 * (4 * a + bb) + 1];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const double yr = y[2 * (3 * a + c)], yi = y[2 * (3 * a + c) + 1];
                     const double fr = f[2 * (3 * bb + c)], fi = f[2 * (3 * bb + c) + 1];
-                    re += yr * fr + yi * fi;
-                    im += yr * fi - yi * fr;
+                    re = fma_(yr, fr, re);
+                    re = fma_(yi, fi, re);
+                    im = fma_(yr, fi, im);
+                    im = fma_(-yi, fr, im);
                 }
-                acc[2 * (4 * a + bb)] += re;
-                acc[2 * (4 * a + bb) + 1] += im;
+                acc[2 * (4 * a + bb)] = re;
+                acc[2 * (4 * a + bb) + 1] = im;
             }
     FS_SLOT_LOOP_END
     block_partials<32, 4>(acc, w.nr, part, wg_id);

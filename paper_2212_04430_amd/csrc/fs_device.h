@@ -112,6 +112,11 @@ constexpr int kBufFlags = 0x00020000;  // raw 32-bit data format (gfx9 family)
 // construction, so they are moved to scalar registers explicitly.
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// a * b + c with one rounding (an explicit multiply-add, so a chain of them
+// is not split into products and separate additions)
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
     const uint64_t p = reinterpret_cast<uint64_t>(base);
     const uint64_t q = ((uint64_t)uni((uint32_t)(p >> 32)) << 32) | uni((uint32_t)p);
@@ -316,10 +321,18 @@ __device__ __forceinline__ void su3_third_row(A u[18]) {
         const int k = (j + 1) % 3, l = (j + 2) % 3;
         const A akr = u[2 * k], aki = u[2 * k + 1], alr = u[2 * l], ali = u[2 * l + 1];
         const A bkr = u[6 + 2 * k], bki = u[7 + 2 * k], blr = u[6 + 2 * l], bli = u[7 + 2 * l];
-        const A re = (akr * blr - aki * bli) - (alr * bkr - ali * bki);
-        const A im = (akr * bli + aki * blr) - (alr * bki + ali * bkr);
+        // re = akr blr - aki bli - alr bkr + ali bki, -im = -(akr bli + aki blr - alr bki - ali bkr),
+        // each one multiply-add chain
+        A re = akr * blr;
+        re = fma_(-aki, bli, re);
+        re = fma_(-alr, bkr, re);
+        re = fma_(ali, bki, re);
+        A nim = -akr * bli;
+        nim = fma_(-aki, blr, nim);
+        nim = fma_(alr, bki, nim);
+        nim = fma_(ali, bkr, nim);
         u[12 + 2 * j] = re;
-        u[13 + 2 * j] = -im;
+        u[13 + 2 * j] = nim;
     }
 }
 

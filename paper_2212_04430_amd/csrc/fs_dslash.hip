@@ -75,38 +75,51 @@ using PzP = Proj<2, 1, 3, 3, 0, 3, 1, 1>;  // 1 + g3
 using PtM = Proj<2, 2, 3, 2, 0, 2, 1, 2>;  // 1 - g4
 using PtP = Proj<2, 0, 3, 0, 0, 0, 1, 0>;  // 1 + g4
 
+// Complex 3x3 matrix times the two colour vectors of a half spinor, as chains
+// of fused multiply-adds: 4 operations per complex product, the first of each
+// sum a plain product.  (Written as re += ur*hr - ui*hi the compiler keeps the
+// difference as its own rounding step and spends 6.)
 template <typename A>
 __device__ __forceinline__ void mul_u(const A u[18], const A h[12], A w[12]) {
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            A re = 0, im = 0;
+            const A* hs = h + 6 * s;
+            const A* ur = u + 6 * i;  // row i
+            A re = ur[0] * hs[0], im = ur[0] * hs[1];
+            re = fma_(-ur[1], hs[1], re);
+            im = fma_(ur[1], hs[0], im);
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                A ur = u[2 * (3 * i + j)], ui = u[2 * (3 * i + j) + 1];
-                A hr = h[6 * s + 2 * j], hi = h[6 * s + 2 * j + 1];
-                re += ur * hr - ui * hi;
-                im += ur * hi + ui * hr;
+            for (int j = 1; j < 3; ++j) {
+                re = fma_(ur[2 * j], hs[2 * j], re);
+                re = fma_(-ur[2 * j + 1], hs[2 * j + 1], re);
+                im = fma_(ur[2 * j], hs[2 * j + 1], im);
+                im = fma_(ur[2 * j + 1], hs[2 * j], im);
             }
             w[6 * s + 2 * i] = re;
             w[6 * s + 2 * i + 1] = im;
         }
 }
 
+// The same with the Hermitian conjugate U^dagger (column i of U, conjugated).
 template <typename A>
 __device__ __forceinline__ void mul_udag(const A u[18], const A h[12], A w[12]) {
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            A re = 0, im = 0;
+            const A* hs = h + 6 * s;
+            A re = u[2 * i] * hs[0], im = u[2 * i] * hs[1];
+            re = fma_(u[2 * i + 1], hs[1], re);
+            im = fma_(-u[2 * i + 1], hs[0], im);
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                A ur = u[2 * (3 * j + i)], ui = -u[2 * (3 * j + i) + 1];
-                A hr = h[6 * s + 2 * j], hi = h[6 * s + 2 * j + 1];
-                re += ur * hr - ui * hi;
-                im += ur * hi + ui * hr;
+            for (int j = 1; j < 3; ++j) {
+                const A cr = u[2 * (3 * j + i)], ci = u[2 * (3 * j + i) + 1];
+                re = fma_(cr, hs[2 * j], re);
+                re = fma_(ci, hs[2 * j + 1], re);
+                im = fma_(cr, hs[2 * j + 1], im);
+                im = fma_(-ci, hs[2 * j], im);
             }
             w[6 * s + 2 * i] = re;
             w[6 * s + 2 * i + 1] = im;
