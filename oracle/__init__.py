@@ -13,6 +13,10 @@ Multilevel Monte Carlo for Disconnected Diagrams in Lattice QCD"):
 * `lattice`  -- site indexing, gamma matrices, Gamma_n, the Wilson-Dirac
                 operator (matrix-free and dense), Omega_p = W Pi_p
                 (Introduction: the target Tr(Gamma Omega_p D^-1)).
+* `clover`   -- the clover (Sheikholeslami-Wohlert) term of the improved
+                Wilson operator named in the Results section: field strength
+                from the four plaquette leaves, sigma_{mu nu} F_{mu nu} per site
+                (a reading of conventions the paper does not print).
 * `philox`   -- Philox4x64-10 counter RNG and the Z4 noise drawn from it
                 (Introduction, eq. test: entries from {1,-1,i,-i}).
 * `solver`   -- BiCGStab (van der Vorst 1992) for (D + sigma I) x = b

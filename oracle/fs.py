@@ -31,7 +31,7 @@ stochastic estimates by unbiasedness against the exact values.
 import numpy as np
 import scipy.linalg as sla
 
-from . import lattice as lat
+from . import clover, lattice as lat
 from .philox import z4_noise
 from .solver import bicgstab
 
@@ -41,11 +41,15 @@ from .solver import bicgstab
 # ---------------------------------------------------------------------------
 
 class DenseSolver:
-    """(D + sigma)^-1 via one LU factorisation per shift (scipy)."""
+    """(D + sigma)^-1 via one LU factorisation per shift (scipy); with c_sw != 0
+    D is the clover-improved operator of oracle.clover."""
 
-    def __init__(self, U, dims, m0, antiperiodic=False):
-        self.U, self.dims, self.m0, self.ap = U, dims, m0, antiperiodic
-        self.D0 = lat.wilson_dense(U, m0, 0.0, dims, antiperiodic)
+    def __init__(self, U, dims, m0, antiperiodic=False, c_sw=0.0):
+        self.U, self.dims, self.m0, self.ap, self.c_sw = U, dims, m0, antiperiodic, c_sw
+        if c_sw == 0.0:
+            self.D0 = lat.wilson_dense(U, m0, 0.0, dims, antiperiodic)
+        else:
+            self.D0 = clover.clover_dense(U, m0, 0.0, c_sw, dims, antiperiodic)
         self._lu = {}
 
     def _factor(self, sigma):
@@ -66,12 +70,15 @@ class DenseSolver:
 class IterativeSolver:
     """(D + sigma)^-1 b via the oracle BiCGStab on the matrix-free operator."""
 
-    def __init__(self, U, dims, m0, antiperiodic=False, tol=1e-13):
-        self.U, self.dims, self.m0, self.ap, self.tol = U, dims, m0, antiperiodic, tol
+    def __init__(self, U, dims, m0, antiperiodic=False, tol=1e-13, c_sw=0.0):
+        self.U, self.dims, self.m0, self.ap, self.tol, self.c_sw = U, dims, m0, antiperiodic, tol, c_sw
+        self.C = clover.clover_term(U, dims, c_sw) if c_sw != 0.0 else None
         self.last_info = None
 
     def solve(self, sigma, b):
         def A(v):
+            if self.C is not None:
+                return clover.clover_apply(self.U, v, self.m0, sigma, self.c_sw, self.dims, self.ap, C=self.C)
             return lat.wilson_apply(self.U, v, self.m0, sigma, self.dims, self.ap)
         x, info = bicgstab(A, b, tol=self.tol)
         self.last_info = info
