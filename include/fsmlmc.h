@@ -101,6 +101,28 @@ fs_status fs_set_instance(fs_ctx ctx, uint32_t instance);
 fs_status fs_upload_gauge(fs_ctx ctx, const double* links, int32_t is_device);
 
 /*
+ * fs_set_clover -- use the clover-improved Wilson operator D + C (the
+ * operator of the paper's Results section) in every later call on ctx:
+ *   C(x) = -(c_sw / 2) sum_{mu<nu} sigma_{mu nu} F_{mu nu}(x),
+ *   sigma_{mu nu} = (i/2) [g_mu, g_nu] (DeGrand-Rossi basis),
+ *   F_{mu nu}(x)  = traceless part of (Q - Q^dagger) / (8 i), Q the sum of the
+ *                   four plaquettes of the (mu, nu) plane at x, each taken
+ *                   counter-clockwise.
+ * With the forward hop carrying (1 - g_mu) this sign makes c_sw = 1 the
+ * tree-level improvement coefficient.  The term is built on the device from the
+ * uploaded links (and rebuilt by fs_upload_gauge); c_sw = 0 returns to the
+ * plain operator.  Requires even extents.  With a nonzero c_sw, stencils run in
+ * FP64 or FP32 storage only and solves need even_odd = 1 (the Schur complement
+ * (C_e + a) - D_eo (C_o + a)^-1 D_oe, a = 4 + m0 + sigma, with the inverses
+ * formed once per shift in FP64); other settings return FS_E_ARG, and so does
+ * a shift at which C_o + a is singular.  The s_min bound behind err_bound then
+ * also subtracts max ||C(x)|| (largest absolute row sum of its blocks).
+ * Errors: FS_E_STATE before fs_upload_gauge, FS_E_ARG for a non-finite c_sw or
+ * odd extents.
+ */
+fs_status fs_set_clover(fs_ctx ctx, double c_sw);
+
+/*
  * fs_gauge_info -- how the uploaded links are stored.
  *   two_rows    1: FP32 stencils rebuild row 2 of each link from rows 0-1
  *               (the links are special unitary to 1e-9); 0: whole links.
@@ -110,7 +132,8 @@ fs_status fs_upload_gauge(fs_ctx ctx, const double* links, int32_t is_device);
 fs_status fs_gauge_info(fs_ctx ctx, int32_t* two_rows, double* su3_defect);
 
 /*
- * fs_apply_dirac -- out = (D + sigma) in for n_rhs spinors (canonical layout).
+ * fs_apply_dirac -- out = (D + sigma) in for n_rhs spinors (canonical layout);
+ * D includes the clover term when fs_set_clover set one.
  * storage: precision the spinors and links are held in while the stencil runs
  * (inputs are rounded to it; FP64 accumulates in FP64, the others in FP32).
  * Used for parity tests and the bandwidth benchmark.

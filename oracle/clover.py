@@ -136,3 +136,17 @@ def chiral_blocks(C):
     if off > 1e-13 * max(1.0, np.abs(C).max()):
         raise ValueError("clover term mixes chiralities")
     return np.stack([C[:, :6, :6], C[:, 6:, 6:]], axis=1)
+
+
+def norm_bound(C):
+    """Upper bound on max_x ||C(x)||_2: the largest absolute row sum of the site
+    matrices (for a Hermitian matrix the spectral norm is at most any induced norm)."""
+    return float(np.abs(np.asarray(C)).sum(axis=-1).max())
+
+
+def smin_lower_bound(U, m0, sigma, c_sw, dims):
+    """Lower bound on the smallest singular value of D_sw + sigma:
+    D_sw + sigma = (4 + m0 + sigma) + C - H with ||H|| <= 4 u (lattice.smin_lower_bound)
+    and ||C|| <= norm_bound(C), so s_min >= 4 + m0 + sigma - 4 u - norm_bound(C)
+    (Weyl's inequality).  Parity: pinned against dense SVD (tests)."""
+    return lat.smin_lower_bound(U, m0, sigma) - norm_bound(clover_term(U, dims, c_sw))

@@ -105,6 +105,7 @@ _sig = {
     "fs_set_instance": (C.c_int, [_P, C.c_uint32]),
     "fs_upload_gauge": (C.c_int, [_P, _P, C.c_int32]),
     "fs_gauge_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "fs_set_clover": (C.c_int, [_P, C.c_double]),
     "fs_apply_dirac": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, _P, _P, C.c_int32, C.c_int32]),
     "fs_apply_dirac_noalloc": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, _P, _P, C.c_int32]),
     "fs_z4_noise": (C.c_int, [_P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, _P, C.c_int32]),
@@ -222,6 +223,11 @@ def fs_upload_gauge(ctx, links):
         links = _host_c128(links)
     p, dev = _ptr(links)
     _check(_lib.fs_upload_gauge(ctx, p, dev))
+
+
+def fs_set_clover(ctx, c_sw):
+    """Use the clover-improved operator with coefficient c_sw (0: plain Wilson)."""
+    _check(_lib.fs_set_clover(ctx, float(c_sw)))
 
 
 def fs_gauge_info(ctx):

@@ -13,7 +13,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfsmlmc.so")
-SOURCES = ["fs_dslash.hip", "fs_blas.hip", "fs_shift.hip", "fs_probe.hip", "fs_api.hip"]
+SOURCES = ["fs_dslash.hip", "fs_clover.hip", "fs_blas.hip", "fs_shift.hip", "fs_probe.hip", "fs_api.hip"]
 ARCH = os.environ.get("FSMLMC_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

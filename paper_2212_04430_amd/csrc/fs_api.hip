@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/fsmlmc.h"
+#include "fs_clover.h"
 #include "fs_kernels.h"
 #include "fs_probe.h"
 #include "fs_shift.h"
@@ -29,6 +30,22 @@
 using namespace fs;
 
 // ============================================================== errors
+
+// DeGrand-Rossi gamma_1..gamma_4 (g[mu][row][col]); gamma_5 = g1 g2 g3 g4 =
+// diag(1, 1, -1, -1).  The stencil's spin projectors encode the same matrices.
+void fs::dr_gammas(std::complex<double> g[4][4][4]) {
+    using C = std::complex<double>;
+    const C I(0, 1);
+    const C t[4][4][4] = {
+        {{0, 0, 0, I}, {0, 0, I, 0}, {0, -I, 0, 0}, {-I, 0, 0, 0}},
+        {{0, 0, 0, -1}, {0, 0, 1, 0}, {0, 1, 0, 0}, {-1, 0, 0, 0}},
+        {{0, 0, I, 0}, {0, 0, 0, -I}, {-I, 0, 0, 0}, {0, I, 0, 0}},
+        {{0, 0, 1, 0}, {0, 0, 0, 1}, {1, 0, 0, 0}, {0, 1, 0, 0}},
+    };
+    for (int m = 0; m < 4; ++m)
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) g[m][a][b] = t[m][a][b];
+}
 
 namespace {
 
@@ -307,12 +324,8 @@ double link_norm_bound(const double* u, size_t n_links) {
 GammaTab make_gamma_tab() {
     using C = std::complex<double>;
     const C I(0, 1);
-    C g[4][4][4] = {
-        {{0, 0, 0, I}, {0, 0, I, 0}, {0, -I, 0, 0}, {-I, 0, 0, 0}},
-        {{0, 0, 0, -1}, {0, 0, 1, 0}, {0, 1, 0, 0}, {-1, 0, 0, 0}},
-        {{0, 0, I, 0}, {0, 0, 0, -I}, {-I, 0, 0, 0}, {0, I, 0, 0}},
-        {{0, 0, 1, 0}, {0, 0, 0, 1}, {1, 0, 0, 0}, {0, 1, 0, 0}},
-    };
+    C g[4][4][4];
+    dr_gammas(g);
     GammaTab t;
     for (int n = 0; n < 16; ++n) {
         C M[4][4] = {};
@@ -365,6 +378,9 @@ struct fs_ctx_s {
     bool two_rows = false;           // gauge_q2 is filled: every link is special unitary
     double su3_defect = 0.0;         // max |U_2j - conj(U_0 x U_1)_j| over the uploaded links
     double link_norm = 1.0;          // upper bound on the spectral norm of every uploaded link
+    double c_sw = 0.0;               // clover coefficient (0: the plain Wilson operator)
+    DevBuf clv[2];                   // clover term C, [parity][chunk][V/2]: FP64 (36 chunks), FP32 (18)
+    double clv_norm = 0.0;           // upper bound on the spectral norm of every block of C
     std::map<int, TuneEntry> tune;   // per precision
     std::map<int, std::array<int, 2>> eo_tune;  // per precision: even-odd stencil variant, residency cap
     HostBuf pinned;
@@ -399,6 +415,7 @@ LatDesc lat_desc(const fs_ctx_s* c, int P, int eo = 0, bool two_rows = false) {
     d.gauge = c->gauge[P].p;
     d.gauge_q = (two_rows && P == P32) ? c->gauge_q2[P].p : c->gauge_q[P].p;
     d.pty = d.ptz = 0;
+    d.clv = (c->c_sw != 0.0 && (P == P64 || P == P32)) ? c->clv[P].p : nullptr;
     return d;
 }
 
@@ -844,6 +861,11 @@ struct BatchSolver {
     Field b, xhi, rhi, r, p, v, t, xlo;
     Field sb_, sx_, sr_, tmp, tmp64;  // even-odd: FP64 Schur b, x, r; odd-site scratch
     DevBuf d_diag, d_st, d_part, d_flags, d_rkeys, d_vl;
+    // clover term: per (lattice, shift) the inverses of C + a at the odd sites
+    bool clv = false;
+    DevBuf d_inv64, d_inv32, d_off64, d_off32;
+    Clv cl64, cl32;
+    const Clv& clv_of(int P) const { return P == P64 ? cl64 : cl32; }
     VList vl_run, vl_pend, vl_conv;
     std::vector<SysState> st_host;
     long long dslash_calls = 0;
@@ -855,6 +877,15 @@ struct BatchSolver {
         : full(plan), eo_pl(opts.eo ? eo_plan_of(plan, l, stream, opts.P, opts.eo_var, opts.eo_occ) : nullptr),
           pl(opts.eo ? *eo_pl : plan),
           cur(&pl), lats(l), s(stream), o(opts) {
+        int n_clv = 0;
+        for (const BlockDesc& bd : pl.blocks) n_clv += lats[bd.lat]->c_sw != 0.0;
+        if (n_clv) {
+            if (n_clv != (int)pl.blocks.size())
+                fail(FS_E_ARG, "a batch mixes lattices with and without the clover term");
+            if (!o.eo) fail(FS_E_ARG, "the clover term needs even-odd preconditioning (even_odd = 1)");
+            if (o.P != P64 && o.P != P32) fail(FS_E_ARG, "the clover term needs FP64 or FP32 storage");
+            clv = true;
+        }
         const long long S = pl.total_slots;
         b.alloc(P64, full.total_slots);
         xhi.alloc(P64, full.total_slots);
@@ -889,6 +920,7 @@ struct BatchSolver {
     // systems, so rhat = r0 = b).
     void setup(const std::vector<double>& diag, const std::vector<char>& idle, const std::vector<NoiseKey>& rkeys) {
         HC(hipMemcpyAsync(d_diag.p, diag.data(), sizeof(double) * pl.nsys, hipMemcpyHostToDevice, s));
+        if (clv) setup_clover(diag);
         d_rkeys.alloc(sizeof(NoiseKey) * pl.nsys);
         HC(hipMemcpyAsync(d_rkeys.p, rkeys.data(), sizeof(NoiseKey) * pl.nsys, hipMemcpyHostToDevice, s));
         for (int i = 0; i < pl.nsys; ++i) {
@@ -902,6 +934,54 @@ struct BatchSolver {
         }
         HC(hipMemcpyAsync(d_st.p, st_host.data(), sizeof(SysState) * pl.nsys, hipMemcpyHostToDevice, s));
         HC(hipStreamSynchronize(s));  // the host vectors may go out of scope
+    }
+    // One inverse field per (lattice, 4 + m0 + sigma) of the plan's systems
+    // (padding systems included: every system's offset points at a field).
+    void setup_clover(const std::vector<double>& diag) {
+        std::map<std::pair<int, double>, long long> fld;  // key -> offset in FP32 chunks
+        std::vector<std::pair<int, double>> order;
+        std::vector<long long> off32(pl.nsys, 0);
+        long long tot = 0;
+        for (const BlockDesc& bd : pl.blocks)
+            for (int r = 0; r < pl.nr; ++r) {
+                const int sys = bd.sys0 + r;
+                const auto key = std::make_pair(bd.lat, diag[sys]);
+                auto it = fld.find(key);
+                if (it == fld.end()) {
+                    it = fld.emplace(key, tot).first;
+                    order.push_back(key);
+                    tot += 18ll * (lats[bd.lat]->V / 2);
+                }
+                off32[sys] = it->second;
+            }
+        if (order.empty()) return;
+        std::vector<long long> off64(off32.size());
+        for (size_t i = 0; i < off32.size(); ++i) off64[i] = 2 * off32[i];
+        d_inv64.alloc((size_t)tot * 2 * 16);
+        if (o.P == P32) d_inv32.alloc((size_t)tot * 16);
+        d_off64.alloc(sizeof(long long) * off64.size());
+        d_off32.alloc(sizeof(long long) * off32.size());
+        HC(hipMemcpyAsync(d_off64.p, off64.data(), sizeof(long long) * off64.size(), hipMemcpyHostToDevice, s));
+        HC(hipMemcpyAsync(d_off32.p, off32.data(), sizeof(long long) * off32.size(), hipMemcpyHostToDevice, s));
+        DevBuf bad(sizeof(int));
+        HC(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+        for (const auto& key : order) {
+            const fs_ctx_s* c = lats[key.first];
+            const int vh = c->V / 2;
+            const long long o32 = fld[key];
+            launch_clover_invert(c->clv[P64].as<uint4>() + (size_t)36 * vh, vh, key.second,
+                                 d_inv64.as<uint4>() + 2 * o32, o.P == P32 ? d_inv32.as<uint4>() + o32 : nullptr,
+                                 bad.as<int>(), s);
+        }
+        HC(hipGetLastError());
+        int h_bad = 0;
+        HC(hipMemcpyAsync(&h_bad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HC(hipStreamSynchronize(s));
+        if (h_bad) fail(FS_E_ARG, "C + 4 + m0 + sigma is singular at an odd site");
+        cl64.inv = d_inv64.as<uint4>();
+        cl64.off = d_off64.as<long long>();
+        cl32.inv = d_inv32.as<uint4>();
+        cl32.off = d_off32.as<long long>();
     }
     const NoiseKey* rk() const { return d_rkeys.as<NoiseKey>(); }
     // the FP64 fields of the system the iteration solves
@@ -919,6 +999,13 @@ struct BatchSolver {
             return;
         }
         const int hp = mode == D_RESID ? P64 : prec;
+        if (clv) {  // the hop's odd-site output times (C_o + a)^-1, then (C_e + a) in - D_eo (.)
+            launch_dslash_eo_clv(hp, D_HOP, ws, scratch, in, Fld(), Fld(), dg, st(), mask, part(), s, rk(), 1,
+                                 clv_of(hp));
+            launch_dslash_eo_clv(hp, mode, ws, out, scratch, in, aux, dg, st(), mask, part(), s, rk(), 0,
+                                 clv_of(hp));
+            return;
+        }
         launch_dslash_eo(hp, D_HOP, ws, scratch, in, Fld(), Fld(), dg, st(), mask, part(), s, rk(), 1);
         launch_dslash_eo(hp, mode, ws, out, scratch, in, aux, dg, st(), mask, part(), s, rk(), 0);
     }
@@ -1032,7 +1119,13 @@ struct BatchSolver {
         if (o.eo) {  // Schur source and the full |b|^2 the tolerance refers to
             // streaming mapping over t; the finish reads that mapping's rows
             const Work wp = pl.work_stream(P64);
-            launch_eo_prep(wp, full.d_blocks.as<BlockDesc>(), b.f(), sb_.f(), d_diag.as<double>(), part(), s);
+            if (clv) {  // sb_ = b_e - D_eo (C_o + a)^-1 b_o
+                launch_clover_bo_inv(pl.work(P64, false), full.d_blocks.as<BlockDesc>(), b.f(), tmp64.f(), cl64, s);
+                launch_eo_prep_clv(wp, full.d_blocks.as<BlockDesc>(), b.f(), tmp64.f(), sb_.f(),
+                                   d_diag.as<double>(), part(), s);
+            } else {
+                launch_eo_prep(wp, full.d_blocks.as<BlockDesc>(), b.f(), sb_.f(), d_diag.as<double>(), part(), s);
+            }
             launch_finish(F_BNORM, wp, st(), part(), nullptr, nullptr, s);
         }
         launch_init(o.P, pl.work(o.P, false), fb().f(), fx().f(), xlo.f(), fr().f(), r.f(), rk(), p.f(), part(), s);
@@ -1106,7 +1199,10 @@ struct BatchSolver {
             throw;
         }
         drop_graph();
-        if (o.eo)
+        if (o.eo && clv)
+            launch_eo_post_clv(pl.work_stream(P64), full.d_blocks.as<BlockDesc>(), b.f(), sx_.f(), xhi.f(),
+                               d_diag.as<double>(), cl64, s);
+        else if (o.eo)
             launch_eo_post(pl.work_stream(P64), full.d_blocks.as<BlockDesc>(), b.f(), sx_.f(), xhi.f(),
                            d_diag.as<double>(), s);
         HC(hipMemcpyAsync(st_host.data(), d_st.p, sizeof(SysState) * pl.nsys, hipMemcpyDeviceToHost, s));
@@ -1123,6 +1219,11 @@ void check_ctx(fs_ctx c, bool need_gauge = true) {
 
 void check_prec(int P) {
     if (P < 0 || P > 3) fail(FS_E_ARG, "invalid precision");
+}
+
+// The clover term is kept in FP64 and FP32 only.
+void check_clover_prec(const fs_ctx_s* c, int P) {
+    if (c->c_sw != 0.0 && P != P64 && P != P32) fail(FS_E_ARG, "the clover term needs FP64 or FP32 storage");
 }
 
 void check_eo(bool eo, const fs_ctx_s* c) {
@@ -1184,8 +1285,30 @@ struct EstResult {
 // + P_+ Pi_mu^-1 U_mu^+ psi with P_-+ = (1 -+ g_mu)/2 orthogonal projectors
 // commuting with the colour and site maps, so ||H_mu psi||^2 <= u^2
 // (||P_- psi||^2 + ||P_+ psi||^2) = u^2 ||psi||^2 for links of norm <= u.
+// With the clover term, D + sigma = (4 + m0 + sigma) + C - H and ||C|| is at
+// most the largest absolute row sum of its blocks (clv_norm).
 double smin_lower(const fs_ctx_s* c, double m0, double sigma) {
-    return 4.0 + m0 + sigma - 4.0 * c->link_norm;
+    return 4.0 + m0 + sigma - 4.0 * c->link_norm - c->clv_norm;
+}
+
+// C of the context's links at its c_sw (FP64 and FP32 copies) and its norm bound.
+void build_clover(fs_ctx_s* c) {
+    static const SigmaTab tab = make_sigma_tab();
+    const size_t vh = (size_t)c->V / 2;
+    c->clv[P64].alloc((size_t)2 * 36 * vh * 16);
+    c->clv[P32].alloc((size_t)2 * 18 * vh * 16);
+    DevBuf nb(sizeof(unsigned long long));
+    HC(hipMemsetAsync(nb.p, 0, sizeof(unsigned long long), c->stream));
+    launch_clover_build(lat_desc(c, P64), c->c_sw, tab, c->clv[P64].as<uint4>(), c->clv[P32].as<uint4>(),
+                        nb.as<unsigned long long>(), c->stream);
+    HC(hipGetLastError());
+    unsigned long long bits = 0;
+    HC(hipMemcpyAsync(&bits, nb.p, sizeof(bits), hipMemcpyDeviceToHost, c->stream));
+    HC(hipStreamSynchronize(c->stream));
+    double nrm;
+    std::memcpy(&nrm, &bits, sizeof(nrm));
+    if (!std::isfinite(nrm)) fail(FS_E_ARG, "the clover term is not finite (links not finite?)");
+    c->clv_norm = nrm;
 }
 
 // One batched pass over a set of (instance, level, sample) units.  For each
@@ -2076,6 +2199,7 @@ size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 void apply_dirac_noalloc(fs_ctx c, double m0, double sigma, int storage, const double* in, double* out, int n_rhs) {
     check_ctx(c);
     check_prec(storage);
+    check_clover_prec(c, storage);
     if (!in || !out) fail(FS_E_ARG, "null buffer");
     if (n_rhs < 1) fail(FS_E_ARG, "n_rhs must be >= 1");
     DeviceScope ds(c->device);
@@ -2131,6 +2255,7 @@ void apply_dirac_noalloc(fs_ctx c, double m0, double sigma, int storage, const d
     const long long stride = 24ll * c->V;
     launch_pack(storage, pl.work(storage, false), fi, in, stride, sys_map, s);
     launch_dslash(storage, D_PLAIN, pl.work(storage, false, true), fo, fi, Fld(), diag, nullptr, M_ALL, nullptr, s);
+    if (c->c_sw != 0.0) launch_clover_add(storage, pl.work(storage, false), fo, fi, s);
     launch_unpack(storage, pl.work(storage, false), out, fo, stride, sys_map, s);
     HC(hipGetLastError());
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -2293,6 +2418,31 @@ fs_status fs_upload_gauge(fs_ctx c, const double* links, int32_t is_device) {
         }
         HC(hipStreamSynchronize(c->stream));
         c->has_gauge = true;
+        if (c->c_sw != 0.0) build_clover(c);
+    });
+}
+
+fs_status fs_set_clover(fs_ctx c, double c_sw) {
+    return guard([&] {
+        check_ctx(c);
+        if (!std::isfinite(c_sw)) fail(FS_E_ARG, "c_sw must be finite");
+        if (c_sw != 0.0 && (c->dims[0] % 2 || c->dims[1] % 2 || c->dims[2] % 2 || c->dims[3] % 2))
+            fail(FS_E_ARG, "the clover term needs even extents (even-odd layout)");
+        DeviceScope ds(c->device);
+        c->c_sw = c_sw;
+        if (c_sw == 0.0) {
+            c->clv[P64].release();
+            c->clv[P32].release();
+            c->clv_norm = 0.0;
+            return;
+        }
+        try {
+            build_clover(c);
+        } catch (...) {
+            c->c_sw = 0.0;
+            c->clv_norm = 0.0;
+            throw;
+        }
     });
 }
 
@@ -2309,6 +2459,7 @@ fs_status fs_apply_dirac(fs_ctx c, double m0, double sigma, fs_prec storage, con
     return guard([&] {
         check_ctx(c);
         check_prec(storage);
+        check_clover_prec(c, storage);
         if (!in || !out) fail(FS_E_ARG, "null buffer");
         if (n_rhs < 1) fail(FS_E_ARG, "n_rhs must be >= 1");
         DeviceScope ds(c->device);
@@ -2335,6 +2486,7 @@ fs_status fs_apply_dirac(fs_ctx c, double m0, double sigma, fs_prec storage, con
         DevBuf d_diag = to_device(diag.data(), sizeof(double) * diag.size(), 0, s);
         launch_dslash(storage, D_PLAIN, pl->work(storage, false, true), fo.f(), fi.f(), Fld(), d_diag.as<double>(),
                       nullptr, M_ALL, nullptr, s);
+        if (c->c_sw != 0.0) launch_clover_add(storage, pl->work(storage, false), fo.f(), fi.f(), s);
         launch_unpack(storage, pl->work(storage, false), dout.as<double>(), fo.f(), stride, d_map.as<int>(), s);
         HC(hipGetLastError());
         from_device(out, dout, nb, is_device, s);

@@ -28,27 +28,6 @@ __device__ __forceinline__ bool mask_ok(int mask, const SysState* __restrict__ s
     return st[sys].upd_p != 0;
 }
 
-// Common prologue: for every virtual workgroup of this launch, bind the block
-// and its geometry; the body runs once per virtual workgroup (FS_WG_EPILOGUE
-// closes it).
-#define FS_WG_PROLOGUE(w)                                                   \
-    for_each_vwg((w), [&](const int wg_id, const int b) {                   \
-    (void)b;                                                                \
-    const BlockDesc bd = (w).blocks[b];                                     \
-    const LatDesc ld = (w).lats[bd.lat];                                    \
-    const int wgb = wg_id - (w).wg_start[b];                                \
-    const size_t gs = (size_t)ld.Vf << (w).lognr;
-
-#define FS_WG_EPILOGUE });
-
-#define FS_SLOT_LOOP(w)                                                     \
-    for (int it = 0; it < (w).tpw; ++it) {                                  \
-        const size_t slot = ((size_t)wgb * (w).tpw + it) * (w).wg + threadIdx.x; \
-        if (slot >= gs) break;                                              \
-        const int rhs = (int)(slot & (size_t)((w).nr - 1));                 \
-        const int sys = bd.sys0 + rhs;
-
-#define FS_SLOT_LOOP_END }
 
 template <int P>
 __device__ __forceinline__ const uint4* fbase(const Fld& f, const BlockDesc& bd) {

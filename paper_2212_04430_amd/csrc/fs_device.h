@@ -34,6 +34,8 @@ struct LatDesc {
                          // rows 0-1 only ([mu][site][QCR], FP32) in plans that rebuild row 2
     int pty, ptz;        // one-parity plans with the x-pair stencil: tile of TY x TZ pairs
                          // (dividing Ly, Lz) per workgroup; 0 otherwise
+    const void* clv;     // clover term C of the lattice in the launch precision (FP64 or
+                         // FP32), [parity][chunk][V/2] packed Hermitian blocks; null: none
 };
 
 struct BlockDesc {

@@ -99,9 +99,44 @@ __device__ __forceinline__ void for_each_vwg(const Work& w, F&& body) {
 }
 
 
+// Common prologue: for every virtual workgroup of this launch, bind the block
+// and its geometry; the body runs once per virtual workgroup (FS_WG_EPILOGUE
+// closes it).
+#define FS_WG_PROLOGUE(w)                                                   \
+    for_each_vwg((w), [&](const int wg_id, const int b) {                   \
+    (void)b;                                                                \
+    const BlockDesc bd = (w).blocks[b];                                     \
+    const LatDesc ld = (w).lats[bd.lat];                                    \
+    const int wgb = wg_id - (w).wg_start[b];                                \
+    const size_t gs = (size_t)ld.Vf << (w).lognr;
+
+#define FS_WG_EPILOGUE });
+
+#define FS_SLOT_LOOP(w)                                                     \
+    for (int it = 0; it < (w).tpw; ++it) {                                  \
+        const size_t slot = ((size_t)wgb * (w).tpw + it) * (w).wg + threadIdx.x; \
+        if (slot >= gs) break;                                              \
+        const int rhs = (int)(slot & (size_t)((w).nr - 1));                 \
+        const int sys = bd.sys0 + rhs;
+
+#define FS_SLOT_LOOP_END }
+
 struct Fld {
     uint4* v = nullptr;    // block-layout field (16-byte groups)
     float* n = nullptr;    // FP16 scales (per slot) or null
+};
+
+// Clover term of the even-odd operator.  Per site the term is two Hermitian
+// 6 x 6 blocks (spins 0-1 and 2-3, index spin * 3 + colour within the block),
+// each packed as 36 reals: the 6 diagonal entries, then the 15 entries above
+// the diagonal row by row as (re, im).  A field of such sites is stored
+// [chunk][half-lattice site] in 16-byte chunks: 36 chunks per site in FP64, 18
+// in FP32.  `inv` holds, per (lattice, shift), the inverses of C + 4 + m0 +
+// sigma at the odd sites; off[sys] is the chunk offset of system sys's field.
+constexpr int CLV_REALS = 72;  // two packed blocks
+struct Clv {
+    const uint4* inv = nullptr;
+    const long long* off = nullptr;
 };
 
 // Z4 noise.  Block layout (FP64) for systems with noise keys, or canonical.

@@ -183,3 +183,17 @@ def test_sign_cancels_the_wilson_shift_of_zero_modes():
     assert abs(w - th / 2) < 0.05 * th
     assert abs(c) < 0.02 * abs(w)
     assert abs(anti - 2 * w) < 0.05 * th
+
+
+@pytest.mark.parametrize("eps,csw", [(0.3, 1.0), (0.8, 1.9)])
+def test_smin_lower_bound_holds(eps, csw):
+    dims = (4, 2, 2, 4)
+    U = synth.gauge_field(dims, eps=eps, seed=6)
+    for sigma in (0.0, 0.5):
+        D = cl.clover_dense(U, 0.3, sigma, csw, dims)
+        smin = np.linalg.svd(D, compute_uv=False).min()
+        bound = cl.smin_lower_bound(U, 0.3, sigma, csw, dims)
+        assert bound <= smin + 1e-12, (bound, smin)
+    # the row-sum bound is at least the exact spectral norm of every site block
+    C = cl.clover_term(U, dims, csw)
+    assert cl.norm_bound(C) >= np.linalg.norm(C, ord=2, axis=(1, 2)).max() - 1e-14
