@@ -18,8 +18,8 @@ it with the library's a-posteriori error bounds, the dslash roofline of the
 batched kernel (median of 100 launches timed with HIP events), the uneven
 half-precision batch (8^3x16, 12^3x24, 16^3x32, 24^3x48, the paper's six
 shifts, 24 Z4 vectors each) against the FP64 plain path, a 32^3 x 64 solve rate
-and single-RHS dslash (working set far above the 256 MB last-level cache), and
-the CPU oracle.
+and single-RHS dslash (working set far above the 256 MB last-level cache), the
+same workload on the clover-improved operator (c_sw = 1), and the CPU oracle.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -242,6 +242,39 @@ def probed_estimate(L, ctx, nr, dims):
             "max_true_rel_residual": rep.max_rel_residual}
 
 
+def clover_leg(L, ctx, nr, n64, c_sw=1.0):
+    """The same workload on the clover-improved operator (c_sw = 1, the tree-level
+    coefficient): the batched FP32 even-odd estimate against the plain FP64
+    even-odd path on n64 noise vectors per level, as for the Wilson operator."""
+    w = WORKLOAD
+    L.fs_set_clover(ctx, c_sw)
+    try:
+        prm = est_params(L, "f32", 1, w["n_noise"], nr=nr, eo=1)
+        L.fs_estimate(ctx, prm, w["sigma"])  # warm-up (inverse fields, graphs)
+        t0 = time.perf_counter()
+        _, _, rep = L.fs_estimate(ctx, prm, w["sigma"])
+        dt = time.perf_counter() - t0
+        prm64 = est_params(L, "f64", 0, n64, graph=0, eo=1)
+        L.fs_estimate(ctx, est_params(L, "f64", 0, 1, graph=0, eo=1), w["sigma"])
+        t1 = time.perf_counter()
+        _, _, rep64 = L.fs_estimate(ctx, prm64, w["sigma"])
+        dt64 = time.perf_counter() - t1
+    finally:
+        L.fs_set_clover(ctx, 0.0)
+    out = {"c_sw": c_sw,
+           "fp32_batched_solves_per_s": round(rep.systems / dt, 3),
+           "iters_per_system": round(rep.iterations / rep.systems, 2),
+           "reliable_updates_per_system": round(rep.reliable_updates / rep.systems, 2),
+           "max_true_rel_residual": rep.max_rel_residual,
+           "fp64_plain_solves_per_s": round(rep64.systems / dt64, 3),
+           "fp64_plain_systems": int(rep64.systems),
+           "speedup_vs_fp64_plain": round((rep.systems / dt) / (rep64.systems / dt64), 3),
+           "solver": "even-odd Schur complement (C_e + a) - D_eo (C_o + a)^-1 D_oe, inverses per shift in FP64"}
+    log(f"clover c_sw={c_sw}: f32 batched {out['fp32_batched_solves_per_s']} solves/s "
+        f"({out['iters_per_system']} iters/system), f64 plain {out['fp64_plain_solves_per_s']} solves/s")
+    return out
+
+
 def sampling_and_selection(L, ctx, nr):
     """Variance sampling on the paper's sampling set with N_s = 5 (Sec. 3.1), then
     shift selection with six shifts (Sec. 3.2-3.3) for every (Gamma_n, p) on the
@@ -362,6 +395,7 @@ def main():
     ap.add_argument("--roofline-only", action="store_true", help="only the copy and stencil launches of the roofline")
     ap.add_argument("--roofline-storage", default="f32", choices=["f64", "f32", "f16", "bf16"],
                     help="precision of the stencil timed by --roofline-only")
+    ap.add_argument("--no-clover", action="store_true", help="skip the clover-improved operator leg")
     ap.add_argument("--no-select", action="store_true", help="skip variance sampling and shift selection")
     ap.add_argument("--no-probe", action="store_true", help="skip the probed, spin-colour diluted estimate")
     ap.add_argument("--tuning-cache", default=None, help="autotune cache file (default: a temporary copy of the "
@@ -502,6 +536,7 @@ def main():
                 "copy_kernel_GBs": round(2 * (1 << 30) / (ms_c * 1e-3) / 1e9, 1)}
     log(f"dslash f32 batched even-odd hop: {ms_d:.4f} ms, {achieved:.0f} GB/s; full lattice {ms_full:.4f} ms, "
         f"{full_gbs:.0f} GB/s")
+    clover = None if args.no_clover else clover_leg(L, ctx, nr, args.fp64_noise)
     select, sel_inputs = (None, None) if args.no_select else sampling_and_selection(L, ctx, nr)
     uneven = None if args.no_uneven else uneven_batch(L, args)
     probed = None if args.no_probe else probed_estimate(L, ctx, nr, dims)
@@ -569,6 +604,7 @@ def main():
         "uneven_half_precision_batch": uneven,
         "dslash_32c64_single_rhs": headline,
         "mixed_half_precision": half or None,
+        "clover_operator": clover,
         "sampling_and_shift_selection": select,
         "probed_diluted_estimate": probed,
     }
