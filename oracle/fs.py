@@ -222,7 +222,40 @@ def sampling_slots(m):
     return [("single", i, i) for i in range(m)] + [("pair", i, j) for i in range(m) for j in range(i, m)]
 
 
-def sampling_samples(U, dims, shifts, n_samples, seed, gammas, p_max, solver, instance=0):
+# ---------------------------------------------------------------------------
+# Generalized Hopping Parameter Expansion (Sec. 3.1, closing paragraph of
+# "Sampling the Variance"): with D + sigma = a - H, a = 4 + m0 + sigma and H
+# the hopping term,
+#   (D + sigma)^-1 = sum_{j<k} (H/a)^j / a + (H/a)^k (D + sigma)^-1,
+# so the trace of Gamma Omega_p (D + sigma)^-1 is the trace of the first k
+# terms (computable exactly) plus that of Gamma Omega_p (H/a)^k (D + sigma)^-1,
+# whose stochastic estimate has the smaller variance when m0 + sigma is large.
+# The paper samples V_L that way at order k = 4 for the shifts with
+# m0 + s > 0.  (Plain Wilson operator; the generalized form replaces a by the
+# site-local diagonal block.)
+# ---------------------------------------------------------------------------
+
+def hopping_apply(U, psi, m0, sigma, dims, antiperiodic=False):
+    """H psi with D + sigma = (4 + m0 + sigma) - H (H depends on neither m0 nor sigma)."""
+    return (4.0 + m0 + sigma) * np.asarray(psi, np.complex128) - lat.wilson_apply(U, psi, m0, sigma, dims,
+                                                                                  antiperiodic)
+
+
+def hpe_apply(U, x, m0, sigma, k, dims, antiperiodic=False):
+    """(H / a)^k x, a = 4 + m0 + sigma."""
+    a = 4.0 + m0 + sigma
+    w = np.asarray(x, np.complex128)
+    for _ in range(k):
+        w = hopping_apply(U, w, m0, sigma, dims, antiperiodic) / a
+    return w
+
+
+def hpe_eligible(m0, s):
+    """The sampling shifts the expansion is used for (m_q + s > 0 in the paper's notation)."""
+    return m0 + s > 0.0
+
+
+def sampling_samples(U, dims, shifts, n_samples, seed, gammas, p_max, solver, instance=0, hpe_order=0):
     """Per-sample values of the sampling algorithm, X[slot, k, n_idx, p].
 
     For each noise vector z_k and each sampling shift s_i: x_i = (D+s_i)^-1 z_k
@@ -231,7 +264,11 @@ def sampling_samples(U, dims, shifts, n_samples, seed, gammas, p_max, solver, in
     (A = Gamma Omega_p (D+s_i)^-1) and Vbar_l(s_i, s_j), j >= i, samples
     y_i^dagger Gamma Omega_p x_j (A = (D+s_i)^-1 Gamma Omega_p (D+s_j)^-1),
     without the (s_j - s_i)^2 factor of V_l (eq. sampled_prod, eq. bar_vl).
+    With hpe_order = k > 0 the V_L samples of the shifts with m0 + s_i > 0
+    are z_k^dagger Gamma Omega_p (H/a_i)^k x_i (the expansion's remainder).
     """
+    if hpe_order > 0 and getattr(solver, "c_sw", 0.0) != 0.0:
+        raise NotImplementedError("the expansion is written for the plain Wilson operator")
     m = len(shifts)
     V = lat.volume(dims)
     slots = sampling_slots(m)
@@ -242,16 +279,29 @@ def sampling_samples(U, dims, shifts, n_samples, seed, gammas, p_max, solver, in
         ys = [lat.apply_gamma5(solver.solve(s, lat.apply_gamma5(z))) for s in shifts]
         for q, (kind, i, j) in enumerate(slots):
             y = z if kind == "single" else ys[i]
-            X[q, k] = bilinears(U, dims, y, xs[j], gammas, p_max)
+            x = xs[j]
+            if kind == "single" and hpe_order > 0 and hpe_eligible(solver.m0, shifts[j]):
+                x = hpe_apply(U, x, solver.m0, shifts[j], hpe_order, dims, solver.ap)
+            X[q, k] = bilinears(U, dims, y, x, gammas, p_max)
     return X
 
 
-def exact_sampling(solver, shifts, gammas, p_list):
-    """Exact traces and one-sample variances of every sampled matrix, per slot."""
+def exact_sampling(solver, shifts, gammas, p_list, hpe_order=0):
+    """Exact traces and one-sample variances of every sampled matrix, per slot
+    (with hpe_order as in sampling_samples: the singles of eligible shifts are
+    Gamma Omega_p (H/a)^k (D + s)^-1)."""
     U, dims = solver.U, solver.dims
     V = lat.volume(dims)
     m = len(shifts)
     invs = [solver.inverse(s) for s in shifts]
+    singles = list(invs)
+    if hpe_order > 0 and getattr(solver, "c_sw", 0.0) != 0.0:
+        raise NotImplementedError("the expansion is written for the plain Wilson operator")
+    if hpe_order > 0:
+        Hd = (4.0 + solver.m0) * np.eye(solver.D0.shape[0]) - solver.D0  # D0 = D at sigma = 0
+        for i, s in enumerate(shifts):
+            if hpe_eligible(solver.m0, s):
+                singles[i] = np.linalg.matrix_power(Hd / (4.0 + solver.m0 + s), hpe_order) @ invs[i]
     slots = sampling_slots(m)
     T = np.zeros((len(slots), len(gammas), len(p_list)), dtype=np.complex128)
     Var = np.zeros((len(slots), len(gammas), len(p_list)))
@@ -260,7 +310,8 @@ def exact_sampling(solver, shifts, gammas, p_list):
         for ig, n in enumerate(gammas):
             G = lat.gamma_dense(n, V) @ Om
             for q, (kind, i, j) in enumerate(slots):
-                A = level_matrix(None if kind == "single" else invs[i], invs[j], G, 1.0)
+                A = level_matrix(None if kind == "single" else invs[i], singles[j] if kind == "single" else invs[j],
+                                 G, 1.0)
                 T[q, ig, ip] = np.trace(A)
                 Var[q, ig, ip] = offdiag_frobenius(A)
     return T, Var
