@@ -57,7 +57,7 @@ class fs_solve_stats(C.Structure):
 class fs_est_params(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_noise", C.c_int32), ("gamma_mask", C.c_uint16),
                 ("p_max", C.c_int32), ("solve", fs_solve_params), ("n_level", C.POINTER(C.c_int32)),
-                ("shared_noise", C.c_int32), ("report_fp64_error", C.c_int32)]
+                ("shared_noise", C.c_int32), ("report_fp64_error", C.c_int32), ("hpe_order", C.c_int32)]
 
     def set_n_level(self, counts):
         """Per-level sample counts N_l (None: n_noise on every level); the array is kept alive here."""

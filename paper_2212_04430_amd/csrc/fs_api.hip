@@ -1518,6 +1518,7 @@ void probed_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sigma_in, 
                  int n_col, fs_level_stat* out, double* samples_out, fs_est_report* report) {
     if (!prm || !sigma_in || !out || !colours) fail(FS_E_ARG, "null argument");
     if (L < 0) fail(FS_E_ARG, "L must be >= 0");
+    if (prm->hpe_order != 0) fail(FS_E_ARG, "hpe_order applies to fs_sample_variances only");
     if (prm->n_noise < 1) fail(FS_E_ARG, "n_noise must be >= 1");
     if (prm->p_max < 0 || prm->p_max >= c->dims[2]) fail(FS_E_ARG, "p_max must be in [0, Lz)");
     check_prec(prm->solve.storage);
@@ -1728,6 +1729,9 @@ void sampling_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sh_in, i
     if (!(prm->solve.tol > 0)) fail(FS_E_ARG, "tol must be > 0");
     if (prm->solve.max_iter < 1) fail(FS_E_ARG, "max_iter must be >= 1");
     if (prm->solve.rhs_block != 0 && !pow2_ok(prm->solve.rhs_block)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
+    if (prm->hpe_order < 0 || prm->hpe_order > 16) fail(FS_E_ARG, "hpe_order must be in 0..16");
+    if (prm->hpe_order > 0 && c->c_sw != 0.0)
+        fail(FS_E_ARG, "the hopping parameter expansion is implemented for the plain Wilson operator");
     std::vector<double> sh(sh_in, sh_in + m);
     if (sh[0] != 0.0) fail(FS_E_ARG, "shifts[0] must be 0");
     for (int i = 0; i + 1 < m; ++i)
@@ -1794,6 +1798,32 @@ void sampling_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sh_in, i
     DevBuf d_M(sizeof(double) * (size_t)nsys * P1 * 32);
     Field phi1;
     phi1.alloc(P64, pl->total_slots);
+    // hopping parameter expansion of the singles: w = (H/a)^k x for the x-blocks
+    // of shifts with m0 + s > 0 (x elsewhere), H = a - (D + s): k rounds of the
+    // stencil with a zero diagonal (giving -H w) and a scale by -1/a
+    Field whpe;
+    {
+        std::vector<BlockDesc> eb;
+        for (int b = 0; b < nblk; b += 2)
+            if (prm->hpe_order > 0 && prm->solve.m0 + sh[(b / 2) / nch] > 0.0) eb.push_back(pl->blocks[b]);
+        if (!eb.empty()) {
+            whpe.alloc(P64, pl->total_slots);
+            HC(hipMemcpyAsync(whpe.v.p, bs.xhi.v.p, whpe.v.n < bs.xhi.v.n ? whpe.v.n : bs.xhi.v.n,
+                              hipMemcpyDeviceToDevice, s));
+            auto sp = plan_from_blocks(eb, lats, nr, pl->wg, s, pl->ilp, pl->occ, 0);
+            std::vector<double> zero(nsys, 0.0), coef(nsys);
+            for (int i = 0; i < nsys; ++i) coef[i] = -1.0 / diag[i];
+            DevBuf d_zero = to_device(zero.data(), sizeof(double) * nsys, 0, s);
+            DevBuf d_coef = to_device(coef.data(), sizeof(double) * nsys, 0, s);
+            for (int it = 0; it < prm->hpe_order; ++it) {
+                launch_dslash(P64, D_PLAIN, sp->work(P64, false, true), phi1.f(), whpe.f(), Fld(),
+                              d_zero.as<double>(), nullptr, M_ALL, nullptr, s);
+                launch_scale_sys(sp->work(P64, false), whpe.f(), phi1.f(), d_coef.as<double>(), s);
+            }
+            HC(hipGetLastError());
+            HC(hipStreamSynchronize(s));  // the tables die with this scope
+        }
+    }
     for (int q = 0; q <= m; ++q) {
         const int iy = q - 1;
         std::vector<int> yb(2 * nblk, -1), hop_start(nblk + 1, 0);
@@ -1823,7 +1853,7 @@ void sampling_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sh_in, i
         Work wh = pl->work(P64, false);
         wh.wg_start = d_hop_start.as<int>();
         wh.total_wg = hop_start.back();
-        Fld cur = bs.xhi.f();
+        Fld cur = (q == 0 && whpe.v.p) ? whpe.f() : bs.xhi.f();
         for (int p = 0; p <= prm->p_max; ++p) {
             Fld outf = (p % 2 == 1) ? bs.rhi.f() : phi1.f();
             launch_hop_reduce(wh, p, outf, cur, bs.xhi.f(), bs.b.f(), d_yb.as<int>(), bs.part(), s);
@@ -1889,6 +1919,7 @@ void estimate_impl(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm,
     if (!prm || !sigma_in || !out) fail(FS_E_ARG, "null argument");
     if (L < 0) fail(FS_E_ARG, "L must be >= 0");
     if (prm->p_max < 0) fail(FS_E_ARG, "p_max must be >= 0");
+    if (prm->hpe_order != 0) fail(FS_E_ARG, "hpe_order applies to fs_sample_variances only");
     // samples per level: n_level[l], or n_noise for every level
     std::vector<int> Nl(L + 1);
     for (int l = 0; l <= L; ++l) {

@@ -739,6 +739,22 @@ __global__ void k_noise_canonical(double* __restrict__ dst, int V, NoiseKey k) {
     for (int j = 0; j < 12; ++j) d[j] = make_double2(v[2 * j], v[2 * j + 1]);
 }
 
+// out = coef[sys] * in (FP64), e.g. one factor 1/a of a hopping expansion.
+__global__ void __launch_bounds__(256) k_scale_sys(Work w, Fld out, Fld in, const double* __restrict__ coef) {
+    FS_WG_PROLOGUE(w)
+    const uint4* ib = fbase<P64>(in, bd);
+    uint4* ob = fbase_w<P64>(out, bd);
+    FS_SLOT_LOOP(w)
+        const double c = coef[sys];
+        double v[24];
+        load_sp<P64, double>(ib, nullptr, gs, slot, v);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) v[k] *= c;
+        store_sp<P64, double>(ob, nullptr, gs, slot, v);
+    FS_SLOT_LOOP_END
+    FS_WG_EPILOGUE
+}
+
 // ------------------------------------------------------------------ displacement + bilinear
 
 // phi(x) = U_z(x) phi_in(x + z) per spin (colour product), or phi_in(x) at p = 0;
@@ -1012,6 +1028,9 @@ void launch_unpack(int prec, const Work& w, double* dst, Fld src, long long sys_
                    hipStream_t s) {
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_unpack<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, dst, src, sys_stride,
                                            sys_map))
+}
+void launch_scale_sys(const Work& w, Fld out, Fld in, const double* coef, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_sys, dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, coef);
 }
 void launch_gauge_convert(int prec, void* dst, const double* src, int V, hipStream_t s) {
     const int n = 4 * V;

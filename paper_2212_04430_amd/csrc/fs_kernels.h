@@ -396,5 +396,7 @@ inline int persistent_grid(int wg) { return 2048 * (256 / wg); }
 
 // copy kernel of known size (bandwidth calibration)
 void launch_copy(uint4* dst, const uint4* src, size_t n16, hipStream_t s);
+// out = coef[sys] * in over the slots of w (FP64 fields)
+void launch_scale_sys(const Work& w, Fld out, Fld in, const double* coef, hipStream_t s);
 
 }  // namespace fs

@@ -165,3 +165,43 @@ def test_sampling_full_size_identities(L):
             assert np.abs(g5.imag).max() <= 1e-5 * np.abs(g5.real).max(), i
     finally:
         L.fs_destroy(ctx)
+
+
+@pytest.mark.parametrize("m0,storage,tol,ts", [(-0.1, "f64", 1e-12, 1e-9), (0.2, "f64", 1e-12, 1e-9),
+                                                (0.2, "f32", 1e-10, 1e-7)])
+def test_hopping_expansion_singles(L, m0, storage, tol, ts):
+    """Order-4 expansion of the V_L samples (Sec. 3.1): the singles of shifts with
+    m0 + s > 0 are z^+ Gamma Omega_p (H/a)^4 x, the others and the pairs unchanged.
+    At m0 = -0.1 only the shifts 0.25 and 0.5 qualify."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, eps=0.3, seed=5)
+    shifts = [0.0, 0.05, 0.25, 0.5]
+    dense = ofs.DenseSolver(U, dims, m0)
+    X_ref = ofs.sampling_samples(U, dims, shifts, 8, seed=3, gammas=list(range(16)), p_max=2, solver=dense,
+                                 hpe_order=4)
+    print(f"sampling hpe m0={m0} {storage}", flush=True)
+    ctx = L.fs_create(dims, 0, 0)
+    try:
+        L.fs_upload_gauge(ctx, U)
+        prm = _params(L, m0, 8, 2, storage=storage, tol=tol, nr=4)
+        prm.hpe_order = 4
+        single, pair, X, _, rep = L.fs_sample_variances(ctx, prm, shifts, want_samples=True)
+        assert rep.max_rel_residual <= tol
+        _check(L, single, pair, X, X_ref, len(shifts), ts)
+        prm.hpe_order = 0
+        _, _, X0, _, _ = L.fs_sample_variances(ctx, prm, shifts, want_samples=True)
+        for i, s in enumerate(shifts):
+            same = np.array_equal(X[i], X0[i])
+            assert same == (not ofs.hpe_eligible(m0, s)), (i, s)
+        assert np.array_equal(X[len(shifts):], X0[len(shifts):])
+        # the order is rejected where it does not apply
+        prm.hpe_order = 4
+        with pytest.raises(L.FsError) as e:
+            L.fs_estimate(ctx, prm, [0.0, 0.5])
+        assert e.value.code == L.FS_E_ARG
+        prm.hpe_order = 17
+        with pytest.raises(L.FsError) as e:
+            L.fs_sample_variances(ctx, prm, shifts)
+        assert e.value.code == L.FS_E_ARG
+    finally:
+        L.fs_destroy(ctx)
