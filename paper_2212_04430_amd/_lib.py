@@ -46,7 +46,7 @@ class fs_solve_params(C.Structure):
     _fields_ = [("m0", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("storage", C.c_int32), ("rhs_block", C.c_int32), ("use_graph", C.c_int32),
                 ("reliable_delta", C.c_double), ("check_every", C.c_int32), ("batched", C.c_int32),
-                ("even_odd", C.c_int32)]
+                ("even_odd", C.c_int32), ("multi_shift", C.c_int32)]
 
 
 class fs_solve_stats(C.Structure):
@@ -187,9 +187,9 @@ def _prec(p):
 
 
 def solve_params(m0, tol=1e-10, max_iter=10000, storage="f64", rhs_block=0, use_graph=0,
-                 reliable_delta=0.0, check_every=0, batched=0, even_odd=0):
+                 reliable_delta=0.0, check_every=0, batched=0, even_odd=0, multi_shift=0):
     return fs_solve_params(m0, tol, max_iter, _prec(storage), rhs_block, int(use_graph), reliable_delta,
-                           check_every, int(batched), int(even_odd))
+                           check_every, int(batched), int(even_odd), int(multi_shift))
 
 
 # ------------------------------------------------------------------ entry points

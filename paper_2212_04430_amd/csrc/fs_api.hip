@@ -844,6 +844,16 @@ struct SolveOpts {
     int eo_var = 0, eo_occ = -1;  // even-odd stencil (eo_tuning)
 };
 
+// Multi-shift members carried along a batch's base systems (FP64, full
+// lattice): member k of every system solves (A + d[k]) x = b from the base
+// system's Krylov space (shifted BiCGStab; launch_ms_scalars).
+struct MultiShift {
+    int nm = 0;
+    std::vector<Field> xs, ps;
+    DevBuf d_d, d_state, d_coef;
+    MsFields f;
+};
+
 // Systems of a plan, with sources in `b` (FP64 block layout) and per-system
 // shifts.  On return xhi holds the solutions and `st_host` the final states.
 // With even-odd preconditioning the Krylov iteration runs on a one-parity plan
@@ -861,6 +871,7 @@ struct BatchSolver {
     Field b, xhi, rhi, r, p, v, t, xlo;
     Field sb_, sx_, sr_, tmp, tmp64;  // even-odd: FP64 Schur b, x, r; odd-site scratch
     DevBuf d_diag, d_st, d_part, d_flags, d_rkeys, d_vl;
+    MultiShift* ms = nullptr;  // optional members of a multi-shift solve (FP64, full lattice)
     // clover term: per (lattice, shift) the inverses of C + a at the odd sites
     bool clv = false;
     DevBuf d_inv64, d_inv32, d_off64, d_off32;
@@ -1048,6 +1059,11 @@ struct BatchSolver {
         launch_axpy_s(o.P, wr, r.f(), v.f(), st(), s);
         apply(o.P, D_TS, wd, t.f(), r.f(), Fld(), M_RUN, tmp.f());
         launch_finish(F_OMEGA, wd, st(), part(), f_run(), f_pend(), s);
+        if (ms) {  // the members' x and p, from s (in r), v and t before the base overwrites them
+            launch_ms_scalars(pl.nsys, ms->nm, ms->d_d.as<double>(), st(), ms->d_state.as<MsState>(),
+                              ms->d_coef.as<MsCoef>(), s);
+            launch_ms_update(wr, ms->nm, r.f(), v.f(), t.f(), ms->f, ms->d_coef.as<MsCoef>(), s);
+        }
         build_list(f_run(), vl_run);
         launch_update_xrp(o.P, listed(vl_run, o.P, false), xlo.f(), p.f(), r.f(), t.f(), v.f(), st(), s);
         dslash_calls += 2;
@@ -1209,6 +1225,7 @@ struct BatchSolver {
         HC(hipStreamSynchronize(s));
     }
 };
+
 
 // ============================================================== argument checks
 
@@ -1519,6 +1536,7 @@ void probed_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sigma_in, 
     if (!prm || !sigma_in || !out || !colours) fail(FS_E_ARG, "null argument");
     if (L < 0) fail(FS_E_ARG, "L must be >= 0");
     if (prm->hpe_order != 0) fail(FS_E_ARG, "hpe_order applies to fs_sample_variances only");
+    if (prm->solve.multi_shift != 0) fail(FS_E_ARG, "multi_shift applies to fs_solve_shifted only");
     if (prm->n_noise < 1) fail(FS_E_ARG, "n_noise must be >= 1");
     if (prm->p_max < 0 || prm->p_max >= c->dims[2]) fail(FS_E_ARG, "p_max must be in [0, Lz)");
     check_prec(prm->solve.storage);
@@ -1730,6 +1748,7 @@ void sampling_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sh_in, i
     if (prm->solve.max_iter < 1) fail(FS_E_ARG, "max_iter must be >= 1");
     if (prm->solve.rhs_block != 0 && !pow2_ok(prm->solve.rhs_block)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
     if (prm->hpe_order < 0 || prm->hpe_order > 16) fail(FS_E_ARG, "hpe_order must be in 0..16");
+    if (prm->solve.multi_shift != 0) fail(FS_E_ARG, "multi_shift applies to fs_solve_shifted only");
     if (prm->hpe_order > 0 && c->c_sw != 0.0)
         fail(FS_E_ARG, "the hopping parameter expansion is implemented for the plain Wilson operator");
     std::vector<double> sh(sh_in, sh_in + m);
@@ -1920,6 +1939,7 @@ void estimate_impl(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm,
     if (L < 0) fail(FS_E_ARG, "L must be >= 0");
     if (prm->p_max < 0) fail(FS_E_ARG, "p_max must be >= 0");
     if (prm->hpe_order != 0) fail(FS_E_ARG, "hpe_order applies to fs_sample_variances only");
+    if (prm->solve.multi_shift != 0) fail(FS_E_ARG, "multi_shift applies to fs_solve_shifted only");
     // samples per level: n_level[l], or n_noise for every level
     std::vector<int> Nl(L + 1);
     for (int l = 0; l <= L; ++l) {
@@ -2347,6 +2367,127 @@ double time_eo_apply_impl(fs_ctx c, int P, int n_sys, int nr, int var, int occ, 
     return (double)ms / n_launch;
 }
 
+// Multi-shift solve of X[s][r] = (D + sigma_s)^-1 B[r] (FP64, unpreconditioned):
+// one batched BiCGStab on the smallest shift per rhs, the other shifts carried
+// as members; then every solution's FP64 true residual.  dB, dX device,
+// canonical; stats as fs_solve_shifted.  Returns the worst status.
+fs_status ms_solve(fs_ctx_s* c, const fs_solve_params* prm, const double* sigma, int n_shift, const DevBuf& dB,
+                   int n_rhs, DevBuf& dX, fs_solve_stats* stats) {
+    hipStream_t s = c->stream;
+    int base = 0;
+    for (int k = 1; k < n_shift; ++k)
+        if (sigma[k] < sigma[base]) base = k;
+    std::vector<int> member;  // shift index of member j
+    std::vector<double> dsh;
+    for (int k = 0; k < n_shift; ++k)
+        if (k != base) {
+            member.push_back(k);
+            dsh.push_back(sigma[k] - sigma[base]);
+        }
+    const int nm = (int)member.size();
+    const int nr = prm->batched ? (prm->rhs_block ? prm->rhs_block : tuned_nr(c, P64, n_rhs)) : 1;
+    const int nblk = (n_rhs + nr - 1) / nr;
+    std::vector<int> blk_lat(nblk, 0);
+    std::vector<fs_ctx_s*> lats{c};
+    auto pl = make_plan(blk_lat, lats, nr, tuned_wg(c, P64), s, tuned_ilp(c, P64), tuned_occ(c, P64));
+    const int nsys = pl->nsys;
+    SolveOpts o;
+    o.P = P64;
+    o.tol = prm->tol;
+    o.max_iter = prm->max_iter;
+    o.delta = 0.0;
+    o.check_every = prm->check_every > 0 ? prm->check_every : 8;
+    o.use_graph = prm->use_graph != 0;
+    o.eo = false;
+    BatchSolver bs(*pl, lats, s, o);
+    std::vector<double> diag(nsys, 4.0 + prm->m0 + sigma[base]);
+    std::vector<char> idle(nsys);
+    std::vector<int> src(nsys);
+    std::vector<NoiseKey> rkeys(nsys);
+    for (int i = 0; i < nsys; ++i) {
+        idle[i] = i >= n_rhs;
+        src[i] = i < n_rhs ? i : -1;
+        std::memset(&rkeys[i], 0, sizeof(NoiseKey));
+        rkeys[i].seed = 0x5A4E4F4953452121ull;
+        rkeys[i].instance = 0x40000001u;
+        rkeys[i].sample = (uint64_t)(i < n_rhs ? i : 0);
+        rkeys[i].pad = idle[i] ? 1 : 0;
+    }
+    bs.setup(diag, idle, rkeys);
+    DevBuf d_src = to_device(src.data(), sizeof(int) * nsys, 0, s);
+    launch_pack(P64, pl->work(P64, false), bs.b.f(), dB.as<double>(), 24ll * c->V, d_src.as<int>(), s);
+    // members: x = 0, p = b, recurrence state zeta = tau = alpha_prev = 1, beta_prev = 0
+    MultiShift ms;
+    ms.nm = nm;
+    ms.xs.resize(nm);
+    ms.ps.resize(nm);
+    std::memset(&ms.f, 0, sizeof(ms.f));
+    const size_t fbytes = (size_t)pl->total_slots * prec_group_bytes_spinor(P64);
+    for (int j = 0; j < nm; ++j) {
+        ms.xs[j].alloc(P64, pl->total_slots);
+        ms.ps[j].alloc(P64, pl->total_slots);
+        HC(hipMemsetAsync(ms.xs[j].v.p, 0, fbytes, s));
+        HC(hipMemcpyAsync(ms.ps[j].v.p, bs.b.v.p, fbytes, hipMemcpyDeviceToDevice, s));
+        ms.f.x[j] = ms.xs[j].v.as<uint4>();
+        ms.f.p[j] = ms.ps[j].v.as<uint4>();
+    }
+    std::vector<MsState> st0((size_t)nsys * std::max(nm, 1));
+    for (auto& m : st0) {
+        std::memset(&m, 0, sizeof(m));
+        m.zp[0] = m.z[0] = m.tau[0] = m.ap[0] = 1.0;
+    }
+    if (nm > 0) {  // a single shift is the plain batched solve
+        ms.d_d = to_device(dsh.data(), sizeof(double) * nm, 0, s);
+        ms.d_state = to_device(st0.data(), sizeof(MsState) * st0.size(), 0, s);
+        ms.d_coef.alloc(sizeof(MsCoef) * st0.size());
+        bs.ms = &ms;
+    }
+    bs.run();
+    bs.ms = nullptr;
+    // true residuals of every solution: r = b - (D + sigma_k) x in FP64 and |r|^2
+    fs_status worst = FS_OK;
+    Field rtmp;
+    rtmp.alloc(P64, pl->total_slots);
+    const Work wsten = pl->work(P64, false, true);
+    DevBuf flags1(sizeof(int) * std::max(nblk, 1)), flags2(sizeof(int) * std::max(nblk, 1));
+    for (int k = 0; k < n_shift; ++k) {
+        const int j = k == base ? -1 : (int)(std::find(member.begin(), member.end(), k) - member.begin());
+        Fld xk = j < 0 ? bs.xhi.f() : ms.xs[j].f();
+        std::vector<double> dk(nsys, 4.0 + prm->m0 + sigma[k]);
+        std::vector<SysState> sk(bs.st_host);
+        for (int i = 0; i < nsys; ++i)
+            if (!idle[i]) sk[i].state = S_CHK;
+        DevBuf d_dk = to_device(dk.data(), sizeof(double) * nsys, 0, s);
+        DevBuf d_sk = to_device(sk.data(), sizeof(SysState) * nsys, 0, s);
+        launch_dslash(P64, D_RESID, wsten, rtmp.f(), xk, bs.b.f(), d_dk.as<double>(), d_sk.as<SysState>(), M_ALL,
+                      bs.part(), s, bs.rk());
+        launch_finish(F_TRUE, wsten, d_sk.as<SysState>(), bs.part(), flags1.as<int>(), flags2.as<int>(), s);
+        std::vector<int> dst(nsys);
+        for (int i = 0; i < nsys; ++i) dst[i] = i < n_rhs ? k * n_rhs + i : -1;
+        DevBuf d_dst = to_device(dst.data(), sizeof(int) * nsys, 0, s);
+        launch_unpack(P64, pl->work(P64, false), dX.as<double>(), xk, 24ll * c->V, d_dst.as<int>(), s);
+        HC(hipGetLastError());
+        HC(hipMemcpyAsync(sk.data(), d_sk.p, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, s));
+        HC(hipStreamSynchronize(s));
+        for (int i = 0; i < n_rhs; ++i) {
+            const SysState& B0 = bs.st_host[i];
+            const double rel = true_rel(sk[i]);
+            const fs_status code = (rel <= prm->tol && B0.state == S_DONE) ? FS_OK : FS_E_NOCONV;
+            if (code != FS_OK) worst = code;
+            if (stats) {
+                fs_solve_stats& o2 = stats[k * n_rhs + i];
+                o2.iters = B0.iters;
+                o2.reliable_updates = B0.n_rel;
+                o2.status = code;
+                o2.restarts = B0.restarts;
+                o2.true_rel_residual = rel;
+            }
+        }
+    }
+    return worst;
+}
+
+
 }  // namespace
 
 // ============================================================== C ABI
@@ -2648,11 +2789,24 @@ fs_status fs_solve_shifted(fs_ctx c, const fs_solve_params* prm, const double* s
         if (prm->max_iter < 1) fail(FS_E_ARG, "max_iter must be >= 1");
         if (prm->rhs_block != 0 && !pow2_ok(prm->rhs_block)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
         check_eo(prm->even_odd != 0, c);
+        if (prm->multi_shift) {
+            if (prm->storage != P64) fail(FS_E_ARG, "multi-shift solves run in FP64 storage");
+            if (prm->even_odd)
+                fail(FS_E_ARG, "multi-shift solves need even_odd = 0 (Schur complements of different shifts "
+                               "share no Krylov space)");
+            if (n_shift > MS_MAX + 1) fail(FS_E_ARG, "at most 17 shifts per multi-shift solve");
+            if (c->c_sw != 0.0) fail(FS_E_ARG, "multi-shift solves use the plain operator (no clover term)");
+        }
         DeviceScope ds(c->device);
         hipStream_t s = c->stream;
         const size_t nb1 = sizeof(double) * 24 * (size_t)c->V;
         DevBuf dB = to_device(B, nb1 * n_rhs, is_device, s);
         DevBuf dX(nb1 * n_rhs * n_shift);
+        if (prm->multi_shift) {
+            worst = ms_solve(c, prm, sigma, n_shift, dB, n_rhs, dX, stats);
+            from_device(X, dX, nb1 * n_rhs * n_shift, is_device, s);
+            return;
+        }
         const int P = prm->storage;
         SolveOpts o;
         o.P = P;

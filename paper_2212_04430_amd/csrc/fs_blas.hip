@@ -755,6 +755,120 @@ __global__ void __launch_bounds__(256) k_scale_sys(Work w, Fld out, Fld in, cons
     FS_WG_EPILOGUE
 }
 
+// ------------------------------------------------------------------ multi-shift BiCGStab
+
+struct Cx {
+    double r, i;
+};
+__device__ __forceinline__ Cx cx(const double* a) { return {a[0], a[1]}; }
+__device__ __forceinline__ Cx operator+(Cx a, Cx b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ Cx operator-(Cx a, Cx b) { return {a.r - b.r, a.i - b.i}; }
+__device__ __forceinline__ Cx operator*(Cx a, Cx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ Cx operator/(Cx a, Cx b) {
+    const double d = b.r * b.r + b.i * b.i;
+    return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
+__device__ __forceinline__ void put(double* o, Cx a) {
+    o[0] = a.r;
+    o[1] = a.i;
+}
+
+// Per (system, member) with relative shift d: the shifted BiCG factor
+//   zeta_{n+1} = zeta_n zeta_{n-1} alpha_{n-1} /
+//                (zeta_{n-1} alpha_{n-1} (1 + alpha_n d) + alpha_n beta_{n-1} (zeta_{n-1} - zeta_n)),
+// alpha^d = alpha zeta_{n+1} / zeta_n, beta^d = (zeta_{n+1} / zeta_n)^2 beta,
+// omega^d = omega / (1 + omega d), tau_{n+1} = tau_n (1 + omega d); with
+// r^d_n = (zeta_n / tau_n) r_n, s^d_n = (zeta_{n+1} / tau_n) s_n and
+// r_n = s_n + alpha v_n the member's update is
+//   x^d += alpha^d p^d + omega^d s^d_n,
+//   p^d = (zeta_{n+1} / tau_{n+1}) (s - omega t) + beta^d (p^d - (omega^d / alpha^d)(r^d_n - s^d_n)).
+__global__ void k_ms_scalars(int nsys, int nm, const double* __restrict__ dsh, const SysState* __restrict__ st,
+                             MsState* __restrict__ ms, MsCoef* __restrict__ co) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsys * nm) return;
+    const int sys = i / nm, k = i - sys * nm;
+    const SysState& S = st[sys];
+    MsState M = ms[i];
+    MsCoef C;
+    memset(&C, 0, sizeof(C));
+    if (S.upd_x && !M.done) {
+        if (S.n_rel != 0 || S.restarts != 0 || !S.upd_p) {
+            M.done = 1;  // the base restarted: the members' recurrences no longer hold
+        } else {
+            const Cx one = {1.0, 0.0}, d = {dsh[k], 0.0};
+            const Cx al = cx(S.alpha), om = cx(S.omega), be = cx(S.beta);
+            const Cx zn = cx(M.z), zp = cx(M.zp), tau = cx(M.tau), ap = cx(M.ap), bp = cx(M.bp);
+            const Cx zn1 = zn * zp * ap / (zp * ap * (one + al * d) + al * bp * (zp - zn));
+            const Cx ak = al * zn1 / zn;
+            const Cx wk = om / (one + om * d);
+            const Cx bk = (zn1 / zn) * (zn1 / zn) * be;
+            const Cx tau1 = tau * (one + om * d);
+            const Cx q = bk * wk / ak;
+            put(C.cxp, ak);
+            put(C.cxs, wk * zn1 / tau);
+            put(C.cpp, bk);
+            put(C.cps, zn1 / tau1 - q * (zn - zn1) / tau);
+            put(C.cpv, Cx{0.0, 0.0} - q * zn * al / tau);
+            put(C.cpt, Cx{0.0, 0.0} - zn1 / tau1 * om);
+            C.on = 1;
+            put(M.zp, zn);
+            put(M.z, zn1);
+            put(M.tau, tau1);
+            put(M.ap, al);
+            put(M.bp, be);
+            const Cx e = zn1 / tau1;
+            // a margin of 2 in the residual norm for the drift of the recurrences
+            if ((e.r * e.r + e.i * e.i) * S.rr <= 0.25 * S.tol2 * S.bb) M.done = 1;
+            if (!isfinite(e.r) || !isfinite(e.i)) {
+                M.done = 1;
+                C.on = 0;
+            }
+        }
+    }
+    ms[i] = M;
+    co[i] = C;
+}
+
+__global__ void __launch_bounds__(256) k_ms_update(Work w, int nm, Fld sf, Fld vf, Fld tf, MsFields f,
+                                                   const MsCoef* __restrict__ co) {
+    FS_WG_PROLOGUE(w)
+    const uint4* sb = fbase<P64>(sf, bd);
+    const uint4* vb = fbase<P64>(vf, bd);
+    const uint4* tb = fbase<P64>(tf, bd);
+    FS_SLOT_LOOP(w)
+        bool any = false;
+        for (int k = 0; k < nm; ++k) any |= co[sys * nm + k].on != 0;
+        if (!any) continue;
+        double sv[24], vv[24], tv[24];
+        load_sp<P64, double>(sb, nullptr, gs, slot, sv);
+        load_sp<P64, double>(vb, nullptr, gs, slot, vv);
+        load_sp<P64, double>(tb, nullptr, gs, slot, tv);
+        for (int k = 0; k < nm; ++k) {
+            const MsCoef C = co[sys * nm + k];
+            if (!C.on) continue;
+            uint4* xb = f.x[k] + (size_t)bd.slot_off * Tr<P64>::G;
+            uint4* pb = f.p[k] + (size_t)bd.slot_off * Tr<P64>::G;
+            double xv[24], pv[24];
+            load_sp<P64, double>(xb, nullptr, gs, slot, xv);
+            load_sp<P64, double>(pb, nullptr, gs, slot, pv);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) {
+                const Cx p = {pv[2 * j], pv[2 * j + 1]}, s = {sv[2 * j], sv[2 * j + 1]};
+                const Cx v = {vv[2 * j], vv[2 * j + 1]}, t = {tv[2 * j], tv[2 * j + 1]};
+                const Cx x = Cx{xv[2 * j], xv[2 * j + 1]} + cx(C.cxp) * p + cx(C.cxs) * s;
+                const Cx pn = cx(C.cpp) * p + cx(C.cps) * s + cx(C.cpv) * v + cx(C.cpt) * t;
+                xv[2 * j] = x.r;
+                xv[2 * j + 1] = x.i;
+                pv[2 * j] = pn.r;
+                pv[2 * j + 1] = pn.i;
+            }
+            store_sp<P64, double>(xb, nullptr, gs, slot, xv);
+            store_sp<P64, double>(pb, nullptr, gs, slot, pv);
+        }
+    FS_SLOT_LOOP_END
+    FS_WG_EPILOGUE
+}
+
 // ------------------------------------------------------------------ displacement + bilinear
 
 // phi(x) = U_z(x) phi_in(x + z) per spin (colour product), or phi_in(x) at p = 0;
@@ -1028,6 +1142,15 @@ void launch_unpack(int prec, const Work& w, double* dst, Fld src, long long sys_
                    hipStream_t s) {
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_unpack<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, dst, src, sys_stride,
                                            sys_map))
+}
+void launch_ms_scalars(int nsys, int nm, const double* d, const SysState* st, MsState* ms, MsCoef* co,
+                       hipStream_t s) {
+    const int n = nsys * nm;
+    if (n > 0) hipLaunchKernelGGL(k_ms_scalars, dim3((n + 255) / 256), dim3(256), 0, s, nsys, nm, d, st, ms, co);
+}
+void launch_ms_update(const Work& w, int nm, Fld s_, Fld v, Fld t, const MsFields& f, const MsCoef* co,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_ms_update, dim3(grid_of(w)), dim3(w.wg), 0, s, w, nm, s_, v, t, f, co);
 }
 void launch_scale_sys(const Work& w, Fld out, Fld in, const double* coef, hipStream_t s) {
     hipLaunchKernelGGL(k_scale_sys, dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, coef);

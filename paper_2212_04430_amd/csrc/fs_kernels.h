@@ -324,6 +324,32 @@ void launch_dslash(int prec, int mode, const Work& w, Fld out, Fld in, Fld aux, 
 void launch_axpy_s(int prec, const Work& w, Fld r, Fld v, const SysState* st, hipStream_t s);
 // x += alpha p + omega s, r = s - omega t for the systems that iterated (s held
 // in r), then p = r + beta (p - omega v) for those that continue
+// Multi-shift BiCGStab: the systems (A + d_k) x_k = b, k < nm, carried along the
+// base system A x = b of each (system) slot without operator applications of
+// their own.  Per (system, member): the recurrence state and this iteration's
+// update coefficients (complex, (re, im)).
+constexpr int MS_MAX = 16;
+struct MsState {
+    double zp[2], z[2], tau[2], ap[2], bp[2];  // zeta_{n-1}, zeta_n, tau_n, alpha_{n-1}, beta_{n-1}
+    int done, pad_;
+};
+struct MsCoef {
+    double cxp[2], cxs[2];                     // x += cxp p + cxs s
+    double cpp[2], cps[2], cpv[2], cpt[2];     // p = cpp p + cps s + cpv v + cpt t
+    int on, pad_;
+};
+struct MsFields {
+    uint4* x[MS_MAX];
+    uint4* p[MS_MAX];
+};
+// After the F_OMEGA finish: the members' scalars from the base's alpha, omega,
+// beta (systems that iterated, before any reliable update or restart); a member
+// stops once |zeta/tau| |r| <= tol |b| / 2 (its residual estimate, with a margin).
+void launch_ms_scalars(int nsys, int nm, const double* d, const SysState* st, MsState* ms, MsCoef* co,
+                       hipStream_t s);
+// Before the base's vector update (s held in r): every active member's x and p (FP64).
+void launch_ms_update(const Work& w, int nm, Fld s_, Fld v, Fld t, const MsFields& f, const MsCoef* co,
+                      hipStream_t s);
 void launch_update_xrp(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, Fld v, const SysState* st,
                        hipStream_t s);
 
