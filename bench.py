@@ -19,7 +19,8 @@ batched kernel (median of 100 launches timed with HIP events), the uneven
 half-precision batch (8^3x16, 12^3x24, 16^3x32, 24^3x48, the paper's six
 shifts, 24 Z4 vectors each) against the FP64 plain path, a 32^3 x 64 solve rate
 and single-RHS dslash (working set far above the 256 MB last-level cache), the
-same workload on the clover-improved operator (c_sw = 1), and the CPU oracle.
+same workload on the clover-improved operator (c_sw = 1), multi-shift BiCGStab on
+the sampling phase's shape, and the CPU oracle.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -242,6 +243,35 @@ def probed_estimate(L, ctx, nr, dims):
             "max_true_rel_residual": rep.max_rel_residual}
 
 
+def multishift_leg(L, ctx, n_rhs=24):
+    """The sampling phase's shape (the five sampling shifts from one Z4 vector per
+    rhs) solved by multi-shift BiCGStab (FP64, one Krylov space per rhs) against
+    independent batched FP64 solves, unpreconditioned and even-odd."""
+    import torch
+    w = WORKLOAD
+    V = int(np.prod(w["dims"]))
+    sig = [0.0, 0.05, 0.25, 0.5, 1.0]
+    B = torch.empty((n_rhs, V, 4, 3), dtype=torch.complex128, device="cuda")
+    for k in range(n_rhs):
+        B[k].copy_(L.fs_z4_noise(ctx, V, 7, 0, 0, k, device=B[k]))
+    out = {"shifts": sig, "rhs": n_rhs, "tol": w["tol"]}
+    for name, kw in (("multi_shift_f64", dict(multi_shift=1)), ("batched_f64", {}),
+                     ("batched_f64_even_odd", dict(even_odd=1))):
+        prm = L.solve_params(w["m0"], tol=w["tol"], storage="f64", batched=1, rhs_block=4, use_graph=1, **kw)
+        L.fs_solve_shifted(ctx, prm, sig, B[:4])  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st, _ = L.fs_solve_shifted(ctx, prm, sig, B)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"solves_per_s": round(len(sig) * n_rhs / dt, 2),
+                     "iters_per_system": round(float(np.mean([x.iters for x in st])), 2),
+                     "max_true_rel_residual": max(x.true_rel_residual for x in st)}
+    log(f"multi-shift f64: {out['multi_shift_f64']['solves_per_s']} solves/s against "
+        f"{out['batched_f64']['solves_per_s']} (independent), {out['batched_f64_even_odd']['solves_per_s']} (even-odd)")
+    return out
+
+
 def clover_leg(L, ctx, nr, n64, c_sw=1.0):
     """The same workload on the clover-improved operator (c_sw = 1, the tree-level
     coefficient): the batched FP32 even-odd estimate against the plain FP64
@@ -396,6 +426,7 @@ def main():
     ap.add_argument("--roofline-storage", default="f32", choices=["f64", "f32", "f16", "bf16"],
                     help="precision of the stencil timed by --roofline-only")
     ap.add_argument("--no-clover", action="store_true", help="skip the clover-improved operator leg")
+    ap.add_argument("--no-multishift", action="store_true", help="skip the multi-shift solver leg")
     ap.add_argument("--no-select", action="store_true", help="skip variance sampling and shift selection")
     ap.add_argument("--no-probe", action="store_true", help="skip the probed, spin-colour diluted estimate")
     ap.add_argument("--tuning-cache", default=None, help="autotune cache file (default: a temporary copy of the "
@@ -537,6 +568,7 @@ def main():
     log(f"dslash f32 batched even-odd hop: {ms_d:.4f} ms, {achieved:.0f} GB/s; full lattice {ms_full:.4f} ms, "
         f"{full_gbs:.0f} GB/s")
     clover = None if args.no_clover else clover_leg(L, ctx, nr, args.fp64_noise)
+    multishift = None if args.no_multishift else multishift_leg(L, ctx)
     select, sel_inputs = (None, None) if args.no_select else sampling_and_selection(L, ctx, nr)
     uneven = None if args.no_uneven else uneven_batch(L, args)
     probed = None if args.no_probe else probed_estimate(L, ctx, nr, dims)
@@ -605,6 +637,7 @@ def main():
         "dslash_32c64_single_rhs": headline,
         "mixed_half_precision": half or None,
         "clover_operator": clover,
+        "multi_shift_solver": multishift,
         "sampling_and_shift_selection": select,
         "probed_diluted_estimate": probed,
     }
