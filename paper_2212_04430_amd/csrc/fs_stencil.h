@@ -441,8 +441,10 @@ __device__ __forceinline__ void hop_tile(const LatDesc& ld, const uint4* __restr
 // live state does not fit take fewer rather than spill (FP64 arithmetic
 // doubles every register, BF16 needs its rounding temporaries).
 template <int P, int MODE> struct TileW {
-    // the rhat launches regenerate the shadow residual in their epilogue: two waves
-    static constexpr int v = (P == P32 || P == P16) ? ((MODE != D_RHAT && MODE != D_TS) ? 3 : 2) : 1;
+    // D_TS keeps eight FP64 partial sums live through the slice loop: at three
+    // waves it spills ~400 B per lane and the FP32 estimate loses 8%, so it takes
+    // two; D_RHAT (two partial sums) spills 44-88 B at three and gains 1%
+    static constexpr int v = (P == P32 || P == P16) ? (MODE != D_TS ? 3 : 2) : 1;
 };
 
 template <int P> constexpr int tile_nbuf() { return sizeof(typename Tr<P>::acc) == 4 ? 2 : 1; }
