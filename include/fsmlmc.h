@@ -197,14 +197,17 @@ typedef struct {
                               Krylov solver works on the even-site Schur complement
                               S = a - D_eo D_oe / a (a = 4 + m0 + sigma) and the
                               odd sites follow; the stopping rule is unchanged    */
-    int32_t multi_shift;   /* fs_solve_shifted only (0 elsewhere, else FS_E_ARG): 1 =
-                              one Krylov space per rhs for every shift -- BiCGStab on
-                              the smallest shift with the others carried along as
-                              shifted systems (their residuals are multiples of the
-                              base residual; no operator applications of their own);
-                              FP64 storage, even_odd = 0, plain operator, at most 17
-                              shifts; every solution's FP64 true residual is checked
-                              at exit (FS_E_NOCONV above tol)                      */
+    int32_t multi_shift;   /* fs_solve_shifted and fs_sample_variances only (0
+                              elsewhere, else FS_E_ARG): 1 = one Krylov space per rhs
+                              (per sample and source family in the sampling phase)
+                              for every shift -- BiCGStab on the smallest shift with
+                              the others carried along as shifted systems (their
+                              residuals are multiples of the base residual; no
+                              operator applications of their own); FP64 storage,
+                              even_odd = 0, plain operator, at most 17 shifts; every
+                              solution's FP64 true residual is checked at exit
+                              (FS_E_NOCONV above tol); iteration counts are each
+                              shift's own Krylov steps                             */
 } fs_solve_params;
 
 typedef struct {

@@ -1736,6 +1736,9 @@ void probed_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sigma_in, 
 // samples (Vbar_l(s_{q-1}, s_j)).  Slot order: singles i, then pairs (i, j).
 constexpr uint32_t kSamplingLevel = 0xFFFFFFFFu;
 
+void sampling_multishift(fs_ctx_s* c, const fs_solve_params* prm, const std::vector<double>& sh, int nch, int nr,
+                         BatchSolver& bs, const std::vector<NoiseKey>& keys);
+
 void sampling_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sh_in, int m, fs_level_stat* single,
                    fs_level_stat* pair, double* samples_out, double* iters_out, fs_est_report* report) {
     if (!prm || !sh_in || !single || !pair) fail(FS_E_ARG, "null argument");
@@ -1748,7 +1751,11 @@ void sampling_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sh_in, i
     if (prm->solve.max_iter < 1) fail(FS_E_ARG, "max_iter must be >= 1");
     if (prm->solve.rhs_block != 0 && !pow2_ok(prm->solve.rhs_block)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
     if (prm->hpe_order < 0 || prm->hpe_order > 16) fail(FS_E_ARG, "hpe_order must be in 0..16");
-    if (prm->solve.multi_shift != 0) fail(FS_E_ARG, "multi_shift applies to fs_solve_shifted only");
+    if (prm->solve.multi_shift) {
+        if (prm->solve.storage != P64) fail(FS_E_ARG, "multi-shift solves run in FP64 storage");
+        if (prm->solve.even_odd) fail(FS_E_ARG, "multi-shift solves need even_odd = 0");
+        if (c->c_sw != 0.0) fail(FS_E_ARG, "multi-shift solves use the plain operator (no clover term)");
+    }
     if (prm->hpe_order > 0 && c->c_sw != 0.0)
         fail(FS_E_ARG, "the hopping parameter expansion is implemented for the plain Wilson operator");
     std::vector<double> sh(sh_in, sh_in + m);
@@ -1807,7 +1814,8 @@ void sampling_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sh_in, i
     bs.setup(diag, idle, keys);
     DevBuf d_keys = to_device(keys.data(), sizeof(NoiseKey) * nsys, 0, s);
     launch_noise_block(P64, pl->work(P64, false), bs.b.f(), d_keys.as<NoiseKey>(), s);
-    bs.run();
+    if (prm->solve.multi_shift) sampling_multishift(c, &prm->solve, sh, nch, nr, bs, keys);
+    else bs.run();
 
     // bilinears, one pass per pairing
     static const GammaTab gt = make_gamma_tab();
@@ -2367,30 +2375,31 @@ double time_eo_apply_impl(fs_ctx c, int P, int n_sys, int nr, int var, int occ, 
     return (double)ms / n_launch;
 }
 
-// Multi-shift solve of X[s][r] = (D + sigma_s)^-1 B[r] (FP64, unpreconditioned):
-// one batched BiCGStab on the smallest shift per rhs, the other shifts carried
-// as members; then every solution's FP64 true residual.  dB, dX device,
-// canonical; stats as fs_solve_shifted.  Returns the worst status.
-fs_status ms_solve(fs_ctx_s* c, const fs_solve_params* prm, const double* sigma, int n_shift, const DevBuf& dB,
-                   int n_rhs, DevBuf& dX, fs_solve_stats* stats) {
+// Multi-shift core: the systems of plan pl (one lattice, FP64, unpreconditioned)
+// solved at every shift of `shifts` from one Krylov space each: batched
+// BiCGStab on shifts[base] (the smallest) with the others carried along as
+// members (launch_ms_scalars).  fill_b(bs) writes the sources into bs.b;
+// consume(k, x_k, states_k) receives each shift's solutions (plan layout) and
+// the states with their FP64 true residuals (rr_true; state S_DONE where the
+// residual meets tol and the base converged, else S_FAIL).
+template <class FillB, class Consume>
+void ms_core(fs_ctx_s* c, const fs_solve_params* prm, const std::vector<double>& shifts, Plan& pl,
+             const std::vector<char>& idle, const std::vector<NoiseKey>& rkeys, FillB&& fill_b, Consume&& consume) {
     hipStream_t s = c->stream;
+    const int n_shift = (int)shifts.size();
     int base = 0;
     for (int k = 1; k < n_shift; ++k)
-        if (sigma[k] < sigma[base]) base = k;
-    std::vector<int> member;  // shift index of member j
+        if (shifts[k] < shifts[base]) base = k;
+    std::vector<int> member;
     std::vector<double> dsh;
     for (int k = 0; k < n_shift; ++k)
         if (k != base) {
             member.push_back(k);
-            dsh.push_back(sigma[k] - sigma[base]);
+            dsh.push_back(shifts[k] - shifts[base]);
         }
     const int nm = (int)member.size();
-    const int nr = prm->batched ? (prm->rhs_block ? prm->rhs_block : tuned_nr(c, P64, n_rhs)) : 1;
-    const int nblk = (n_rhs + nr - 1) / nr;
-    std::vector<int> blk_lat(nblk, 0);
-    std::vector<fs_ctx_s*> lats{c};
-    auto pl = make_plan(blk_lat, lats, nr, tuned_wg(c, P64), s, tuned_ilp(c, P64), tuned_occ(c, P64));
-    const int nsys = pl->nsys;
+    const int nsys = pl.nsys;
+    const int nblk = (int)pl.blocks.size();
     SolveOpts o;
     o.P = P64;
     o.tol = prm->tol;
@@ -2399,8 +2408,118 @@ fs_status ms_solve(fs_ctx_s* c, const fs_solve_params* prm, const double* sigma,
     o.check_every = prm->check_every > 0 ? prm->check_every : 8;
     o.use_graph = prm->use_graph != 0;
     o.eo = false;
-    BatchSolver bs(*pl, lats, s, o);
-    std::vector<double> diag(nsys, 4.0 + prm->m0 + sigma[base]);
+    std::vector<fs_ctx_s*> lats{c};
+    BatchSolver bs(pl, lats, s, o);
+    bs.setup(std::vector<double>(nsys, 4.0 + prm->m0 + shifts[base]), idle, rkeys);
+    fill_b(bs);
+    // members: x = 0, p = b, recurrence state zeta = tau = alpha_prev = 1, beta_prev = 0
+    MultiShift ms;
+    ms.nm = nm;
+    ms.xs.resize(nm);
+    ms.ps.resize(nm);
+    std::memset(&ms.f, 0, sizeof(ms.f));
+    const size_t fbytes = (size_t)pl.total_slots * prec_group_bytes_spinor(P64);
+    for (int j = 0; j < nm; ++j) {
+        ms.xs[j].alloc(P64, pl.total_slots);
+        ms.ps[j].alloc(P64, pl.total_slots);
+        HC(hipMemsetAsync(ms.xs[j].v.p, 0, fbytes, s));
+        HC(hipMemcpyAsync(ms.ps[j].v.p, bs.b.v.p, fbytes, hipMemcpyDeviceToDevice, s));
+        ms.f.x[j] = ms.xs[j].v.as<uint4>();
+        ms.f.p[j] = ms.ps[j].v.as<uint4>();
+    }
+    if (nm > 0) {  // a single shift is the plain batched solve
+        std::vector<MsState> st0((size_t)nsys * nm);
+        for (auto& m : st0) {
+            std::memset(&m, 0, sizeof(m));
+            m.zp[0] = m.z[0] = m.tau[0] = m.ap[0] = 1.0;
+        }
+        ms.d_d = to_device(dsh.data(), sizeof(double) * nm, 0, s);
+        ms.d_state = to_device(st0.data(), sizeof(MsState) * st0.size(), 0, s);
+        ms.d_coef.alloc(sizeof(MsCoef) * st0.size());
+        bs.ms = &ms;
+    }
+    bs.run();
+    bs.ms = nullptr;
+    std::vector<MsState> msh((size_t)nsys * nm);
+    if (nm > 0) {
+        HC(hipMemcpyAsync(msh.data(), ms.d_state.p, sizeof(MsState) * msh.size(), hipMemcpyDeviceToHost, s));
+        HC(hipStreamSynchronize(s));
+    }
+    // true residuals of every solution: r = b - (D + sigma_k) x in FP64 and |r|^2
+    Field rtmp;
+    rtmp.alloc(P64, pl.total_slots);
+    const Work wsten = pl.work(P64, false, true);
+    DevBuf flags1(sizeof(int) * std::max(nblk, 1)), flags2(sizeof(int) * std::max(nblk, 1));
+    for (int k = 0; k < n_shift; ++k) {
+        const int j = k == base ? -1 : (int)(std::find(member.begin(), member.end(), k) - member.begin());
+        Fld xk = j < 0 ? bs.xhi.f() : ms.xs[j].f();
+        std::vector<double> dk(nsys, 4.0 + prm->m0 + shifts[k]);
+        std::vector<SysState> sk(bs.st_host);
+        for (int i = 0; i < nsys; ++i)
+            if (!idle[i]) sk[i].state = S_CHK;
+        DevBuf d_dk = to_device(dk.data(), sizeof(double) * nsys, 0, s);
+        DevBuf d_sk = to_device(sk.data(), sizeof(SysState) * nsys, 0, s);
+        launch_dslash(P64, D_RESID, wsten, rtmp.f(), xk, bs.b.f(), d_dk.as<double>(), d_sk.as<SysState>(), M_ALL,
+                      bs.part(), s, bs.rk());
+        launch_finish(F_TRUE, wsten, d_sk.as<SysState>(), bs.part(), flags1.as<int>(), flags2.as<int>(), s);
+        HC(hipGetLastError());
+        HC(hipMemcpyAsync(sk.data(), d_sk.p, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, s));
+        HC(hipStreamSynchronize(s));
+        for (int i = 0; i < nsys; ++i) {
+            if (idle[i]) continue;
+            const SysState& B0 = bs.st_host[i];
+            sk[i].state = (true_rel(sk[i]) <= prm->tol && B0.state == S_DONE) ? S_DONE : S_FAIL;
+            sk[i].iters = j < 0 ? B0.iters : msh[(size_t)i * nm + j].iters;  // the member's own Krylov steps
+            sk[i].n_rel = B0.n_rel;
+            sk[i].restarts = B0.restarts;
+        }
+        consume(k, xk, sk);
+        HC(hipStreamSynchronize(s));  // consume's host tables may die with its scope
+    }
+}
+
+// The sampling solves by ms_core: per chunk of nr samples one x-family (source z)
+// and one y-family (source g5 z) solved at every sampling shift from one Krylov
+// space; the solutions go to the blocks of the sampling plan (x(i, ch) =
+// 2 (i nch + ch), y = x + 1) in bs.xhi, and their states to bs.st_host.
+void sampling_multishift(fs_ctx_s* c, const fs_solve_params* prm, const std::vector<double>& sh, int nch, int nr,
+                         BatchSolver& bs, const std::vector<NoiseKey>& keys) {
+    hipStream_t s = c->stream;
+    std::vector<int> blk_lat(2 * nch, 0);
+    std::vector<fs_ctx_s*> lats{c};
+    auto pl = make_plan(blk_lat, lats, nr, tuned_wg(c, P64), s, tuned_ilp(c, P64), tuned_occ(c, P64));
+    const int nsys = pl->nsys;  // the shift-0 systems of the sampling plan, in the same order
+    std::vector<NoiseKey> k0(keys.begin(), keys.begin() + nsys);
+    std::vector<char> idle(nsys);
+    for (int i = 0; i < nsys; ++i) idle[i] = k0[i].pad != 0;
+    DevBuf d_k0 = to_device(k0.data(), sizeof(NoiseKey) * nsys, 0, s);
+    const size_t blk_bytes = (size_t)Tr<P64>::G * 16 * (size_t)c->V * nr;
+    ms_core(
+        c, prm, sh, *pl, idle, k0,
+        [&](BatchSolver& b2) { launch_noise_block(P64, pl->work(P64, false), b2.b.f(), d_k0.as<NoiseKey>(), s); },
+        [&](int k, Fld xk, const std::vector<SysState>& sk) {
+            for (int bb = 0; bb < 2 * nch; ++bb) {
+                const int ch = bb / 2, f = bb % 2;
+                const int bf = 2 * (k * nch + ch) + f;  // block of the sampling plan
+                HC(hipMemcpyAsync(reinterpret_cast<char*>(bs.xhi.v.p) + (size_t)bs.pl.blocks[bf].slot_off * Tr<P64>::G * 16,
+                                  reinterpret_cast<const char*>(xk.v) + (size_t)pl->blocks[bb].slot_off * Tr<P64>::G * 16,
+                                  blk_bytes, hipMemcpyDeviceToDevice, s));
+                for (int r = 0; r < nr; ++r) bs.st_host[(size_t)bf * nr + r] = sk[(size_t)bb * nr + r];
+            }
+        });
+}
+
+// X[s][r] = (D + sigma_s)^-1 B[r] by ms_core; dB, dX device, canonical; stats as
+// fs_solve_shifted.  Returns the worst status.
+fs_status ms_solve(fs_ctx_s* c, const fs_solve_params* prm, const double* sigma, int n_shift, const DevBuf& dB,
+                   int n_rhs, DevBuf& dX, fs_solve_stats* stats) {
+    hipStream_t s = c->stream;
+    const int nr = prm->batched ? (prm->rhs_block ? prm->rhs_block : tuned_nr(c, P64, n_rhs)) : 1;
+    const int nblk = (n_rhs + nr - 1) / nr;
+    std::vector<int> blk_lat(nblk, 0);
+    std::vector<fs_ctx_s*> lats{c};
+    auto pl = make_plan(blk_lat, lats, nr, tuned_wg(c, P64), s, tuned_ilp(c, P64), tuned_occ(c, P64));
+    const int nsys = pl->nsys;
     std::vector<char> idle(nsys);
     std::vector<int> src(nsys);
     std::vector<NoiseKey> rkeys(nsys);
@@ -2413,77 +2532,33 @@ fs_status ms_solve(fs_ctx_s* c, const fs_solve_params* prm, const double* sigma,
         rkeys[i].sample = (uint64_t)(i < n_rhs ? i : 0);
         rkeys[i].pad = idle[i] ? 1 : 0;
     }
-    bs.setup(diag, idle, rkeys);
     DevBuf d_src = to_device(src.data(), sizeof(int) * nsys, 0, s);
-    launch_pack(P64, pl->work(P64, false), bs.b.f(), dB.as<double>(), 24ll * c->V, d_src.as<int>(), s);
-    // members: x = 0, p = b, recurrence state zeta = tau = alpha_prev = 1, beta_prev = 0
-    MultiShift ms;
-    ms.nm = nm;
-    ms.xs.resize(nm);
-    ms.ps.resize(nm);
-    std::memset(&ms.f, 0, sizeof(ms.f));
-    const size_t fbytes = (size_t)pl->total_slots * prec_group_bytes_spinor(P64);
-    for (int j = 0; j < nm; ++j) {
-        ms.xs[j].alloc(P64, pl->total_slots);
-        ms.ps[j].alloc(P64, pl->total_slots);
-        HC(hipMemsetAsync(ms.xs[j].v.p, 0, fbytes, s));
-        HC(hipMemcpyAsync(ms.ps[j].v.p, bs.b.v.p, fbytes, hipMemcpyDeviceToDevice, s));
-        ms.f.x[j] = ms.xs[j].v.as<uint4>();
-        ms.f.p[j] = ms.ps[j].v.as<uint4>();
-    }
-    std::vector<MsState> st0((size_t)nsys * std::max(nm, 1));
-    for (auto& m : st0) {
-        std::memset(&m, 0, sizeof(m));
-        m.zp[0] = m.z[0] = m.tau[0] = m.ap[0] = 1.0;
-    }
-    if (nm > 0) {  // a single shift is the plain batched solve
-        ms.d_d = to_device(dsh.data(), sizeof(double) * nm, 0, s);
-        ms.d_state = to_device(st0.data(), sizeof(MsState) * st0.size(), 0, s);
-        ms.d_coef.alloc(sizeof(MsCoef) * st0.size());
-        bs.ms = &ms;
-    }
-    bs.run();
-    bs.ms = nullptr;
-    // true residuals of every solution: r = b - (D + sigma_k) x in FP64 and |r|^2
     fs_status worst = FS_OK;
-    Field rtmp;
-    rtmp.alloc(P64, pl->total_slots);
-    const Work wsten = pl->work(P64, false, true);
-    DevBuf flags1(sizeof(int) * std::max(nblk, 1)), flags2(sizeof(int) * std::max(nblk, 1));
-    for (int k = 0; k < n_shift; ++k) {
-        const int j = k == base ? -1 : (int)(std::find(member.begin(), member.end(), k) - member.begin());
-        Fld xk = j < 0 ? bs.xhi.f() : ms.xs[j].f();
-        std::vector<double> dk(nsys, 4.0 + prm->m0 + sigma[k]);
-        std::vector<SysState> sk(bs.st_host);
-        for (int i = 0; i < nsys; ++i)
-            if (!idle[i]) sk[i].state = S_CHK;
-        DevBuf d_dk = to_device(dk.data(), sizeof(double) * nsys, 0, s);
-        DevBuf d_sk = to_device(sk.data(), sizeof(SysState) * nsys, 0, s);
-        launch_dslash(P64, D_RESID, wsten, rtmp.f(), xk, bs.b.f(), d_dk.as<double>(), d_sk.as<SysState>(), M_ALL,
-                      bs.part(), s, bs.rk());
-        launch_finish(F_TRUE, wsten, d_sk.as<SysState>(), bs.part(), flags1.as<int>(), flags2.as<int>(), s);
-        std::vector<int> dst(nsys);
-        for (int i = 0; i < nsys; ++i) dst[i] = i < n_rhs ? k * n_rhs + i : -1;
-        DevBuf d_dst = to_device(dst.data(), sizeof(int) * nsys, 0, s);
-        launch_unpack(P64, pl->work(P64, false), dX.as<double>(), xk, 24ll * c->V, d_dst.as<int>(), s);
-        HC(hipGetLastError());
-        HC(hipMemcpyAsync(sk.data(), d_sk.p, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, s));
-        HC(hipStreamSynchronize(s));
-        for (int i = 0; i < n_rhs; ++i) {
-            const SysState& B0 = bs.st_host[i];
-            const double rel = true_rel(sk[i]);
-            const fs_status code = (rel <= prm->tol && B0.state == S_DONE) ? FS_OK : FS_E_NOCONV;
-            if (code != FS_OK) worst = code;
-            if (stats) {
-                fs_solve_stats& o2 = stats[k * n_rhs + i];
-                o2.iters = B0.iters;
-                o2.reliable_updates = B0.n_rel;
-                o2.status = code;
-                o2.restarts = B0.restarts;
-                o2.true_rel_residual = rel;
+    ms_core(
+        c, prm, std::vector<double>(sigma, sigma + n_shift), *pl, idle, rkeys,
+        [&](BatchSolver& bs) {
+            launch_pack(P64, pl->work(P64, false), bs.b.f(), dB.as<double>(), 24ll * c->V, d_src.as<int>(), s);
+        },
+        [&](int k, Fld xk, const std::vector<SysState>& sk) {
+            std::vector<int> dst(nsys);
+            for (int i = 0; i < nsys; ++i) dst[i] = i < n_rhs ? k * n_rhs + i : -1;
+            DevBuf d_dst = to_device(dst.data(), sizeof(int) * nsys, 0, s);
+            launch_unpack(P64, pl->work(P64, false), dX.as<double>(), xk, 24ll * c->V, d_dst.as<int>(), s);
+            HC(hipGetLastError());
+            HC(hipStreamSynchronize(s));
+            for (int i = 0; i < n_rhs; ++i) {
+                const fs_status code = sk[i].state == S_DONE ? FS_OK : FS_E_NOCONV;
+                if (code != FS_OK) worst = code;
+                if (stats) {
+                    fs_solve_stats& o2 = stats[k * n_rhs + i];
+                    o2.iters = sk[i].iters;
+                    o2.reliable_updates = sk[i].n_rel;
+                    o2.status = code;
+                    o2.restarts = sk[i].restarts;
+                    o2.true_rel_residual = true_rel(sk[i]);
+                }
             }
-        }
-    }
+        });
     return worst;
 }
 

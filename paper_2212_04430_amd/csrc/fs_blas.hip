@@ -811,6 +811,7 @@ __global__ void k_ms_scalars(int nsys, int nm, const double* __restrict__ dsh, c
             put(C.cpv, Cx{0.0, 0.0} - q * zn * al / tau);
             put(C.cpt, Cx{0.0, 0.0} - zn1 / tau1 * om);
             C.on = 1;
+            M.iters += 1;
             put(M.zp, zn);
             put(M.z, zn1);
             put(M.tau, tau1);

@@ -331,7 +331,7 @@ void launch_axpy_s(int prec, const Work& w, Fld r, Fld v, const SysState* st, hi
 constexpr int MS_MAX = 16;
 struct MsState {
     double zp[2], z[2], tau[2], ap[2], bp[2];  // zeta_{n-1}, zeta_n, tau_n, alpha_{n-1}, beta_{n-1}
-    int done, pad_;
+    int done, iters;                           // iters: Krylov steps the member took
 };
 struct MsCoef {
     double cxp[2], cxs[2];                     // x += cxp p + cxs s

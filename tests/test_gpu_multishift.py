@@ -52,11 +52,13 @@ def test_multishift_against_dense(L, nr, graph, sig):
         X, stats, code = L.fs_solve_shifted(ctx, prm, sig, B)
         assert code == 0
         _check(U, dims, m0, sig, B, X, stats, 1e-10, ofs.DenseSolver(U, dims, m0))
-        # every shift reports the base system's iteration count
+        # each shift reports the Krylov steps it took: the base (smallest shift) the most
         base = int(np.argmin(sig))
         for r in range(len(B)):
-            assert len({stats[i * len(B) + r].iters for i in range(len(sig))}) == 1
-            assert stats[base * len(B) + r].iters > 0
+            its = [stats[i * len(B) + r].iters for i in range(len(sig))]
+            assert its[base] == max(its) and min(its) > 0
+            for i, j in zip(np.argsort(sig)[:-1], np.argsort(sig)[1:]):
+                assert its[j] <= its[i]  # larger shifts converge no later
     finally:
         L.fs_destroy(ctx)
 

@@ -205,3 +205,26 @@ def test_hopping_expansion_singles(L, m0, storage, tol, ts):
         assert e.value.code == L.FS_E_ARG
     finally:
         L.fs_destroy(ctx)
+
+
+@pytest.mark.parametrize("nr", [4, 16])
+def test_sampling_multishift_per_sample_parity(L, ref_4444, nr):
+    """The sampling solves by multi-shift BiCGStab (one Krylov space per sample and
+    family for every sampling shift): the same per-sample parity as independent solves."""
+    dims, U, shifts, X_ref = ref_4444
+    print(f"sampling multishift nr={nr}", flush=True)
+    ctx = L.fs_create(dims, 0, 0)
+    try:
+        L.fs_upload_gauge(ctx, U)
+        prm = _params(L, 0.1, 12, 2, nr=nr)
+        prm.solve.multi_shift = 1
+        single, pair, X, iters, rep = L.fs_sample_variances(ctx, prm, shifts, want_samples=True)
+        assert rep.systems == 2 * 3 * 12 and rep.max_rel_residual <= 1e-12
+        assert iters[0] == max(iters) and np.all(np.diff(iters) <= 0)  # each shift's own Krylov steps
+        _check(L, single, pair, X, X_ref, 3, 1e-9)
+        prm.solve.storage = 2  # FP16: rejected
+        with pytest.raises(L.FsError) as e:
+            L.fs_sample_variances(ctx, prm, shifts)
+        assert e.value.code == L.FS_E_ARG
+    finally:
+        L.fs_destroy(ctx)
