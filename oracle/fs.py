@@ -231,8 +231,8 @@ def sampling_slots(m):
 # terms (computable exactly) plus that of Gamma Omega_p (H/a)^k (D + sigma)^-1,
 # whose stochastic estimate has the smaller variance when m0 + sigma is large.
 # The paper samples V_L that way at order k = 4 for the shifts with
-# m0 + s > 0.  (Plain Wilson operator; the generalized form replaces a by the
-# site-local diagonal block.)
+# m0 + s > 0.  With the clover term the expansion is the generalized one:
+# D_sw + sigma = A - H with the site-local A = C + a, and (H/a) becomes A^-1 H.
 # ---------------------------------------------------------------------------
 
 def hopping_apply(U, psi, m0, sigma, dims, antiperiodic=False):
@@ -241,12 +241,20 @@ def hopping_apply(U, psi, m0, sigma, dims, antiperiodic=False):
                                                                                   antiperiodic)
 
 
-def hpe_apply(U, x, m0, sigma, k, dims, antiperiodic=False):
-    """(H / a)^k x, a = 4 + m0 + sigma."""
+def hpe_apply(U, x, m0, sigma, k, dims, antiperiodic=False, C=None):
+    """(H / a)^k x, a = 4 + m0 + sigma; with the clover term C (per site, (V, 12, 12))
+    the generalized (A^-1 H)^k x, A = C + a.  H is the hopping term either way."""
     a = 4.0 + m0 + sigma
     w = np.asarray(x, np.complex128)
+    if C is not None:
+        A = C + a * np.eye(12)
     for _ in range(k):
-        w = hopping_apply(U, w, m0, sigma, dims, antiperiodic) / a
+        h = hopping_apply(U, w, m0, sigma, dims, antiperiodic)
+        if C is None:
+            w = h / a
+        else:
+            V = A.shape[0]
+            w = np.linalg.solve(A, h.reshape(V, 12, 1)).reshape(h.shape)
     return w
 
 
@@ -267,8 +275,7 @@ def sampling_samples(U, dims, shifts, n_samples, seed, gammas, p_max, solver, in
     With hpe_order = k > 0 the V_L samples of the shifts with m0 + s_i > 0
     are z_k^dagger Gamma Omega_p (H/a_i)^k x_i (the expansion's remainder).
     """
-    if hpe_order > 0 and getattr(solver, "c_sw", 0.0) != 0.0:
-        raise NotImplementedError("the expansion is written for the plain Wilson operator")
+    C = clover.clover_term(U, dims, solver.c_sw) if getattr(solver, "c_sw", 0.0) != 0.0 and hpe_order > 0 else None
     m = len(shifts)
     V = lat.volume(dims)
     slots = sampling_slots(m)
@@ -281,7 +288,7 @@ def sampling_samples(U, dims, shifts, n_samples, seed, gammas, p_max, solver, in
             y = z if kind == "single" else ys[i]
             x = xs[j]
             if kind == "single" and hpe_order > 0 and hpe_eligible(solver.m0, shifts[j]):
-                x = hpe_apply(U, x, solver.m0, shifts[j], hpe_order, dims, solver.ap)
+                x = hpe_apply(U, x, solver.m0, shifts[j], hpe_order, dims, solver.ap, C=C)
             X[q, k] = bilinears(U, dims, y, x, gammas, p_max)
     return X
 
@@ -295,13 +302,19 @@ def exact_sampling(solver, shifts, gammas, p_list, hpe_order=0):
     m = len(shifts)
     invs = [solver.inverse(s) for s in shifts]
     singles = list(invs)
-    if hpe_order > 0 and getattr(solver, "c_sw", 0.0) != 0.0:
-        raise NotImplementedError("the expansion is written for the plain Wilson operator")
     if hpe_order > 0:
-        Hd = (4.0 + solver.m0) * np.eye(solver.D0.shape[0]) - solver.D0  # D0 = D at sigma = 0
+        n = solver.D0.shape[0]
+        Ad = (4.0 + solver.m0) * np.eye(n, dtype=np.complex128)  # A at sigma = 0
+        csw = getattr(solver, "c_sw", 0.0)
+        if csw != 0.0:
+            Cs = clover.clover_term(U, dims, csw)
+            for q in range(V):
+                Ad[12 * q:12 * q + 12, 12 * q:12 * q + 12] += Cs[q]
+        Hd = Ad - solver.D0  # D0 = D at sigma = 0; H is the hopping term
         for i, s in enumerate(shifts):
             if hpe_eligible(solver.m0, s):
-                singles[i] = np.linalg.matrix_power(Hd / (4.0 + solver.m0 + s), hpe_order) @ invs[i]
+                M = np.linalg.solve(Ad + s * np.eye(n), Hd)  # A^-1 H
+                singles[i] = np.linalg.matrix_power(M, hpe_order) @ invs[i]
     slots = sampling_slots(m)
     T = np.zeros((len(slots), len(gammas), len(p_list)), dtype=np.complex128)
     Var = np.zeros((len(slots), len(gammas), len(p_list)))

@@ -128,3 +128,35 @@ def test_samples_are_bilinears_of_the_dense_remainder():
                     ref = np.vdot(z, G @ (R @ z))
                     assert abs(X[i, k, ig, p] - ref) < 1e-10 * max(1.0, abs(ref))
     assert np.array_equal(X[len(shifts):], X0[len(shifts):])
+
+
+def test_generalized_expansion_with_the_clover_term():
+    """D_sw + sigma = A - H with A = C + a: the identity
+    (D_sw + sigma)^-1 = sum_{j<k} (A^-1 H)^j A^-1 + (A^-1 H)^k (D_sw + sigma)^-1
+    with the dense clover inverse; H is the Wilson hopping term; the sampled
+    remainder equals the bilinears of the dense remainder."""
+    from oracle import clover as cl
+    dims = (4, 4, 2, 2)
+    U = synth.gauge_field(dims, eps=0.4, seed=3)
+    m0, sigma, csw, k = 0.2, 0.1, 1.3, 4
+    V = lat.volume(dims)
+    C = cl.clover_term(U, dims, csw)
+    A = (4.0 + m0 + sigma) * np.eye(12 * V, dtype=np.complex128)
+    for q in range(V):
+        A[12 * q:12 * q + 12, 12 * q:12 * q + 12] += C[q]
+    D = cl.clover_dense(U, m0, sigma, csw, dims)
+    H = A - D
+    assert np.abs(H - _dense_h(U, dims)).max() < 1e-13  # the hopping term does not change
+    inv = np.linalg.inv(D)
+    M = np.linalg.solve(A, H)
+    lhs = sum(np.linalg.matrix_power(M, j) @ np.linalg.inv(A) for j in range(k)) + np.linalg.matrix_power(M, k) @ inv
+    assert np.abs(lhs - inv).max() < 1e-12 * np.abs(inv).max()
+    solver = ofs.DenseSolver(U, dims, m0, c_sw=csw)
+    X = ofs.sampling_samples(U, dims, [0.0, sigma], 2, 5, [0, 11], 1, solver, hpe_order=k)
+    z = z4_noise(V, 5, 0, ofs.SAMPLING_LEVEL, 1).ravel()
+    R = np.linalg.matrix_power(M, k) @ inv
+    for ig, n in enumerate([0, 11]):
+        for p in range(2):
+            G = lat.gamma_dense(n, V) @ lat.omega_dense(U, p, dims)
+            ref = np.vdot(z, G @ (R @ z))
+            assert abs(X[1, 1, ig, p] - ref) < 1e-10 * max(1.0, abs(ref))
