@@ -343,13 +343,15 @@ fs_status fs_estimate(fs_ctx ctx, const fs_est_params* prm, const double* sigma,
  *   pair[i][j]    samples y_i^+ Gamma_n Omega_p x_j, j >= i  (Vbar_l(s_i, s_j), eq. bar_vl;
  *                 V_l = (s_j - s_i)^2 Vbar_l, eq. sampled_prod)
  * each reported as mean, eq. practical_variance and the (N-1) form.
- * With prm->hpe_order = k > 0 (plain Wilson operator only, FS_E_ARG with a
- * clover term) the single samples of every shift with m0 + s_i > 0 are
- * z_k^+ Gamma_n Omega_p (H/a_i)^k x_i, where D + s_i = a_i - H, a_i = 4 + m0 + s_i:
- * the stochastic part of the hopping parameter expansion
+ * With prm->hpe_order = k > 0 the single samples of every shift with
+ * m0 + s_i > 0 are z_k^+ Gamma_n Omega_p (H/a_i)^k x_i, where D + s_i = a_i - H,
+ * a_i = 4 + m0 + s_i: the stochastic part of the hopping parameter expansion
  *   (D + s)^-1 = sum_{j<k} (H/a)^j / a + (H/a)^k (D + s)^-1,
  * whose variance is the smaller one when m0 + s is large (Sec. 3.1 uses k = 4).
- * The traces of the first k terms are not computed here.
+ * With the clover term it is the generalized expansion: a_i is replaced by the
+ * site-local A_i = C + a_i, i.e. (A_i^-1 H)^k (inverse blocks of C + a_i formed in
+ * FP64 at every site; FS_E_ARG where one is singular).  The traces of the first
+ * k terms are not computed here.
  *   shifts       s[0..m-1] with s[0] = 0, strictly increasing, 1 <= m <= 16
  *   prm          seed, n_noise (the N_s samples, >= 2), gamma_mask, p_max, solver
  *   single       [m][16][p_max+1]

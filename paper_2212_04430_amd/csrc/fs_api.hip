@@ -1756,8 +1756,6 @@ void sampling_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sh_in, i
         if (prm->solve.even_odd) fail(FS_E_ARG, "multi-shift solves need even_odd = 0");
         if (c->c_sw != 0.0) fail(FS_E_ARG, "multi-shift solves use the plain operator (no clover term)");
     }
-    if (prm->hpe_order > 0 && c->c_sw != 0.0)
-        fail(FS_E_ARG, "the hopping parameter expansion is implemented for the plain Wilson operator");
     std::vector<double> sh(sh_in, sh_in + m);
     if (sh[0] != 0.0) fail(FS_E_ARG, "shifts[0] must be 0");
     for (int i = 0; i + 1 < m; ++i)
@@ -1842,10 +1840,42 @@ void sampling_impl(fs_ctx_s* c, const fs_est_params* prm, const double* sh_in, i
             for (int i = 0; i < nsys; ++i) coef[i] = -1.0 / diag[i];
             DevBuf d_zero = to_device(zero.data(), sizeof(double) * nsys, 0, s);
             DevBuf d_coef = to_device(coef.data(), sizeof(double) * nsys, 0, s);
+            // with the clover term the factor is A^-1 = (C + a)^-1 at every site (the
+            // generalized expansion): inverse blocks of both parities per eligible shift
+            DevBuf d_inv, d_off;
+            Clv cfull;
+            if (c->c_sw != 0.0) {
+                const int vh = c->V / 2;
+                std::vector<long long> off(nsys, 0);
+                std::map<double, long long> fld;
+                for (const BlockDesc& bd : eb)
+                    for (int r = 0; r < nr; ++r) {
+                        const int sys = bd.sys0 + r;
+                        auto it = fld.find(diag[sys]);
+                        if (it == fld.end()) it = fld.emplace(diag[sys], (long long)fld.size() * 72 * vh).first;
+                        off[sys] = it->second;
+                    }
+                d_inv.alloc((size_t)fld.size() * 72 * vh * 16);
+                DevBuf bad(sizeof(int));
+                HC(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+                for (const auto& kv : fld)
+                    for (int par = 0; par < 2; ++par)
+                        launch_clover_invert(c->clv[P64].as<uint4>() + (size_t)par * 36 * vh, vh, kv.first,
+                                             d_inv.as<uint4>() + kv.second + (size_t)par * 36 * vh, nullptr,
+                                             bad.as<int>(), s);
+                int h_bad = 0;
+                HC(hipMemcpyAsync(&h_bad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+                HC(hipStreamSynchronize(s));
+                if (h_bad) fail(FS_E_ARG, "C + 4 + m0 + s is singular at a site");
+                d_off = to_device(off.data(), sizeof(long long) * nsys, 0, s);
+                cfull.inv = d_inv.as<uint4>();
+                cfull.off = d_off.as<long long>();
+            }
             for (int it = 0; it < prm->hpe_order; ++it) {
                 launch_dslash(P64, D_PLAIN, sp->work(P64, false, true), phi1.f(), whpe.f(), Fld(),
                               d_zero.as<double>(), nullptr, M_ALL, nullptr, s);
-                launch_scale_sys(sp->work(P64, false), whpe.f(), phi1.f(), d_coef.as<double>(), s);
+                if (c->c_sw != 0.0) launch_clover_inv_full(sp->work(P64, false), whpe.f(), phi1.f(), cfull, s);
+                else launch_scale_sys(sp->work(P64, false), whpe.f(), phi1.f(), d_coef.as<double>(), s);
             }
             HC(hipGetLastError());
             HC(hipStreamSynchronize(s));  // the tables die with this scope

@@ -52,6 +52,11 @@ void launch_clover_invert(const uint4* c64_odd, int vh, double a, uint4* inv64, 
 void launch_clover_bo_inv(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld out, const Clv& cl64,
                           hipStream_t s);
 
+// out = -(C + a_sys)^-1 in over every site of a full-lattice plan (FP64), with
+// cl64.inv + cl64.off[sys] the system's inverse blocks of both parities
+// ([2][36][V/2], e.g. from launch_clover_invert on each parity).
+void launch_clover_inv_full(const Work& w, Fld out, Fld in, const Clv& cl64, hipStream_t s);
+
 // out += C in over every site of a full-lattice plan (FP64 or FP32 storage;
 // the lattices' ld.clv in that precision).
 void launch_clover_add(int prec, const Work& w, Fld out, Fld in, hipStream_t s);

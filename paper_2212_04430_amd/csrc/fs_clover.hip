@@ -315,6 +315,31 @@ __global__ void __launch_bounds__(256) k_clover_bo_inv(Work w, const BlockDesc* 
     FS_WG_EPILOGUE
 }
 
+// out = -(C + a_sys)^-1 in at every site of a full-lattice plan (FP64): cl.inv +
+// cl.off[sys] holds the system's inverse blocks for both parities, [2][36][V/2].
+__global__ void __launch_bounds__(256) k_clover_inv_full(Work w, Fld out, Fld in, Clv cl) {
+    FS_WG_PROLOGUE(w)
+    const uint4* ib = in.v + (size_t)bd.slot_off * Tr<P64>::G;
+    uint4* ob = out.v + (size_t)bd.slot_off * Tr<P64>::G;
+    const size_t vh = (size_t)ld.V >> 1;
+    FS_SLOT_LOOP(w)
+        const int site = (int)(slot >> w.lognr);
+        int c = site, par = 0;
+        for (int k = 0; k < 4; ++k) {
+            par += c % ld.L[k];
+            c /= ld.L[k];
+        }
+        par &= 1;
+        double v[24];
+        load_sp<P64, double>(ib, nullptr, gs, slot, v);
+        clv_mul<P64, double>(cl.inv + cl.off[sys] + (size_t)par * 36 * vh, vh, (size_t)(site >> 1), v);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) v[k] = -v[k];
+        store_sp<P64, double>(ob, nullptr, gs, slot, v);
+    FS_SLOT_LOOP_END
+    FS_WG_EPILOGUE
+}
+
 template <int P>
 __global__ void __launch_bounds__(256) k_clover_add(Work w, Fld out, Fld in) {
     using A = typename Tr<P>::acc;
@@ -401,6 +426,10 @@ void launch_clover_invert(const uint4* c64_odd, int vh, double a, uint4* inv64, 
 void launch_clover_bo_inv(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld out, const Clv& cl64,
                           hipStream_t s) {
     hipLaunchKernelGGL(k_clover_bo_inv, dim3(grid_of(wh)), dim3(wh.wg), 0, s, wh, fblocks, bfull, out, cl64);
+}
+
+void launch_clover_inv_full(const Work& w, Fld out, Fld in, const Clv& cl64, hipStream_t s) {
+    hipLaunchKernelGGL(k_clover_inv_full, dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cl64);
 }
 
 void launch_clover_add(int prec, const Work& w, Fld out, Fld in, hipStream_t s) {

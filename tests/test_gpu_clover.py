@@ -199,3 +199,32 @@ def test_full_size_solves_at_the_benchmark_configuration(L):
         assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
     finally:
         L.fs_destroy(ctx)
+
+
+@pytest.mark.parametrize("storage,tol,ts", [("f64", 1e-12, 1e-9), ("f32", 1e-10, 1e-7)])
+def test_sampling_generalized_expansion(L, storage, tol, ts):
+    """The variance-sampling singles through the generalized hopping parameter
+    expansion (A^-1 H)^4, A = C + a (Sec. 3.1), on the clover operator, against
+    the oracle per sample."""
+    dims = (4, 4, 4, 4)
+    m0, csw = 0.1, 1.2
+    U = synth.gauge_field(dims, eps=0.3, seed=0)
+    shifts = [0.0, 0.3, 1.0]
+    dense = ofs.DenseSolver(U, dims, m0, c_sw=csw)
+    X_ref = ofs.sampling_samples(U, dims, shifts, 8, seed=3, gammas=list(range(16)), p_max=1, solver=dense,
+                                 hpe_order=4)
+    print(f"clover sampling hpe {storage}", flush=True)
+    ctx = L.fs_create(dims, 0, 0)
+    try:
+        L.fs_upload_gauge(ctx, U)
+        L.fs_set_clover(ctx, csw)
+        sp = L.solve_params(m0, tol=tol, storage=storage, batched=1, rhs_block=4, use_graph=1, even_odd=1)
+        prm = L.fs_est_params(3, 8, 0, 1, sp)
+        prm.hpe_order = 4
+        single, pair, X, _, rep = L.fs_sample_variances(ctx, prm, shifts, want_samples=True)
+        assert rep.max_rel_residual <= tol
+        scale = np.abs(X_ref).mean(axis=1)
+        scale = np.where(scale > 0, scale, 1.0)
+        assert (np.abs(X - X_ref).max(axis=1) / scale).max() <= ts
+    finally:
+        L.fs_destroy(ctx)
