@@ -870,7 +870,7 @@ struct BatchSolver {
     SolveOpts o;
     Field b, xhi, rhi, r, p, v, t, xlo;
     Field sb_, sx_, sr_, tmp, tmp64;  // even-odd: FP64 Schur b, x, r; odd-site scratch
-    DevBuf d_diag, d_st, d_part, d_flags, d_rkeys, d_vl;
+    DevBuf d_diag, d_st, d_part, d_flags, d_rkeys, d_rc, d_vl;  // d_rc: shadow-residual code words per slot
     MultiShift* ms = nullptr;  // optional members of a multi-shift solve (FP64, full lattice)
     // clover term: per (lattice, shift) the inverses of C + a at the odd sites
     bool clv = false;
@@ -906,6 +906,7 @@ struct BatchSolver {
             tmp.alloc(o.P, S);
         }
         for (Field* f : {&r, &p, &v, &t, &xlo}) f->alloc(o.P, S);
+        d_rc.alloc(sizeof(uint32_t) * (size_t)S);
         d_diag.alloc(sizeof(double) * pl.nsys);
         d_st.alloc(sizeof(SysState) * pl.nsys);
         // partial sums: at most 8 doubles per rhs per workgroup (32 for the hop
@@ -995,6 +996,7 @@ struct BatchSolver {
         cl32.off = d_off32.as<long long>();
     }
     const NoiseKey* rk() const { return d_rkeys.as<NoiseKey>(); }
+    uint32_t* rc() { return d_rc.as<uint32_t>(); }
     // the FP64 fields of the system the iteration solves
     Field& fb() { return o.eo ? sb_ : b; }
     Field& fx() { return o.eo ? sx_ : xhi; }
@@ -1006,19 +1008,19 @@ struct BatchSolver {
     void apply(int prec, int mode, const Work& ws, Fld out, Fld in, Fld aux, int mask, Fld scratch) {
         const double* dg = d_diag.as<double>();
         if (!o.eo) {
-            launch_dslash(prec, mode, ws, out, in, aux, dg, st(), mask, part(), s, rk());
+            launch_dslash(prec, mode, ws, out, in, aux, dg, st(), mask, part(), s, rc());
             return;
         }
         const int hp = mode == D_RESID ? P64 : prec;
         if (clv) {  // the hop's odd-site output times (C_o + a)^-1, then (C_e + a) in - D_eo (.)
-            launch_dslash_eo_clv(hp, D_HOP, ws, scratch, in, Fld(), Fld(), dg, st(), mask, part(), s, rk(), 1,
+            launch_dslash_eo_clv(hp, D_HOP, ws, scratch, in, Fld(), Fld(), dg, st(), mask, part(), s, rc(), 1,
                                  clv_of(hp));
-            launch_dslash_eo_clv(hp, mode, ws, out, scratch, in, aux, dg, st(), mask, part(), s, rk(), 0,
+            launch_dslash_eo_clv(hp, mode, ws, out, scratch, in, aux, dg, st(), mask, part(), s, rc(), 0,
                                  clv_of(hp));
             return;
         }
-        launch_dslash_eo(hp, D_HOP, ws, scratch, in, Fld(), Fld(), dg, st(), mask, part(), s, rk(), 1);
-        launch_dslash_eo(hp, mode, ws, out, scratch, in, aux, dg, st(), mask, part(), s, rk(), 0);
+        launch_dslash_eo(hp, D_HOP, ws, scratch, in, Fld(), Fld(), dg, st(), mask, part(), s, rc(), 1);
+        launch_dslash_eo(hp, mode, ws, out, scratch, in, aux, dg, st(), mask, part(), s, rc(), 0);
     }
 
     SysState* st() { return d_st.as<SysState>(); }
@@ -1083,7 +1085,7 @@ struct BatchSolver {
         launch_finish(F_TRUE, wpd, st(), part(), f_conv(), f_pend(), s);  // clears f_pend
         build_list(f_conv(), vl_conv);
         const Work wc = listed(vl_conv, o.P, false);
-        launch_convert(o.P, wc, fr().f(), r.f(), rk(), p.f(), st(), part(), s);
+        launch_convert(o.P, wc, fr().f(), r.f(), rk(), rc(), p.f(), st(), part(), s);
         launch_finish(F_RESUME, wc, st(), part(), f_run(), f_conv(), s);  // clears f_conv
         build_list(f_run(), vl_run);
     }
@@ -1144,7 +1146,8 @@ struct BatchSolver {
             }
             launch_finish(F_BNORM, wp, st(), part(), nullptr, nullptr, s);
         }
-        launch_init(o.P, pl.work(o.P, false), fb().f(), fx().f(), xlo.f(), fr().f(), r.f(), rk(), p.f(), part(), s);
+        launch_init(o.P, pl.work(o.P, false), fb().f(), fx().f(), xlo.f(), fr().f(), r.f(), rk(), rc(), p.f(), part(),
+                    s);
         launch_finish(F_INIT, pl.work(o.P, false), st(), part(), f_run(), nullptr, s);
         {
             const Work w = cur->work(o.P, false);
@@ -2374,10 +2377,12 @@ double time_eo_apply_impl(fs_ctx c, int P, int n_sys, int nr, int var, int occ, 
     }
     DevBuf d_keys = to_device(keys.data(), sizeof(NoiseKey) * keys.size(), 0, s);
     launch_noise_block(P, pl->work(P, false), in.f(), d_keys.as<NoiseKey>(), s);
+    DevBuf d_rc(sizeof(uint32_t) * (size_t)pl->total_slots);
+    launch_rhat_codes(pl->work(P, false), d_keys.as<NoiseKey>(), d_rc.as<uint32_t>(), s);
     std::vector<double> diag(pl->nsys, 4.1);
     DevBuf d_diag = to_device(diag.data(), sizeof(double) * diag.size(), 0, s);
-    // the Schur launch's partial sums read each system's shadow-residual key and
-    // restart count (all systems "running", no restarts)
+    // the Schur launch's partial sums read each system's state (all "running")
+    // and its shadow residual's code words
     std::vector<SysState> sts(pl->nsys);
     std::memset(sts.data(), 0, sizeof(SysState) * sts.size());
     DevBuf d_st = to_device(sts.data(), sizeof(SysState) * sts.size(), 0, s);
@@ -2386,9 +2391,9 @@ double time_eo_apply_impl(fs_ctx c, int P, int n_sys, int nr, int var, int occ, 
     const Work w = pl->work(P, false, true);
     auto apply = [&]() {
         launch_dslash_eo(P, D_HOP, w, tmp.f(), in.f(), Fld(), Fld(), d_diag.as<double>(), d_st.as<SysState>(), M_ALL,
-                         nullptr, s, d_keys.as<NoiseKey>(), 1);
+                         nullptr, s, d_rc.as<uint32_t>(), 1);
         launch_dslash_eo(P, D_TS, w, out.f(), tmp.f(), in.f(), Fld(), d_diag.as<double>(), d_st.as<SysState>(),
-                         M_ALL, d_part.as<double>(), s, d_keys.as<NoiseKey>(), 0);
+                         M_ALL, d_part.as<double>(), s, d_rc.as<uint32_t>(), 0);
     };
     for (int i = 0; i < 2; ++i) apply();
     hipEvent_t e0, e1;
@@ -2490,7 +2495,7 @@ void ms_core(fs_ctx_s* c, const fs_solve_params* prm, const std::vector<double>&
         DevBuf d_dk = to_device(dk.data(), sizeof(double) * nsys, 0, s);
         DevBuf d_sk = to_device(sk.data(), sizeof(SysState) * nsys, 0, s);
         launch_dslash(P64, D_RESID, wsten, rtmp.f(), xk, bs.b.f(), d_dk.as<double>(), d_sk.as<SysState>(), M_ALL,
-                      bs.part(), s, bs.rk());
+                      bs.part(), s, bs.rc());
         launch_finish(F_TRUE, wsten, d_sk.as<SysState>(), bs.part(), flags1.as<int>(), flags2.as<int>(), s);
         HC(hipGetLastError());
         HC(hipMemcpyAsync(sk.data(), d_sk.p, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, s));

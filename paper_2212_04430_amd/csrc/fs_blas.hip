@@ -271,11 +271,12 @@ __global__ void __launch_bounds__(256) k_fold(Work w, Fld xhi, Fld xlo, const Sy
     FS_WG_EPILOGUE
 }
 
-// r = round(r_hi); restart systems also set p = r (their shadow residual is a
-// fresh Z4 stream).  Partials (rhat, r), |r|^2
+// r = round(r_hi); restart systems also set p = r and write the code words of
+// their fresh shadow residual.  Partials (rhat, r), |r|^2
 template <int P>
-__global__ void __launch_bounds__(256) k_convert(Work w, Fld rhi, Fld r, const NoiseKey* __restrict__ rk, Fld p,
-                                                 const SysState* __restrict__ st, double* __restrict__ part) {
+__global__ void __launch_bounds__(256) k_convert(Work w, Fld rhi, Fld r, const NoiseKey* __restrict__ rk,
+                                                 uint32_t* __restrict__ rc, Fld p, const SysState* __restrict__ st,
+                                                 double* __restrict__ part) {
     using A = typename Tr<P>::acc;
     FS_WG_PROLOGUE(w)
     double acc[3] = {0.0, 0.0, 0.0};
@@ -293,24 +294,37 @@ __global__ void __launch_bounds__(256) k_convert(Work w, Fld rhi, Fld r, const N
         store_sp<P, A>(rb, rn, gs, slot, q);
         if (s == S_RST) store_sp<P, A>(fbase_w<P>(p, bd), nbase(p, bd), gs, slot, q);
         round_sp<P, A>(q);  // the stored value the iteration will see
-        A hv[24];
-        rhat_site<A>(rk[sys], st[sys].restarts, (long long)(slot >> w.lognr), hv);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const double hr = hv[2 * k], hi = hv[2 * k + 1], qr = q[2 * k], qi = q[2 * k + 1];
-            acc[0] += hr * qr + hi * qi;
-            acc[1] += hr * qi - hi * qr;
-            acc[2] += qr * qr + qi * qi;
+        uint32_t code;
+        if (s == S_RST) {
+            code = rhat_code(rk[sys], st[sys].restarts, (long long)(slot >> w.lognr));
+            rc[bd.slot_off + slot] = code;
+        } else {
+            code = rc[bd.slot_off + slot];
         }
+        rhat_code_dots<1, A>(code, q, q, acc, acc);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[2] += (double)q[k] * (double)q[k];
     FS_SLOT_LOOP_END
     block_partials<3, 4>(acc, w.nr, part, wg_id);
     FS_WG_EPILOGUE
 }
 
-// x_hi = x_lo = 0, r_hi = b, r = p = round(b).  Partials |b|^2, (rhat, r), |r|^2
+// The shadow residual's code words of every slot of the plan (restart count 0).
+__global__ void __launch_bounds__(256) k_rhat_codes(Work w, const NoiseKey* __restrict__ rk,
+                                                    uint32_t* __restrict__ rc) {
+    FS_WG_PROLOGUE(w)
+    FS_SLOT_LOOP(w)
+        rc[bd.slot_off + slot] = rhat_code(rk[sys], 0, (long long)(slot >> w.lognr));
+    FS_SLOT_LOOP_END
+    FS_WG_EPILOGUE
+}
+
+// x_hi = x_lo = 0, r_hi = b, r = p = round(b), the shadow residual's code
+// words.  Partials |b|^2, (rhat, r), |r|^2
 template <int P>
 __global__ void __launch_bounds__(256) k_init(Work w, Fld bf, Fld xhi, Fld xlo, Fld rhi, Fld r,
-                                              const NoiseKey* __restrict__ rk, Fld p, double* __restrict__ part) {
+                                              const NoiseKey* __restrict__ rk, uint32_t* __restrict__ rc, Fld p,
+                                              double* __restrict__ part) {
     using A = typename Tr<P>::acc;
     FS_WG_PROLOGUE(w)
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -334,15 +348,11 @@ __global__ void __launch_bounds__(256) k_init(Work w, Fld bf, Fld xhi, Fld xlo, 
         store_sp<P, A>(fbase_w<P>(r, bd), nbase(r, bd), gs, slot, q);
         store_sp<P, A>(fbase_w<P>(p, bd), nbase(p, bd), gs, slot, q);
         round_sp<P, A>(q);  // the stored value
-        A hv[24];
-        rhat_site<A>(rk[sys], 0, (long long)(slot >> w.lognr), hv);
+        const uint32_t code = rhat_code(rk[sys], 0, (long long)(slot >> w.lognr));
+        rc[bd.slot_off + slot] = code;
+        rhat_code_dots<1, A>(code, q, q, acc + 1, acc + 1);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const double hr = hv[2 * k], hi = hv[2 * k + 1], qr = q[2 * k], qi = q[2 * k + 1];
-            acc[1] += hr * qr + hi * qi;
-            acc[2] += hr * qi - hi * qr;
-            acc[3] += qr * qr + qi * qi;
-        }
+        for (int k = 0; k < 24; ++k) acc[3] += (double)q[k] * (double)q[k];
     FS_SLOT_LOOP_END
     block_partials<4, 4>(acc, w.nr, part, wg_id);
     FS_WG_EPILOGUE
@@ -1105,15 +1115,18 @@ void launch_update_xrp(int prec, const Work& w, Fld x, Fld p, Fld r, Fld t, Fld 
 void launch_fold(int prec, const Work& w, Fld xhi, Fld xlo, const SysState* st, hipStream_t s) {
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_fold<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, xhi, xlo, st))
 }
-void launch_convert(int prec, const Work& w, Fld rhi, Fld r, const NoiseKey* rk, Fld p, const SysState* st,
-                    double* part, hipStream_t s) {
-    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_convert<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, rhi, r, rk, p, st,
-                                           part))
+void launch_convert(int prec, const Work& w, Fld rhi, Fld r, const NoiseKey* rk, uint32_t* rc, Fld p,
+                    const SysState* st, double* part, hipStream_t s) {
+    FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_convert<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, rhi, r, rk, rc, p,
+                                           st, part))
 }
-void launch_init(int prec, const Work& w, Fld b, Fld xhi, Fld xlo, Fld rhi, Fld r, const NoiseKey* rk, Fld p,
-                 double* part, hipStream_t s) {
+void launch_rhat_codes(const Work& w, const NoiseKey* rk, uint32_t* rc, hipStream_t s) {
+    hipLaunchKernelGGL(k_rhat_codes, dim3(grid_of(w)), dim3(w.wg), 0, s, w, rk, rc);
+}
+void launch_init(int prec, const Work& w, Fld b, Fld xhi, Fld xlo, Fld rhi, Fld r, const NoiseKey* rk, uint32_t* rc,
+                 Fld p, double* part, hipStream_t s) {
     FS_DISPATCH_P(prec, hipLaunchKernelGGL(k_init<PP>, dim3(grid_of(w)), dim3(w.wg), 0, s, w, b, xhi, xlo, rhi, r,
-                                           rk, p, part))
+                                           rk, rc, p, part))
 }
 void launch_finish(int stage, const Work& w, SysState* st, const double* part, int* out, int* out2, hipStream_t s) {
     Work wf = w;

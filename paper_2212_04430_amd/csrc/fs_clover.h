@@ -65,7 +65,7 @@ void launch_clover_add(int prec, const Work& w, Fld out, Fld in, hipStream_t s);
 // FP32): D_HOP (odd output) is followed by (C_o + a)^-1, the Schur modes form
 // (C_e + a) in - D_eo (hop input).
 void launch_dslash_eo_clv(int prec, int mode, const Work& w, Fld out, Fld in, Fld cen, Fld aux, const double* diag,
-                          const SysState* st, int mask, double* part, hipStream_t s, const NoiseKey* rk, int par_out,
+                          const SysState* st, int mask, double* part, hipStream_t s, const uint32_t* rc, int par_out,
                           const Clv& cl);
 
 // Even-odd source with the clover term: bh = b_e - D_eo bo_inv (bo_inv from

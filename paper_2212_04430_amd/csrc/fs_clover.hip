@@ -370,13 +370,13 @@ __global__ void __launch_bounds__(256) k_clover_add(Work w, Fld out, Fld in) {
 
 template <int P>
 void launch_eo_clv_p(int mode, const Work& w, Fld out, Fld in, Fld cen, Fld aux, const double* diag,
-                     const SysState* st, int mask, double* part, hipStream_t s, const NoiseKey* rk, int par_out,
+                     const SysState* st, int mask, double* part, hipStream_t s, const uint32_t* rc, int par_out,
                      const Clv& cl) {
     switch (mode) {
-        case D_HOP: launch_eo_q<P, D_HOP, 1>(w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out, cl); break;
-        case D_PLAIN: launch_eo_q<P, D_PLAIN, 1>(w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out, cl); break;
-        case D_RHAT: launch_eo_q<P, D_RHAT, 1>(w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out, cl); break;
-        case D_TS: launch_eo_q<P, D_TS, 1>(w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out, cl); break;
+        case D_HOP: launch_eo_q<P, D_HOP, 1>(w, out, in, cen, aux, diag, st, mask, part, s, rc, par_out, cl); break;
+        case D_PLAIN: launch_eo_q<P, D_PLAIN, 1>(w, out, in, cen, aux, diag, st, mask, part, s, rc, par_out, cl); break;
+        case D_RHAT: launch_eo_q<P, D_RHAT, 1>(w, out, in, cen, aux, diag, st, mask, part, s, rc, par_out, cl); break;
+        case D_TS: launch_eo_q<P, D_TS, 1>(w, out, in, cen, aux, diag, st, mask, part, s, rc, par_out, cl); break;
         default: break;
     }
 }
@@ -438,14 +438,14 @@ void launch_clover_add(int prec, const Work& w, Fld out, Fld in, hipStream_t s) 
 }
 
 void launch_dslash_eo_clv(int prec, int mode, const Work& w, Fld out, Fld in, Fld cen, Fld aux, const double* diag,
-                          const SysState* st, int mask, double* part, hipStream_t s, const NoiseKey* rk, int par_out,
+                          const SysState* st, int mask, double* part, hipStream_t s, const uint32_t* rc, int par_out,
                           const Clv& cl) {
     if (mode == D_RESID) {
-        launch_eo_q<P64, D_RESID, 1>(w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out, cl);
+        launch_eo_q<P64, D_RESID, 1>(w, out, in, cen, aux, diag, st, mask, part, s, rc, par_out, cl);
         return;
     }
-    if (prec == P64) launch_eo_clv_p<P64>(mode, w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out, cl);
-    else if (prec == P32) launch_eo_clv_p<P32>(mode, w, out, in, cen, aux, diag, st, mask, part, s, rk, par_out, cl);
+    if (prec == P64) launch_eo_clv_p<P64>(mode, w, out, in, cen, aux, diag, st, mask, part, s, rc, par_out, cl);
+    else if (prec == P32) launch_eo_clv_p<P32>(mode, w, out, in, cen, aux, diag, st, mask, part, s, rc, par_out, cl);
 }
 
 void launch_eo_prep_clv(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld bo_inv, Fld bh, const double* diag,

@@ -183,54 +183,16 @@ __device__ __forceinline__ void z4_site(const NoiseKey& k, long long site, doubl
     }
 }
 
-// Components j0 and j0 + 1 (j0 even) of z4_site: both come from one Philox
-// block, since site*12 + j0 is even.
-__device__ __forceinline__ void z4_pair(const NoiseKey& k, long long site, int j0, double v[4]) {
-    const long long c = site * 12 + j0;
-    const U64x4 o = philox4x64_10((uint64_t)(c >> 7), k.sample, k.level, k.instance, k.seed, 0ull);
-    const int e = (int)(c & 127);  // e and e + 1 share a word (e even)
-    const int wi = e >> 5;
-    const uint64_t w01 = wi == 0 ? o.v[0] : o.v[1];
-    const uint64_t w23 = wi == 2 ? o.v[2] : o.v[3];
-    const uint64_t word = wi < 2 ? w01 : w23;
-    const double sg = (k.g5 && j0 >= 6) ? -1.0 : 1.0;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int code = (int)((word >> (2 * ((e + i) & 31))) & 3ull);
-        v[2 * i] = sg * (code == 0 ? 1.0 : code == 2 ? -1.0 : 0.0);
-        v[2 * i + 1] = sg * (code == 1 ? 1.0 : code == 3 ? -1.0 : 0.0);
-    }
-}
-
 // BiCGStab shadow residual of a system: its Z4 source stream (rhat = r0 = b
 // for estimator systems, x0 = 0); after the n-th breakdown restart a fresh Z4
 // stream (instance bit 31 set, level + n).  Padding systems: zero.
-template <typename A>
-__device__ __forceinline__ void rhat_site(const NoiseKey& k0, int restarts, long long site, A v[24]) {
-    if (k0.pad) {
-#pragma unroll
-        for (int j = 0; j < 24; ++j) v[j] = A(0);
-        return;
-    }
-    NoiseKey k = k0;
-    if (restarts > 0) {
-        k.instance ^= 0x80000000u;
-        k.level += (uint32_t)restarts;
-    }
-    double d[24];
-    z4_site(k, site, d);
-#pragma unroll
-    for (int j = 0; j < 24; ++j) v[j] = (A)d[j];
-}
-// sum_j conj(rhat_j) v_j and sum_j conj(rhat_j) w_j over the 12 components of
-// `site` (NW = 1: v only), rhat as rhat_site, without forming rhat: every
-// component is a power of i, so conj(i^k) v is v with its parts swapped and
-// negated (k = 1: (vi, -vr); 2: -v; 3: (-vi, vr)).  The sums equal those of
-// the products with rhat_site's values exactly.  Padding systems add nothing.
-template <int NW, typename A>
-__device__ __forceinline__ void rhat_dots(const NoiseKey& k0, int restarts, long long site, const A v[24],
-                                          const A w[24], double acc_v[2], double acc_w[2]) {
-    if (k0.pad) return;
+//
+// The solver keeps rhat as one 32-bit code word per slot: bits 2j, 2j + 1 hold
+// k_j of component j (rhat_j = i^k_j, the key's gamma_5 folded in as k_j + 2),
+// bit 31 marks the zero vector.  rhat_code forms the word of one site from the
+// Philox words of z4_site (same components, same values).
+__device__ __forceinline__ uint32_t rhat_code(const NoiseKey& k0, int restarts, long long site) {
+    if (k0.pad) return 0x80000000u;
     NoiseKey k = k0;
     if (restarts > 0) {
         k.instance ^= 0x80000000u;
@@ -241,6 +203,7 @@ __device__ __forceinline__ void rhat_dots(const NoiseKey& k0, int restarts, long
     U64x4 o0 = philox4x64_10((uint64_t)b0, k.sample, k.level, k.instance, k.seed, 0ull);
     U64x4 o1 = o0;
     if (b1 != b0) o1 = philox4x64_10((uint64_t)b1, k.sample, k.level, k.instance, k.seed, 0ull);
+    uint32_t word = 0;
 #pragma unroll
     for (int j = 0; j < 12; ++j) {
         const long long c = c0 + j;
@@ -249,40 +212,46 @@ __device__ __forceinline__ void rhat_dots(const NoiseKey& k0, int restarts, long
         const int wi = e >> 5;
         const uint64_t w01 = wi == 0 ? (first ? o0.v[0] : o1.v[0]) : (first ? o0.v[1] : o1.v[1]);
         const uint64_t w23 = wi == 2 ? (first ? o0.v[2] : o1.v[2]) : (first ? o0.v[3] : o1.v[3]);
-        const int code = (int)(((wi < 2 ? w01 : w23) >> (2 * (e & 31))) & 3ull);
-        const double sg = (k.g5 && j >= 6) ? -1.0 : 1.0;
-        const bool sw = code & 1;                                   // parts swapped (odd powers)
-        const double s_re = (code == 2 || code == 3) ? -sg : sg;    // sign of the new real part
-        const double s_im = (code == 1 || code == 2) ? -sg : sg;    // sign of the new imaginary part
-        {
-            const double xr = (double)v[2 * j], xi = (double)v[2 * j + 1];
-            acc_v[0] += s_re * (sw ? xi : xr);
-            acc_v[1] += s_im * (sw ? xr : xi);
-        }
-        if constexpr (NW == 2) {
-            const double xr = (double)w[2 * j], xi = (double)w[2 * j + 1];
-            acc_w[0] += s_re * (sw ? xi : xr);
-            acc_w[1] += s_im * (sw ? xr : xi);
-        }
+        uint32_t code = (uint32_t)(((wi < 2 ? w01 : w23) >> (2 * (e & 31))) & 3ull);
+        if (k.g5 && j >= 6) code = (code + 2u) & 3u;
+        word |= code << (2 * j);
     }
+    return word;
 }
 
-// Components j0, j0 + 1 of rhat_site (j0 even).
-__device__ __forceinline__ void rhat_pair(const NoiseKey& k0, int restarts, long long site, int j0, float v[4]) {
-    if (k0.pad) {
+// sum_j conj(rhat_j) v_j and sum_j conj(rhat_j) w_j over the 12 components of
+// one site (NW = 1: v only), rhat given by its code word.  conj(i^k) v is v
+// with its parts swapped and negated (k = 1: (vi, -vr); 2: -v; 3: (-vi, vr)),
+// so no complex product is formed.  The 12 terms are summed in A, then added
+// to the FP64 sums.  The zero vector adds nothing.
+template <int NW, typename A>
+__device__ __forceinline__ void rhat_code_dots(uint32_t code, const A v[24], const A w[24], double acc_v[2],
+                                               double acc_w[2]) {
+    if (code >> 31) return;
+    A fv0 = A(0), fv1 = A(0), fw0 = A(0), fw1 = A(0);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) v[j] = 0.0f;
-        return;
+    for (int j = 0; j < 12; ++j) {
+        const uint32_t k = (code >> (2 * j)) & 3u;
+        const bool sw = k & 1u;                 // parts swapped (odd powers)
+        const bool nre = k & 2u;                // new real part negated (k = 2, 3)
+        const bool nim = (k ^ (k >> 1)) & 1u;   // new imaginary part negated (k = 1, 2)
+        {
+            const A re = sw ? v[2 * j + 1] : v[2 * j], im = sw ? v[2 * j] : v[2 * j + 1];
+            fv0 += nre ? -re : re;
+            fv1 += nim ? -im : im;
+        }
+        if constexpr (NW == 2) {
+            const A re = sw ? w[2 * j + 1] : w[2 * j], im = sw ? w[2 * j] : w[2 * j + 1];
+            fw0 += nre ? -re : re;
+            fw1 += nim ? -im : im;
+        }
     }
-    NoiseKey k = k0;
-    if (restarts > 0) {
-        k.instance ^= 0x80000000u;
-        k.level += (uint32_t)restarts;
+    acc_v[0] += (double)fv0;
+    acc_v[1] += (double)fv1;
+    if constexpr (NW == 2) {
+        acc_w[0] += (double)fw0;
+        acc_w[1] += (double)fw1;
     }
-    double d[4];
-    z4_pair(k, site, j0, d);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = (float)d[j];
 }
 enum Mask : int { M_ALL = 0, M_RUN = 1, M_PEND = 2, M_CONVERT = 3, M_UPDP = 4 };
 
@@ -302,12 +271,13 @@ enum DMode : int {
 // operator on even sites is S = a - D_eo D_oe / a.  launch_dslash_eo:
 //   D_HOP:    out = D_{par_out, 1-par_out} in
 //   other modes (par_out = even): out = a cen - D_eo in / a with in = D_oe cen,
-//   and the partial sums of launch_dslash (D_RESID: out = b - S cen, b in aux).
+//   and the partial sums of launch_dslash (D_RESID: out = b - S cen, b in aux;
+//   D_RHAT and D_TS: rhat from rc).
 // With the stencil mapping of a one-parity plan (w.tc > 0) the kernel streams
 // over t; with the tile mapping it takes one slot per lane.  The finish that
 // follows takes the same mapping.
 void launch_dslash_eo(int prec, int mode, const Work& w, Fld out, Fld in, Fld cen, Fld aux, const double* diag,
-                      const SysState* st, int mask, double* part, hipStream_t s, const NoiseKey* rk, int par_out);
+                      const SysState* st, int mask, double* part, hipStream_t s, const uint32_t* rc, int par_out);
 // Over a one-parity plan whose blocks match fblocks (full-lattice layout) one
 // for one, FP64: bh = b_e - D_eo b_o / a, plus partial |b|^2 of both parities
 // (finished by F_BNORM); and x = (x_e, (b_o - D_oe x_e) / a) in full layout.
@@ -316,9 +286,10 @@ void launch_eo_prep(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld bh,
 void launch_eo_post(const Work& wh, const BlockDesc* fblocks, Fld bfull, Fld xh, Fld xfull, const double* diag,
                     hipStream_t s);
 
-// D_RHAT takes the shadow residual from rk (per-system keys); D_RESID reads b from aux.
+// D_RHAT and D_TS take the shadow residual from rc (one rhat_code word per slot
+// of the plan's fields); D_RESID reads b from aux.
 void launch_dslash(int prec, int mode, const Work& w, Fld out, Fld in, Fld aux, const double* diag,
-                   const SysState* st, int mask, double* part, hipStream_t s, const NoiseKey* rk = nullptr);
+                   const SysState* st, int mask, double* part, hipStream_t s, const uint32_t* rc = nullptr);
 
 // BiCGStab vector kernels (precision of the Krylov fields)
 void launch_axpy_s(int prec, const Work& w, Fld r, Fld v, const SysState* st, hipStream_t s);
@@ -362,10 +333,15 @@ void launch_finish(int stage, const Work& w, SysState* st, const double* part, i
 
 // reliable update / init
 void launch_fold(int prec, const Work& w, Fld xhi, Fld xlo, const SysState* st, hipStream_t s);
-void launch_convert(int prec, const Work& w, Fld rhi, Fld r, const NoiseKey* rk, Fld p, const SysState* st,
-                    double* part, hipStream_t s);
-void launch_init(int prec, const Work& w, Fld b, Fld xhi, Fld xlo, Fld rhi, Fld r, const NoiseKey* rk, Fld p,
-                 double* part, hipStream_t s);
+// rc: the shadow residual's code words (one per slot).  launch_init writes
+// them from rk (restart count 0); launch_convert rewrites those of restarting
+// systems (their restart count) and reads the others.
+void launch_convert(int prec, const Work& w, Fld rhi, Fld r, const NoiseKey* rk, uint32_t* rc, Fld p,
+                    const SysState* st, double* part, hipStream_t s);
+void launch_init(int prec, const Work& w, Fld b, Fld xhi, Fld xlo, Fld rhi, Fld r, const NoiseKey* rk, uint32_t* rc,
+                 Fld p, double* part, hipStream_t s);
+// rc = the code words of rk's shadow residuals (restart count 0) over plan w.
+void launch_rhat_codes(const Work& w, const NoiseKey* rk, uint32_t* rc, hipStream_t s);
 
 // layout conversion between canonical complex128 [sys][site][spin][col] and block layout;
 // sys_map[sys] = canonical index, -1 = write zeros (pack) / skip (unpack), < -1 = skip

@@ -178,20 +178,25 @@ template <> struct NDots<D_TS> { static constexpr int v = 8; };
 // Partial sums of a D_TS launch (t = out, s = the input at the output site):
 // (t, s), (t, t), (s, s), (rhat, s) and (rhat, t), from which the omega finish
 // forms omega and, for r = s - omega t, (rhat, r) and |r|^2 (so the vector
-// update needs no reduction of its own).  rhat is the system's shadow residual
-// at field site `fsite`.
+// update needs no reduction of its own).  rcode: the system's shadow residual
+// at this slot (rhat_code).  Each site's 12 terms are summed in A, then added
+// to the FP64 sums.
 template <typename A>
-__device__ __forceinline__ void ts_dots(const A o[24], const A s[24], const NoiseKey& key, int restarts,
-                                        long long fsite, double acc[8]) {
+__device__ __forceinline__ void ts_dots(const A o[24], const A s[24], uint32_t rcode, double acc[8]) {
+    A f0 = A(0), f1 = A(0), f2 = A(0), f3 = A(0);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-        const double tr = o[2 * k], ti = o[2 * k + 1], sr = s[2 * k], si = s[2 * k + 1];
-        acc[0] += tr * sr + ti * si;
-        acc[1] += tr * si - ti * sr;
-        acc[2] += tr * tr + ti * ti;
-        acc[3] += sr * sr + si * si;
+        const A tr = o[2 * k], ti = o[2 * k + 1], sr = s[2 * k], si = s[2 * k + 1];
+        f0 = fma_(tr, sr, fma_(ti, si, f0));
+        f1 = fma_(tr, si, fma_(-ti, sr, f1));
+        f2 = fma_(tr, tr, fma_(ti, ti, f2));
+        f3 = fma_(sr, sr, fma_(si, si, f3));
     }
-    rhat_dots<2, A>(key, restarts, fsite, s, o, acc + 4, acc + 6);
+    acc[0] += (double)f0;
+    acc[1] += (double)f1;
+    acc[2] += (double)f2;
+    acc[3] += (double)f3;
+    rhat_code_dots<2, A>(rcode, s, o, acc + 4, acc + 6);
 }
 template <> struct NDots<D_RESID> { static constexpr int v = 1; };
 
@@ -217,7 +222,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Wpe<P,
 k_dslash(Work w, Fld out, Fld in, Fld aux,
                                                 const double* __restrict__ diag,
                                                 const SysState* __restrict__ st, int mask,
-                                                double* __restrict__ part, const NoiseKey* __restrict__ rk) {
+                                                double* __restrict__ part, const uint32_t* __restrict__ rc) {
     using A = typename Tr<P>::acc;
     constexpr int G = Tr<P>::G;
     constexpr int ND = NDots<MODE>::v;
@@ -312,7 +317,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
 #pragma unroll
                 for (int k = 0; k < 12; ++k) bw[k] = bn[k];
                 if constexpr (MODE == D_TS) {
-                    if (act) ts_dots<A>(o, v, rk[sys], st[sys].restarts, site, acc);
+                    if (act) ts_dots<A>(o, v, rc[bd.slot_off + slot], acc);
                 }
             }
             // A lane whose system is not running (possible only with quad-shared
@@ -328,7 +333,7 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
             store_sp<P, A, true>(ob, on, gs, slot, o);
             if (act) {
                 if constexpr (MODE == D_RHAT) {
-                    rhat_dots<1, A>(rk[sys], st[sys].restarts, site, o, o, acc, acc);
+                    rhat_code_dots<1, A>(rc[bd.slot_off + slot], o, o, acc, acc);
                 } else if constexpr (MODE == D_RESID) {
 #pragma unroll
                     for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
@@ -453,7 +458,7 @@ template <int P, int MODE, int Q>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<P, MODE>::v, 8))) k_dslash_tile(Work w, Fld out, Fld in, Fld aux,
                                                      const double* __restrict__ diag,
                                                      const SysState* __restrict__ st, int mask,
-                                                     double* __restrict__ part, const NoiseKey* __restrict__ rk) {
+                                                     double* __restrict__ part, const uint32_t* __restrict__ rc) {
     using A = typename Tr<P>::acc;
     using V16 = typename LdsVec<A>::T;
     constexpr int G = Tr<P>::G;
@@ -558,7 +563,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
                 mul_u(u, h, ww);
                 PtM::accum(o, ww, (wrap && ld.tsign < 0) ? A(0.5) : A(-0.5));
                 if constexpr (MODE == D_TS) {
-                    if (act) ts_dots<A>(o, v, rk[sys], st[sys].restarts, site, acc);
+                    if (act) ts_dots<A>(o, v, rc[bd.slot_off + slot], acc);
                 }
             }
 #pragma unroll
@@ -576,7 +581,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<
             store_sp<P, A, true>(ob, on, gs, slot, o);
             if (act) {
                 if constexpr (MODE == D_RHAT) {
-                    rhat_dots<1, A>(rk[sys], st[sys].restarts, site, o, o, acc, acc);
+                    rhat_code_dots<1, A>(rc[bd.slot_off + slot], o, o, acc, acc);
                 } else if constexpr (MODE == D_RESID) {
 #pragma unroll
                     for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
@@ -742,7 +747,7 @@ template <int P, int MODE, int Q>
 __global__ void __launch_bounds__(256) k_dslash_eo(Work w, Fld out, Fld in, Fld cen, Fld aux,
                                                    const double* __restrict__ diag,
                                                    const SysState* __restrict__ st, int mask,
-                                                   double* __restrict__ part, const NoiseKey* __restrict__ rk,
+                                                   double* __restrict__ part, const uint32_t* __restrict__ rc,
                                                    int par_out) {
     using A = typename Tr<P>::acc;
     constexpr int G = Tr<P>::G;
@@ -791,9 +796,9 @@ __global__ void __launch_bounds__(256) k_dslash_eo(Work w, Fld out, Fld in, Fld 
         store_sp<P, A, true>(ob, on, gs, slot, o);
         if (act) {
             if constexpr (MODE == D_RHAT) {
-                rhat_dots<1, A>(rk[sys], st[sys].restarts, cb, o, o, acc, acc);
+                rhat_code_dots<1, A>(rc[bd.slot_off + slot], o, o, acc, acc);
             } else if constexpr (MODE == D_TS) {
-                ts_dots<A>(o, cv, rk[sys], st[sys].restarts, cb, acc);
+                ts_dots<A>(o, cv, rc[bd.slot_off + slot], acc);
             } else if constexpr (MODE == D_RESID) {
 #pragma unroll
                 for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
@@ -819,7 +824,7 @@ template <int P, int MODE, int Q, int CLV = 0>
 __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fld cen, Fld aux,
                                                      const double* __restrict__ diag,
                                                      const SysState* __restrict__ st, int mask,
-                                                     double* __restrict__ part, const NoiseKey* __restrict__ rk,
+                                                     double* __restrict__ part, const uint32_t* __restrict__ rc,
                                                      int par_out, const BlockDesc* __restrict__ fblocks, Clv cl) {
     using A = typename Tr<P>::acc;
     constexpr int G = Tr<P>::G;
@@ -991,9 +996,9 @@ __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fl
             store_sp<P, A, true>(ob, on, gs, slot, o);
             if (act) {
                 if constexpr (MODE == D_RHAT) {
-                    rhat_dots<1, A>(rk[sys], st[sys].restarts, site >> 1, o, o, acc, acc);
+                    rhat_code_dots<1, A>(rc[bd.slot_off + slot], o, o, acc, acc);
                 } else if constexpr (MODE == D_TS) {
-                    ts_dots<A>(o, cv, rk[sys], st[sys].restarts, site >> 1, acc);
+                    ts_dots<A>(o, cv, rc[bd.slot_off + slot], acc);
                 } else if constexpr (MODE == D_RESID) {
 #pragma unroll
                     for (int j = 0; j < 24; ++j) acc[0] += (double)o[j] * (double)o[j];
@@ -1074,7 +1079,7 @@ template <int P, int MODE, int Q, int CLV = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileW<P, MODE>::v, 8)))
 k_dslash_eo_pair(Work w, Fld out, Fld in, Fld cen, Fld aux, const double* __restrict__ diag,
                  const SysState* __restrict__ st, int mask, double* __restrict__ part,
-                 const NoiseKey* __restrict__ rk, int par_out, Clv cl) {
+                 const uint32_t* __restrict__ rc, int par_out, Clv cl) {
     static_assert(!CLV || P == P64 || P == P32, "the clover term is kept in FP64 and FP32");
     using A = typename Tr<P>::acc;
     using V16 = typename LdsVec<A>::T;
@@ -1224,9 +1229,9 @@ k_dslash_eo_pair(Work w, Fld out, Fld in, Fld cen, Fld aux, const double* __rest
             store_sp<P, A, true>(ob, on, gs, slot, o);
             if (act) {
                 if constexpr (MODE == D_RHAT) {
-                    rhat_dots<1, A>(rk[sys], st[sys].restarts, cb, o, o, acc, acc);
+                    rhat_code_dots<1, A>(rc[bd.slot_off + slot], o, o, acc, acc);
                 } else if constexpr (MODE == D_TS) {
-                    ts_dots<A>(o, cv, rk[sys], st[sys].restarts, cb, acc);
+                    ts_dots<A>(o, cv, rc[bd.slot_off + slot], acc);
                 } else if constexpr (MODE == D_RESID) {
 #pragma unroll
                     for (int k = 0; k < 24; ++k) acc[0] += (double)o[k] * (double)o[k];
@@ -1342,7 +1347,7 @@ static int qmode(const Work& w) { return w.nr < 4 ? 0 : (P == P32 && w.two_rows)
 
 template <int P, int MODE, int CLV = 0>
 static void launch_eo_q(const Work& w, Fld out, Fld in, Fld cen, Fld aux, const double* diag, const SysState* st,
-                        int mask, double* part, hipStream_t s, const NoiseKey* rk, int par_out,
+                        int mask, double* part, hipStream_t s, const uint32_t* rc, int par_out,
                         Clv cl = Clv()) {
     const int q = qmode<P>(w);
     if (w.tc > 0 && w.ilp == 2) {  // x-pair stencil mapping with LDS sharing
@@ -1352,15 +1357,15 @@ static void launch_eo_q(const Work& w, Fld out, Fld in, Fld cen, Fld aux, const 
             case 2:
                 if constexpr (P == P32)
                     hipLaunchKernelGGL((k_dslash_eo_pair<P, MODE, 2, CLV>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out,
-                                       in, cen, aux, diag, st, mask, part, rk, par_out, cl);
+                                       in, cen, aux, diag, st, mask, part, rc, par_out, cl);
                 break;
             case 1:
                 hipLaunchKernelGGL((k_dslash_eo_pair<P, MODE, 1, CLV>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in,
-                                   cen, aux, diag, st, mask, part, rk, par_out, cl);
+                                   cen, aux, diag, st, mask, part, rc, par_out, cl);
                 break;
             default:
                 hipLaunchKernelGGL((k_dslash_eo_pair<P, MODE, 0, CLV>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in,
-                                   cen, aux, diag, st, mask, part, rk, par_out, cl);
+                                   cen, aux, diag, st, mask, part, rc, par_out, cl);
         }
         return;
     }
@@ -1370,15 +1375,15 @@ static void launch_eo_q(const Work& w, Fld out, Fld in, Fld cen, Fld aux, const 
             case 2:
                 if constexpr (P == P32)
                     hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, 2, CLV>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in,
-                                       cen, aux, diag, st, mask, part, rk, par_out, nullptr, cl);
+                                       cen, aux, diag, st, mask, part, rc, par_out, nullptr, cl);
                 break;
             case 1:
                 hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, 1, CLV>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, cen,
-                                   aux, diag, st, mask, part, rk, par_out, nullptr, cl);
+                                   aux, diag, st, mask, part, rc, par_out, nullptr, cl);
                 break;
             default:
                 hipLaunchKernelGGL((k_dslash_eo_t<P, MODE, 0, CLV>), dim3(grid_of(w)), dim3(w.wg), lds, s, w, out, in, cen,
-                                   aux, diag, st, mask, part, rk, par_out, nullptr, cl);
+                                   aux, diag, st, mask, part, rc, par_out, nullptr, cl);
         }
         return;
     }
@@ -1387,15 +1392,15 @@ static void launch_eo_q(const Work& w, Fld out, Fld in, Fld cen, Fld aux, const 
             case 2:
                 if constexpr (P == P32)
                     hipLaunchKernelGGL((k_dslash_eo<P, MODE, 2>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen,
-                                       aux, diag, st, mask, part, rk, par_out);
+                                       aux, diag, st, mask, part, rc, par_out);
                 break;
             case 1:
                 hipLaunchKernelGGL((k_dslash_eo<P, MODE, 1>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen, aux,
-                                   diag, st, mask, part, rk, par_out);
+                                   diag, st, mask, part, rc, par_out);
                 break;
             default:
                 hipLaunchKernelGGL((k_dslash_eo<P, MODE, 0>), dim3(grid_of(w)), dim3(w.wg), 0, s, w, out, in, cen, aux,
-                                   diag, st, mask, part, rk, par_out);
+                                   diag, st, mask, part, rc, par_out);
         }
     }
 }
