@@ -776,14 +776,12 @@ int eo_occ(int P, int nr) { return (P == P32 && nr == 4) ? 3 : 0; }
 // Even-odd stencil configuration of a context for one storage precision:
 // variant 0 (t-streaming over one parity class of columns) or 2 (x-pairs
 // with LDS sharing), residency cap (-1: the variant's default).  Without a
-// setting: x-pairs for FP32 and FP64 storage, streaming for FP16 and BF16,
-// whose Schur launches in the x-pair form run at two waves per SIMD (the
-// 432-system FP16 estimate of the 16^3x32 workload: 661 solves/s streaming,
-// 613 in x-pairs; FP32: 603 and 631).
+// setting: x-pairs for FP64, FP32 and FP16 storage (FP16 in its packed form),
+// streaming for BF16, whose x-pair Schur launches run at one wave per SIMD.
 std::array<int, 2> eo_tuning(const fs_ctx_s* c, int P) {
     auto it = c->eo_tune.find(P);
     if (it != c->eo_tune.end()) return it->second;
-    return {(P == P32 || P == P64) ? 2 : 0, -1};
+    return {P != PBF ? 2 : 0, -1};
 }
 
 // The one-parity plan of a full-lattice plan: the same blocks and systems, each

@@ -24,6 +24,28 @@ namespace fs {
 
 namespace {
 
+// Packed FP16 complex (re, im): the FP16 x-pair stencil works on stored
+// spinors in this form (see PairIn).
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h2 as_h2(uint32_t w) { return __builtin_bit_cast(h2, w); }
+template <int K>
+__device__ __forceinline__ h2 ph_h(h2 b) {  // i^K b
+    if constexpr (K == 0) return b;
+    else if constexpr (K == 1) return (h2){-b.y, b.x};
+    else if constexpr (K == 2) return -b;
+    else return (h2){b.y, -b.x};
+}
+__device__ __forceinline__ h2 conj_h(h2 z) { return (h2){z.x, -z.y}; }
+// a.x b.x + a.y b.y in FP32 (the first term of a chain): the three-operand
+// encoding with an inline zero; the builtin with a zero accumulator compiles to
+// the two-operand accumulate-in-place form plus a copy of the zero.
+__device__ __forceinline__ float dot2_first(h2 a, h2 b) {
+    float r;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ h2 swap_h(h2 z) { return (h2){z.y, z.x}; }
+
 template <typename A>
 __device__ __forceinline__ void ph(int code, A re, A im, A& ore, A& oim) {
     // multiply (re + i im) by i^code
@@ -49,6 +71,32 @@ struct Proj {
             ph<A>(A1, v[2 * (J1 * 3 + c)], v[2 * (J1 * 3 + c) + 1], re, im);
             h[6 + 2 * c] = v[2 * (3 + c)] + re;
             h[6 + 2 * c + 1] = v[2 * (3 + c) + 1] + im;
+        }
+    }
+    // The same projection of a stored FP16 spinor (12 packed complex), in the
+    // two operand forms its link product takes: for U h, conj(h) and swap(h)
+    // = (Im h, Re h); for U^+ h, h and -i h.  Each form is one packed FP16 add
+    // per complex (the phases become operand swaps and negations).
+    __device__ __forceinline__ static void project_fwd_h(const uint32_t v[12], h2 hc[6], h2 hs[6]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const h2 a0 = as_h2(v[c]), b0 = ph_h<A0>(as_h2(v[J0 * 3 + c]));
+            const h2 a1 = as_h2(v[3 + c]), b1 = ph_h<A1>(as_h2(v[J1 * 3 + c]));
+            hc[c] = conj_h(a0) + conj_h(b0);
+            hs[c] = swap_h(a0) + swap_h(b0);
+            hc[3 + c] = conj_h(a1) + conj_h(b1);
+            hs[3 + c] = swap_h(a1) + swap_h(b1);
+        }
+    }
+    __device__ __forceinline__ static void project_bwd_h(const uint32_t v[12], h2 hh[6], h2 hn[6]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const h2 a0 = as_h2(v[c]), b0 = ph_h<A0>(as_h2(v[J0 * 3 + c]));
+            const h2 a1 = as_h2(v[3 + c]), b1 = ph_h<A1>(as_h2(v[J1 * 3 + c]));
+            hh[c] = a0 + b0;
+            hn[c] = ph_h<3>(a0) + ph_h<3>(b0);
+            hh[3 + c] = a1 + b1;
+            hn[3 + c] = ph_h<3>(a1) + ph_h<3>(b1);
         }
     }
     template <typename A>
@@ -129,6 +177,70 @@ __device__ __forceinline__ void mul_udag(const A u[18], const A h[12], A w[12]) 
             w[6 * s + 2 * i] = re;
             w[6 * s + 2 * i + 1] = im;
         }
+}
+
+// U h for a half spinor in its packed forms hc = conj(h), hs = swap(h): each
+// complex product is two v_dot2_f32_f16 (Re: u . conj(h), Im: u . swap(h)),
+// summed in FP32.  u: 9 packed FP16 complex, row-major.
+__device__ __forceinline__ void mul_u_h(const uint32_t u[9], const h2 hc[6], const h2 hs[6], float w[12]) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            float re = dot2_first(as_h2(u[3 * i]), hc[3 * s]);
+            float im = dot2_first(as_h2(u[3 * i]), hs[3 * s]);
+#pragma unroll
+            for (int j = 1; j < 3; ++j) {
+                re = __builtin_amdgcn_fdot2(as_h2(u[3 * i + j]), hc[3 * s + j], re, false);
+                im = __builtin_amdgcn_fdot2(as_h2(u[3 * i + j]), hs[3 * s + j], im, false);
+            }
+            w[6 * s + 2 * i] = re;
+            w[6 * s + 2 * i + 1] = im;
+        }
+}
+
+// U^+ h with hh = h, hn = -i h: Re conj(u) h = u . h, Im conj(u) h = u . (-i h).
+__device__ __forceinline__ void mul_udag_h(const uint32_t u[9], const h2 hh[6], const h2 hn[6], float w[12]) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            float re = dot2_first(as_h2(u[i]), hh[3 * s]);
+            float im = dot2_first(as_h2(u[i]), hn[3 * s]);
+#pragma unroll
+            for (int j = 1; j < 3; ++j) {
+                re = __builtin_amdgcn_fdot2(as_h2(u[3 * j + i]), hh[3 * s + j], re, false);
+                im = __builtin_amdgcn_fdot2(as_h2(u[3 * j + i]), hn[3 * s + j], im, false);
+            }
+            w[6 * s + 2 * i] = re;
+            w[6 * s + 2 * i + 1] = im;
+        }
+}
+
+// FP16 link U_mu(site) as 9 packed complex, by link variant Q (see link()).
+template <int Q>
+__device__ __forceinline__ void link_h(const LatDesc& ld, int mu, int site, uint32_t u[9]) {
+    if constexpr (Q == 0) {
+        const uint32_t plane = uni((uint32_t)ld.V * 4u);
+        const auto rs = buf_rsrc(reinterpret_cast<const char*>(ld.gauge) + (size_t)mu * 9 * plane, 9 * plane);
+        const uint32_t off = (uint32_t)site * 4u;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) u[k] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, k * plane, 0);
+    } else {
+        // quad-shared: three 16-byte chunks per site, lanes 0-2 load one each
+        constexpr uint32_t QB = 16u * Tr<P16>::QC;
+        const int qd = threadIdx.x & 3;
+        const uint32_t plane = uni((uint32_t)ld.V * QB);
+        const auto rs = buf_rsrc(reinterpret_cast<const char*>(ld.gauge_q) + (size_t)mu * plane, plane);
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, (uint32_t)site * QB + 16u * (qd < 2 ? qd : 2), 0, 0);
+        const uint4 c = make_uint4(q[0], q[1], q[2], q[3]);
+        uint32_t w[12];
+        chunk_bcast<0>(c, w + 0);
+        chunk_bcast<1>(c, w + 4);
+        chunk_bcast<2>(c, w + 8);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) u[k] = w[k];
+    }
 }
 
 template <int P, int Q, int MU, typename PF, typename PB>
@@ -446,10 +558,12 @@ __device__ __forceinline__ void hop_tile(const LatDesc& ld, const uint4* __restr
 // live state does not fit take fewer rather than spill (FP64 arithmetic
 // doubles every register, BF16 needs its rounding temporaries).
 template <int P, int MODE> struct TileW {
-    // D_TS keeps eight FP64 partial sums live through the slice loop: at three
-    // waves it spills ~400 B per lane and the FP32 estimate loses 8%, so it takes
-    // two; D_RHAT (two partial sums) spills 44-88 B at three and gains 1%
-    static constexpr int v = (P == P32 || P == P16) ? (MODE != D_TS ? 3 : 2) : 1;
+    // FP32 D_TS keeps eight FP64 partial sums and 24 FP32 centre values live
+    // through the slice loop: at three waves it spills 112-144 B per lane and
+    // measured no faster, so it takes two; D_RHAT (two partial sums) spills
+    // 36-64 B at three and gains 1%.  The packed FP16 forms hold half the input
+    // state and take three throughout.
+    static constexpr int v = P == P16 ? 3 : P == P32 ? (MODE != D_TS ? 3 : 2) : 1;
 };
 
 template <int P> constexpr int tile_nbuf() { return sizeof(typename Tr<P>::acc) == 4 ? 2 : 1; }
@@ -1026,19 +1140,157 @@ __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fl
 // (the lane's other column) is formed from the pair's input site and carried
 // in registers.  Modes as k_dslash_eo_t (D_HOP, and with par_out = 0 the
 // Schur modes).
+// Input spinors of the x-pair stencil, as loaded, exchanged through LDS and
+// selected.  FP64, FP32 and BF16: the 24 reals in the arithmetic type.  FP16:
+// the stored form, 12 packed complex and the slot's scale, so the projection
+// adds in FP16 and every link product is a v_dot2_f32_f16 (two FP16 products
+// summed in FP32); the hop results are scaled and accumulated in FP32.  The
+// projection rounds once more than storage does, by at most half an FP16 ulp
+// of the normalised sum.
+struct SpH {
+    uint32_t w[12];  // component spin * 3 + colour as a (re, im) FP16 pair
+    float s;         // scale: the spinor is s * w
+};
+template <int P> struct PairIn {
+    struct T {
+        typename Tr<P>::acc v[24];
+    };
+};
+template <> struct PairIn<P16> { using T = SpH; };
+
+// LDS bytes per lane of one slice buffer: [groups][lanes] 16-byte groups (FP16:
+// then [lanes] scales).
+template <int P> constexpr int in_lds_bytes() { return P == P16 ? 52 : 24 * (int)sizeof(typename Tr<P>::acc); }
+
+template <int P>
+__device__ __forceinline__ void in_load(const uint4* __restrict__ ib, const float* __restrict__ inn, size_t gs,
+                                        size_t slot, typename PairIn<P>::T& x) {
+    if constexpr (P == P16) {
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            const uint4 d = ld16<false>(ib + g * gs + slot);
+            x.w[4 * g] = d.x;
+            x.w[4 * g + 1] = d.y;
+            x.w[4 * g + 2] = d.z;
+            x.w[4 * g + 3] = d.w;
+        }
+        x.s = inn[slot];
+    } else {
+        load_sp<P, typename Tr<P>::acc>(ib, inn, gs, slot, x.v);
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void in_put(char* sh, int wg, int lane, const typename PairIn<P>::T& x) {
+    if constexpr (P == P16) {
+        uint4* q = reinterpret_cast<uint4*>(sh);
+#pragma unroll
+        for (int g = 0; g < 3; ++g)
+            q[g * wg + lane] = make_uint4(x.w[4 * g], x.w[4 * g + 1], x.w[4 * g + 2], x.w[4 * g + 3]);
+        reinterpret_cast<float*>(q + 3 * wg)[lane] = x.s;
+    } else {
+        using A = typename Tr<P>::acc;
+        lds_put<A>(reinterpret_cast<typename LdsVec<A>::T*>(sh), wg, lane, x.v);
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void in_get(const char* sh, int wg, int lane, typename PairIn<P>::T& x) {
+    if constexpr (P == P16) {
+        const uint4* q = reinterpret_cast<const uint4*>(sh);
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            const uint4 d = q[g * wg + lane];
+            x.w[4 * g] = d.x;
+            x.w[4 * g + 1] = d.y;
+            x.w[4 * g + 2] = d.z;
+            x.w[4 * g + 3] = d.w;
+        }
+        x.s = reinterpret_cast<const float*>(q + 3 * wg)[lane];
+    } else {
+        using A = typename Tr<P>::acc;
+        lds_get<A>(reinterpret_cast<const typename LdsVec<A>::T*>(sh), wg, lane, x.v);
+    }
+}
+
+// o = c ? a : b, without a branch
+template <int P>
+__device__ __forceinline__ void in_sel(bool c, const typename PairIn<P>::T& a, const typename PairIn<P>::T& b,
+                                       typename PairIn<P>::T& o) {
+    if constexpr (P == P16) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) o.w[k] = c ? a.w[k] : b.w[k];
+        o.s = c ? a.s : b.s;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) o.v[k] = c ? a.v[k] : b.v[k];
+    }
+}
+
+// o += cf (1 -/+ g_mu) U_mu(lsite) x: the hop from the forward neighbour x
+template <int P, int Q, typename PF>
+__device__ __forceinline__ void hop_fwd(const LatDesc& ld, int mu, int lsite, const typename PairIn<P>::T& x,
+                                        typename Tr<P>::acc o[24], typename Tr<P>::acc cf) {
+    using A = typename Tr<P>::acc;
+    if constexpr (P == P16) {
+        uint32_t u[9];
+        h2 hc[6], hs[6];
+        float w[12];
+        PF::project_fwd_h(x.w, hc, hs);
+        link_h<Q>(ld, mu, lsite, u);
+        mul_u_h(u, hc, hs, w);
+        PF::accum(o, w, cf * x.s);
+    } else {
+        A h[12], u[18], w[12];
+        PF::project(x.v, h);
+        link<P, Q, A>(ld, mu, lsite, u);
+        mul_u(u, h, w);
+        PF::accum(o, w, cf);
+    }
+}
+
+// w = U_mu(lsite)^+ (1 +/- g_mu) x without x's scale, which goes to ws (1
+// except for FP16): the hop from the backward neighbour before accumulation.
+template <int P, int Q, typename PB>
+__device__ __forceinline__ void half_bwd(const LatDesc& ld, int mu, int lsite, const typename PairIn<P>::T& x,
+                                         typename Tr<P>::acc w[12], typename Tr<P>::acc& ws) {
+    using A = typename Tr<P>::acc;
+    if constexpr (P == P16) {
+        uint32_t u[9];
+        h2 hh[6], hn[6];
+        PB::project_bwd_h(x.w, hh, hn);
+        link_h<Q>(ld, mu, lsite, u);
+        mul_udag_h(u, hh, hn, w);
+        ws = x.s;
+    } else {
+        A h[12], u[18];
+        PB::project(x.v, h);
+        link<P, Q, A>(ld, mu, lsite, u);
+        mul_udag(u, h, w);
+        ws = A(1);
+    }
+}
+
+template <int P, int Q, typename PB>
+__device__ __forceinline__ void hop_bwd(const LatDesc& ld, int mu, int lsite, const typename PairIn<P>::T& x,
+                                        typename Tr<P>::acc o[24], typename Tr<P>::acc cf) {
+    using A = typename Tr<P>::acc;
+    A w[12], ws;
+    half_bwd<P, Q, PB>(ld, mu, lsite, x, w, ws);
+    PB::accum(o, w, cf * ws);
+}
+
 // One neighbour of the x-pair stencil: from LDS when it is inside the tile,
 // else from memory; every lane issues the memory load (interior lanes load
 // slot 0, a broadcast) and the value is selected, so the code has no branch.
 template <int P>
 __device__ __forceinline__ void pair_fetch(bool inside, const uint4* __restrict__ ib, const float* __restrict__ inn,
-                                           size_t gs, size_t gslot, const typename LdsVec<typename Tr<P>::acc>::T* sh,
-                                           int wg, int nl, typename Tr<P>::acc v[24]) {
-    using A = typename Tr<P>::acc;
-    A g[24], l[24];
-    load_sp<P, A>(ib, inn, gs, inside ? (size_t)0 : gslot, g);
-    lds_get<A>(sh, wg, nl, l);
-#pragma unroll
-    for (int k = 0; k < 24; ++k) v[k] = inside ? l[k] : g[k];
+                                           size_t gs, size_t gslot, const char* sh, int wg, int nl,
+                                           typename PairIn<P>::T& v) {
+    typename PairIn<P>::T g, l;
+    in_load<P>(ib, inn, gs, inside ? (size_t)0 : gslot, g);
+    in_get<P>(sh, wg, nl, l);
+    in_sel<P>(inside, l, g, v);
 }
 
 // One spatial axis of the x-pair stencil: forward and backward hops of the
@@ -1046,32 +1298,25 @@ __device__ __forceinline__ void pair_fetch(bool inside, const uint4* __restrict_
 // tile coordinate i of extent T, LDS lane stride ls).
 template <int P, int Q, int MU, typename PF, typename PB>
 __device__ __forceinline__ void pair_hop(const LatDesc& ld, const uint4* __restrict__ ib,
-                                         const float* __restrict__ inn, size_t gs,
-                                         const typename LdsVec<typename Tr<P>::acc>::T* sh, int wg, int lane,
+                                         const float* __restrict__ inn, size_t gs, const char* sh, int wg, int lane,
                                          int i, int T, int Lm, int ls, int c, int cb, int cstride, int so,
                                          int sstride, int r, int lognr, typename Tr<P>::acc o[24]) {
     using A = typename Tr<P>::acc;
     const bool whole = T == Lm;  // the tile spans the axis: wrap-around inside it
     {
         const int cbf = (c == Lm - 1) ? cb - (Lm - 1) * cstride : cb + cstride;
-        A v[24], h[12], u[18], w[12];
+        typename PairIn<P>::T v;
         pair_fetch<P>(whole || i < T - 1, ib, inn, gs, ((size_t)cbf << lognr) + r, sh, wg,
                       (i < T - 1) ? lane + ls : lane - (T - 1) * ls, v);
-        PF::project(v, h);
-        link<P, Q, A>(ld, MU, so, u);
-        mul_u(u, h, w);
-        PF::accum(o, w, A(-0.5));
+        hop_fwd<P, Q, PF>(ld, MU, so, v, o, A(-0.5));
     }
     {
         const int cbb = (c == 0) ? cb + (Lm - 1) * cstride : cb - cstride;
         const int sb = (c == 0) ? so + (Lm - 1) * sstride : so - sstride;
-        A v[24], h[12], u[18], w[12];
+        typename PairIn<P>::T v;
         pair_fetch<P>(whole || i > 0, ib, inn, gs, ((size_t)cbb << lognr) + r, sh, wg,
                       (i > 0) ? lane - ls : lane + (T - 1) * ls, v);
-        PB::project(v, h);
-        link<P, Q, A>(ld, MU, sb, u);
-        mul_udag(u, h, w);
-        PB::accum(o, w, A(-0.5));
+        hop_bwd<P, Q, PB>(ld, MU, sb, v, o, A(-0.5));
     }
 }
 
@@ -1082,13 +1327,13 @@ k_dslash_eo_pair(Work w, Fld out, Fld in, Fld cen, Fld aux, const double* __rest
                  const uint32_t* __restrict__ rc, int par_out, Clv cl) {
     static_assert(!CLV || P == P64 || P == P32, "the clover term is kept in FP64 and FP32");
     using A = typename Tr<P>::acc;
-    using V16 = typename LdsVec<A>::T;
+    using In = typename PairIn<P>::T;
     constexpr int G = Tr<P>::G;
     constexpr int ND = NDotsEo<MODE>::v;
     constexpr int NBUF = tile_nbuf<P>();
-    constexpr int NG = 24 * (int)sizeof(A) / 16;
+    constexpr int LB = in_lds_bytes<P>();
     extern __shared__ uint4 lds_dyn[];
-    V16* const shb = reinterpret_cast<V16*>(lds_dyn);
+    char* const shb = reinterpret_cast<char*>(lds_dyn);
     for_each_vwg(w, [&](const int wg_id, const int b) {
     const BlockDesc bd = w.blocks[b];
     const LatDesc ld = w.lats[bd.lat];
@@ -1127,37 +1372,33 @@ k_dslash_eo_pair(Work w, Fld out, Fld in, Fld cen, Fld aux, const double* __rest
     double acc[ND];
 #pragma unroll
     for (int k = 0; k < ND; ++k) acc[k] = 0.0;
-    A bw[12];
+    // backward-t term of the next output, U^+ (1 + g4) psi, and its scale
+    A bw[12], bws = A(0);
 #pragma unroll
     for (int k = 0; k < 12; ++k) bw[k] = A(0);
     if (valid) {
         {
-            A e[24];
-            load_sp<P, A>(ib, inn, gs, ((size_t)(cb0 + t0 * vxyzh) << w.lognr) + r, e);
-            lds_put<A>(shb, w.wg, lane, e);
+            In e;
+            in_load<P>(ib, inn, gs, ((size_t)(cb0 + t0 * vxyzh) << w.lognr) + r, e);
+            in_put<P>(shb, w.wg, lane, e);
         }
         // backward-t term of the first output: its column at t0 - 1 is this
         // pair's input site there
         const int tb = t0 == 0 ? Lt - 1 : t0 - 1;
         const int xo0 = 2 * xh + ((y + z + t0 + par_out) & 1);
-        A v[24], h[12], u[18];
-        load_sp<P, A>(ib, inn, gs, ((size_t)(cb0 + tb * vxyzh) << w.lognr) + r, v);
-        PtP::project(v, h);
-        link<P, Q, A>(ld, 3, xo0 + sy * y + sz * z + stt * tb, u);
-        mul_udag(u, h, bw);
-        if (t0 == 0 && ld.tsign < 0) {
-#pragma unroll
-            for (int k = 0; k < 12; ++k) bw[k] = -bw[k];
-        }
+        In v;
+        in_load<P>(ib, inn, gs, ((size_t)(cb0 + tb * vxyzh) << w.lognr) + r, v);
+        half_bwd<P, Q, PtP>(ld, 3, xo0 + sy * y + sz * z + stt * tb, v, bw, bws);
+        if (t0 == 0 && ld.tsign < 0) bws = -bws;
     }
     __syncthreads();
 #pragma unroll 1
     for (int t = t0; t < t1; ++t) {
-        const V16* const sh = shb + (NBUF == 2 ? ((t - t0) & 1) : 0) * NG * w.wg;           // slice t
-        V16* const shn = shb + (NBUF == 2 ? ((t - t0 + 1) & 1) : 0) * NG * w.wg;            // slice t + 1
+        const char* const sh = shb + (NBUF == 2 ? ((t - t0) & 1) : 0) * LB * w.wg;   // slice t
+        char* const shn = shb + (NBUF == 2 ? ((t - t0 + 1) & 1) : 0) * LB * w.wg;    // slice t + 1
         const bool wrap = t == Lt - 1;
         const int cb = cb0 + t * vxyzh;
-        A nxt[24];
+        In nxt;
         if (valid) {
             const int par = (y + z + t + par_out) & 1;  // output column 2 xh + par
             const int so = 2 * xh + par + sy * y + sz * z + stt * t;
@@ -1165,28 +1406,18 @@ k_dslash_eo_pair(Work w, Fld out, Fld in, Fld cen, Fld aux, const double* __rest
             A o[24];
 #pragma unroll
             for (int k = 0; k < 24; ++k) o[k] = A(0);
-            PtP::accum(o, bw, A(-0.5));
+            PtP::accum(o, bw, A(-0.5) * bws);
             {  // x: one neighbour is the pair's own input site, the other the next pair's;
                // the own site also gives the next output's backward-t term
-                A e[24], l[24], v[24], h[12], u[18], ww[12];
-                lds_get<A>(sh, w.wg, lane, e);
-                PtP::project(e, h);
-                link<P, Q, A>(ld, 3, so ^ 1, u);
-                mul_udag(u, h, bw);
-                lds_get<A>(sh, w.wg, par ? lxp : lxm, l);
-#pragma unroll
-                for (int k = 0; k < 24; ++k) v[k] = par ? l[k] : e[k];
-                PxM::project(v, h);
-                link<P, Q, A>(ld, 0, so, u);
-                mul_u(u, h, ww);
-                PxM::accum(o, ww, A(-0.5));
-#pragma unroll
-                for (int k = 0; k < 24; ++k) v[k] = par ? e[k] : l[k];
-                PxP::project(v, h);
+                In e, l, v;
+                in_get<P>(sh, w.wg, lane, e);
+                half_bwd<P, Q, PtP>(ld, 3, so ^ 1, e, bw, bws);
+                in_get<P>(sh, w.wg, par ? lxp : lxm, l);
+                in_sel<P>(par, l, e, v);
+                hop_fwd<P, Q, PxM>(ld, 0, so, v, o, A(-0.5));
+                in_sel<P>(par, e, l, v);
                 const int xo = 2 * xh + par;
-                link<P, Q, A>(ld, 0, xo == 0 ? so + Lx - 1 : so - 1, u);
-                mul_udag(u, h, ww);
-                PxP::accum(o, ww, A(-0.5));
+                hop_bwd<P, Q, PxP>(ld, 0, xo == 0 ? so + Lx - 1 : so - 1, v, o, A(-0.5));
             }
             // scheduling barriers keep each axis's loads in its own phase: hoisted
             // together they overflow the register file
@@ -1198,14 +1429,10 @@ k_dslash_eo_pair(Work w, Fld out, Fld in, Fld cen, Fld aux, const double* __rest
                                         r, w.lognr, o);
             __builtin_amdgcn_sched_barrier(0);
             {  // t: forward hop from the pair's input site at t + 1 (the next slice's LDS entry)
-                load_sp<P, A>(ib, inn, gs, ((size_t)(wrap ? cb0 : cb + vxyzh) << w.lognr) + r, nxt);
-                A h[12], u[18], ww[12];
-                PtM::project(nxt, h);
-                link<P, Q, A>(ld, 3, so, u);
-                mul_u(u, h, ww);
-                PtM::accum(o, ww, (wrap && ld.tsign < 0) ? A(0.5) : A(-0.5));
+                in_load<P>(ib, inn, gs, ((size_t)(wrap ? cb0 : cb + vxyzh) << w.lognr) + r, nxt);
+                hop_fwd<P, Q, PtM>(ld, 3, so, nxt, o, (wrap && ld.tsign < 0) ? A(0.5) : A(-0.5));
             }
-            if (NBUF == 2) lds_put<A>(shn, w.wg, lane, nxt);
+            if (NBUF == 2) in_put<P>(shn, w.wg, lane, nxt);
             A cv[24];
             if constexpr (MODE != D_HOP) {
                 load_sp<P, A>(cen.v + (size_t)bd.slot_off * G, cen.n ? cen.n + bd.slot_off : nullptr, gs, slot, cv);
@@ -1240,7 +1467,7 @@ k_dslash_eo_pair(Work w, Fld out, Fld in, Fld cen, Fld aux, const double* __rest
         }
         if (NBUF == 1) {  // one buffer: every read of slice t ends before slice t + 1 is written
             __syncthreads();
-            if (valid) lds_put<A>(shn, w.wg, lane, nxt);
+            if (valid) in_put<P>(shn, w.wg, lane, nxt);
         }
         __syncthreads();
     }
@@ -1351,7 +1578,7 @@ static void launch_eo_q(const Work& w, Fld out, Fld in, Fld cen, Fld aux, const 
                         Clv cl = Clv()) {
     const int q = qmode<P>(w);
     if (w.tc > 0 && w.ilp == 2) {  // x-pair stencil mapping with LDS sharing
-        const size_t need = (size_t)tile_nbuf<P>() * 24 * sizeof(typename Tr<P>::acc) * w.wg;
+        const size_t need = (size_t)tile_nbuf<P>() * in_lds_bytes<P>() * w.wg;
         const size_t lds = std::max(need, lds_cap(w.wg, w.occ));
         switch (q) {
             case 2:
