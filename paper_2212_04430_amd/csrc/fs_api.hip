@@ -829,7 +829,7 @@ struct Field {
 // a storage format with unit roundoff u drifts from the true one by ~u/delta;
 // the values below were the fastest of a sweep on the 16^3x32 workload (a
 // smaller delta means fewer FP64 updates at a slightly higher drift).
-double default_delta(int P) { return P == P32 ? 1e-5 : P == P16 ? 0.02 : 0.03; }
+double default_delta(int P) { return P == P32 ? 1e-5 : P == P16 ? 0.005 : 0.03; }
 
 struct SolveOpts {
     int P = P64;

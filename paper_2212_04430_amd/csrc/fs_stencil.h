@@ -243,6 +243,178 @@ __device__ __forceinline__ void link_h(const LatDesc& ld, int mu, int site, uint
     }
 }
 
+// LDS entries of a spinor in the tiled stencils: [16-byte group][lane].
+template <typename A> struct LdsVec;
+template <> struct LdsVec<float> { using T = float4; };
+template <> struct LdsVec<double> { using T = double2; };
+
+template <typename A>
+__device__ __forceinline__ void lds_put(typename LdsVec<A>::T* sh, int wg, int lane, const A v[24]) {
+    constexpr int K = 16 / sizeof(A);
+#pragma unroll
+    for (int g = 0; g < 24 / K; ++g) {
+        typename LdsVec<A>::T q;
+        if constexpr (K == 4) q = make_float4(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]);
+        else q = make_double2(v[2 * g], v[2 * g + 1]);
+        sh[g * wg + lane] = q;
+    }
+}
+
+template <typename A>
+__device__ __forceinline__ void lds_get(const typename LdsVec<A>::T* sh, int wg, int lane, A v[24]) {
+    constexpr int K = 16 / sizeof(A);
+#pragma unroll
+    for (int g = 0; g < 24 / K; ++g) {
+        const typename LdsVec<A>::T q = sh[g * wg + lane];
+        if constexpr (K == 4) {
+            v[4 * g] = q.x; v[4 * g + 1] = q.y; v[4 * g + 2] = q.z; v[4 * g + 3] = q.w;
+        } else {
+            v[2 * g] = q.x; v[2 * g + 1] = q.y;
+        }
+    }
+}
+
+// Input spinors of the hop stencils as loaded, exchanged through LDS and
+// selected.  FP64, FP32 and BF16: the 24 reals in the arithmetic type.  FP16:
+// the stored form, 12 packed complex and the slot's scale, so the projection
+// adds in FP16 and every link product is a v_dot2_f32_f16 (two FP16 products
+// summed in FP32); the hop results are scaled and accumulated in FP32.  The
+// projection rounds once more than storage does, by at most half an FP16 ulp
+// of the normalised sum.  (The x-pair stencil takes every hop in this form;
+// the streaming stencils their x, y and z hops.)
+struct SpH {
+    uint32_t w[12];  // component spin * 3 + colour as a (re, im) FP16 pair
+    float s;         // scale: the spinor is s * w
+};
+template <int P> struct PairIn {
+    struct T {
+        typename Tr<P>::acc v[24];
+    };
+};
+template <> struct PairIn<P16> { using T = SpH; };
+
+// LDS bytes per lane of one slice buffer: [groups][lanes] 16-byte groups (FP16:
+// then [lanes] scales).
+template <int P> constexpr int in_lds_bytes() { return P == P16 ? 52 : 24 * (int)sizeof(typename Tr<P>::acc); }
+
+template <int P>
+__device__ __forceinline__ void in_load(const uint4* __restrict__ ib, const float* __restrict__ inn, size_t gs,
+                                        size_t slot, typename PairIn<P>::T& x) {
+    if constexpr (P == P16) {
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            const uint4 d = ld16<false>(ib + g * gs + slot);
+            x.w[4 * g] = d.x;
+            x.w[4 * g + 1] = d.y;
+            x.w[4 * g + 2] = d.z;
+            x.w[4 * g + 3] = d.w;
+        }
+        x.s = inn[slot];
+    } else {
+        load_sp<P, typename Tr<P>::acc>(ib, inn, gs, slot, x.v);
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void in_put(char* sh, int wg, int lane, const typename PairIn<P>::T& x) {
+    if constexpr (P == P16) {
+        uint4* q = reinterpret_cast<uint4*>(sh);
+#pragma unroll
+        for (int g = 0; g < 3; ++g)
+            q[g * wg + lane] = make_uint4(x.w[4 * g], x.w[4 * g + 1], x.w[4 * g + 2], x.w[4 * g + 3]);
+        reinterpret_cast<float*>(q + 3 * wg)[lane] = x.s;
+    } else {
+        using A = typename Tr<P>::acc;
+        lds_put<A>(reinterpret_cast<typename LdsVec<A>::T*>(sh), wg, lane, x.v);
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void in_get(const char* sh, int wg, int lane, typename PairIn<P>::T& x) {
+    if constexpr (P == P16) {
+        const uint4* q = reinterpret_cast<const uint4*>(sh);
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            const uint4 d = q[g * wg + lane];
+            x.w[4 * g] = d.x;
+            x.w[4 * g + 1] = d.y;
+            x.w[4 * g + 2] = d.z;
+            x.w[4 * g + 3] = d.w;
+        }
+        x.s = reinterpret_cast<const float*>(q + 3 * wg)[lane];
+    } else {
+        using A = typename Tr<P>::acc;
+        lds_get<A>(reinterpret_cast<const typename LdsVec<A>::T*>(sh), wg, lane, x.v);
+    }
+}
+
+// o = c ? a : b, without a branch
+template <int P>
+__device__ __forceinline__ void in_sel(bool c, const typename PairIn<P>::T& a, const typename PairIn<P>::T& b,
+                                       typename PairIn<P>::T& o) {
+    if constexpr (P == P16) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) o.w[k] = c ? a.w[k] : b.w[k];
+        o.s = c ? a.s : b.s;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) o.v[k] = c ? a.v[k] : b.v[k];
+    }
+}
+
+// o += cf (1 -/+ g_mu) U_mu(lsite) x: the hop from the forward neighbour x
+template <int P, int Q, typename PF>
+__device__ __forceinline__ void hop_fwd(const LatDesc& ld, int mu, int lsite, const typename PairIn<P>::T& x,
+                                        typename Tr<P>::acc o[24], typename Tr<P>::acc cf) {
+    using A = typename Tr<P>::acc;
+    if constexpr (P == P16) {
+        uint32_t u[9];
+        h2 hc[6], hs[6];
+        float w[12];
+        PF::project_fwd_h(x.w, hc, hs);
+        link_h<Q>(ld, mu, lsite, u);
+        mul_u_h(u, hc, hs, w);
+        PF::accum(o, w, cf * x.s);
+    } else {
+        A h[12], u[18], w[12];
+        PF::project(x.v, h);
+        link<P, Q, A>(ld, mu, lsite, u);
+        mul_u(u, h, w);
+        PF::accum(o, w, cf);
+    }
+}
+
+// w = U_mu(lsite)^+ (1 +/- g_mu) x without x's scale, which goes to ws (1
+// except for FP16): the hop from the backward neighbour before accumulation.
+template <int P, int Q, typename PB>
+__device__ __forceinline__ void half_bwd(const LatDesc& ld, int mu, int lsite, const typename PairIn<P>::T& x,
+                                         typename Tr<P>::acc w[12], typename Tr<P>::acc& ws) {
+    using A = typename Tr<P>::acc;
+    if constexpr (P == P16) {
+        uint32_t u[9];
+        h2 hh[6], hn[6];
+        PB::project_bwd_h(x.w, hh, hn);
+        link_h<Q>(ld, mu, lsite, u);
+        mul_udag_h(u, hh, hn, w);
+        ws = x.s;
+    } else {
+        A h[12], u[18];
+        PB::project(x.v, h);
+        link<P, Q, A>(ld, mu, lsite, u);
+        mul_udag(u, h, w);
+        ws = A(1);
+    }
+}
+
+template <int P, int Q, typename PB>
+__device__ __forceinline__ void hop_bwd(const LatDesc& ld, int mu, int lsite, const typename PairIn<P>::T& x,
+                                        typename Tr<P>::acc o[24], typename Tr<P>::acc cf) {
+    using A = typename Tr<P>::acc;
+    A w[12], ws;
+    half_bwd<P, Q, PB>(ld, mu, lsite, x, w, ws);
+    PB::accum(o, w, cf * ws);
+}
+
 template <int P, int Q, int MU, typename PF, typename PB>
 __device__ __forceinline__ void hop_dir(const LatDesc& ld, const uint4* __restrict__ ib,
                                         const float* __restrict__ inn, size_t gs, int site, int coord,
@@ -257,20 +429,14 @@ __device__ __forceinline__ void hop_dir(const LatDesc& ld, const uint4* __restri
         if (coord == 0) cb = A(0.5);
     }
     {
-        A v[24], h[12], u[18], w[12];
-        load_sp<P, A>(ib, inn, gs, ((size_t)sf << lognr) + r, v);
-        PF::project(v, h);
-        link<P, Q, A>(ld, MU, site, u);
-        mul_u(u, h, w);
-        PF::accum(o, w, cf);
+        typename PairIn<P>::T v;
+        in_load<P>(ib, inn, gs, ((size_t)sf << lognr) + r, v);
+        hop_fwd<P, Q, PF>(ld, MU, site, v, o, cf);
     }
     {
-        A v[24], h[12], u[18], w[12];
-        load_sp<P, A>(ib, inn, gs, ((size_t)sb << lognr) + r, v);
-        PB::project(v, h);
-        link<P, Q, A>(ld, MU, sb, u);
-        mul_udag(u, h, w);
-        PB::accum(o, w, cb);
+        typename PairIn<P>::T v;
+        in_load<P>(ib, inn, gs, ((size_t)sb << lognr) + r, v);
+        hop_bwd<P, Q, PB>(ld, MU, sb, v, o, cb);
     }
 }
 
@@ -463,35 +629,6 @@ k_dslash(Work w, Fld out, Fld in, Fld aux,
 // a neighbour inside the tile is read from LDS and only the lanes on a tile
 // face load their outside neighbour from memory: per site ~sum_mu 2/T_mu of
 // the six spatial neighbour spinors instead of all six.
-template <typename A> struct LdsVec;
-template <> struct LdsVec<float> { using T = float4; };
-template <> struct LdsVec<double> { using T = double2; };
-
-template <typename A>
-__device__ __forceinline__ void lds_put(typename LdsVec<A>::T* sh, int wg, int lane, const A v[24]) {
-    constexpr int K = 16 / sizeof(A);
-#pragma unroll
-    for (int g = 0; g < 24 / K; ++g) {
-        typename LdsVec<A>::T q;
-        if constexpr (K == 4) q = make_float4(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]);
-        else q = make_double2(v[2 * g], v[2 * g + 1]);
-        sh[g * wg + lane] = q;
-    }
-}
-
-template <typename A>
-__device__ __forceinline__ void lds_get(const typename LdsVec<A>::T* sh, int wg, int lane, A v[24]) {
-    constexpr int K = 16 / sizeof(A);
-#pragma unroll
-    for (int g = 0; g < 24 / K; ++g) {
-        const typename LdsVec<A>::T q = sh[g * wg + lane];
-        if constexpr (K == 4) {
-            v[4 * g] = q.x; v[4 * g + 1] = q.y; v[4 * g + 2] = q.z; v[4 * g + 3] = q.w;
-        } else {
-            v[2 * g] = q.x; v[2 * g + 1] = q.y;
-        }
-    }
-}
 
 // One spatial direction of the tiled stencil: forward and backward hop of
 // slice-t site `site` (tile coordinate i of extent T = 1 << lt, lattice
@@ -726,20 +863,14 @@ __device__ __forceinline__ void hop_dir_h(const LatDesc& ld, const uint4* __rest
         if (coord == 0) cb = A(0.5);
     }
     {
-        A v[24], h[12], u[18], w[12];
-        load_sp<P, A>(ib, inn, gs, ((size_t)(HALF ? (sf >> 1) : sf) << lognr) + r, v);
-        PF::project(v, h);
-        link<P, Q, A>(ld, MU, site, u);
-        mul_u(u, h, w);
-        PF::accum(o, w, cf);
+        typename PairIn<P>::T v;
+        in_load<P>(ib, inn, gs, ((size_t)(HALF ? (sf >> 1) : sf) << lognr) + r, v);
+        hop_fwd<P, Q, PF>(ld, MU, site, v, o, cf);
     }
     {
-        A v[24], h[12], u[18], w[12];
-        load_sp<P, A>(ib, inn, gs, ((size_t)(HALF ? (sb >> 1) : sb) << lognr) + r, v);
-        PB::project(v, h);
-        link<P, Q, A>(ld, MU, sb, u);
-        mul_udag(u, h, w);
-        PB::accum(o, w, cb);
+        typename PairIn<P>::T v;
+        in_load<P>(ib, inn, gs, ((size_t)(HALF ? (sb >> 1) : sb) << lognr) + r, v);
+        hop_bwd<P, Q, PB>(ld, MU, sb, v, o, cb);
     }
 }
 
@@ -1140,146 +1271,6 @@ __global__ void __launch_bounds__(256) k_dslash_eo_t(Work w, Fld out, Fld in, Fl
 // (the lane's other column) is formed from the pair's input site and carried
 // in registers.  Modes as k_dslash_eo_t (D_HOP, and with par_out = 0 the
 // Schur modes).
-// Input spinors of the x-pair stencil, as loaded, exchanged through LDS and
-// selected.  FP64, FP32 and BF16: the 24 reals in the arithmetic type.  FP16:
-// the stored form, 12 packed complex and the slot's scale, so the projection
-// adds in FP16 and every link product is a v_dot2_f32_f16 (two FP16 products
-// summed in FP32); the hop results are scaled and accumulated in FP32.  The
-// projection rounds once more than storage does, by at most half an FP16 ulp
-// of the normalised sum.
-struct SpH {
-    uint32_t w[12];  // component spin * 3 + colour as a (re, im) FP16 pair
-    float s;         // scale: the spinor is s * w
-};
-template <int P> struct PairIn {
-    struct T {
-        typename Tr<P>::acc v[24];
-    };
-};
-template <> struct PairIn<P16> { using T = SpH; };
-
-// LDS bytes per lane of one slice buffer: [groups][lanes] 16-byte groups (FP16:
-// then [lanes] scales).
-template <int P> constexpr int in_lds_bytes() { return P == P16 ? 52 : 24 * (int)sizeof(typename Tr<P>::acc); }
-
-template <int P>
-__device__ __forceinline__ void in_load(const uint4* __restrict__ ib, const float* __restrict__ inn, size_t gs,
-                                        size_t slot, typename PairIn<P>::T& x) {
-    if constexpr (P == P16) {
-#pragma unroll
-        for (int g = 0; g < 3; ++g) {
-            const uint4 d = ld16<false>(ib + g * gs + slot);
-            x.w[4 * g] = d.x;
-            x.w[4 * g + 1] = d.y;
-            x.w[4 * g + 2] = d.z;
-            x.w[4 * g + 3] = d.w;
-        }
-        x.s = inn[slot];
-    } else {
-        load_sp<P, typename Tr<P>::acc>(ib, inn, gs, slot, x.v);
-    }
-}
-
-template <int P>
-__device__ __forceinline__ void in_put(char* sh, int wg, int lane, const typename PairIn<P>::T& x) {
-    if constexpr (P == P16) {
-        uint4* q = reinterpret_cast<uint4*>(sh);
-#pragma unroll
-        for (int g = 0; g < 3; ++g)
-            q[g * wg + lane] = make_uint4(x.w[4 * g], x.w[4 * g + 1], x.w[4 * g + 2], x.w[4 * g + 3]);
-        reinterpret_cast<float*>(q + 3 * wg)[lane] = x.s;
-    } else {
-        using A = typename Tr<P>::acc;
-        lds_put<A>(reinterpret_cast<typename LdsVec<A>::T*>(sh), wg, lane, x.v);
-    }
-}
-
-template <int P>
-__device__ __forceinline__ void in_get(const char* sh, int wg, int lane, typename PairIn<P>::T& x) {
-    if constexpr (P == P16) {
-        const uint4* q = reinterpret_cast<const uint4*>(sh);
-#pragma unroll
-        for (int g = 0; g < 3; ++g) {
-            const uint4 d = q[g * wg + lane];
-            x.w[4 * g] = d.x;
-            x.w[4 * g + 1] = d.y;
-            x.w[4 * g + 2] = d.z;
-            x.w[4 * g + 3] = d.w;
-        }
-        x.s = reinterpret_cast<const float*>(q + 3 * wg)[lane];
-    } else {
-        using A = typename Tr<P>::acc;
-        lds_get<A>(reinterpret_cast<const typename LdsVec<A>::T*>(sh), wg, lane, x.v);
-    }
-}
-
-// o = c ? a : b, without a branch
-template <int P>
-__device__ __forceinline__ void in_sel(bool c, const typename PairIn<P>::T& a, const typename PairIn<P>::T& b,
-                                       typename PairIn<P>::T& o) {
-    if constexpr (P == P16) {
-#pragma unroll
-        for (int k = 0; k < 12; ++k) o.w[k] = c ? a.w[k] : b.w[k];
-        o.s = c ? a.s : b.s;
-    } else {
-#pragma unroll
-        for (int k = 0; k < 24; ++k) o.v[k] = c ? a.v[k] : b.v[k];
-    }
-}
-
-// o += cf (1 -/+ g_mu) U_mu(lsite) x: the hop from the forward neighbour x
-template <int P, int Q, typename PF>
-__device__ __forceinline__ void hop_fwd(const LatDesc& ld, int mu, int lsite, const typename PairIn<P>::T& x,
-                                        typename Tr<P>::acc o[24], typename Tr<P>::acc cf) {
-    using A = typename Tr<P>::acc;
-    if constexpr (P == P16) {
-        uint32_t u[9];
-        h2 hc[6], hs[6];
-        float w[12];
-        PF::project_fwd_h(x.w, hc, hs);
-        link_h<Q>(ld, mu, lsite, u);
-        mul_u_h(u, hc, hs, w);
-        PF::accum(o, w, cf * x.s);
-    } else {
-        A h[12], u[18], w[12];
-        PF::project(x.v, h);
-        link<P, Q, A>(ld, mu, lsite, u);
-        mul_u(u, h, w);
-        PF::accum(o, w, cf);
-    }
-}
-
-// w = U_mu(lsite)^+ (1 +/- g_mu) x without x's scale, which goes to ws (1
-// except for FP16): the hop from the backward neighbour before accumulation.
-template <int P, int Q, typename PB>
-__device__ __forceinline__ void half_bwd(const LatDesc& ld, int mu, int lsite, const typename PairIn<P>::T& x,
-                                         typename Tr<P>::acc w[12], typename Tr<P>::acc& ws) {
-    using A = typename Tr<P>::acc;
-    if constexpr (P == P16) {
-        uint32_t u[9];
-        h2 hh[6], hn[6];
-        PB::project_bwd_h(x.w, hh, hn);
-        link_h<Q>(ld, mu, lsite, u);
-        mul_udag_h(u, hh, hn, w);
-        ws = x.s;
-    } else {
-        A h[12], u[18];
-        PB::project(x.v, h);
-        link<P, Q, A>(ld, mu, lsite, u);
-        mul_udag(u, h, w);
-        ws = A(1);
-    }
-}
-
-template <int P, int Q, typename PB>
-__device__ __forceinline__ void hop_bwd(const LatDesc& ld, int mu, int lsite, const typename PairIn<P>::T& x,
-                                        typename Tr<P>::acc o[24], typename Tr<P>::acc cf) {
-    using A = typename Tr<P>::acc;
-    A w[12], ws;
-    half_bwd<P, Q, PB>(ld, mu, lsite, x, w, ws);
-    PB::accum(o, w, cf * ws);
-}
-
 // One neighbour of the x-pair stencil: from LDS when it is inside the tile,
 // else from memory; every lane issues the memory load (interior lanes load
 // slot 0, a broadcast) and the value is selected, so the code has no branch.
