@@ -177,7 +177,7 @@ def kernel_source_hash():
     configuration rules: counters taken on other code do not apply."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("fs_dslash.hip", "fs_device.h", "fs_kernels.h", "fs_api.hip"):
+    for f in ("fs_stencil.h", "fs_dslash.hip", "fs_device.h", "fs_kernels.h", "fs_api.hip"):
         with open(os.path.join(ROOT, "paper_2212_04430_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -425,6 +425,9 @@ def main():
     ap.add_argument("--roofline-only", action="store_true", help="only the copy and stencil launches of the roofline")
     ap.add_argument("--roofline-storage", default="f32", choices=["f64", "f32", "f16", "bf16"],
                     help="precision of the stencil timed by --roofline-only")
+    ap.add_argument("--estimate-only", default=None, choices=["f32", "f16", "bf16"],
+                    help="only the step's estimate in this storage, warm-up and timed steps as given (for "
+                         "kernel-trace runs); prints a short JSON line")
     ap.add_argument("--no-clover", action="store_true", help="skip the clover-improved operator leg")
     ap.add_argument("--no-multishift", action="store_true", help="skip the multi-shift solver leg")
     ap.add_argument("--no-select", action="store_true", help="skip variance sampling and shift selection")
@@ -453,6 +456,19 @@ def main():
     cache = setup_tuning(args.tuning_cache)
     nr, wg = L.fs_autotune(ctx, "f32", systems_per_step, cache)
     log(f"tuning f32: rhs_block={nr} wg={wg}")
+    if args.estimate_only:
+        prm_e = est_params(L, args.estimate_only, 1, w["n_noise"], nr=nr if args.estimate_only == "f32" else 4, eo=1)
+        for i in range(args.warmup):
+            L.fs_estimate(ctx, prm_e, w["sigma"])
+        t0 = time.perf_counter()
+        reps = [L.fs_estimate(ctx, prm_e, w["sigma"])[2] for _ in range(args.steps)]
+        dt = time.perf_counter() - t0
+        print(json.dumps({"storage": args.estimate_only, "solves_per_s": round(systems_per_step * args.steps / dt, 2),
+                          "iters_per_system": round(float(np.mean([r.iterations / r.systems for r in reps])), 2),
+                          "reliable_updates_per_system":
+                              round(float(np.mean([r.reliable_updates / r.systems for r in reps])), 2),
+                          "max_true_rel_residual": max(r.max_rel_residual for r in reps)}))
+        return
     if args.roofline_only:
         if args.roofline_storage != "f32":
             nr, wg = L.fs_autotune(ctx, args.roofline_storage, systems_per_step, cache)
@@ -461,11 +477,12 @@ def main():
 
     # ---- batched mixed path, even-odd preconditioned: warmup + timed steps
     prm = est_params(L, "f32", 1, w["n_noise"], nr=nr, eo=1)
+    import torch
+    torch.cuda.synchronize()  # torch's own device state, before the warm-up
     for i in range(args.warmup):
         t0 = time.perf_counter()
         L.fs_estimate(ctx, prm, w["sigma"])
         log(f"warmup step {i}: {time.perf_counter() - t0:.2f} s")
-    import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = []
@@ -567,6 +584,16 @@ def main():
                 "copy_kernel_GBs": round(2 * (1 << 30) / (ms_c * 1e-3) / 1e9, 1)}
     log(f"dslash f32 batched even-odd hop: {ms_d:.4f} ms, {achieved:.0f} GB/s; full lattice {ms_full:.4f} ms, "
         f"{full_gbs:.0f} GB/s")
+    # the same hop in FP16 storage, as the FP16 step runs it (rhs block 4, packed halves)
+    each_h, bytes_h = L.fs_time_dslash_eo_each(ctx, "f16", ROOFLINE_NSYS, 4, 100)
+    ms_h = float(np.median(each_h))
+    gbs_h = bytes_h / (ms_h * 1e-3) / 1e9
+    roofline["fp16_hop"] = {"kernel": f"k_dslash_eo_pair<P16> D_HOP on packed halves (v_pk_add_f16 projections, "
+                                      f"v_dot2_f32_f16 link products, FP32 sums), {ROOFLINE_NSYS} systems, "
+                                      f"rhs_block 4, whole FP16 links",
+                            "algorithmic_bytes_per_launch": bytes_h, "median_launch_ms": round(ms_h, 5),
+                            "achieved": round(gbs_h, 1), "frac": round(gbs_h / HBM_PEAK_GBS, 4)}
+    log(f"dslash f16 batched even-odd hop: {ms_h:.4f} ms, {gbs_h:.0f} GB/s")
     clover = None if args.no_clover else clover_leg(L, ctx, nr, args.fp64_noise)
     multishift = None if args.no_multishift else multishift_leg(L, ctx)
     select, sel_inputs = (None, None) if args.no_select else sampling_and_selection(L, ctx, nr)

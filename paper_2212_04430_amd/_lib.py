@@ -314,12 +314,15 @@ def fs_solve_shifted(ctx, params, sigma, B, allow_noconv=False):
 STAT_FIELDS = ("tr_re", "tr_im", "var_paper", "var_unbiased", "n", "max_rel_residual", "fp64_rel_err", "err_bound")
 
 
+_STAT_DTYPE = np.dtype([(f, np.int64 if t is C.c_int64 else np.float64) for f, t in fs_level_stat._fields_])
+
+
 def _stats_array(stats, shape):
-    a = np.zeros(shape + (len(STAT_FIELDS),))
-    flat = a.reshape(-1, len(STAT_FIELDS))
-    for i, s in enumerate(stats):
-        flat[i] = tuple(getattr(s, f) for f in STAT_FIELDS)
-    return a
+    """fs_level_stat array (ctypes) -> float array shape + (len(STAT_FIELDS),)."""
+    assert _STAT_DTYPE.itemsize == C.sizeof(fs_level_stat)
+    rec = np.frombuffer(stats, dtype=_STAT_DTYPE, count=len(stats))
+    a = np.stack([rec[f].astype(np.float64) for f in STAT_FIELDS], axis=-1)
+    return a.reshape(shape + (len(STAT_FIELDS),))
 
 
 def fs_estimate(ctx, params, sigma, want_samples=False, allow_noconv=False, raw=False):
@@ -337,7 +340,7 @@ def fs_estimate(ctx, params, sigma, want_samples=False, allow_noconv=False, raw=
     code = _lib.fs_estimate(ctx, C.byref(params), C.c_void_p(sig.ctypes.data), L, out,
                             C.c_void_p(samples.ctypes.data) if want_samples else None, C.byref(rep))
     _check(code, allow=(FS_E_NOCONV,) if allow_noconv else ())
-    st = _stats_array(list(out), (L + 1, 16, P1))
+    st = _stats_array(out, (L + 1, 16, P1))
     return (st, samples, rep, out) if raw else (st, samples, rep)
 
 
@@ -381,7 +384,7 @@ def fs_sample_variances(ctx, params, shifts, want_samples=False, allow_noconv=Fa
                                     C.c_void_p(samples.ctypes.data) if want_samples else None,
                                     C.c_void_p(iters.ctypes.data), C.byref(rep))
     _check(code, allow=(FS_E_NOCONV,) if allow_noconv else ())
-    return (_stats_array(list(single), (m, 16, P1)), _stats_array(list(pair), (m, m, 16, P1)), samples, iters,
+    return (_stats_array(single, (m, 16, P1)), _stats_array(pair, (m, m, 16, P1)), samples, iters,
             rep)
 
 
@@ -405,7 +408,7 @@ def fs_batch_estimate(batch, n_inst, params, sigma, allow_noconv=False, want_sam
     code = _lib.fs_batch_estimate(batch, C.byref(params), C.c_void_p(sig.ctypes.data), L, out,
                                   C.c_void_p(samples.ctypes.data) if want_samples else None, C.byref(rep))
     _check(code, allow=(FS_E_NOCONV,) if allow_noconv else ())
-    st = _stats_array(list(out), (n_inst, L + 1, 16, P1))
+    st = _stats_array(out, (n_inst, L + 1, 16, P1))
     return (st, samples, rep) if want_samples else (st, rep)
 
 
@@ -539,4 +542,4 @@ def fs_estimate_probed(ctx, params, sigma, colours, want_samples=False, allow_no
                                    col.ctypes.data_as(C.POINTER(C.c_int32)), n_col, out,
                                    C.c_void_p(samples.ctypes.data) if want_samples else None, C.byref(rep))
     _check(code, allow=(FS_E_NOCONV,) if allow_noconv else ())
-    return _stats_array(list(out), (L + 1, 16, P1)), samples, rep
+    return _stats_array(out, (L + 1, 16, P1)), samples, rep
