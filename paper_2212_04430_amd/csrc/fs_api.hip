@@ -94,12 +94,19 @@ fs_status guard(F&& f) {
 
 // Caching device allocator: freed blocks are kept per (device, size) and
 // reused, so repeated solves and estimates do not call hipMalloc/hipFree in
-// their loops.  Sizes are rounded up to 2 MiB above 1 MiB.
+// their loops.  Sizes are rounded up to 2 MiB above 1 MiB.  Over the cache
+// limit the least recently released blocks go first, so the fields of the
+// call just finished stay for the next call of the same shape.
 struct Pool {
+    struct Block {
+        void* p;
+        unsigned long long seq;  // release order
+    };
     std::recursive_mutex mu;  // several host threads may drive contexts at once
-    std::multimap<std::pair<int, size_t>, void*> free_;
+    std::multimap<std::pair<int, size_t>, Block> free_;
     size_t cached = 0;
     size_t cap = 0;
+    unsigned long long seq = 0;
     // Cache limit: half the device memory, so that the fields of a large batch
     // (tens of GB) are reused by the next solve of the same shape instead of
     // being released and allocated again, which costs about as much as the
@@ -125,7 +132,7 @@ struct Pool {
         (void)hipGetDevice(&dev);
         auto it = free_.find({dev, n});
         if (it != free_.end()) {
-            void* p = it->second;
+            void* p = it->second.p;
             free_.erase(it);
             cached -= n;
             *err = hipSuccess;
@@ -152,18 +159,30 @@ struct Pool {
         std::lock_guard<std::recursive_mutex> lk(mu);
         int dev = 0;
         (void)hipGetDevice(&dev);
-        free_.insert({{dev, n}, p});
+        free_.insert({{dev, n}, Block{p, ++seq}});
         cached += n;
-        if (cached > limit()) trim(limit() / 2);
+        if (cached > limit()) trim(limit());
     }
+    size_t cached_bytes() {
+        std::lock_guard<std::recursive_mutex> lk(mu);
+        return cached;
+    }
+    // release cached blocks, least recently released first, until at most
+    // `keep` bytes stay cached
     void trim(size_t keep) {
         std::lock_guard<std::recursive_mutex> lk(mu);
+        bool synced = false;
         while (cached > keep && !free_.empty()) {
-            auto it = std::prev(free_.end());  // largest first
-            (void)hipDeviceSynchronize();
-            (void)hipFree(it->second);
-            cached -= it->first.second;
-            free_.erase(it);
+            auto old = free_.begin();
+            for (auto it = free_.begin(); it != free_.end(); ++it)
+                if (it->second.seq < old->second.seq) old = it;
+            if (!synced) {
+                (void)hipDeviceSynchronize();
+                synced = true;
+            }
+            (void)hipFree(old->second.p);
+            cached -= old->first.second;
+            free_.erase(old);
         }
     }
 };
@@ -1262,9 +1281,12 @@ void from_device(void* dst, const DevBuf& d, size_t n, int is_device, hipStream_
     HC(hipStreamSynchronize(s));
 }
 
+// Untuned rhs block: 4 for FP64 and FP32 (FP32 at 8 ran at half the rate on
+// the uneven 8^3x16 ... 24^3x48 batch, 147 against 314 solves/s), 8 for FP16
+// and BF16 (FP16: 370 and 380 solves/s at 8 and 4).
 int tuned_nr(fs_ctx c, int P, int n_sys) {
     auto it = c->tune.find(P);
-    int nr = it != c->tune.end() ? it->second.nr : (P == P64 ? 4 : 8);
+    int nr = it != c->tune.end() ? it->second.nr : (P == P64 || P == P32 ? 4 : 8);
     while (nr > 1 && nr > n_sys) nr >>= 1;
     return nr;
 }
@@ -2040,28 +2062,49 @@ void estimate_impl(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm,
     } else {
         int nr = prm->solve.rhs_block ? prm->solve.rhs_block : tuned_nr(c0, P, N);
         const int wg = tuned_wg(c0, P);
-        // memory budget per pass: fields per system ~ (4 FP64 + 6 low) spinors
+        // memory budget per pass: fields per system ~ (4 FP64 + 6 low) spinors.
+        // Free memory counts the blocks the allocator holds for reuse, so the
+        // budget, and with it the passes, do not depend on what earlier calls
+        // left cached.
         size_t bytes_per_site_sys = 4 * 192 + 6 * (size_t)prec_group_bytes_spinor(P) + (P == P16 ? 24 : 0);
         size_t free_b = 0, total_b = 0;
         HC(hipMemGetInfo(&free_b, &total_b));
-        const size_t budget = std::min<size_t>(free_b / 2, (size_t)96 << 30);
-        std::vector<std::array<int, 3>> units;
-        size_t used = 0;
-        auto flush = [&]() {
-            if (units.empty()) return;
-            run_units(ctxs, prm, sigma, units, nr, wg, s, res, N);
-            units.clear();
-            used = 0;
+        const size_t budget = std::min<size_t>((free_b + pool().cached_bytes()) / 2, (size_t)96 << 30);
+        // units in chunks of nr samples of one (instance, level): the rhs blocks
+        struct Chunk {
+            int c;  // chunk index within its (instance, level)
+            std::vector<std::array<int, 3>> units;
         };
+        std::vector<Chunk> chunks;
+        size_t total_need = 0;
+        int max_nch = 1;
         for (int l = 0; l <= L; ++l)
-            for (int smp = 0; smp < Nl[l]; ++smp)
-                for (size_t i = 0; i < ctxs.size(); ++i) {
-                    const size_t need = (size_t)ctxs[i]->V * bytes_per_site_sys * (l < L ? 2 : 1);
-                    if (used + need > budget && !units.empty()) flush();
-                    units.push_back({(int)i, l, smp});
-                    used += need;
+            for (size_t i = 0; i < ctxs.size(); ++i) {
+                const int nch = (Nl[l] + nr - 1) / nr;
+                max_nch = std::max(max_nch, nch);
+                for (int c = 0; c < nch; ++c) {
+                    Chunk ch{c, {}};
+                    for (int smp = c * nr; smp < std::min(Nl[l], (c + 1) * nr); ++smp) ch.units.push_back({(int)i, l, smp});
+                    total_need += (size_t)ctxs[i]->V * bytes_per_site_sys * nr * (l < L ? 2 : 1);
+                    chunks.push_back(std::move(ch));
                 }
-        flush();
+            }
+        // Passes of equal make-up, so that every pass, and the next call of the
+        // same shape, reuses the same field sizes: with d passes dividing the
+        // chunks per (instance, level), pass k takes the chunks c = k mod d of
+        // every one; more passes than that deal the chunks round-robin.
+        const int need_pass = (int)std::max<size_t>(1, (total_need + budget - 1) / budget);
+        int d = need_pass;
+        while (d <= max_nch && max_nch % d) ++d;
+        const bool by_index = d <= max_nch;
+        if (!by_index) d = need_pass;
+        for (int k = 0; k < d; ++k) {
+            std::vector<std::array<int, 3>> units;
+            for (size_t j = 0; j < chunks.size(); ++j)
+                if ((by_index ? chunks[j].c : (int)j) % d == k)
+                    units.insert(units.end(), chunks[j].units.begin(), chunks[j].units.end());
+            if (!units.empty()) run_units(ctxs, prm, sigma, units, nr, wg, s, res, N);
+        }
     }
     // deviation from the plain FP64 path: the same estimate (same noise) solved in FP64
     std::vector<double> t64, scale64;
