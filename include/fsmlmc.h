@@ -68,6 +68,15 @@ typedef struct fs_batch_s* fs_batch;
 /* Library version string (static storage). */
 const char* fs_version(void);
 
+/*
+ * fs_struct_sizes -- sizeof of the structs of this header, in the order
+ * fs_solve_params, fs_solve_stats, fs_est_params, fs_level_stat,
+ * fs_total_stat, fs_est_report, fs_shift_model, into out[0 .. min(n, count)-1]
+ * (out may be null); returns the count.  Bindings compare them with their own
+ * layouts before the first call that takes a struct.
+ */
+int32_t fs_struct_sizes(int64_t* out, int32_t n);
+
 /* Message of the last failing call on the calling thread (never NULL). */
 const char* fs_last_error(void);
 
@@ -247,6 +256,13 @@ typedef struct {
                                 k in 1..16 samples V_L of every shift with m0 + s > 0
                                 through the hopping parameter expansion of order k
                                 (Sec. 3.1); 0: plain samples                        */
+    int32_t pad_;            /* reserved, 0                                          */
+    int64_t pass_bytes;      /* batched fs_estimate / fs_batch_estimate: upper bound
+                                on the device memory one pass of solves may take
+                                (the systems are split into passes of equal make-up
+                                within it); 0: min(half the free device memory,
+                                96 GiB).  Results do not depend on it beyond the
+                                rounding order of FP64 sums.                          */
 } fs_est_params;
 
 typedef struct {

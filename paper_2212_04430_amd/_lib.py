@@ -57,7 +57,8 @@ class fs_solve_stats(C.Structure):
 class fs_est_params(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_noise", C.c_int32), ("gamma_mask", C.c_uint16),
                 ("p_max", C.c_int32), ("solve", fs_solve_params), ("n_level", C.POINTER(C.c_int32)),
-                ("shared_noise", C.c_int32), ("report_fp64_error", C.c_int32), ("hpe_order", C.c_int32)]
+                ("shared_noise", C.c_int32), ("report_fp64_error", C.c_int32), ("hpe_order", C.c_int32),
+                ("pad_", C.c_int32), ("pass_bytes", C.c_int64)]
 
     def set_n_level(self, counts):
         """Per-level sample counts N_l (None: n_noise on every level); the array is kept alive here."""
@@ -99,6 +100,7 @@ class fs_shift_model(C.Structure):
 _P = C.c_void_p
 _sig = {
     "fs_version": (C.c_char_p, []),
+    "fs_struct_sizes": (C.c_int32, [_P, C.c_int32]),
     "fs_last_error": (C.c_char_p, []),
     "fs_create": (C.c_int, [C.POINTER(_P), C.POINTER(C.c_int32), C.c_int32, C.c_int32, _P]),
     "fs_destroy": (C.c_int, [_P]),
@@ -196,6 +198,18 @@ def solve_params(m0, tol=1e-10, max_iter=10000, storage="f64", rhs_block=0, use_
 
 def fs_version():
     return _lib.fs_version().decode()
+
+
+STRUCTS = (fs_solve_params, fs_solve_stats, fs_est_params, fs_level_stat, fs_total_stat, fs_est_report,
+           fs_shift_model)
+
+
+def fs_struct_sizes():
+    """sizeof of the header's structs, in the order of STRUCTS."""
+    n = _lib.fs_struct_sizes(None, 0)
+    out = (C.c_int64 * n)()
+    _lib.fs_struct_sizes(C.cast(out, _P), n)
+    return list(out)
 
 
 def fs_last_error():

@@ -2069,7 +2069,10 @@ void estimate_impl(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm,
         size_t bytes_per_site_sys = 4 * 192 + 6 * (size_t)prec_group_bytes_spinor(P) + (P == P16 ? 24 : 0);
         size_t free_b = 0, total_b = 0;
         HC(hipMemGetInfo(&free_b, &total_b));
-        const size_t budget = std::min<size_t>((free_b + pool().cached_bytes()) / 2, (size_t)96 << 30);
+        if (prm->pass_bytes < 0) fail(FS_E_ARG, "pass_bytes must be >= 0");
+        const size_t budget = prm->pass_bytes > 0 ? (size_t)prm->pass_bytes
+                                                  : std::min<size_t>((free_b + pool().cached_bytes()) / 2,
+                                                                     (size_t)96 << 30);
         // units in chunks of nr samples of one (instance, level): the rhs blocks
         struct Chunk {
             int c;  // chunk index within its (instance, level)
@@ -2093,7 +2096,8 @@ void estimate_impl(const std::vector<fs_ctx_s*>& ctxs, const fs_est_params* prm,
         // same shape, reuses the same field sizes: with d passes dividing the
         // chunks per (instance, level), pass k takes the chunks c = k mod d of
         // every one; more passes than that deal the chunks round-robin.
-        const int need_pass = (int)std::max<size_t>(1, (total_need + budget - 1) / budget);
+        const int need_pass =
+            (int)std::min<size_t>(chunks.size(), std::max<size_t>(1, (total_need + budget - 1) / budget));
         int d = need_pass;
         while (d <= max_nch && max_nch % d) ++d;
         const bool by_index = d <= max_nch;
@@ -2646,6 +2650,17 @@ fs_status ms_solve(fs_ctx_s* c, const fs_solve_params* prm, const double* sigma,
 extern "C" {
 
 const char* fs_version(void) { return "fsmlmc 0.1 (gfx950)"; }
+
+int32_t fs_struct_sizes(int64_t* out, int32_t n) {
+    const int64_t sz[] = {(int64_t)sizeof(fs_solve_params), (int64_t)sizeof(fs_solve_stats),
+                          (int64_t)sizeof(fs_est_params),   (int64_t)sizeof(fs_level_stat),
+                          (int64_t)sizeof(fs_total_stat),   (int64_t)sizeof(fs_est_report),
+                          (int64_t)sizeof(fs_shift_model)};
+    const int32_t count = (int32_t)(sizeof(sz) / sizeof(sz[0]));
+    if (out)
+        for (int32_t i = 0; i < std::min(n, count); ++i) out[i] = sz[i];
+    return count;
+}
 
 const char* fs_last_error(void) { return g_err.c_str(); }
 

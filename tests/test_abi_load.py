@@ -49,6 +49,16 @@ def test_binding_names_match_header():
         assert callable(getattr(L, f))
 
 
+def test_struct_layouts_match_header():
+    """Every struct the binding passes has the size the library was compiled with."""
+    import ctypes as C
+    from paper_2212_04430_amd import _lib as L
+    sizes = L.fs_struct_sizes()
+    assert len(sizes) == len(L.STRUCTS)
+    for st, n in zip(L.STRUCTS, sizes):
+        assert C.sizeof(st) == n, (st.__name__, C.sizeof(st), n)
+
+
 def test_argument_errors_before_device_work():
     from paper_2212_04430_amd import _lib as L
     with pytest.raises(L.FsError) as e:

@@ -6,6 +6,8 @@
   meets the FP64 residual bound and each instance's statistics equal those of
   the same instance estimated alone (both solved to 1e-10, so they agree to
   ~kappa * 1e-10 of the sample scale; asserted at 1e-6).
+* Passes: a batch split into several passes (pass_bytes) gives the samples of
+  the one-pass estimate to the solver tolerance, every system solved once.
 * Reproducibility: reductions are summed in a fixed order, so two estimates
   of the same inputs are bit-identical, in every storage precision.
 * Failure handling, forced from the host: a source orthogonal to the solver's
@@ -59,6 +61,55 @@ def test_uneven_batch_full_size_half_precision(L):
             scale = np.where(scale > 0, scale, 1.0)
             dev = np.abs((stats[k][..., 0] - single[..., 0]) + 1j * (stats[k][..., 1] - single[..., 1])) / scale
             assert dev.max() <= 1e-6, (k, dev.max())
+    finally:
+        for c in ctxs:
+            L.fs_destroy(c)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-8), ("f32", 1e-6)])
+def test_batch_estimate_in_passes_matches_one_pass(L, storage, tol):
+    """A pass bound (pass_bytes) below the batch's need splits the systems into
+    passes: rhs-block chunks of every (instance, level) dealt by chunk index
+    (two passes here), or one chunk per pass (a bound of one byte).  Every
+    sample must agree with the one-pass estimate to the solver tolerance (the
+    passes change only the workgroup split of the FP64 dot products), and every
+    system is solved exactly once."""
+    shapes = [(4, 4, 4, 4), (4, 4, 8, 4), (6, 4, 4, 4)]
+    sigma = [0.0, 0.3, 1.0]
+    nr, n = 2, 8
+    ctxs = []
+    try:
+        for k, d in enumerate(shapes):
+            c = L.fs_create(d, 0, 0)
+            L.fs_set_instance(c, k)
+            L.fs_upload_gauge(c, synth.gauge_field(d, eps=0.3, seed=10 + k))
+            ctxs.append(c)
+        batch = L.fs_batch_create(ctxs)
+        try:
+            sp = L.solve_params(0.1, tol=1e-10, storage=storage, batched=1, use_graph=1, rhs_block=nr,
+                                even_odd=1)
+            prm = L.fs_est_params(1, n, 0, 2, sp)
+            st1, X1, rep1 = L.fs_batch_estimate(batch, len(ctxs), prm, sigma, want_samples=True)
+            # the library's estimate of a pass's device memory: per site and system
+            # 4 FP64 spinors and 6 in the storage precision (+ FP16 scales)
+            low = {"f64": 192, "f32": 96}[storage]
+            per_site = 4 * 192 + 6 * low
+            Lv = len(sigma) - 1
+            need = sum(int(np.prod(d)) * per_site * nr * (2 if l < Lv else 1) * ((n + nr - 1) // nr)
+                       for d in shapes for l in range(Lv + 1))
+            for pb in (need // 2 + 1, 1):
+                print(f"{storage}: pass_bytes {pb} (one-pass need {need})", flush=True)
+                prm.pass_bytes = pb
+                st2, X2, rep2 = L.fs_batch_estimate(batch, len(ctxs), prm, sigma, want_samples=True)
+                assert rep2.systems == rep1.systems == len(shapes) * n * (2 * Lv + 1)
+                assert rep2.max_rel_residual <= 1e-10
+                scale = np.abs(X1).mean(axis=2, keepdims=True)
+                scale = np.where(scale > 0, scale, 1.0)
+                dev = (np.abs(X2 - X1) / scale).max()
+                assert dev <= tol, (pb, dev)
+                assert np.allclose(st2[..., 4], st1[..., 4])  # sample counts
+        finally:
+            L.fs_batch_destroy(batch)
     finally:
         for c in ctxs:
             L.fs_destroy(c)
