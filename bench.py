@@ -41,7 +41,9 @@ METRIC = "dslash GB/s (% HBM peak); shifted solves/sec at 1e-10, mixed+batched v
 HBM_PEAK_GBS = 8000.0
 TUNING = os.path.join(ROOT, "paper_2212_04430_amd", "tuning", "gfx950.txt")
 TRAFFIC = os.path.join(ROOT, "profiles", "dslash_eo_f32_batched_16c32_traffic.md")
-ROOFLINE_NSYS = 96
+# systems of the roofline launch: the step's whole batch (48 Z4 x 9 solves), the
+# size of the solver's hop launches while every block still runs
+ROOFLINE_NSYS = 432
 
 WORKLOAD = dict(dims=(16, 16, 16, 32), eps=0.2, m0=0.02, sigma=[0.0, 0.05, 0.25, 0.5, 1.0], n_noise=48,
                 p_max=8, seed=1, gauge_seed=0, tol=1e-10)
@@ -214,14 +216,14 @@ def link_form(L, ctx):
     return "2row" if L.fs_gauge_info(ctx)[0] else "whole"
 
 
-def roofline_only(L, ctx, nr, wg, storage="f32"):
+def roofline_only(L, ctx, nr, wg, storage="f32", nsys=ROOFLINE_NSYS):
     """The launches the roofline reports, alone (for hardware-counter runs);
-    another storage times the same hop in that precision."""
+    another storage or system count times the same hop in that configuration."""
     ms_c = L.fs_time_copy(ctx, 1 << 30, 20)
-    each, by = L.fs_time_dslash_eo_each(ctx, storage, ROOFLINE_NSYS, nr, 100)
+    each, by = L.fs_time_dslash_eo_each(ctx, storage, nsys, nr, 100)
     print(json.dumps({"copy_bytes": 1 << 30, "copy_ms": ms_c, "dslash_ms": float(np.median(each)),
                       "dslash_bytes": by,
-                      "config": f"{storage}-eo,nsys={ROOFLINE_NSYS},nr={nr},wg=256,links={link_form(L, ctx)}",
+                      "config": f"{storage}-eo,nsys={nsys},nr={nr},wg=256,links={link_form(L, ctx)}",
                       "hash": kernel_source_hash()}))
 
 
@@ -427,6 +429,8 @@ def main():
     ap.add_argument("--roofline-only", action="store_true", help="only the copy and stencil launches of the roofline")
     ap.add_argument("--roofline-storage", default="f32", choices=["f64", "f32", "f16", "bf16"],
                     help="precision of the stencil timed by --roofline-only")
+    ap.add_argument("--roofline-nsys", type=int, default=ROOFLINE_NSYS,
+                    help="systems of the stencil launch timed by --roofline-only")
     ap.add_argument("--estimate-only", default=None, choices=["f32", "f16", "bf16"],
                     help="only the step's estimate in this storage, warm-up and timed steps as given (for "
                          "kernel-trace runs); prints a short JSON line")
@@ -474,7 +478,7 @@ def main():
     if args.roofline_only:
         if args.roofline_storage != "f32":
             nr, wg = L.fs_autotune(ctx, args.roofline_storage, systems_per_step, cache)
-        roofline_only(L, ctx, nr, wg, args.roofline_storage)
+        roofline_only(L, ctx, nr, wg, args.roofline_storage, args.roofline_nsys)
         return
 
     # ---- batched mixed path, even-odd preconditioned: warmup + timed steps
