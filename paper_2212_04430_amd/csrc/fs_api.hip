@@ -283,7 +283,7 @@ int prec_link_complex_bytes(int P) { return P == P64 ? 16 : P == P32 ? 8 : 4; }
 // FP32, the two-row (6 complex) form.
 int prec_link_site_bytes(int P, bool two_rows) {
     if (two_rows && P == P32) return 48;
-    return P == P64 ? 144 : P == P32 ? 80 : 48;
+    return P == P64 ? 144 : P == P32 ? 80 : 36;
 }
 
 // Links whose third row equals the conjugated cross product of the first two
@@ -392,7 +392,7 @@ struct fs_ctx_s {
     uint32_t instance = 0;
     bool has_gauge = false;
     DevBuf gauge[4];                 // [mu][9][site] per precision
-    DevBuf gauge_q[4];               // [mu][site][QC 16-byte chunks] per precision
+    DevBuf gauge_q[4];               // [mu][site][link_q_bytes] per precision
     DevBuf gauge_q2[4];              // rows 0-1 only, [mu][site][QCR chunks] (FP32 entry only)
     bool two_rows = false;           // gauge_q2 is filled: every link is special unitary
     double su3_defect = 0.0;         // max |U_2j - conj(U_0 x U_1)_j| over the uploaded links

@@ -668,22 +668,23 @@ __global__ void k_gauge_convert(void* __restrict__ dst, const double* __restrict
     }
 }
 
-// Site-major copy of the links for quad-shared loads: link (mu, site) is QC
-// 16-byte chunks at ((mu * V + site) * QC), the complex entries packed
-// row-major in the storage precision, the tail padded with zeros.  The full
-// form (R = false, QC = Tr<P>::QC) keeps all 9 entries; the two-row form
-// (R = true, FP32 only, QC = Tr<P32>::QCR) keeps rows 0 and 1, whose cross
-// product gives row 2 of a special unitary link.
+// Site-major copy of the links for quad-shared loads: link (mu, site) is NW
+// 32-bit words at ((mu * V + site) * NW), the complex entries packed row-major
+// in the storage precision.  The full form (R = false) keeps all 9 entries in
+// link_q_bytes<P>() (FP64 and FP32 in 16-byte chunks, the tail padded with
+// zeros; FP16 and BF16 as nine words); the two-row form (R = true, FP32 only,
+// Tr<P32>::QCR chunks) keeps rows 0 and 1, whose cross product gives row 2 of a
+// special unitary link.
 template <int P, bool R>
 __global__ void k_gauge_convert_q(uint4* __restrict__ dst, const double* __restrict__ src, int V) {
     static_assert(!R || P == P32, "only FP32 links are kept in the two-row form");
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (size_t)4 * V) return;
-    constexpr int QC = R ? Tr<P32>::QCR : Tr<P>::QC;
+    constexpr int NW = R ? 4 * Tr<P32>::QCR : (int)(link_q_bytes<P>() / 4u);
     constexpr int NE = R ? 6 : 9;
-    uint32_t w[4 * QC];
+    uint32_t w[NW];
 #pragma unroll
-    for (int k = 0; k < 4 * QC; ++k) w[k] = 0u;
+    for (int k = 0; k < NW; ++k) w[k] = 0u;
     const double* s = src + i * 18;
 #pragma unroll
     for (int k = 0; k < NE; ++k) {
@@ -702,9 +703,15 @@ __global__ void k_gauge_convert_q(uint4* __restrict__ dst, const double* __restr
             w[k] = (uint32_t)f_to_bf16((float)re) | ((uint32_t)f_to_bf16((float)im) << 16);
         }
     }
-    uint4* d = dst + i * QC;  // i = mu * V + site
+    if constexpr (NW % 4 == 0) {
+        uint4* d = dst + i * (NW / 4);  // i = mu * V + site
 #pragma unroll
-    for (int c = 0; c < QC; ++c) d[c] = make_uint4(w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3]);
+        for (int c = 0; c < NW / 4; ++c) d[c] = make_uint4(w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3]);
+    } else {
+        uint32_t* d = reinterpret_cast<uint32_t*>(dst) + i * NW;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) d[k] = w[k];
+    }
 }
 
 // ------------------------------------------------------------------ Z4 noise

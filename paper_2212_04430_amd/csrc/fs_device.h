@@ -30,7 +30,7 @@ struct LatDesc {
     int eo;            // 1: fields hold one parity, field site = site >> 1
     int tsign;         // +1 periodic, -1 antiperiodic in t
     const void* gauge; // links in the launch's storage precision, [mu][9][site]
-    const void* gauge_q; // the same links site-major, [mu][site][QC 16-byte chunks], or
+    const void* gauge_q; // the same links site-major, [mu][site][link_q_bytes], or
                          // rows 0-1 only ([mu][site][QCR], FP32) in plans that rebuild row 2
     int pty, ptz;        // one-parity plans with the x-pair stencil: tile of TY x TZ pairs
                          // (dividing Ly, Lz) per workgroup; 0 otherwise
@@ -90,15 +90,20 @@ template <> struct Tr<P16> {
     static constexpr int G = 3;
     static constexpr int GB = 4;
     static constexpr int SB = 48;
-    static constexpr int QC = 3;   // 36 B padded to 48 B
 };
 template <> struct Tr<PBF> {
     using acc = float;
     static constexpr int G = 3;
     static constexpr int GB = 4;
     static constexpr int SB = 48;
-    static constexpr int QC = 3;   // 36 B padded to 48 B
 };
+
+// Bytes per site-major link (gauge_q): FP64 and FP32 as 16-byte chunks (the
+// FP32 tail padded), FP16 and BF16 as nine packed complex words, unpadded.
+template <int P> constexpr uint32_t link_q_bytes() {
+    if constexpr (P == P64 || P == P32) return 16u * Tr<P>::QC;
+    else return 36u;
+}
 
 // Link loads go through raw buffer instructions: a 128-bit resource holds a
 // wave-uniform base address and extent (scalar registers), each lane supplies
@@ -312,6 +317,18 @@ __device__ __forceinline__ void chunk_bcast(const uint4& c, uint32_t o[4]) {
     o[3] = quad_bcast<J>(c.w);
 }
 
+// Nine 32-bit words at byte offset off of rs, shared by a quad: lanes 0-2 load
+// three each (lane 3 repeats lane 2's), every lane receives all nine.
+__device__ __forceinline__ void load_words9_q(__amdgpu_buffer_rsrc_t rs, uint32_t off, int qd, uint32_t w[9]) {
+    const auto q = __builtin_amdgcn_raw_buffer_load_b96(rs, off + 12u * (uint32_t)(qd < 2 ? qd : 2), 0, 0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        w[k] = quad_bcast<0>(q[k]);
+        w[3 + k] = quad_bcast<1>(q[k]);
+        w[6 + k] = quad_bcast<2>(q[k]);
+    }
+}
+
 // Row 2 of a special unitary 3x3 matrix from rows 0 and 1: the complex
 // conjugate of their cross product, U_2j = conj(U_0k U_1l - U_0l U_1k) with
 // (j, k, l) a cyclic permutation of (0, 1, 2).  u holds the matrix row-major
@@ -365,7 +382,7 @@ __device__ __forceinline__ void load_link_q2(const void* __restrict__ gauge_q, i
 
 template <int P, typename A>
 __device__ __forceinline__ void load_link_q(const void* __restrict__ gauge_q, int V, int mu, int site, A u[18]) {
-    constexpr uint32_t QB = 16u * Tr<P>::QC;  // bytes per site
+    constexpr uint32_t QB = link_q_bytes<P>();  // bytes per site
     const int qd = threadIdx.x & 3;
     const uint32_t plane = uni((uint32_t)V * QB);
     const auto rs = buf_rsrc(reinterpret_cast<const char*>(gauge_q) + (size_t)mu * plane, plane);
@@ -403,13 +420,8 @@ __device__ __forceinline__ void load_link_q(const void* __restrict__ gauge_q, in
 #pragma unroll
         for (int k = 0; k < 18; ++k) u[k] = (A)__uint_as_float(w[k]);
     } else {
-        // three chunks: lanes 0-2 load one each (lane 3 repeats chunk 2)
-        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16u * (qd < 2 ? qd : 2), 0, 0);
-        const uint4 c = make_uint4(q[0], q[1], q[2], q[3]);
-        uint32_t w[12];
-        chunk_bcast<0>(c, w + 0);
-        chunk_bcast<1>(c, w + 4);
-        chunk_bcast<2>(c, w + 8);
+        uint32_t w[9];
+        load_words9_q(rs, off, qd, w);
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             if constexpr (P == P16) {

@@ -227,19 +227,11 @@ __device__ __forceinline__ void link_h(const LatDesc& ld, int mu, int site, uint
 #pragma unroll
         for (int k = 0; k < 9; ++k) u[k] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, k * plane, 0);
     } else {
-        // quad-shared: three 16-byte chunks per site, lanes 0-2 load one each
-        constexpr uint32_t QB = 16u * Tr<P16>::QC;
-        const int qd = threadIdx.x & 3;
+        // quad-shared: nine packed words per site, lanes 0-2 load three each
+        constexpr uint32_t QB = link_q_bytes<P16>();
         const uint32_t plane = uni((uint32_t)ld.V * QB);
         const auto rs = buf_rsrc(reinterpret_cast<const char*>(ld.gauge_q) + (size_t)mu * plane, plane);
-        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, (uint32_t)site * QB + 16u * (qd < 2 ? qd : 2), 0, 0);
-        const uint4 c = make_uint4(q[0], q[1], q[2], q[3]);
-        uint32_t w[12];
-        chunk_bcast<0>(c, w + 0);
-        chunk_bcast<1>(c, w + 4);
-        chunk_bcast<2>(c, w + 8);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) u[k] = w[k];
+        load_words9_q(rs, (uint32_t)site * QB, threadIdx.x & 3, u);
     }
 }
 
