@@ -32,7 +32,8 @@
  *    owns every buffer it passes; the library never frees or keeps them.
  *  * Every call returns fs_status and never aborts or throws across the ABI.
  *    FS_E_ARG is returned before anything is written.  The message of the
- *    last failing call on this thread is returned by fs_last_error().
+ *    last failing call is returned by fs_last_error(NULL) for the calling
+ *    thread and by fs_last_error(ctx) for the calls on a context.
  *  * Threads: calls on different contexts may come from different host
  *    threads (the library's device-memory cache is locked); calls on one
  *    context, or on a batch and its contexts, must not overlap.
@@ -77,8 +78,15 @@ const char* fs_version(void);
  */
 int32_t fs_struct_sizes(int64_t* out, int32_t n);
 
-/* Message of the last failing call on the calling thread (never NULL). */
-const char* fs_last_error(void);
+/*
+ * Message of the last failing call (never NULL; "no error" before any):
+ * ctx NULL -- of the calling thread, whatever the call;
+ * ctx set  -- of the calls made on that context (those whose first argument
+ *             is it, fs_destroy aside).  The string is owned by the library
+ *             and stays valid until the next failing call on that thread or
+ *             context, or fs_destroy(ctx).
+ */
+const char* fs_last_error(fs_ctx ctx);
 
 /*
  * fs_create -- one lattice instance on one device.

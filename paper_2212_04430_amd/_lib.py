@@ -101,7 +101,7 @@ _P = C.c_void_p
 _sig = {
     "fs_version": (C.c_char_p, []),
     "fs_struct_sizes": (C.c_int32, [_P, C.c_int32]),
-    "fs_last_error": (C.c_char_p, []),
+    "fs_last_error": (C.c_char_p, [_P]),
     "fs_create": (C.c_int, [C.POINTER(_P), C.POINTER(C.c_int32), C.c_int32, C.c_int32, _P]),
     "fs_destroy": (C.c_int, [_P]),
     "fs_set_instance": (C.c_int, [_P, C.c_uint32]),
@@ -154,7 +154,7 @@ EXPORTED = tuple(_sig)
 
 def _check(code, allow=()):
     if code != FS_OK and code not in allow:
-        raise FsError(code, _lib.fs_last_error().decode())
+        raise FsError(code, _lib.fs_last_error(None).decode())
     return code
 
 
@@ -212,8 +212,9 @@ def fs_struct_sizes():
     return list(out)
 
 
-def fs_last_error():
-    return _lib.fs_last_error().decode()
+def fs_last_error(ctx=None):
+    """Message of the last failing call on ctx, or on this thread (ctx None)."""
+    return _lib.fs_last_error(ctx).decode()
 
 
 def fs_create(dims, t_antiperiodic=0, device=0, stream=None):

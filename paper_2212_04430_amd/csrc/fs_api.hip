@@ -383,6 +383,7 @@ struct TuneEntry {
 };
 
 struct fs_ctx_s {
+    std::string last_err = "no error";  // message of the last failing call on this context
     int dims[4] = {0, 0, 0, 0};
     int V = 0;
     int tsign = 1;
@@ -410,6 +411,15 @@ struct fs_batch_s {
 };
 
 namespace {
+
+// guard() for calls on a context: a failure's message is also kept on the
+// context (fs_last_error(c)); a null context keeps it on the thread only.
+template <typename F>
+fs_status guard_ctx(fs_ctx c, F&& f) {
+    const fs_status st = guard(std::forward<F>(f));
+    if (st != FS_OK && c) c->last_err = g_err;
+    return st;
+}
 
 struct DeviceScope {
     int prev = -1;
@@ -2662,7 +2672,7 @@ int32_t fs_struct_sizes(int64_t* out, int32_t n) {
     return count;
 }
 
-const char* fs_last_error(void) { return g_err.c_str(); }
+const char* fs_last_error(fs_ctx c) { return c ? c->last_err.c_str() : g_err.c_str(); }
 
 fs_status fs_create(fs_ctx* out, const int32_t dims[4], int32_t t_antiperiodic, int32_t device, void* hip_stream) {
     return guard([&] {
@@ -2719,14 +2729,14 @@ fs_status fs_destroy(fs_ctx c) {
 }
 
 fs_status fs_set_instance(fs_ctx c, uint32_t instance) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c, false);
         c->instance = instance;
     });
 }
 
 fs_status fs_upload_gauge(fs_ctx c, const double* links, int32_t is_device) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c, false);
         if (!links) fail(FS_E_ARG, "null links");
         DeviceScope ds(c->device);
@@ -2761,7 +2771,7 @@ fs_status fs_upload_gauge(fs_ctx c, const double* links, int32_t is_device) {
 }
 
 fs_status fs_set_clover(fs_ctx c, double c_sw) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c);
         if (!std::isfinite(c_sw)) fail(FS_E_ARG, "c_sw must be finite");
         if (c_sw != 0.0 && (c->dims[0] % 2 || c->dims[1] % 2 || c->dims[2] % 2 || c->dims[3] % 2))
@@ -2785,7 +2795,7 @@ fs_status fs_set_clover(fs_ctx c, double c_sw) {
 }
 
 fs_status fs_gauge_info(fs_ctx c, int32_t* two_rows, double* su3_defect) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c);
         if (two_rows) *two_rows = c->two_rows ? 1 : 0;
         if (su3_defect) *su3_defect = c->su3_defect;
@@ -2794,7 +2804,7 @@ fs_status fs_gauge_info(fs_ctx c, int32_t* two_rows, double* su3_defect) {
 
 fs_status fs_apply_dirac(fs_ctx c, double m0, double sigma, fs_prec storage, const double* in, double* out,
                          int32_t n_rhs, int32_t is_device) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c);
         check_prec(storage);
         check_clover_prec(c, storage);
@@ -2833,12 +2843,12 @@ fs_status fs_apply_dirac(fs_ctx c, double m0, double sigma, fs_prec storage, con
 
 fs_status fs_apply_dirac_noalloc(fs_ctx c, double m0, double sigma, fs_prec storage, const double* in, double* out,
                                  int32_t n_rhs) {
-    return guard([&] { apply_dirac_noalloc(c, m0, sigma, storage, in, out, n_rhs); });
+    return guard_ctx(c, [&] { apply_dirac_noalloc(c, m0, sigma, storage, in, out, n_rhs); });
 }
 
 fs_status fs_z4_noise(fs_ctx c, uint64_t seed, uint32_t instance, uint32_t level, uint64_t sample, double* out,
                       int32_t is_device) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c, false);
         if (!out) fail(FS_E_ARG, "null buffer");
         DeviceScope ds(c->device);
@@ -2857,7 +2867,7 @@ fs_status fs_z4_noise(fs_ctx c, uint64_t seed, uint32_t instance, uint32_t level
 }
 
 fs_status fs_displace(fs_ctx c, int32_t p, const double* in, double* out, int32_t is_device) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c);
         if (!in || !out) fail(FS_E_ARG, "null buffer");
         if (p < 0) fail(FS_E_ARG, "p must be >= 0");
@@ -2876,7 +2886,7 @@ fs_status fs_displace(fs_ctx c, int32_t p, const double* in, double* out, int32_
 }
 
 fs_status fs_bilinear(fs_ctx c, int32_t p_max, const double* y, const double* x, double* out, int32_t is_device) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c);
         if (!y || !x || !out) fail(FS_E_ARG, "null buffer");
         if (p_max < 0 || p_max >= c->dims[2]) fail(FS_E_ARG, "p_max must be in [0, Lz)");
@@ -2946,7 +2956,7 @@ fs_status fs_bilinear(fs_ctx c, int32_t p_max, const double* y, const double* x,
 fs_status fs_solve_shifted(fs_ctx c, const fs_solve_params* prm, const double* sigma, int32_t n_shift, const double* B,
                            int32_t n_rhs, double* X, int32_t is_device, fs_solve_stats* stats) {
     fs_status worst = FS_OK;
-    fs_status st = guard([&] {
+    fs_status st = guard_ctx(c, [&] {
         check_ctx(c);
         if (!prm || !sigma || !B || !X) fail(FS_E_ARG, "null argument");
         if (n_shift < 1 || n_rhs < 1) fail(FS_E_ARG, "n_shift and n_rhs must be >= 1");
@@ -3055,13 +3065,16 @@ fs_status fs_solve_shifted(fs_ctx c, const fs_solve_params* prm, const double* s
         from_device(X, dX, nb1 * n_rhs * n_shift, is_device, s);
     });
     if (st != FS_OK) return st;
-    if (worst != FS_OK) g_err = "some systems did not reach tol";
+    if (worst != FS_OK) {
+        g_err = "some systems did not reach tol";
+        c->last_err = g_err;
+    }
     return worst;
 }
 
 fs_status fs_estimate(fs_ctx c, const fs_est_params* prm, const double* sigma, int32_t L, fs_level_stat* out,
                       double* samples_out, fs_est_report* report) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c);
         estimate_impl({c}, prm, sigma, L, out, samples_out, report);
     });
@@ -3070,7 +3083,7 @@ fs_status fs_estimate(fs_ctx c, const fs_est_params* prm, const double* sigma, i
 fs_status fs_sample_variances(fs_ctx c, const fs_est_params* prm, const double* shifts, int32_t m,
                               fs_level_stat* single, fs_level_stat* pair, double* samples_out,
                               double* iters_out, fs_est_report* report) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c);
         sampling_impl(c, prm, shifts, m, single, pair, samples_out, iters_out, report);
     });
@@ -3131,7 +3144,7 @@ fs_status fs_select_shifts(const fs_shift_model* model, int32_t L, int32_t* idx,
 }
 
 fs_status fs_sweep_shifts(fs_ctx c, const fs_shift_model* model, int32_t L, int32_t* idx, double* c_fs, double* ms) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c, false);
         if (!model || !idx || !c_fs) fail(FS_E_ARG, "null argument");
         if (L < 1 || L > kSweepMaxL) fail(FS_E_ARG, "L must be in 1..8 for the sweep");
@@ -3219,7 +3232,7 @@ fs_status fs_probing_colours(const int32_t dims[4], int32_t p, int32_t k, int32_
 fs_status fs_estimate_probed(fs_ctx c, const fs_est_params* prm, const double* sigma, int32_t L,
                              const int32_t* colours, int32_t n_colours, fs_level_stat* out, double* samples_out,
                              fs_est_report* report) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c);
         probed_impl(c, prm, sigma, L, colours, n_colours, out, samples_out, report);
     });
@@ -3304,7 +3317,7 @@ fs_status fs_batch_destroy(fs_batch b) {
 
 fs_status fs_time_dslash(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_block, int32_t wg, int32_t ilp,
                          int32_t occ, int32_t n_launch, double* avg_ms, double* bytes) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c);
         check_prec(storage);
         if (n_sys < 1 || n_launch < 1) fail(FS_E_ARG, "n_sys and n_launch must be >= 1");
@@ -3325,7 +3338,7 @@ fs_status fs_time_dslash(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_b
 
 fs_status fs_time_dslash_eo(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_block, int32_t occ,
                             int32_t n_launch, double* avg_ms, double* bytes) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c);
         check_prec(storage);
         check_eo(true, c);
@@ -3343,7 +3356,7 @@ fs_status fs_time_dslash_eo(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rh
 
 fs_status fs_time_dslash_eo_each(fs_ctx c, fs_prec storage, int32_t n_sys, int32_t rhs_block, int32_t n_launch,
                                  float* ms_each, double* bytes) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c);
         check_prec(storage);
         check_eo(true, c);
@@ -3360,7 +3373,7 @@ fs_status fs_time_dslash_eo_each(fs_ctx c, fs_prec storage, int32_t n_sys, int32
 }
 
 fs_status fs_set_eo_tuning(fs_ctx c, fs_prec storage, int32_t variant, int32_t occ) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c, false);
         check_prec(storage);
         if (variant != 0 && variant != 2) fail(FS_E_ARG, "even-odd variant must be 0 or 2");
@@ -3370,7 +3383,7 @@ fs_status fs_set_eo_tuning(fs_ctx c, fs_prec storage, int32_t variant, int32_t o
 }
 
 fs_status fs_time_copy(fs_ctx c, uint64_t bytes, int32_t n_launch, double* avg_ms) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c, false);
         if (bytes < 16 || n_launch < 1 || !avg_ms) fail(FS_E_ARG, "invalid copy size or count");
         DeviceScope ds(c->device);
@@ -3396,7 +3409,7 @@ fs_status fs_time_copy(fs_ctx c, uint64_t bytes, int32_t n_launch, double* avg_m
 }
 
 fs_status fs_set_tuning(fs_ctx c, fs_prec storage, int32_t rhs_block, int32_t wg, int32_t variant, int32_t occ) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c, false);
         check_prec(storage);
         if (!pow2_ok(rhs_block)) fail(FS_E_ARG, "rhs_block must be 1,2,4,8,16");
@@ -3414,7 +3427,7 @@ fs_status fs_set_tuning(fs_ctx c, fs_prec storage, int32_t rhs_block, int32_t wg
 
 fs_status fs_autotune(fs_ctx c, fs_prec storage, int32_t n_sys, const char* cache_path, int32_t* best_rhs_block,
                       int32_t* best_wg) {
-    return guard([&] {
+    return guard_ctx(c, [&] {
         check_ctx(c);
         check_prec(storage);
         if (n_sys < 1) fail(FS_E_ARG, "n_sys must be >= 1");

@@ -167,3 +167,31 @@ def test_error_bound_holds_sample_by_sample(L, cfg1, storage, tol):
     else:
         assert np.allclose(stats[..., 6], want, rtol=1e-6, atol=1e-15)
         assert stats[..., 6].max() <= 1e-7
+
+
+def test_last_error_per_context(L, cfg1):
+    """fs_last_error(ctx) keeps the message of the last failing call on each
+    context; fs_last_error(NULL) that of the last failing call on the thread."""
+    U, _ = cfg1
+    a = L.fs_create(DIMS, 0, 0)
+    b = _ctx(L, U)
+    try:
+        assert L.fs_last_error(a) == "no error" and L.fs_last_error(b) == "no error"
+        psi = synth.random_spinor(DIMS, seed=3)
+        with pytest.raises(L.FsError) as e:
+            L.fs_apply_dirac(a, M0, 0.0, "f64", psi)  # no gauge field on a
+        assert e.value.code == L.FS_E_STATE
+        msg_a = L.fs_last_error(a)
+        assert "gauge" in msg_a and L.fs_last_error(None) == msg_a
+        assert L.fs_last_error(b) == "no error"
+        with pytest.raises(L.FsError) as e:
+            L.fs_displace(b, -1, psi)
+        assert e.value.code == L.FS_E_ARG
+        msg_b = L.fs_last_error(b)
+        assert "p must be" in msg_b and L.fs_last_error(None) == msg_b
+        assert L.fs_last_error(a) == msg_a  # a keeps its own message
+        L.fs_apply_dirac(b, M0, 0.0, "f64", psi)  # a call that succeeds leaves it
+        assert L.fs_last_error(b) == msg_b
+    finally:
+        L.fs_destroy(a)
+        L.fs_destroy(b)
